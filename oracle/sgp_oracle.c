@@ -175,7 +175,10 @@ orc_graph *orc_collide_cells(int64_t n, const double *pos, const double *R, int 
         if (!(R[i] >= 0.0) || !isfinite(R[i])) { *status = ORC_EINVAL; return NULL; }
         if (R[i] > rmax) rmax = R[i];
     }
-    double h = 2.0 * rmax;
+    /* A touching pair is closer than 2 max R; the small margin keeps a pair
+     * that is closer than h by less than a rounding error of (x - lo)/h from
+     * landing two cells apart.  A larger cell never loses a pair. */
+    double h = 2.0 * rmax * (1.0 + 0x1p-20);
     if (h <= 0.0) h = 1.0;
     int64_t dim[3];
     for (int a = 0; a < 3; a++) dim[a] = (int64_t)floor((hi[a] - lo[a]) / h) + 1;
