@@ -1,0 +1,264 @@
+/*
+ * sgp.h -- C ABI of libsgp: support-graph (maximum-spanning-tree)
+ * preconditioned conjugate gradients for the friction equation Gamma v = F of
+ * off-lattice cell-based models, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Steinman & Buttenschoen, "Support Graph Preconditioners for
+ * Off-Lattice Cell-Based Models", arXiv 2410.04512.  The call chain follows
+ * the paper's simulation step (Section 2, Steps 1-4):
+ *
+ *   sgp_collide        Steps 1-2   which cells touch (collision graph)
+ *   sgp_assemble_gamma Step 3      friction blocks, Gamma as 3x3-block CSR
+ *   sgp_build_tree     Section 3.1 maximum spanning forest, rooted
+ *   sgp_factor_tree    Section 3.3 block LDL^T of the forest's Laplacian P
+ *   sgp_pcg_solve      Section 1.1 + Appendix B.1: PCG with z = P^{-1} r
+ *
+ * Conventions shared by every entry point
+ *  - Every int-returning call returns an sgp_status (0 = success, negative =
+ *    error).  No C++ exception crosses this boundary.  sgp_last_error(ctx)
+ *    gives a human-readable message for the last failing call on ctx.
+ *  - Pointers named as "device" must point to device memory of the GPU that
+ *    was current when the context was created; "host" pointers to host memory.
+ *    Caller-owned buffers stay owned by the caller; the library never frees
+ *    them and never keeps them after the call returns.
+ *  - Handles (sgp_graph, sgp_bsr, sgp_tree, sgp_prec) are library-owned and
+ *    are released with their *_free function.  A handle keeps its device
+ *    buffers between calls and only grows them, so repeated calls of the same
+ *    size allocate nothing.
+ *  - All work is ordered on the context's stream (borrowed from the caller).
+ *    Calls that must report a data-dependent size synchronise that stream;
+ *    each such call says so.
+ *  - Vectors of cell quantities are [n][3] row-major FP64 (x, y, z per cell).
+ *  - One context per host thread; a context is not thread-safe.
+ *  - Layouts of exported arrays are the canonical order: edges (i, j), i < j,
+ *    lexicographic; neighbour rows ascending; tree edges ascending.
+ */
+#ifndef SGP_H
+#define SGP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SGP_OK = 0,
+    SGP_EINVAL = -1,      /* bad argument (null pointer, negative size, coincident centres) */
+    SGP_ENOMEM = -2,      /* device allocation failed */
+    SGP_EHIP = -3,        /* a HIP runtime call failed */
+    SGP_ECAPACITY = -4,   /* a cell has more than max_deg contacts */
+    SGP_ENOTSPD = -5,     /* a 3x3 pivot block is not symmetric positive definite */
+    SGP_ENOCONV = -6,     /* max_iter reached before the tolerance */
+    SGP_EBREAKDOWN = -7,  /* CG breakdown: p.Gamma p <= 0 or not finite */
+    SGP_ENONFINITE = -8   /* NaN or Inf in an input or an iterate */
+} sgp_status;
+
+typedef struct sgp_ctx_ *sgp_ctx;
+typedef struct sgp_graph_ *sgp_graph;
+typedef struct sgp_bsr_ *sgp_bsr;
+typedef struct sgp_tree_ *sgp_tree;
+typedef struct sgp_prec_ *sgp_prec;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on the current HIP device that orders its work on
+ * `hip_stream` (a hipStream_t; NULL = the default stream).  The stream is
+ * borrowed: the caller keeps it alive until sgp_destroy. */
+int sgp_create(sgp_ctx *out, void *hip_stream);
+void sgp_destroy(sgp_ctx ctx);
+/* Message of the last failing call on ctx ("" if none).  Owned by ctx. */
+const char *sgp_last_error(sgp_ctx ctx);
+/* Change the stream subsequent calls are ordered on. */
+int sgp_set_stream(sgp_ctx ctx, void *hip_stream);
+
+/* ------------------------------------------------- Steps 1-2: collide */
+
+int sgp_graph_create(sgp_ctx ctx, sgp_graph *out);
+void sgp_graph_free(sgp_graph g);
+
+/* Collision graph of n spheres (Section 2, Steps 1-2).  pos [n][3] and
+ * radius [n] are device FP64.  Cells i < j touch iff d_ij < R_i + R_j with
+ * d_ij = sqrt((dx*dx + dy*dy) + dz*dz), dx = x_j - x_i (IEEE, no fused
+ * multiply-add); the overlap w_ij = (R_i + R_j) - d_ij stands in for the
+ * contact area A_ij and u_ij = (r_j - r_i)/d_ij is the unit contact vector.
+ * max_deg bounds the contacts of any one cell (SGP_ECAPACITY beyond it).
+ * Coincident centres in contact give SGP_EINVAL; non-finite positions
+ * SGP_ENONFINITE.  Synchronises the stream once (edge count). */
+int sgp_collide(sgp_ctx ctx, int64_t n, const double *pos, const double *radius,
+                int32_t max_deg, sgp_graph g);
+
+/* Same, for n_inst independent cell clusters stored back to back: cluster k
+ * owns cells [offsets[k], offsets[k+1]) (offsets: host int64 [n_inst+1],
+ * offsets[0] = 0).  Cells of different clusters never touch, wherever they
+ * are.  The result is the disjoint union of the clusters' graphs; edge ids of
+ * cluster k follow those of cluster k-1. */
+int sgp_collide_batched(sgp_ctx ctx, int64_t n_inst, const int64_t *offsets,
+                        const double *pos, const double *radius, int32_t max_deg, sgp_graph g);
+
+/* Sizes: n cells, m contacts.  Host outputs; either may be NULL. */
+int sgp_graph_size(sgp_graph g, int64_t *n, int64_t *m);
+
+/* Copy the graph into caller buffers (device pointers; NULL = skip):
+ * rowptr [n+1], col [2m] (neighbour rows ascending), ei, ej [m] (edges
+ * (i, j), i < j, lexicographic), w [m], u [m][3]. */
+int sgp_graph_export(sgp_ctx ctx, sgp_graph g, int32_t *rowptr, int32_t *col,
+                     int32_t *ei, int32_t *ej, double *w, double *u);
+
+/* ---------------------------------------- Step 3: friction matrix Gamma */
+
+int sgp_bsr_create(sgp_ctx ctx, sgp_bsr *out);
+void sgp_bsr_free(sgp_bsr A);
+
+/* Gamma as a 3x3-block CSR matrix (eq. cell_cell_friction and the block
+ * Laplacian definition of Section 2): for every contact e = (i, j),
+ * W_e = w_e (g_par u u^T + g_perp (I - u u^T)), Gamma_ij = Gamma_ji = -W_e;
+ * Gamma_ii = g_med I + the W_e of cell i's contacts added in ascending
+ * neighbour order.  Row i holds its neighbours and itself, columns ascending.
+ * g_par, g_perp > 0 and g_med >= 0, else SGP_EINVAL. */
+int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double g_perp, double g_med,
+                       sgp_bsr A);
+
+/* Sizes of the matrix: n block rows, nnzb stored blocks (n + 2m). */
+int sgp_bsr_size(sgp_bsr A, int64_t *n, int64_t *nnzb);
+
+/* Copy out (device pointers; NULL = skip): rowptr [n+1], bcol [nnzb],
+ * val [nnzb][3][3] row-major blocks. */
+int sgp_bsr_export(sgp_ctx ctx, sgp_bsr A, int32_t *rowptr, int32_t *bcol, double *val);
+
+/* y = Gamma x (device [n][3] FP64; x and y must not overlap). */
+int sgp_spmv(sgp_ctx ctx, sgp_bsr A, const double *x, double *y);
+
+/* ----------------------------- Section 3.1: maximum spanning forest */
+
+int sgp_tree_create(sgp_ctx ctx, sgp_tree *out);
+void sgp_tree_free(sgp_tree T);
+
+/* Maximum spanning forest of the collision graph weighted by w_e (the
+ * smallest eigenvalue of W_e is g_perp w_e or g_par w_e, so the order by w_e
+ * is the paper's order by lambda_min, Section 3.1), ties broken by the
+ * smaller edge id, so the forest is unique and equals Prim's.  Each tree is
+ * rooted at its smallest cell id; parent and hop depth are computed.
+ * Synchronises the stream. */
+int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T);
+
+/* n_tree_edges = n - (number of trees); n_roots; max_depth (host outputs,
+ * NULL = skip). */
+int sgp_tree_size(sgp_tree T, int64_t *n_tree_edges, int64_t *n_roots, int32_t *max_depth);
+
+/* Copy out (device pointers, NULL = skip): tree_edge [n_tree_edges] edge ids
+ * ascending; parent [n] (-1 at roots); depth [n] (0 at roots). */
+int sgp_tree_export(sgp_ctx ctx, sgp_tree T, int32_t *tree_edge, int32_t *parent, int32_t *depth);
+
+/* --------------------------------- Section 3.3: factor the support tree */
+
+int sgp_prec_create(sgp_ctx ctx, sgp_prec *out);
+void sgp_prec_free(sgp_prec M);
+
+/* Elimination schedules for the tree factorisation.  Any order that removes
+ * a vertex only after the vertices it connects to below it gives the exact
+ * LDL^T of P without fill (Lemma nofill):
+ *  SGP_SCHED_LEVEL     decreasing depth, one parallel step per level
+ *                      (Alg. 2's own order);
+ *  SGP_SCHED_CONTRACT  leaves and an independent set of one-child chain
+ *                      vertices are removed together in each step (rake and
+ *                      compress); a removed chain vertex joins its parent and
+ *                      child by a new 3x3 block, so the factor is the exact
+ *                      LDL^T of P in that order with O(log n) steps. */
+enum { SGP_SCHED_LEVEL = 0, SGP_SCHED_CONTRACT = 1 };
+
+/* Factor the block Laplacian P of the forest (self-loops g_med I included,
+ * Section 3.1): P_ii = g_med I + W_e of the tree edges at i (ascending edge
+ * id), P_{p(i),i} = -W_{e(i)}.  Pivot blocks are inverted in FP64 through a
+ * 3x3 Cholesky factor; a non-positive pivot gives SGP_ENOTSPD.
+ * Synchronises the stream. */
+int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_par, double g_perp,
+                    double g_med, int32_t schedule, sgp_prec M);
+
+/* Block-Jacobi preconditioner M = blockdiag(Gamma_ii) (comparison method of
+ * Section 5). */
+int sgp_make_jacobi(sgp_ctx ctx, sgp_bsr A, sgp_prec M);
+
+/* Number of parallel elimination steps of a tree preconditioner (host). */
+int sgp_prec_steps(sgp_prec M, int32_t *steps);
+
+/* z = M^{-1} r (device [n][3] FP64; r and z must not overlap).  For the tree
+ * this is ForwardSolve, DiagSolve and BackwardSolve of Appendix B.1. */
+int sgp_prec_apply(sgp_ctx ctx, sgp_prec M, const double *r, double *z);
+
+/* -------------------------------------------- Section 1.1: the solve */
+
+enum { SGP_PREC_F64 = 0, SGP_PREC_F32_IR = 1 };
+
+typedef struct {
+    double rtol;          /* stop when ||r_k|| / ||F|| <= rtol (recurrence residual) */
+    int32_t max_iter;     /* iteration cap (inner iterations in total for IR) */
+    int32_t fixed_iters;  /* > 0: run exactly this many iterations, ignore rtol */
+    int32_t use_x0;       /* 1: v holds the initial guess on entry; 0: start from 0 */
+    int32_t precision;    /* SGP_PREC_F64, or SGP_PREC_F32_IR: FP32 inner PCG inside FP64 refinement */
+    double inner_rtol;    /* IR only: relative tolerance of each inner FP32 solve */
+    int32_t max_outer;    /* IR only: cap on refinement steps */
+    int32_t check_every;  /* iterations between convergence reads by the host (0 = default) */
+} sgp_solve_opts;
+
+typedef struct {
+    int32_t status;       /* sgp_status of the solve */
+    int32_t iters;        /* CG iterations (all inner iterations for IR) */
+    int32_t outer_iters;  /* IR refinement steps (0 for plain PCG) */
+    int32_t pad;
+    double relres_rec;    /* ||r_k|| / ||F|| of the recurrence (FP64 residual for IR) */
+    double relres_true;   /* ||F - Gamma v|| / ||F|| recomputed at the end */
+} sgp_solve_info;
+
+/* Solve Gamma v = F by preconditioned CG (left form of Section 1.1's split
+ * preconditioning; Saad, Alg. 9.1).  M = NULL means no preconditioner.  F and
+ * v are device [n][3] FP64; v holds x0 on entry if opts->use_x0 and the
+ * solution on return (the last iterate if the status is SGP_ENOCONV).
+ * ||F|| = 0 gives v = 0 with 0 iterations.  info is a host pointer and is
+ * filled on every return; the call synchronises the stream. */
+int sgp_pcg_solve(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const double *F, double *v,
+                  const sgp_solve_opts *opts, sgp_solve_info *info);
+
+/* Independent solves of the block-diagonal system built from a batched
+ * collision graph: cluster k owns rows [offsets[k], offsets[k+1]) (host
+ * int64 [n_inst+1]).  Every cluster runs its own CG (own step lengths and
+ * stopping test) while all clusters share each kernel launch.  info is a
+ * host array [n_inst]. */
+int sgp_pcg_solve_batched(sgp_ctx ctx, sgp_bsr A, sgp_prec M, int64_t n_inst,
+                          const int64_t *offsets, const double *F, double *v,
+                          const sgp_solve_opts *opts, sgp_solve_info *info);
+
+/* ------------------------------------- Section 2, Steps 2 and 5 (dynamics) */
+
+/* F_i = noise_i + sum over contacts j of k_rep w_ij (r_i - r_j) / d_ij: pairwise
+ * repulsion along the line of centres plus a caller-drawn active force.
+ * noise, F device [n][3]. */
+int sgp_forces(sgp_ctx ctx, sgp_graph g, double k_rep, const double *noise, double *F);
+
+/* Forward Euler, Step 5: pos += dt v (device [n][3]). */
+int sgp_euler(sgp_ctx ctx, int64_t n, double dt, const double *v, double *pos);
+
+/* Launch-shape knobs of this process (chosen by the autotuner):
+ *  "spmv_lanes"   lanes per block row of the block-CSR product: 1, 2, 4, 8, 16
+ *  "check_every"  CG iterations between the host's convergence reads (>= 1)
+ * Unknown keys or values give SGP_EINVAL.  Results do not depend on
+ * check_every; spmv_lanes changes only the rounding order of each row sum. */
+int sgp_tune(sgp_ctx ctx, const char *key, int32_t value);
+
+/* Per-launch timing of the CG's block-CSR product: when enabled, every
+ * product launched by sgp_pcg_solve* is bracketed by HIP events on the
+ * context's stream; sgp_kernel_stats returns the summed duration (ms) and the
+ * number of timed launches since timing was enabled (enabling resets them).
+ * Launches of converged clusters exit at once and are still counted. */
+int sgp_kernel_timing(sgp_ctx ctx, int32_t enable);
+int sgp_kernel_stats(sgp_ctx ctx, double *total_ms, int64_t *launches);
+
+/* Duration of the last call of each phase on this context, measured with HIP
+ * events on its stream, in milliseconds:
+ * [0] collide, [1] assemble, [2] build_tree, [3] factor, [4] solve. */
+int sgp_phase_times(sgp_ctx ctx, double *ms5);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGP_H */

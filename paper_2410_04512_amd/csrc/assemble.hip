@@ -1,0 +1,128 @@
+// Step 3 of Section 2: the friction matrix Gamma as a 3x3-block CSR matrix.
+//
+// Gamma is the block Laplacian of the collision graph (Section 2, definition
+// of the block Laplacian): for a contact e = (i, j) with overlap w and unit
+// vector u, W_e = w (g_par u u^T + g_perp (I - u u^T)) (eq.
+// cell_cell_friction); Gamma_ij = Gamma_ji = -W_e; Gamma_ii = g_med I plus
+// the W_e of i's contacts.  Row i of the block matrix is row i of the
+// neighbour list with the diagonal block inserted in column order, so the
+// block layout needs no sort: block k of row i sits at rowptr[i] + i + k'.
+// The diagonal sum runs over the neighbours in ascending column order, with
+// the same operation order as the definition (no fused multiply-add), so the
+// assembled values are reproducible bit for bit.
+#include "sgp_internal.h"
+
+SGP_DEV void friction_block_asm(double w, double ux, double uy, double uz, double gpar, double gperp, double *W)
+{
+    const double u[3] = {ux, uy, uz};
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            double uu = u[a] * u[b];
+            double id = (a == b) ? 1.0 : 0.0;
+            W[3 * a + b] = w * (gpar * uu + gperp * (id - uu));
+        }
+}
+
+__global__ void k_assemble(int64_t n, const int32_t *rowptr, const int32_t *col, const int32_t *ent_edge,
+                           const double4 *wu, double gpar, double gperp, double gmed, int32_t *brow, int32_t *bcol,
+                           double *val, int32_t *diagpos)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = rowptr[i], e = rowptr[i + 1];
+    const int64_t base = (int64_t)b + i;
+    double D[9];
+    for (int t = 0; t < 9; t++) D[t] = (t % 4 == 0) ? gmed : 0.0;
+    int64_t dpos = base + (e - b);   // diagonal last unless a larger column appears
+    bool placed = false;
+    for (int32_t p = b; p < e; p++) {
+        int32_t j = col[p];
+        if (!placed && j > i) {
+            dpos = base + (p - b);
+            placed = true;
+        }
+        int64_t k = base + (p - b) + (placed ? 1 : 0);
+        double4 q = wu[ent_edge[p]];
+        double W[9];
+        friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
+        double *B = val + 9 * k;
+        for (int t = 0; t < 9; t++) {
+            B[t] = -W[t];
+            D[t] = D[t] + W[t];
+        }
+        bcol[k] = j;
+    }
+    for (int t = 0; t < 9; t++) val[9 * dpos + t] = D[t];
+    bcol[dpos] = (int32_t)i;
+    brow[i] = (int32_t)base;
+    diagpos[i] = (int32_t)dpos;
+    if (i == n - 1) brow[n] = (int32_t)(e + n);
+}
+
+extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double g_perp, double g_med, sgp_bsr A)
+{
+    if (!ctx || !g || !A) return set_err(ctx, SGP_EINVAL, "assemble_gamma: null handle");
+    if (!(g_par > 0) || !(g_perp > 0) || !(g_med >= 0))
+        return set_err(ctx, SGP_EINVAL, "assemble_gamma: need g_par > 0, g_perp > 0, g_med >= 0");
+    hipStream_t st = ctx->stream;
+    if (ctx->ev[2]) (void)hipEventRecord(ctx->ev[2], st);
+    const int64_t n = g->n, nnzb = n + 2 * g->m;
+    A->n = n;
+    A->nnzb = nnzb;
+    A->have32 = false;
+    int32_t *brow, *bcol, *dpos;
+    double *val;
+    SGP_TRY(ensure_t(ctx, A->rowptr, n + 1, &brow));
+    SGP_TRY(ensure_t(ctx, A->bcol, nnzb + 1, &bcol));
+    SGP_TRY(ensure_t(ctx, A->val, 9 * nnzb + 9, &val));
+    SGP_TRY(ensure_t(ctx, A->diagpos, n + 1, &dpos));
+    if (n == 0) return fill_i32(ctx, brow, 0, 1);
+    k_assemble<<<grid_for(n, 128), 128, 0, st>>>(n, (const int32_t *)g->rowptr.p, (const int32_t *)g->col.p,
+                                                 (const int32_t *)g->ent_edge.p, (const double4 *)g->wu.p, g_par,
+                                                 g_perp, g_med, brow, bcol, val, dpos);
+    LAUNCH_CHECK(ctx);
+    if (ctx->ev[3]) {
+        (void)hipEventRecord(ctx->ev[3], st);
+        (void)hipEventSynchronize(ctx->ev[3]);
+        (void)hipEventElapsedTime(&ctx->phase_ms[1], ctx->ev[2], ctx->ev[3]);
+    }
+    return SGP_OK;
+}
+
+extern "C" int sgp_bsr_size(sgp_bsr A, int64_t *n, int64_t *nnzb)
+{
+    if (!A) return SGP_EINVAL;
+    if (n) *n = A->n;
+    if (nnzb) *nnzb = A->nnzb;
+    return SGP_OK;
+}
+
+extern "C" int sgp_bsr_export(sgp_ctx ctx, sgp_bsr A, int32_t *rowptr, int32_t *bcol, double *val)
+{
+    if (!ctx || !A) return set_err(ctx, SGP_EINVAL, "bsr_export: null handle");
+    hipStream_t st = ctx->stream;
+    if (rowptr) HIP_TRY(ctx, hipMemcpyAsync(rowptr, A->rowptr.p, (A->n + 1) * 4, hipMemcpyDeviceToDevice, st));
+    if (A->nnzb > 0) {
+        if (bcol) HIP_TRY(ctx, hipMemcpyAsync(bcol, A->bcol.p, A->nnzb * 4, hipMemcpyDeviceToDevice, st));
+        if (val) HIP_TRY(ctx, hipMemcpyAsync(val, A->val.p, A->nnzb * 72, hipMemcpyDeviceToDevice, st));
+    }
+    return SGP_OK;
+}
+
+__global__ void k_round32(int64_t len, const double *a, float *b)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) b[i] = (float)a[i];
+}
+
+// FP32 copy of the values for the refinement's inner solve (rounded once)
+int bsr_make32(sgp_ctx ctx, sgp_bsr A)
+{
+    if (A->have32) return SGP_OK;
+    float *v32;
+    SGP_TRY(ensure_t(ctx, A->val32, 9 * A->nnzb + 9, &v32));
+    if (A->nnzb > 0) k_round32<<<grid_for(9 * A->nnzb, 256), 256, 0, ctx->stream>>>(9 * A->nnzb, (const double *)A->val.p, v32);
+    LAUNCH_CHECK(ctx);
+    A->have32 = true;
+    return SGP_OK;
+}

@@ -1,0 +1,742 @@
+// Section 1.1: preconditioned conjugate gradients on Gamma v = F, plus the
+// 3x3-block CSR product that dominates each iteration.
+//
+// Left-preconditioned CG (the left form of the split preconditioning E^T
+// Gamma E with H = E E^T = M^{-1}; Saad, Alg. 9.1):
+//   r = F - Gamma x0, z = M^{-1} r, p = z, rho = r.z
+//   repeat: q = Gamma p; alpha = rho / p.q; x += alpha p; r -= alpha q
+//           stop if ||r|| / ||F|| <= rtol
+//           z = M^{-1} r; rho' = r.z; p = z + (rho'/rho) p
+//
+// Every scalar lives on the device.  Each dot product is a fixed-shape
+// two-stage reduction (per-block partials in a fixed order, the last block of
+// a cluster sums them in a fixed order), so results are bitwise reproducible.
+// Clusters of a batched graph run independent CG recurrences: every launch
+// covers all clusters, blocks never straddle two clusters, and a cluster that
+// has converged skips its blocks.  The host only reads the "all done" state
+// every few iterations.
+#include "sgp_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+// ---------------------------------------------------------------- block tables
+
+struct BlockTab {
+    const int32_t *row0, *row1, *inst;   // per block
+    const int32_t *ifirst, *inb;         // per cluster: first block, number of blocks
+};
+
+// host-side construction: clusters are cut into blocks of rows_per_block rows
+static void build_tab(const std::vector<int64_t> &off, int rows_per_block, std::vector<int32_t> &buf,
+                      int32_t &nblocks)
+{
+    int64_t K = (int64_t)off.size() - 1;
+    std::vector<int32_t> r0, r1, in, f(K), nb(K);
+    for (int64_t k = 0; k < K; k++) {
+        f[k] = (int32_t)r0.size();
+        int64_t a = off[k], b = off[k + 1];
+        int32_t cnt = 0;
+        for (int64_t s = a; s < b; s += rows_per_block) {
+            r0.push_back((int32_t)s);
+            r1.push_back((int32_t)std::min<int64_t>(s + rows_per_block, b));
+            in.push_back((int32_t)k);
+            cnt++;
+        }
+        if (cnt == 0) {   // empty cluster: one empty block keeps the reductions uniform
+            r0.push_back((int32_t)a);
+            r1.push_back((int32_t)a);
+            in.push_back((int32_t)k);
+            cnt = 1;
+        }
+        nb[k] = cnt;
+    }
+    nblocks = (int32_t)r0.size();
+    buf.clear();
+    buf.insert(buf.end(), r0.begin(), r0.end());
+    buf.insert(buf.end(), r1.begin(), r1.end());
+    buf.insert(buf.end(), in.begin(), in.end());
+    buf.insert(buf.end(), f.begin(), f.end());
+    buf.insert(buf.end(), nb.begin(), nb.end());
+}
+
+static BlockTab tab_ptrs(const int32_t *d, int32_t nblocks, int64_t K)
+{
+    BlockTab t;
+    t.row0 = d;
+    t.row1 = d + nblocks;
+    t.inst = d + 2 * nblocks;
+    t.ifirst = d + 3 * nblocks;
+    t.inb = d + 3 * nblocks + K;
+    return t;
+}
+
+// per-cluster fixed-order reduction of one value per thread; fin(total) runs
+// in thread 0 of the cluster's last block.
+template <class Fin>
+SGP_DEV void cluster_reduce(double v, int b, int inst, const BlockTab &tab, double *part, unsigned *tickets,
+                            double *sh, int *flag, Fin fin)
+{
+    double s = block_sum_256(v, sh);
+    if (threadIdx.x == 0) part[b] = s;
+    if (!last_block(&tickets[inst], (unsigned)tab.inb[inst], flag)) return;
+    double tot = sum_partials(part + tab.ifirst[inst], tab.inb[inst], sh);
+    if (threadIdx.x == 0) fin(tot);
+}
+
+// ---------------------------------------------------------------- SpMV
+
+// G lanes per block row; lane l takes the row's blocks l, l+G, ...; a fixed
+// butterfly sums the G lanes.  mode 1 adds p.q for alpha (PCG).
+template <int G, class T>
+__global__ __launch_bounds__(256) void k_spmv(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ bcol,
+                                              const T *__restrict__ val, const T *__restrict__ x,
+                                              T *__restrict__ y, int64_t n, BlockTab tab, PcgScalars *S,
+                                              double *part, unsigned *tickets, int mode)
+{
+    __shared__ double sh[256];
+    __shared__ int flag;
+    const int b = blockIdx.x;
+    const int inst = tab.inst ? tab.inst[b] : 0;
+    if (S && S[inst].done) return;
+    const int64_t r0 = tab.row0 ? tab.row0[b] : (int64_t)b * (256 / G);
+    const int64_t r1 = tab.row1 ? tab.row1[b] : std::min<int64_t>(r0 + 256 / G, n);
+    const int64_t row = r0 + threadIdx.x / G;
+    const int lane = threadIdx.x % G;
+    const bool ok = row < r1;
+    T a0 = 0, a1 = 0, a2 = 0;
+    if (ok) {
+        const int32_t kb = rowptr[row], ke = rowptr[row + 1];
+        for (int32_t k = kb + lane; k < ke; k += G) {
+            const T *B = val + 9 * (int64_t)k;
+            const int64_t j = bcol[k];
+            const T x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
+            a0 += B[0] * x0 + B[1] * x1 + B[2] * x2;
+            a1 += B[3] * x0 + B[4] * x1 + B[5] * x2;
+            a2 += B[6] * x0 + B[7] * x1 + B[8] * x2;
+        }
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        a0 += __shfl_xor(a0, o, G);
+        a1 += __shfl_xor(a1, o, G);
+        a2 += __shfl_xor(a2, o, G);
+    }
+    if (ok && lane == 0) {
+        y[3 * row] = a0;
+        y[3 * row + 1] = a1;
+        y[3 * row + 2] = a2;
+    }
+    if (mode == 0) return;
+    double d = 0.0;
+    if (ok && lane == 0)
+        d = (double)x[3 * row] * (double)a0 + (double)x[3 * row + 1] * (double)a1 + (double)x[3 * row + 2] * (double)a2;
+    PcgScalars *Sc = S + inst;
+    cluster_reduce(d, b, inst, tab, part, tickets, sh, &flag, [&](double pq) {
+        Sc->pq = pq;
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            Sc->status = SGP_EBREAKDOWN;
+            Sc->done = 1;
+        } else {
+            Sc->alpha = Sc->rho / pq;
+        }
+    });
+}
+
+template <class T>
+static int spmv_dispatch(sgp_ctx ctx, int G, const int32_t *rowptr, const int32_t *bcol, const T *val, const T *x,
+                         T *y, int64_t n, BlockTab tab, int32_t nblocks, PcgScalars *S, double *part,
+                         unsigned *tickets, int mode)
+{
+    hipStream_t st = ctx->stream;
+    unsigned grid = tab.row0 ? (unsigned)nblocks : grid_for(n * G, 256);
+#define SPMV_CASE(g)                                                                                      \
+    case g:                                                                                               \
+        k_spmv<g, T><<<grid, 256, 0, st>>>(rowptr, bcol, val, x, y, n, tab, S, part, tickets, mode); \
+        break;
+    switch (G) {
+        SPMV_CASE(1)
+        SPMV_CASE(2)
+        SPMV_CASE(4)
+        SPMV_CASE(8)
+        SPMV_CASE(16)
+    default:
+        return set_err(ctx, SGP_EINVAL, "spmv: unsupported lanes per row %d", G);
+    }
+#undef SPMV_CASE
+    LAUNCH_CHECK(ctx);
+    return SGP_OK;
+}
+
+static int g_spmv_lanes = 4;   // lanes per block row (tunable through sgp_tune)
+
+extern "C" int sgp_spmv(sgp_ctx ctx, sgp_bsr A, const double *x, double *y)
+{
+    if (!ctx || !A || (A->n > 0 && (!x || !y))) return set_err(ctx, SGP_EINVAL, "spmv: bad arguments");
+    if (A->n == 0) return SGP_OK;
+    BlockTab none = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    return spmv_dispatch<double>(ctx, g_spmv_lanes, (const int32_t *)A->rowptr.p, (const int32_t *)A->bcol.p,
+                                 (const double *)A->val.p, x, y, A->n, none, 0, nullptr, nullptr, nullptr, 0);
+}
+
+// ---------------------------------------------------------------- vector kernels
+
+template <class T>
+SGP_DEV bool block_rows(const BlockTab &tab, int b, int64_t &row, int &inst)
+{
+    inst = tab.inst[b];
+    row = tab.row0[b] + threadIdx.x;
+    return row < tab.row1[b];
+}
+
+// r = F - q (q = Gamma x0) or r = F (x = 0); ||F||^2, ||r||^2, finite check
+template <class T>
+__global__ __launch_bounds__(256) void k_init_res(const double *F, const T *q, T *x, T *r, int use_x0, BlockTab tab,
+                                                  PcgScalars *S, double *part, unsigned *tickets)
+{
+    __shared__ double sh[256];
+    __shared__ int flag;
+    int b = blockIdx.x, inst;
+    int64_t row;
+    bool ok = block_rows<T>(tab, b, row, inst);
+    double ff = 0.0, rr = 0.0, bad = 0.0;
+    if (ok) {
+        for (int a = 0; a < 3; a++) {
+            double f = F[3 * row + a];
+            T ri;
+            if (use_x0) {
+                ri = (T)f - q[3 * row + a];
+                if (!isfinite((double)x[3 * row + a])) bad = 1.0;
+            } else {
+                ri = (T)f;
+                x[3 * row + a] = 0;
+            }
+            r[3 * row + a] = ri;
+            if (!isfinite(f)) bad = 1.0;
+            ff = ff + f * f;
+            rr = rr + (double)ri * (double)ri;
+        }
+    }
+    PcgScalars *Sc = S + inst;
+    double *p2 = part + gridDim.x, *p3 = part + 2 * gridDim.x;
+    double sff = block_sum_256(ff, sh), srr = block_sum_256(rr, sh), sbad = block_sum_256(bad, sh);
+    if (threadIdx.x == 0) {
+        part[b] = sff;
+        p2[b] = srr;
+        p3[b] = sbad;
+    }
+    if (!last_block(&tickets[inst], (unsigned)tab.inb[inst], &flag)) return;
+    double tff = sum_partials(part + tab.ifirst[inst], tab.inb[inst], sh);
+    double trr = sum_partials(p2 + tab.ifirst[inst], tab.inb[inst], sh);
+    double tbad = sum_partials(p3 + tab.ifirst[inst], tab.inb[inst], sh);
+    if (threadIdx.x == 0) {
+        Sc->nF2 = tff;
+        Sc->rr = trr;
+        Sc->iter = 0;
+        Sc->relres2 = tff > 0.0 ? trr / tff : 0.0;
+        if (tbad != 0.0 || !isfinite(trr)) {
+            Sc->status = SGP_ENONFINITE;
+            Sc->done = 1;
+        } else if (tff == 0.0) {
+            Sc->done = 2;   // zero force: the host writes v = 0
+        } else if (!Sc->fixed && Sc->relres2 <= Sc->tol2) {
+            Sc->done = 1;
+        }
+    }
+}
+
+// p = z, rho = r.z
+template <class T>
+__global__ __launch_bounds__(256) void k_init_p(const T *r, const T *z, T *p, BlockTab tab, PcgScalars *S,
+                                                double *part, unsigned *tickets)
+{
+    __shared__ double sh[256];
+    __shared__ int flag;
+    int b = blockIdx.x, inst;
+    int64_t row;
+    bool ok = block_rows<T>(tab, b, row, inst);
+    if (S[inst].done) return;
+    double rz = 0.0;
+    if (ok) {
+        for (int a = 0; a < 3; a++) {
+            T zi = z[3 * row + a];
+            p[3 * row + a] = zi;
+            rz = rz + (double)r[3 * row + a] * (double)zi;
+        }
+    }
+    PcgScalars *Sc = S + inst;
+    cluster_reduce(rz, b, inst, tab, part, tickets, sh, &flag, [&](double t) { Sc->rho = t; });
+}
+
+// x += alpha p; r -= alpha q; ||r||^2; stopping test
+template <class T>
+__global__ __launch_bounds__(256) void k_update_xr(T *x, T *r, const T *p, const T *q, BlockTab tab, PcgScalars *S,
+                                                   double *part, unsigned *tickets)
+{
+    __shared__ double sh[256];
+    __shared__ int flag;
+    int b = blockIdx.x, inst;
+    int64_t row;
+    bool ok = block_rows<T>(tab, b, row, inst);
+    PcgScalars *Sc = S + inst;
+    if (Sc->done) return;
+    const T alpha = (T)Sc->alpha;
+    double rr = 0.0;
+    if (ok) {
+        for (int a = 0; a < 3; a++) {
+            int64_t i = 3 * row + a;
+            x[i] = x[i] + alpha * p[i];
+            T ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            rr = rr + (double)ri * (double)ri;
+        }
+    }
+    cluster_reduce(rr, b, inst, tab, part, tickets, sh, &flag, [&](double t) {
+        Sc->rr = t;
+        Sc->iter = Sc->iter + 1;
+        Sc->relres2 = t / Sc->nF2;
+        if (!isfinite(t)) {
+            Sc->status = SGP_ENONFINITE;
+            Sc->done = 1;
+        } else if (Sc->fixed) {
+            if (Sc->iter >= Sc->fixed) Sc->done = 1;
+        } else if (Sc->relres2 <= Sc->tol2) {
+            Sc->done = 1;
+        } else if (Sc->iter >= Sc->max_iter) {
+            Sc->status = SGP_ENOCONV;
+            Sc->done = 1;
+        }
+    });
+}
+
+// rho' = r.z, beta = rho'/rho
+template <class T>
+__global__ __launch_bounds__(256) void k_rz(const T *r, const T *z, BlockTab tab, PcgScalars *S, double *part,
+                                            unsigned *tickets)
+{
+    __shared__ double sh[256];
+    __shared__ int flag;
+    int b = blockIdx.x, inst;
+    int64_t row;
+    bool ok = block_rows<T>(tab, b, row, inst);
+    PcgScalars *Sc = S + inst;
+    if (Sc->done) return;
+    double rz = 0.0;
+    if (ok)
+        for (int a = 0; a < 3; a++) rz = rz + (double)r[3 * row + a] * (double)z[3 * row + a];
+    cluster_reduce(rz, b, inst, tab, part, tickets, sh, &flag, [&](double t) {
+        Sc->beta = t / Sc->rho;
+        Sc->rho = t;
+    });
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_update_p(T *p, const T *z, BlockTab tab, const PcgScalars *S)
+{
+    int b = blockIdx.x, inst;
+    int64_t row;
+    bool ok = block_rows<T>(tab, b, row, inst);
+    const PcgScalars *Sc = S + inst;
+    if (Sc->done || !ok) return;
+    const T beta = (T)Sc->beta;
+    for (int a = 0; a < 3; a++) {
+        int64_t i = 3 * row + a;
+        p[i] = z[i] + beta * p[i];
+    }
+}
+
+// ||F - Gamma x||^2 per cluster (q = Gamma x given), stored in rz
+__global__ __launch_bounds__(256) void k_true_res(const double *F, const double *q, BlockTab tab, PcgScalars *S,
+                                                  double *part, unsigned *tickets)
+{
+    __shared__ double sh[256];
+    __shared__ int flag;
+    int b = blockIdx.x, inst;
+    int64_t row;
+    bool ok = block_rows<double>(tab, b, row, inst);
+    double rr = 0.0;
+    if (ok)
+        for (int a = 0; a < 3; a++) {
+            double t = F[3 * row + a] - q[3 * row + a];
+            rr = rr + t * t;
+        }
+    PcgScalars *Sc = S + inst;
+    cluster_reduce(rr, b, inst, tab, part, tickets, sh, &flag, [&](double t) { Sc->rz = t; });
+}
+
+template <class T>
+__global__ void k_zero_rows(T *x, BlockTab tab, const PcgScalars *S, int want_done)
+{
+    int b = blockIdx.x, inst;
+    int64_t row;
+    bool ok = block_rows<T>(tab, b, row, inst);
+    if (!ok || S[inst].done != want_done) return;
+    x[3 * row] = 0;
+    x[3 * row + 1] = 0;
+    x[3 * row + 2] = 0;
+}
+
+__global__ void k_set_scalars(PcgScalars *S, int64_t K, double tol2, int fixed, int max_iter)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    PcgScalars s = {};
+    s.tol2 = tol2;
+    s.fixed = fixed;
+    s.max_iter = max_iter;
+    S[k] = s;
+}
+
+__global__ void k_any_open(const PcgScalars *S, int64_t K, int32_t *open)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < K && !S[k].done) atomicAdd(open, 1);
+}
+
+// ---------------------------------------------------------------- the solver state
+
+struct PcgWork {
+    std::vector<int32_t> vec_buf, mv_buf;
+    int32_t vec_nb = 0, mv_nb = 0;
+    BlockTab vec, mv;
+};
+
+static int g_check_every = 8;
+
+template <class T>
+struct Vecs {
+    T *x, *r, *z, *p, *q;
+};
+
+// PCG iterations on prepared r, z (z = M r already), until every cluster is done.
+template <class T>
+static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const T *val, Vecs<T> v, PcgWork &w, PcgScalars *S,
+                       int64_t K, double *part, unsigned *tickets, int32_t *open, int check_every, int max_iter,
+                       int fixed)
+{
+    hipStream_t st = ctx->stream;
+    const int32_t *rowptr = (const int32_t *)A->rowptr.p, *bcol = (const int32_t *)A->bcol.p;
+    int32_t *hopen = (int32_t *)ctx->pinned;
+    const int limit = fixed > 0 ? fixed : max_iter;
+    for (int it = 0; it < limit;) {
+        int chunk = std::min(check_every, limit - it);
+        for (int c = 0; c < chunk; c++) {
+            SGP_TRY(ktimer_begin(ctx));
+            SGP_TRY(spmv_dispatch<T>(ctx, g_spmv_lanes, rowptr, bcol, val, v.p, v.q, A->n, w.mv, w.mv_nb, S, part,
+                                     tickets, 1));
+            SGP_TRY(ktimer_end(ctx));
+            k_update_xr<T><<<w.vec_nb, 256, 0, st>>>(v.x, v.r, v.p, v.q, w.vec, S, part, tickets);
+            if (M) {
+                // one cluster: the sweeps stop with it; several: every sweep runs
+                PcgScalars *gate = K == 1 ? S : nullptr;
+                if (sizeof(T) == 8)
+                    SGP_TRY(prec_apply_f64(ctx, M, (const double *)v.r, (double *)v.z, gate));
+                else
+                    SGP_TRY(prec_apply_f32(ctx, M, (const float *)v.r, (float *)v.z, gate));
+            }
+            k_rz<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.z, w.vec, S, part, tickets);
+            k_update_p<T><<<w.vec_nb, 256, 0, st>>>(v.p, v.z, w.vec, S);
+            LAUNCH_CHECK(ctx);
+        }
+        it += chunk;
+        SGP_TRY(fill_i32(ctx, open, 0, 1));
+        k_any_open<<<grid_for(K, 256), 256, 0, st>>>(S, K, open);
+        SGP_TRY(readback(ctx, hopen, open, 4));
+        SGP_TRY(ktimer_flush(ctx));
+        if (hopen[0] == 0) break;
+    }
+    return SGP_OK;
+}
+
+// Note on the batched tree sweeps: converged clusters are not skipped inside
+// the sweeps (their z is simply not used any more), only in the vector and
+// matrix kernels, which carry the per-cluster test.
+
+static int prepare_tabs(sgp_ctx ctx, const std::vector<int64_t> &off, PcgWork &w, DevBuf &dev)
+{
+    int64_t K = (int64_t)off.size() - 1;
+    build_tab(off, 256, w.vec_buf, w.vec_nb);
+    build_tab(off, 256 / g_spmv_lanes, w.mv_buf, w.mv_nb);
+    int32_t *d;
+    size_t nv = w.vec_buf.size(), nm = w.mv_buf.size();
+    SGP_TRY(ensure_t(ctx, dev, nv + nm + 2, &d));
+    HIP_TRY(ctx, hipMemcpyAsync(d, w.vec_buf.data(), nv * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d + nv, w.mv_buf.data(), nm * 4, hipMemcpyHostToDevice, ctx->stream));
+    w.vec = tab_ptrs(d, w.vec_nb, K);
+    w.mv = tab_ptrs(d + nv, w.mv_nb, K);
+    return SGP_OK;
+}
+
+static int solve_f64(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<int64_t> &off, const double *F, double *x,
+                     const sgp_solve_opts *o, sgp_solve_info *info)
+{
+    hipStream_t st = ctx->stream;
+    const int64_t n = A->n, K = (int64_t)off.size() - 1;
+    PcgWork w;
+    SGP_TRY(prepare_tabs(ctx, off, w, ctx->ws[WS_TMP6]));
+    double *r, *z, *p, *q, *part;
+    PcgScalars *S;
+    unsigned *tickets;
+    int32_t *open;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP0], 3 * n + 3, &r));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP1], 3 * n + 3, &p));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP2], 3 * n + 3, &q));
+    if (M) SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP3], 3 * n + 3, &z));
+    else z = r;   // no preconditioner: z is r
+    int32_t nbmax = std::max(w.vec_nb, w.mv_nb);
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_PART], 3 * (size_t)nbmax + 8, &part));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_SCAL], K + 1, &S));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP4], K + 8, &tickets));
+    open = (int32_t *)(tickets + K + 4);
+    SGP_TRY(fill_i32(ctx, (int32_t *)tickets, 0, K + 1));
+    int fixed = std::max(0, o->fixed_iters);
+    int max_iter = o->max_iter > 0 ? o->max_iter : 10000;
+    k_set_scalars<<<grid_for(K, 256), 256, 0, st>>>(S, K, o->rtol * o->rtol, fixed, max_iter);
+    LAUNCH_CHECK(ctx);
+    const int32_t *rowptr = (const int32_t *)A->rowptr.p, *bcol = (const int32_t *)A->bcol.p;
+    const double *val = (const double *)A->val.p;
+    if (o->use_x0)
+        SGP_TRY(spmv_dispatch<double>(ctx, g_spmv_lanes, rowptr, bcol, val, x, q, n, w.mv, w.mv_nb, nullptr, nullptr,
+                                      nullptr, 0));
+    k_init_res<double><<<w.vec_nb, 256, 0, st>>>(F, q, x, r, o->use_x0, w.vec, S, part, tickets);
+    LAUNCH_CHECK(ctx);
+    k_zero_rows<double><<<w.vec_nb, 256, 0, st>>>(x, w.vec, S, 2);
+    if (M) SGP_TRY(prec_apply_f64(ctx, M, r, z, nullptr));
+    k_init_p<double><<<w.vec_nb, 256, 0, st>>>(r, z, p, w.vec, S, part, tickets);
+    LAUNCH_CHECK(ctx);
+    Vecs<double> v = {x, r, z, p, q};
+    int ce = o->check_every > 0 ? o->check_every : g_check_every;
+    SGP_TRY(pcg_iterate<double>(ctx, A, M, val, v, w, S, K, part, tickets, open, ce, max_iter, fixed));
+    // true residual
+    SGP_TRY(spmv_dispatch<double>(ctx, g_spmv_lanes, rowptr, bcol, val, x, q, n, w.mv, w.mv_nb, nullptr, nullptr,
+                                  nullptr, 0));
+    k_true_res<<<w.vec_nb, 256, 0, st>>>(F, q, w.vec, S, part, tickets);
+    LAUNCH_CHECK(ctx);
+    std::vector<PcgScalars> hs(K);
+    SGP_TRY(readback(ctx, hs.data(), S, K * sizeof(PcgScalars)));
+    for (int64_t k = 0; k < K; k++) {
+        const PcgScalars &s = hs[k];
+        sgp_solve_info &I = info[k];
+        memset(&I, 0, sizeof I);
+        I.status = s.status;
+        if (!s.done && !s.status) I.status = fixed > 0 ? SGP_OK : SGP_ENOCONV;
+        I.iters = s.iter;
+        I.relres_rec = s.nF2 > 0 ? sqrt(s.relres2) : 0.0;
+        I.relres_true = s.nF2 > 0 ? sqrt(s.rz / s.nF2) : 0.0;
+    }
+    return SGP_OK;
+}
+
+// ---------------------------------------------------------------- FP32 inside FP64 refinement
+
+__global__ void k_f64_to_f32_vec(int64_t len, const double *a, float *b)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) b[i] = (float)a[i];
+}
+
+__global__ void k_res64(int64_t len, const double *F, const double *q, double *r)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) r[i] = F[i] - q[i];
+}
+
+__global__ void k_axpy_f32_into_f64(int64_t len, const float *d, double *x)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) x[i] = x[i] + (double)d[i];
+}
+
+// ||r||^2 / ||F||^2 of the FP64 residual, one cluster
+__global__ __launch_bounds__(256) void k_norm2_pair(const double *a, const double *b, BlockTab tab, PcgScalars *S,
+                                                    double *part, unsigned *tickets)
+{
+    __shared__ double sh[256];
+    __shared__ int flag;
+    int bl = blockIdx.x, inst;
+    int64_t row;
+    bool ok = block_rows<double>(tab, bl, row, inst);
+    double sa = 0.0, sb = 0.0;
+    if (ok)
+        for (int t = 0; t < 3; t++) {
+            sa = sa + a[3 * row + t] * a[3 * row + t];
+            sb = sb + b[3 * row + t] * b[3 * row + t];
+        }
+    double *p2 = part + gridDim.x;
+    double ta = block_sum_256(sa, sh), tb = block_sum_256(sb, sh);
+    if (threadIdx.x == 0) {
+        part[bl] = ta;
+        p2[bl] = tb;
+    }
+    if (!last_block(&tickets[inst], (unsigned)tab.inb[inst], &flag)) return;
+    double A2 = sum_partials(part + tab.ifirst[inst], tab.inb[inst], sh);
+    double B2 = sum_partials(p2 + tab.ifirst[inst], tab.inb[inst], sh);
+    if (threadIdx.x == 0) {
+        S[inst].rz = A2;    // ||r||^2
+        S[inst].nF2 = B2;   // ||F||^2
+    }
+}
+
+static int solve_ir(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const double *F, double *x, const sgp_solve_opts *o,
+                    sgp_solve_info *info)
+{
+    hipStream_t st = ctx->stream;
+    const int64_t n = A->n, len = 3 * n;
+    if (!M || M->kind == PREC_NONE) return set_err(ctx, SGP_EINVAL, "IR solve needs a preconditioner");
+    SGP_TRY(bsr_make32(ctx, A));
+    SGP_TRY(prec_make32(ctx, M));
+    std::vector<int64_t> off = {0, n};
+    PcgWork w;
+    SGP_TRY(prepare_tabs(ctx, off, w, ctx->ws[WS_TMP6]));
+    double *r64, *q64, *part;
+    float *r, *z, *p, *q, *d;
+    PcgScalars *S;
+    unsigned *tickets;
+    int32_t *open;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP0], len + 3, &r64));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP1], len + 3, &q64));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP2], 5 * len + 16, &r));
+    z = r + len + 3;
+    p = z + len + 3;
+    q = p + len + 3;
+    d = q + len + 3;
+    int32_t nbmax = std::max(w.vec_nb, w.mv_nb);
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_PART], 3 * (size_t)nbmax + 8, &part));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_SCAL], 2, &S));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP4], 16, &tickets));
+    open = (int32_t *)(tickets + 8);
+    SGP_TRY(fill_i32(ctx, (int32_t *)tickets, 0, 2));
+    const int32_t *rowptr = (const int32_t *)A->rowptr.p, *bcol = (const int32_t *)A->bcol.p;
+    const double *val = (const double *)A->val.p;
+    const float *val32 = (const float *)A->val32.p;
+    int max_outer = o->max_outer > 0 ? o->max_outer : 50;
+    int max_inner = o->max_iter > 0 ? o->max_iter : 10000;
+    double inner = o->inner_rtol > 0 ? o->inner_rtol : 1e-5;
+    int ce = o->check_every > 0 ? o->check_every : g_check_every;
+    if (!o->use_x0) HIP_TRY(ctx, hipMemsetAsync(x, 0, len * sizeof(double), st));
+    int total_inner = 0, outer = 0, status = SGP_OK;
+    double relres = 0.0;
+    PcgScalars hs;
+    for (;;) {
+        SGP_TRY(spmv_dispatch<double>(ctx, g_spmv_lanes, rowptr, bcol, val, x, q64, n, w.mv, w.mv_nb, nullptr,
+                                      nullptr, nullptr, 0));
+        k_res64<<<grid_for(len, 256), 256, 0, st>>>(len, F, q64, r64);
+        k_norm2_pair<<<w.vec_nb, 256, 0, st>>>(r64, F, w.vec, S, part, tickets);
+        LAUNCH_CHECK(ctx);
+        SGP_TRY(readback(ctx, &hs, S, sizeof hs));
+        if (!std::isfinite(hs.rz) || !std::isfinite(hs.nF2)) {
+            status = SGP_ENONFINITE;
+            break;
+        }
+        if (hs.nF2 == 0.0) {
+            HIP_TRY(ctx, hipMemsetAsync(x, 0, len * sizeof(double), st));
+            relres = 0.0;
+            break;
+        }
+        relres = sqrt(hs.rz / hs.nF2);
+        if (relres <= o->rtol) break;
+        if (outer >= max_outer || total_inner >= max_inner) {
+            status = SGP_ENOCONV;
+            break;
+        }
+        // inner FP32 solve of Gamma d = r, relative tolerance `inner`
+        k_set_scalars<<<1, 32, 0, st>>>(S, 1, inner * inner, 0, max_inner - total_inner);
+        k_init_res<float><<<w.vec_nb, 256, 0, st>>>(r64, q, d, r, 0, w.vec, S, part, tickets);
+        SGP_TRY(prec_apply_f32(ctx, M, r, z, nullptr));
+        k_init_p<float><<<w.vec_nb, 256, 0, st>>>(r, z, p, w.vec, S, part, tickets);
+        LAUNCH_CHECK(ctx);
+        Vecs<float> v = {d, r, z, p, q};
+        SGP_TRY(pcg_iterate<float>(ctx, A, M, val32, v, w, S, 1, part, tickets, open, ce, max_inner - total_inner, 0));
+        SGP_TRY(readback(ctx, &hs, S, sizeof hs));
+        total_inner += hs.iter;
+        if (hs.status == SGP_EBREAKDOWN || hs.status == SGP_ENONFINITE) {
+            status = hs.status;
+            break;
+        }
+        k_axpy_f32_into_f64<<<grid_for(len, 256), 256, 0, st>>>(len, d, x);
+        LAUNCH_CHECK(ctx);
+        outer++;
+    }
+    memset(info, 0, sizeof *info);
+    info->status = status;
+    info->iters = total_inner;
+    info->outer_iters = outer;
+    info->relres_rec = relres;
+    info->relres_true = relres;
+    return SGP_OK;
+}
+
+// ---------------------------------------------------------------- entry points
+
+static int solve_common(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<int64_t> &off, const double *F,
+                        double *v, const sgp_solve_opts *opts, sgp_solve_info *info)
+{
+    if (!ctx || !A || !opts || !info) return set_err(ctx, SGP_EINVAL, "pcg_solve: null argument");
+    if (A->n > 0 && (!F || !v)) return set_err(ctx, SGP_EINVAL, "pcg_solve: null vector");
+    if (M && M->kind != PREC_NONE && M->n != A->n) return set_err(ctx, SGP_EINVAL, "pcg_solve: M and A differ in size");
+    if (!(opts->rtol >= 0.0)) return set_err(ctx, SGP_EINVAL, "pcg_solve: rtol must be >= 0");
+    if (M && M->kind == PREC_NONE) M = nullptr;
+    const int64_t K = (int64_t)off.size() - 1;
+    if (A->n == 0) {
+        for (int64_t k = 0; k < K; k++) memset(&info[k], 0, sizeof info[k]);
+        return SGP_OK;
+    }
+    hipStream_t st = ctx->stream;
+    if (ctx->ev[8]) (void)hipEventRecord(ctx->ev[8], st);
+    int s;
+    if (opts->precision == SGP_PREC_F32_IR) {
+        if (K != 1) return set_err(ctx, SGP_EINVAL, "pcg_solve: FP32 refinement is single-cluster only");
+        s = solve_ir(ctx, A, M, F, v, opts, info);
+    } else {
+        s = solve_f64(ctx, A, M, off, F, v, opts, info);
+    }
+    if (s == SGP_OK && ctx->ev[9]) {
+        (void)hipEventRecord(ctx->ev[9], st);
+        (void)hipEventSynchronize(ctx->ev[9]);
+        (void)hipEventElapsedTime(&ctx->phase_ms[4], ctx->ev[8], ctx->ev[9]);
+    }
+    if (s != SGP_OK) return s;
+    int worst = SGP_OK;
+    for (int64_t k = 0; k < K; k++)
+        if (info[k].status != SGP_OK && worst == SGP_OK) worst = info[k].status;
+    if (worst != SGP_OK) set_err(ctx, worst, "pcg_solve: status %d", worst);
+    return worst;
+}
+
+extern "C" int sgp_pcg_solve(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const double *F, double *v,
+                             const sgp_solve_opts *opts, sgp_solve_info *info)
+{
+    if (!A) return set_err(ctx, SGP_EINVAL, "pcg_solve: null matrix");
+    std::vector<int64_t> off = {0, A->n};
+    return solve_common(ctx, A, M, off, F, v, opts, info);
+}
+
+extern "C" int sgp_pcg_solve_batched(sgp_ctx ctx, sgp_bsr A, sgp_prec M, int64_t n_inst, const int64_t *offsets,
+                                     const double *F, double *v, const sgp_solve_opts *opts, sgp_solve_info *info)
+{
+    if (!A || !offsets || n_inst <= 0) return set_err(ctx, SGP_EINVAL, "pcg_solve_batched: bad arguments");
+    if (offsets[0] != 0 || offsets[n_inst] != A->n)
+        return set_err(ctx, SGP_EINVAL, "pcg_solve_batched: offsets must cover [0, n)");
+    for (int64_t k = 0; k < n_inst; k++)
+        if (offsets[k + 1] < offsets[k]) return set_err(ctx, SGP_EINVAL, "pcg_solve_batched: offsets decrease");
+    std::vector<int64_t> off(offsets, offsets + n_inst + 1);
+    return solve_common(ctx, A, M, off, F, v, opts, info);
+}
+
+extern "C" int sgp_tune(sgp_ctx ctx, const char *key, int32_t value)
+{
+    if (!key) return set_err(ctx, SGP_EINVAL, "tune: null key");
+    if (!strcmp(key, "spmv_lanes")) {
+        if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+            return set_err(ctx, SGP_EINVAL, "tune: spmv_lanes must be 1, 2, 4, 8 or 16");
+        g_spmv_lanes = value;
+        return SGP_OK;
+    }
+    if (!strcmp(key, "check_every")) {
+        if (value < 1) return set_err(ctx, SGP_EINVAL, "tune: check_every must be >= 1");
+        g_check_every = value;
+        return SGP_OK;
+    }
+    return set_err(ctx, SGP_EINVAL, "tune: unknown key '%s'", key);
+}

@@ -1,0 +1,248 @@
+// Internal declarations of libsgp (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "sgp.h"
+
+// ---------------------------------------------------------------- buffers
+
+// Grow-only device buffer.  Contents are not preserved across growth.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// Per-context scalar block for the PCG drivers and reductions (device).
+struct PcgScalars {
+    double rho, alpha, beta, pq, rr, rz, nF2, tol2, relres2;
+    int32_t iter, done, status, fixed, max_iter, pad0;
+};
+
+struct sgp_ctx_ {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    unsigned *tickets = nullptr;   // device counters for last-block reductions (kept at 0 between uses)
+    int n_tickets = 0;
+    void *pinned = nullptr;        // small pinned host block for readbacks
+    DevBuf ws[24];                 // scratch workspaces (by role index)
+    hipEvent_t ev[12] = {};
+    float phase_ms[5] = {0, 0, 0, 0, 0};
+    // per-launch timing of the CG's matrix product (events on ctx->stream)
+    int ktiming = 0;
+    std::vector<hipEvent_t> kev;   // pairs (before, after)
+    int kev_used = 0;
+    double ktime_ms = 0.0;
+    int64_t klaunches = 0;
+};
+
+// event pair around one timed launch (no-op unless timing is on)
+int ktimer_begin(sgp_ctx ctx);
+int ktimer_end(sgp_ctx ctx);
+int ktimer_flush(sgp_ctx ctx);   // synchronises: adds finished pairs to the totals
+
+// workspace slots (shared scratch of a context; each call may reuse them)
+enum {
+    WS_KEY_A, WS_KEY_B, WS_VAL_A, WS_VAL_B, WS_HIST, WS_TILES, WS_SLOTS, WS_DEG, WS_TMP0, WS_TMP1,
+    WS_TMP2, WS_TMP3, WS_TMP4, WS_TMP5, WS_TMP6, WS_TMP7, WS_PART, WS_SCAL, WS_TMP8, WS_TMP9,
+    WS_COUNT
+};
+
+struct sgp_graph_ {
+    int64_t n = 0, m = 0, n_inst = 1;
+    DevBuf rowptr, col, ent_edge, ei, ej, wu, inst_off, inst_of;
+    std::vector<int64_t> h_inst_off;
+};
+
+struct sgp_bsr_ {
+    int64_t n = 0, nnzb = 0;
+    DevBuf rowptr, bcol, val, val32, diagpos;
+    bool have32 = false;
+};
+
+struct sgp_tree_ {
+    int64_t n = 0, nt = 0, n_roots = 0;
+    int32_t max_depth = 0;
+    DevBuf tree_edge, parent, pedge, depth, comp;
+    DevBuf tptr, tadj, tadje;   // forest incidence: rows of tree neighbours, ascending edge id
+};
+
+enum { PREC_NONE = 0, PREC_JACOBI = 1, PREC_TREE = 2 };
+
+struct sgp_prec_ {
+    int kind = PREC_NONE;
+    int64_t n = 0;
+    int schedule = 0;
+    int32_t steps = 0;
+    std::vector<int32_t> h_step_ptr;   // [steps+1] elimination-index ranges of each step
+    DevBuf elim, pos, up, in_ptr, in_src, F, Dinv, y;   // tree (F: [n][2][9], Dinv: [n][6])
+    DevBuf F32, Dinv32, y32;                            // FP32 copies for the refinement inner solve
+    bool have32 = false;
+    DevBuf jdinv;                                       // Jacobi: [n][6]
+};
+
+// ---------------------------------------------------------------- errors
+
+int set_err(sgp_ctx ctx, int code, const char *fmt, ...);
+
+#define HIP_TRY(ctx, expr)                                                                  \
+    do {                                                                                    \
+        hipError_t e__ = (expr);                                                            \
+        if (e__ != hipSuccess)                                                              \
+            return set_err((ctx), SGP_EHIP, "%s failed: %s (%s:%d)", #expr,                 \
+                           hipGetErrorString(e__), __FILE__, __LINE__);                     \
+    } while (0)
+
+#define LAUNCH_CHECK(ctx) HIP_TRY(ctx, hipGetLastError())
+
+#define SGP_TRY(expr)              \
+    do {                           \
+        int s__ = (expr);          \
+        if (s__ != SGP_OK) return s__; \
+    } while (0)
+
+int ensure(sgp_ctx ctx, DevBuf &b, size_t bytes);
+template <class T>
+inline int ensure_t(sgp_ctx ctx, DevBuf &b, size_t count, T **out)
+{
+    int s = ensure(ctx, b, count * sizeof(T) + 64);
+    *out = (T *)b.p;
+    return s;
+}
+void release(DevBuf &b);
+int readback(sgp_ctx ctx, void *host, const void *dev, size_t bytes);   // synchronises
+
+inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads) ? (unsigned)((n + threads - 1) / threads) : 1u; }
+
+// ---------------------------------------------------------------- primitives (util.hip)
+
+// out[0..n] = exclusive prefix sum of in[0..n-1]; out[n] = total.  in may alias out.
+int scan_exclusive(sgp_ctx ctx, const int32_t *in, int32_t *out, int64_t n);
+// Stable LSD radix sort of (key, val) pairs on the low key_bits bits.  tmp buffers of n.
+int radix_sort_pairs(sgp_ctx ctx, uint32_t *keys, int32_t *vals, uint32_t *ktmp, int32_t *vtmp,
+                     int64_t n, int key_bits);
+int fill_i32(sgp_ctx ctx, int32_t *p, int32_t v, int64_t n);
+int fill_f64(sgp_ctx ctx, double *p, double v, int64_t n);
+int iota_i32(sgp_ctx ctx, int32_t *p, int64_t n);
+
+// shared by several translation units
+int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScalars *s);
+int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s);
+int prec_make32(sgp_ctx ctx, sgp_prec M);
+int bsr_make32(sgp_ctx ctx, sgp_bsr A);
+int spmv_launch_f64(sgp_ctx ctx, sgp_bsr A, const double *x, double *y, PcgScalars *s, double *part,
+                    unsigned *ticket, int mode);
+int spmv_launch_f32(sgp_ctx ctx, sgp_bsr A, const float *x, float *y, PcgScalars *s, double *part,
+                    unsigned *ticket, int mode);
+
+// ---------------------------------------------------------------- device helpers
+
+#define SGP_DEV __device__ __forceinline__
+
+constexpr int RED_BLOCKS = 512;     // fixed grid of the deterministic reductions
+constexpr int RED_THREADS = 256;
+
+// Sum over a 256-thread block in a fixed order; result valid in thread 0.
+SGP_DEV double block_sum_256(double v, double *sh)
+{
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) sh[t] = sh[t] + sh[t + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Last-block detection for the two-stage reductions: every block writes its
+// partial, then takes a ticket; the block holding the last ticket sees all
+// partials (device-scope release/acquire through the fences) and resets the
+// counter for the next use.
+SGP_DEV bool last_block(unsigned *ticket, unsigned nblocks, int *sh_flag)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned t = atomicAdd(ticket, 1u);
+        *sh_flag = (t == nblocks - 1);
+        if (*sh_flag) {
+            __threadfence();
+            *ticket = 0u;
+        }
+    }
+    __syncthreads();
+    return *sh_flag != 0;
+}
+
+// Fixed-order sum of n partials by one 256-thread block; result in thread 0.
+SGP_DEV double sum_partials(const double *part, int n, double *sh)
+{
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) v = v + part[k];
+    return block_sum_256(v, sh);
+}
+
+// --- 3x3 blocks: full row-major [9]; symmetric packed [6] = (00,01,02,11,12,22)
+
+SGP_DEV void sym_unpack(const double *s, double *f)
+{
+    f[0] = s[0]; f[1] = s[1]; f[2] = s[2];
+    f[3] = s[1]; f[4] = s[3]; f[5] = s[4];
+    f[6] = s[2]; f[7] = s[4]; f[8] = s[5];
+}
+
+// Inverse of an SPD 3x3 block through its Cholesky factor C (D = C C^T);
+// returns false on a non-positive or non-finite pivot.  Result packed sym.
+SGP_DEV bool spd_inverse3(const double *D, double *inv6)
+{
+    double c00 = D[0];
+    if (!(c00 > 0.0) || !isfinite(c00)) return false;
+    c00 = sqrt(c00);
+    double c10 = D[3] / c00, c20 = D[6] / c00;
+    double c11 = D[4] - c10 * c10;
+    if (!(c11 > 0.0) || !isfinite(c11)) return false;
+    c11 = sqrt(c11);
+    double c21 = (D[7] - c20 * c10) / c11;
+    double c22 = D[8] - c20 * c20 - c21 * c21;
+    if (!(c22 > 0.0) || !isfinite(c22)) return false;
+    c22 = sqrt(c22);
+    // inverse of C (lower triangular)
+    double i00 = 1.0 / c00, i11 = 1.0 / c11, i22 = 1.0 / c22;
+    double i10 = -c10 * i00 * i11;
+    double i21 = -c21 * i11 * i22;
+    double i20 = -(c20 * i00 + c21 * i10) * i22;
+    // D^{-1} = C^{-T} C^{-1}
+    inv6[0] = i00 * i00 + i10 * i10 + i20 * i20;
+    inv6[1] = i10 * i11 + i20 * i21;
+    inv6[2] = i20 * i22;
+    inv6[3] = i11 * i11 + i21 * i21;
+    inv6[4] = i21 * i22;
+    inv6[5] = i22 * i22;
+    return true;
+}
+
+template <class T>
+SGP_DEV void sym_mv(const T *s, T x0, T x1, T x2, T &y0, T &y1, T &y2)
+{
+    y0 = s[0] * x0 + s[1] * x1 + s[2] * x2;
+    y1 = s[1] * x0 + s[3] * x1 + s[4] * x2;
+    y2 = s[2] * x0 + s[4] * x1 + s[5] * x2;
+}
+
+// c = a * b (full 3x3)
+SGP_DEV void mm3(const double *a, const double *b, double *c)
+{
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            c[3 * i + j] = a[3 * i + 0] * b[0 + j] + a[3 * i + 1] * b[3 + j] + a[3 * i + 2] * b[6 + j];
+}
