@@ -144,14 +144,38 @@ def test_pcg_velocity_parity_n1000(ctx, prec):
     assert info["relres_true"] <= 1.01e-8
 
 
+def _numpy_pcg(A, f, F, k):
+    """Second CPU implementation of the same CG (numpy dots, scipy product):
+    differs from the oracle only in rounding."""
+    import scipy.sparse as sp
+    S = sp.bsr_matrix((A.val, A.bcol, A.rowptr), shape=(3 * A.n, 3 * A.n)).tocsr()
+    b = F.ravel()
+    x = np.zeros_like(b); r = b.copy(); z = O.tree_solve(f, r).ravel(); p = z.copy(); rho = r @ z
+    for _ in range(k):
+        q = S @ p; a = rho / (p @ q); x += a * p; r -= a * q
+        z = O.tree_solve(f, r).ravel(); rn = r @ z; p = z + (rn / rho) * p; rho = rn
+    return x.reshape(-1, 3)
+
+
 def test_pcg_fixed_iterations_parity(ctx):
+    """The k-th iterate is a well-defined function of the inputs, but CG's
+    intermediate iterates amplify rounding: two correct CPU implementations
+    that differ only in summation order already differ by ~3e-8 (relative) at
+    k = 40 on this system.  Early iterates must agree to 1e-12; later ones to
+    within 10x the spread of the two CPU implementations."""
     c = sphere_cluster(3000, 2)
     for k in (1, 7, 40):
         out = gpu_chain(ctx, c, fixed_iters=k)
         oo = O.solve_pipeline(c["pos"], c["radius"], c["force"], fixed_iters=k)
         assert out["info"]["iters"] == k
         v, vo = host(out["v"]), oo["x"]
-        assert np.linalg.norm(v - vo) <= 1e-10 * np.linalg.norm(vo)
+        err = np.linalg.norm(v - vo) / np.linalg.norm(vo)
+        if k <= 7:
+            assert err <= 1e-12, (k, err)
+        else:
+            x2 = _numpy_pcg(oo["A"], oo["factor"], c["force"], k)
+            spread = np.linalg.norm(x2 - vo) / np.linalg.norm(vo)
+            assert err <= 10 * max(spread, 1e-12), (k, err, spread)
 
 
 def test_level_schedule_solve(ctx):
