@@ -31,9 +31,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-def spmv_bytes(n: int, nnzb: int, val_bytes: int = 72) -> int:
-    """Algorithmic bytes of one block-CSR product y = Gamma x: every stored
-    block (values + column index) once, the row pointers once, x once, y once."""
+def spmv_bytes(n: int, nnzb: int, val_bytes: int = 48) -> int:
+    """Algorithmic bytes of one block-CSR product y = Gamma x as the library
+    stores Gamma: every block's 6 distinct entries (the blocks are symmetric,
+    48 B in FP64) and its column index once, the row pointers once, x once,
+    y once."""
     return nnzb * (val_bytes + 4) + 4 * (n + 1) + 24 * n + 24 * n
 
 

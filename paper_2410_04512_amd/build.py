@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libsgp.so")
 OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["util.hip", "collide.hip", "assemble.hip", "tree.hip", "factor.hip", "pcg.hip",
+SOURCES = ["util.hip", "collide.hip", "assemble.hip", "spmv.hip", "tree.hip", "factor.hip", "pcg.hip",
            "dynamics.hip", "api.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -82,6 +82,7 @@ extern "C" void sgp_bsr_free(sgp_bsr A)
     if (!A) return;
     (void)hipDeviceSynchronize();
     release(A->rowptr); release(A->bcol); release(A->val); release(A->val32); release(A->diagpos);
+    release(A->wrow);
     delete A;
 }
 
@@ -100,6 +101,7 @@ extern "C" void sgp_prec_free(sgp_prec M)
     (void)hipDeviceSynchronize();
     release(M->elim); release(M->pos); release(M->up); release(M->in_ptr); release(M->in_src);
     release(M->F); release(M->Dinv); release(M->y); release(M->F32); release(M->Dinv32); release(M->y32);
+    release(M->tout); release(M->cs); release(M->cs32); release(M->step_ptr);
     release(M->jdinv);
     delete M;
 }

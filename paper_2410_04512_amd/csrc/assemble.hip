@@ -23,6 +23,17 @@ SGP_DEV void friction_block_asm(double w, double ux, double uy, double uz, doubl
         }
 }
 
+SGP_DEV void put_sym(double *val, int64_t k, const double *B)
+{
+    double *g = val + (k >> 6) * 384 + (k & 63);
+    g[0] = B[0];
+    g[64] = B[1];
+    g[128] = B[2];
+    g[192] = B[4];
+    g[256] = B[5];
+    g[320] = B[8];
+}
+
 __global__ void k_assemble(int64_t n, const int32_t *rowptr, const int32_t *col, const int32_t *ent_edge,
                            const double4 *wu, double gpar, double gperp, double gmed, int32_t *brow, int32_t *bcol,
                            double *val, int32_t *diagpos)
@@ -43,16 +54,16 @@ __global__ void k_assemble(int64_t n, const int32_t *rowptr, const int32_t *col,
         }
         int64_t k = base + (p - b) + (placed ? 1 : 0);
         double4 q = wu[ent_edge[p]];
-        double W[9];
+        double W[9], B[9];
         friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
-        double *B = val + 9 * k;
         for (int t = 0; t < 9; t++) {
             B[t] = -W[t];
             D[t] = D[t] + W[t];
         }
+        put_sym(val, k, B);
         bcol[k] = j;
     }
-    for (int t = 0; t < 9; t++) val[9 * dpos + t] = D[t];
+    put_sym(val, dpos, D);
     bcol[dpos] = (int32_t)i;
     brow[i] = (int32_t)base;
     diagpos[i] = (int32_t)dpos;
@@ -74,13 +85,19 @@ extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double
     double *val;
     SGP_TRY(ensure_t(ctx, A->rowptr, n + 1, &brow));
     SGP_TRY(ensure_t(ctx, A->bcol, nnzb + 1, &bcol));
-    SGP_TRY(ensure_t(ctx, A->val, 9 * nnzb + 9, &val));
+    SGP_TRY(ensure_t(ctx, A->val, sym_group_size(nnzb) + 8, &val));
     SGP_TRY(ensure_t(ctx, A->diagpos, n + 1, &dpos));
-    if (n == 0) return fill_i32(ctx, brow, 0, 1);
+    if (n == 0) {
+        A->nwaves = 0;
+        return fill_i32(ctx, brow, 0, 1);
+    }
+    // zero the padding of the last group (read by no row, kept finite)
+    SGP_TRY(fill_f64(ctx, val + (sym_group_size(nnzb) - 384), 0.0, 384));
     k_assemble<<<grid_for(n, 128), 128, 0, st>>>(n, (const int32_t *)g->rowptr.p, (const int32_t *)g->col.p,
                                                  (const int32_t *)g->ent_edge.p, (const double4 *)g->wu.p, g_par,
                                                  g_perp, g_med, brow, bcol, val, dpos);
     LAUNCH_CHECK(ctx);
+    SGP_TRY(bsr_prepare(ctx, A));
     if (ctx->ev[3]) {
         (void)hipEventRecord(ctx->ev[3], st);
         (void)hipEventSynchronize(ctx->ev[3]);
@@ -97,6 +114,18 @@ extern "C" int sgp_bsr_size(sgp_bsr A, int64_t *n, int64_t *nnzb)
     return SGP_OK;
 }
 
+__global__ void k_expand_sym(int64_t nnzb, const double *val, double *out)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnzb) return;
+    const double *g = val + (k >> 6) * 384 + (k & 63);
+    double a = g[0], b = g[64], c = g[128], d = g[192], e = g[256], f = g[320];
+    double *o = out + 9 * k;
+    o[0] = a; o[1] = b; o[2] = c;
+    o[3] = b; o[4] = d; o[5] = e;
+    o[6] = c; o[7] = e; o[8] = f;
+}
+
 extern "C" int sgp_bsr_export(sgp_ctx ctx, sgp_bsr A, int32_t *rowptr, int32_t *bcol, double *val)
 {
     if (!ctx || !A) return set_err(ctx, SGP_EINVAL, "bsr_export: null handle");
@@ -104,7 +133,10 @@ extern "C" int sgp_bsr_export(sgp_ctx ctx, sgp_bsr A, int32_t *rowptr, int32_t *
     if (rowptr) HIP_TRY(ctx, hipMemcpyAsync(rowptr, A->rowptr.p, (A->n + 1) * 4, hipMemcpyDeviceToDevice, st));
     if (A->nnzb > 0) {
         if (bcol) HIP_TRY(ctx, hipMemcpyAsync(bcol, A->bcol.p, A->nnzb * 4, hipMemcpyDeviceToDevice, st));
-        if (val) HIP_TRY(ctx, hipMemcpyAsync(val, A->val.p, A->nnzb * 72, hipMemcpyDeviceToDevice, st));
+        if (val) {
+            k_expand_sym<<<grid_for(A->nnzb, 256), 256, 0, st>>>(A->nnzb, (const double *)A->val.p, val);
+            LAUNCH_CHECK(ctx);
+        }
     }
     return SGP_OK;
 }
@@ -115,13 +147,15 @@ __global__ void k_round32(int64_t len, const double *a, float *b)
     if (i < len) b[i] = (float)a[i];
 }
 
-// FP32 copy of the values for the refinement's inner solve (rounded once)
+// FP32 copy of the values for the refinement's inner solve (rounded once,
+// same layout)
 int bsr_make32(sgp_ctx ctx, sgp_bsr A)
 {
     if (A->have32) return SGP_OK;
     float *v32;
-    SGP_TRY(ensure_t(ctx, A->val32, 9 * A->nnzb + 9, &v32));
-    if (A->nnzb > 0) k_round32<<<grid_for(9 * A->nnzb, 256), 256, 0, ctx->stream>>>(9 * A->nnzb, (const double *)A->val.p, v32);
+    int64_t len = sym_group_size(A->nnzb);
+    SGP_TRY(ensure_t(ctx, A->val32, len + 8, &v32));
+    if (A->nnzb > 0) k_round32<<<grid_for(len, 256), 256, 0, ctx->stream>>>(len, (const double *)A->val.p, v32);
     LAUNCH_CHECK(ctx);
     A->have32 = true;
     return SGP_OK;

@@ -13,7 +13,10 @@
 //    forward   y_q = D_q^{-1} (b_q - sum_{(u,k): up_k(u) = q} F[u][k] y_u)
 //    backward  x_q = y_q - D_q^{-1} sum_k F[q][k]^T x_{up_k(q)}
 // which is ForwardSolve, DiagSolve and BackwardSolve of Appendix B.1 with
-// the pivot solve folded into each sweep.
+// the pivot solve folded into each sweep.  The forward sweep pushes: once y_u
+// is known, u writes F[u][k] y_u into the slot its target reads (the target's
+// in-list entries are contiguous), so a target sums a run of slots in a fixed
+// order instead of chasing source indices.
 //
 // Schedules:
 //  LEVEL     step = max depth - depth: Alg. 2's order (decreasing distance
@@ -156,10 +159,14 @@ __global__ void k_contract_apply(int64_t n, int32_t s, const int32_t *stepv, con
     atomicAdd(cnt, 1);
 }
 
-__global__ void k_step_count(int64_t n, const int32_t *stepv, int32_t *cnt)
+// step boundaries from the keys sorted by step: sptr[s] = first q of step s
+__global__ void k_step_bounds(int64_t n, const uint32_t *skey, int32_t S, int32_t *sptr)
 {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) atomicAdd(&cnt[stepv[v]], 1);
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > n) return;
+    int32_t lo = q == 0 ? -1 : (int32_t)skey[q - 1];
+    int32_t hi = q == n ? S : (int32_t)skey[q];
+    for (int32_t s = lo + 1; s <= hi; s++) sptr[s] = (int32_t)q;
 }
 
 __global__ void k_stepkeys(int64_t n, const int32_t *stepv, uint32_t *key, int32_t *val)
@@ -260,6 +267,12 @@ __global__ void k_factor_step(int32_t q0, int32_t q1, const int32_t *elim, const
     }
 }
 
+__global__ void k_slot_of(const int32_t *n_in, const int32_t *in_src, int32_t *tout)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < *n_in) tout[in_src[t]] = (int32_t)t;
+}
+
 // E is stored per vertex id for the initial blocks; the factor works in
 // elimination numbering: permute once.
 __global__ void k_permute9(int64_t n, const int32_t *elim, const double *src, double *dst)
@@ -272,39 +285,51 @@ __global__ void k_permute9(int64_t n, const int32_t *elim, const double *src, do
 
 // ---------------------------------------------------------------- sweeps
 
+
+// forward substitution of one vertex q (pivot solve folded in), then the
+// push of its contributions to the vertices above it
 template <class T>
-__global__ void k_fwd_step(int32_t q0, int32_t q1, const int32_t *elim, const int32_t *in_ptr,
-                           const int32_t *in_src, const T *F, const T *Dinv, const T *r, T *y,
-                           const PcgScalars *s)
+SGP_DEV void fwd_vertex(int32_t q, const int32_t *elim, const int32_t *in_ptr, const int32_t *tout, const T *F,
+                        const T *Dinv, const T *r, T *y, T *cs)
 {
-    if (s && s->done) return;
-    int32_t q = q0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (q >= q1) return;
     int64_t v = elim[q];
     T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
-    for (int32_t t = in_ptr[q]; t < in_ptr[q + 1]; t++) {
-        int32_t src = in_src[t];
-        const T *Fm = F + 9 * (int64_t)src;
-        int64_t u = src >> 1;
-        T y0 = y[3 * u], y1 = y[3 * u + 1], y2 = y[3 * u + 2];
-        b0 = b0 - (Fm[0] * y0 + Fm[1] * y1 + Fm[2] * y2);
-        b1 = b1 - (Fm[3] * y0 + Fm[4] * y1 + Fm[5] * y2);
-        b2 = b2 - (Fm[6] * y0 + Fm[7] * y1 + Fm[8] * y2);
+    int32_t t = in_ptr[q];
+    const int32_t te = in_ptr[q + 1];
+    // slots are independent loads: fetch four at a time, add in order
+    for (; t + 4 <= te; t += 4) {
+        const T *c = cs + 3 * (int64_t)t;
+        T c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5];
+        T c6 = c[6], c7 = c[7], c8 = c[8], c9 = c[9], c10 = c[10], c11 = c[11];
+        b0 = b0 - c0; b1 = b1 - c1; b2 = b2 - c2;
+        b0 = b0 - c3; b1 = b1 - c4; b2 = b2 - c5;
+        b0 = b0 - c6; b1 = b1 - c7; b2 = b2 - c8;
+        b0 = b0 - c9; b1 = b1 - c10; b2 = b2 - c11;
+    }
+    for (; t < te; t++) {
+        const T *c = cs + 3 * (int64_t)t;
+        b0 = b0 - c[0]; b1 = b1 - c[1]; b2 = b2 - c[2];
     }
     T o0, o1, o2;
     sym_mv(Dinv + 6 * (int64_t)q, b0, b1, b2, o0, o1, o2);
     y[3 * (int64_t)q] = o0;
     y[3 * (int64_t)q + 1] = o1;
     y[3 * (int64_t)q + 2] = o2;
+    for (int k = 0; k < 2; k++) {
+        int32_t to = tout[2 * q + k];
+        if (to < 0) continue;
+        const T *Fm = F + 9 * (2 * (int64_t)q + k);
+        T *c = cs + 3 * (int64_t)to;
+        c[0] = Fm[0] * o0 + Fm[1] * o1 + Fm[2] * o2;
+        c[1] = Fm[3] * o0 + Fm[4] * o1 + Fm[5] * o2;
+        c[2] = Fm[6] * o0 + Fm[7] * o1 + Fm[8] * o2;
+    }
 }
 
+// backward substitution of one vertex q; y holds x for the vertices above
 template <class T>
-__global__ void k_bwd_step(int32_t q0, int32_t q1, const int32_t *elim, const int32_t *upq, const T *F,
-                           const T *Dinv, T *y, T *z, const PcgScalars *s)
+SGP_DEV void bwd_vertex(int32_t q, const int32_t *elim, const int32_t *upq, const T *F, const T *Dinv, T *y, T *z)
 {
-    if (s && s->done) return;
-    int32_t q = q0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (q >= q1) return;
     T a0 = 0, a1 = 0, a2 = 0;
     for (int k = 0; k < 2; k++) {
         int32_t w = upq[2 * q + k];
@@ -325,6 +350,159 @@ __global__ void k_bwd_step(int32_t q0, int32_t q1, const int32_t *elim, const in
     z[3 * v] = x0;
     z[3 * v + 1] = x1;
     z[3 * v + 2] = x2;
+}
+
+template <class T>
+__global__ void k_fwd_step(int32_t q0, int32_t q1, const int32_t *elim, const int32_t *in_ptr,
+                           const int32_t *tout, const T *F, const T *Dinv, const T *r, T *y, T *cs,
+                           const PcgScalars *s)
+{
+    if (s && s->done) return;
+    int32_t q = q0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q < q1) fwd_vertex<T>(q, elim, in_ptr, tout, F, Dinv, r, y, cs);
+}
+
+template <class T>
+__global__ void k_bwd_step(int32_t q0, int32_t q1, const int32_t *elim, const int32_t *upq, const T *F,
+                           const T *Dinv, T *y, T *z, const PcgScalars *s)
+{
+    if (s && s->done) return;
+    int32_t q = q0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q < q1) bwd_vertex<T>(q, elim, upq, F, Dinv, y, z);
+}
+
+// The last, small steps of both sweeps in one workgroup.  The tail vertices
+// q >= Qt (elimination order) and the pushes between them live in LDS:
+//   sv[q - Qt]   the right-hand side, then y_q, then x_q (in place)
+//   slot[i]      the contribution of a tail source to a tail target; the
+//                internal in-entries of a target are the last ones of its
+//                in-list, so its slots form one range iptr[q-Qt]..iptr[q-Qt+1]
+// Contributions from vertices eliminated before the tail are summed first,
+// for all tail vertices in parallel.  A barrier separates two steps; all
+// up-links of tail vertices point into the tail, so the backward steps read
+// x only from LDS.  x is also written to y (global) for the earlier steps.
+constexpr int TAIL_THREADS = 1024;
+constexpr int TAIL_LDS_BYTES = 160 * 1024;
+int g_tail_max = 2200;
+
+template <class T>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, int32_t Qt, int32_t nt, int32_t ni,
+                                                       const int32_t *sp, const int32_t *elim, const int32_t *in_ptr,
+                                                       const int32_t *iptr, const int32_t *tslot, const int32_t *upq,
+                                                       const T *F, const T *Dinv, const T *r, const T *cs, T *y,
+                                                       T *z, const PcgScalars *s)
+{
+    extern __shared__ unsigned char lds_raw[];
+    T *sv = (T *)lds_raw;
+    T *slot = sv + 3 * nt;
+    if (s && s->done) return;
+    (void)ni;
+    // pre-tail contributions
+    for (int32_t i = threadIdx.x; i < nt; i += TAIL_THREADS) {
+        const int32_t q = Qt + i;
+        const int64_t v = elim[q];
+        T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
+        const int32_t te = in_ptr[q + 1] - (iptr[i + 1] - iptr[i]);
+        for (int32_t t = in_ptr[q]; t < te; t++) {
+            b0 = b0 - cs[3 * (int64_t)t];
+            b1 = b1 - cs[3 * (int64_t)t + 1];
+            b2 = b2 - cs[3 * (int64_t)t + 2];
+        }
+        sv[3 * i] = b0;
+        sv[3 * i + 1] = b1;
+        sv[3 * i + 2] = b2;
+    }
+    __syncthreads();
+    // forward steps
+    for (int32_t k = s0; k < S; k++) {
+        for (int32_t q = sp[k] + threadIdx.x; q < sp[k + 1]; q += TAIL_THREADS) {
+            const int32_t i = q - Qt;
+            T b0 = sv[3 * i], b1 = sv[3 * i + 1], b2 = sv[3 * i + 2];
+            for (int32_t j = iptr[i]; j < iptr[i + 1]; j++) {
+                b0 = b0 - slot[3 * j];
+                b1 = b1 - slot[3 * j + 1];
+                b2 = b2 - slot[3 * j + 2];
+            }
+            T o0, o1, o2;
+            sym_mv(Dinv + 6 * (int64_t)q, b0, b1, b2, o0, o1, o2);
+            sv[3 * i] = o0;
+            sv[3 * i + 1] = o1;
+            sv[3 * i + 2] = o2;
+            for (int kk = 0; kk < 2; kk++) {
+                const int32_t d = tslot[2 * i + kk];
+                if (d < 0) continue;
+                const T *Fm = F + 9 * (2 * (int64_t)q + kk);
+                slot[3 * d] = Fm[0] * o0 + Fm[1] * o1 + Fm[2] * o2;
+                slot[3 * d + 1] = Fm[3] * o0 + Fm[4] * o1 + Fm[5] * o2;
+                slot[3 * d + 2] = Fm[6] * o0 + Fm[7] * o1 + Fm[8] * o2;
+            }
+        }
+        __syncthreads();
+    }
+    // backward steps
+    for (int32_t k = S - 1; k >= s0; k--) {
+        for (int32_t q = sp[k] + threadIdx.x; q < sp[k + 1]; q += TAIL_THREADS) {
+            const int32_t i = q - Qt;
+            T a0 = 0, a1 = 0, a2 = 0;
+            for (int kk = 0; kk < 2; kk++) {
+                const int32_t w = upq[2 * q + kk];
+                if (w < 0) continue;
+                const T *Fm = F + 9 * (2 * (int64_t)q + kk);
+                const int32_t wi = w - Qt;
+                const T x0 = sv[3 * wi], x1 = sv[3 * wi + 1], x2 = sv[3 * wi + 2];
+                a0 = a0 + (Fm[0] * x0 + Fm[3] * x1 + Fm[6] * x2);
+                a1 = a1 + (Fm[1] * x0 + Fm[4] * x1 + Fm[7] * x2);
+                a2 = a2 + (Fm[2] * x0 + Fm[5] * x1 + Fm[8] * x2);
+            }
+            T d0, d1, d2;
+            sym_mv(Dinv + 6 * (int64_t)q, a0, a1, a2, d0, d1, d2);
+            const T x0 = sv[3 * i] - d0, x1 = sv[3 * i + 1] - d1, x2 = sv[3 * i + 2] - d2;
+            sv[3 * i] = x0;
+            sv[3 * i + 1] = x1;
+            sv[3 * i + 2] = x2;
+            y[3 * (int64_t)q] = x0;
+            y[3 * (int64_t)q + 1] = x1;
+            y[3 * (int64_t)q + 2] = x2;
+            const int64_t v = elim[q];
+            z[3 * v] = x0;
+            z[3 * v + 1] = x1;
+            z[3 * v + 2] = x2;
+        }
+        __syncthreads();
+    }
+}
+
+int tail_setup_attr(sgp_ctx ctx)
+{
+    static bool done = false;
+    if (done) return SGP_OK;
+    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     TAIL_LDS_BYTES));
+    HIP_TRY(ctx, hipFuncSetAttribute((const void *)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     TAIL_LDS_BYTES));
+    done = true;
+    return SGP_OK;
+}
+
+// tail tables: internal flags of the tail targets' in-entries, their ranks,
+// each target's first internal rank, each tail source's slot
+__global__ void k_tail_flags(int32_t t0, int32_t t1, const int32_t *in_src, int32_t Qt, int32_t *flag)
+{
+    int32_t t = t0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t < t1) flag[t - t0] = (in_src[t] >> 1) >= Qt ? 1 : 0;
+}
+
+__global__ void k_tail_tables(int32_t Qt, int32_t nt, int32_t t0, const int32_t *in_ptr, const int32_t *tout,
+                              const int32_t *rank, int32_t *iptr, int32_t *tslot)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > nt) return;
+    iptr[i] = rank[in_ptr[Qt + i] - t0];
+    if (i == nt) return;
+    for (int k = 0; k < 2; k++) {
+        int32_t to = tout[2 * (Qt + i) + k];
+        tslot[2 * i + k] = to >= 0 ? rank[to - t0] : -1;
+    }
 }
 
 template <class T>
@@ -349,22 +527,30 @@ __global__ void k_copy_vec(int64_t len, const T *a, T *b, const PcgScalars *s)
 }
 
 template <class T>
-static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y, const T *r, T *z,
+static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y, T *cs, const T *r, T *z,
                        PcgScalars *s)
 {
     hipStream_t st = ctx->stream;
     const int32_t *elim = (const int32_t *)M->elim.p, *in_ptr = (const int32_t *)M->in_ptr.p;
-    const int32_t *in_src = (const int32_t *)M->in_src.p, *upq = (const int32_t *)M->up.p;
+    const int32_t *tout = (const int32_t *)M->tout.p, *upq = (const int32_t *)M->up.p;
+    const int32_t *dsp = (const int32_t *)M->step_ptr.p;
     const std::vector<int32_t> &sp = M->h_step_ptr;
-    for (int k = 0; k < M->steps; k++) {
+    const int32_t S = M->steps, ts = M->tail_step;
+    for (int k = 0; k < ts; k++) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
         if (q1 > q0)
-            k_fwd_step<T><<<grid_for(q1 - q0, 128), 128, 0, st>>>(q0, q1, elim, in_ptr, in_src, F, Dinv, r, y, s);
+            k_fwd_step<T><<<grid_for(q1 - q0, 256), 256, 0, st>>>(q0, q1, elim, in_ptr, tout, F, Dinv, r, y, cs, s);
     }
-    for (int k = M->steps - 1; k >= 0; k--) {
+    if (ts < S) {
+        size_t lds = (size_t)3 * sizeof(T) * (M->tail_nt + M->tail_ni);
+        k_tail<T><<<1, TAIL_THREADS, lds, st>>>(ts, S, sp[ts], M->tail_nt, M->tail_ni, dsp, elim, in_ptr,
+                                               (const int32_t *)M->tail_iptr.p, (const int32_t *)M->tail_tslot.p,
+                                               upq, F, Dinv, r, cs, y, z, s);
+    }
+    for (int k = ts - 1; k >= 0; k--) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
         if (q1 > q0)
-            k_bwd_step<T><<<grid_for(q1 - q0, 128), 128, 0, st>>>(q0, q1, elim, upq, F, Dinv, y, z, s);
+            k_bwd_step<T><<<grid_for(q1 - q0, 256), 256, 0, st>>>(q0, q1, elim, upq, F, Dinv, y, z, s);
     }
     LAUNCH_CHECK(ctx);
     return SGP_OK;
@@ -383,8 +569,8 @@ int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScala
         LAUNCH_CHECK(ctx);
         return SGP_OK;
     }
-    return tree_sweeps<double>(ctx, M, (const double *)M->F.p, (const double *)M->Dinv.p, (double *)M->y.p, r, z,
-                               s);
+    return tree_sweeps<double>(ctx, M, (const double *)M->F.p, (const double *)M->Dinv.p, (double *)M->y.p,
+                               (double *)M->cs.p, r, z, s);
 }
 
 int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s)
@@ -395,8 +581,8 @@ int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars
         LAUNCH_CHECK(ctx);
         return SGP_OK;
     }
-    return tree_sweeps<float>(ctx, M, (const float *)M->F32.p, (const float *)M->Dinv32.p, (float *)M->y32.p, r, z,
-                              s);
+    return tree_sweeps<float>(ctx, M, (const float *)M->F32.p, (const float *)M->Dinv32.p, (float *)M->y32.p,
+                              (float *)M->cs32.p, r, z, s);
 }
 
 __global__ void k_to_f32(int64_t len, const double *a, float *b)
@@ -413,9 +599,11 @@ int prec_make32(sgp_ctx ctx, sgp_prec M)
     int64_t n = M->n;
     float *F32, *D32, *y32;
     if (M->kind == PREC_TREE) {
+        float *cs32;
         SGP_TRY(ensure_t(ctx, M->F32, 18 * n + 1, &F32));
         SGP_TRY(ensure_t(ctx, M->Dinv32, 6 * n + 1, &D32));
         SGP_TRY(ensure_t(ctx, M->y32, 3 * n + 1, &y32));
+        SGP_TRY(ensure_t(ctx, M->cs32, 6 * n + 6, &cs32));
         k_to_f32<<<grid_for(18 * n, 256), 256, 0, st>>>(18 * n, (const double *)M->F.p, F32);
         k_to_f32<<<grid_for(6 * n, 256), 256, 0, st>>>(6 * n, (const double *)M->Dinv.p, D32);
     } else if (M->kind == PREC_JACOBI) {
@@ -424,6 +612,39 @@ int prec_make32(sgp_ctx ctx, sgp_prec M)
     }
     LAUNCH_CHECK(ctx);
     M->have32 = true;
+    return SGP_OK;
+}
+
+static int tail_tables(sgp_ctx ctx, sgp_prec M, int64_t n, const int32_t *in_ptr, const int32_t *in_src,
+                       const int32_t *tout)
+{
+    hipStream_t st = ctx->stream;
+    M->tail_nt = 0;
+    M->tail_ni = 0;
+    if (M->tail_step >= M->steps) return SGP_OK;
+    SGP_TRY(tail_setup_attr(ctx));
+    const int32_t Qt = M->h_step_ptr[M->tail_step];
+    const int32_t nt = (int32_t)(n - Qt);
+    int32_t hin[2];
+    HIP_TRY(ctx, hipMemcpyAsync(&hin[0], in_ptr + Qt, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(&hin[1], in_ptr + n, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    const int32_t t0 = hin[0], t1 = hin[1];
+    int32_t *flag, *rank, *iptr, *tslot;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP8], (size_t)(t1 - t0) + 2, &flag));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP7], (size_t)(t1 - t0) + 2, &rank));
+    SGP_TRY(ensure_t(ctx, M->tail_iptr, (size_t)nt + 2, &iptr));
+    SGP_TRY(ensure_t(ctx, M->tail_tslot, 2 * (size_t)nt + 2, &tslot));
+    if (t1 > t0) k_tail_flags<<<grid_for(t1 - t0, 256), 256, 0, st>>>(t0, t1, in_src, Qt, flag);
+    SGP_TRY(scan_exclusive(ctx, flag, rank, t1 - t0));
+    k_tail_tables<<<grid_for(nt + 1, 256), 256, 0, st>>>(Qt, nt, t0, in_ptr, tout, rank, iptr, tslot);
+    LAUNCH_CHECK(ctx);
+    int32_t ni;
+    SGP_TRY(readback(ctx, &ni, rank + (t1 - t0), 4));
+    M->tail_nt = nt;
+    M->tail_ni = ni;
+    if ((size_t)3 * 8 * (nt + ni) > (size_t)TAIL_LDS_BYTES)
+        return set_err(ctx, SGP_EINVAL, "factor_tree: tail does not fit in LDS (%d + %d)", nt, ni);
     return SGP_OK;
 }
 
@@ -501,11 +722,19 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     LAUNCH_CHECK(ctx);
     SGP_TRY(radix_sort_pairs(ctx, ka, elim, kb, vb, n, sbits));
     k_invperm<<<grid_for(n, 256), 256, 0, st>>>(n, elim, pos);
-    SGP_TRY(fill_i32(ctx, scnt, 0, S));
-    k_step_count<<<grid_for(n, 256), 256, 0, st>>>(n, stepv, scnt);
-    SGP_TRY(scan_exclusive(ctx, scnt, sptr, S));
+    (void)scnt;
+    k_step_bounds<<<grid_for(n + 1, 256), 256, 0, st>>>(n, ka, S, sptr);
+    LAUNCH_CHECK(ctx);
     M->h_step_ptr.resize(S + 1);
     SGP_TRY(readback(ctx, M->h_step_ptr.data(), sptr, (S + 1) * sizeof(int32_t)));
+    int32_t *dsp;
+    SGP_TRY(ensure_t(ctx, M->step_ptr, (size_t)S + 2, &dsp));
+    HIP_TRY(ctx, hipMemcpyAsync(dsp, sptr, (S + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    // steps from tail_step on hold at most g_tail_max vertices in all (each
+    // has at most two pushes, so 3 g_tail_max slots of LDS always suffice)
+    M->tail_step = S;
+    int tmax = std::min(g_tail_max, TAIL_LDS_BYTES / (9 * 8));
+    while (M->tail_step > 0 && n - M->h_step_ptr[M->tail_step - 1] <= tmax) M->tail_step--;
     // up links and in-lists
     int32_t *upq, *icnt, *in_ptr, *in_src;
     SGP_TRY(ensure_t(ctx, M->up, 2 * n + 2, &upq));
@@ -545,6 +774,15 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
                                                                   Dinv, status);
     }
     LAUNCH_CHECK(ctx);
+    // push slots of the forward sweep: in-list position of every (q, k)
+    int32_t *tout;
+    double *cs;
+    SGP_TRY(ensure_t(ctx, M->tout, 2 * n + 2, &tout));
+    SGP_TRY(ensure_t(ctx, M->cs, 6 * n + 6, &cs));
+    SGP_TRY(fill_i32(ctx, tout, -1, 2 * n));
+    k_slot_of<<<grid_for(2 * n, 256), 256, 0, st>>>(in_ptr + n, in_src, tout);
+    LAUNCH_CHECK(ctx);
+    SGP_TRY(tail_tables(ctx, M, n, in_ptr, in_src, tout));
     SGP_TRY(readback(ctx, hbuf, status, 4));
     if (ctx->ev[7]) {
         (void)hipEventRecord(ctx->ev[7], st);
@@ -559,9 +797,9 @@ __global__ void k_jacobi_make(int64_t n, const int32_t *diagpos, const double *v
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double *B = val + 9 * (int64_t)diagpos[i];
-    double D[9];
-    for (int t = 0; t < 9; t++) D[t] = B[t];
+    const int64_t k = diagpos[i];
+    const double *g = val + (k >> 6) * 384 + (k & 63);
+    double D[9] = {g[0], g[64], g[128], g[64], g[192], g[256], g[128], g[256], g[320]};
     double inv[6];
     if (!spd_inverse3(D, inv)) {
         atomicOr(status, 1);

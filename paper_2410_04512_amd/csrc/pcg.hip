@@ -72,117 +72,110 @@ static BlockTab tab_ptrs(const int32_t *d, int32_t nblocks, int64_t K)
     return t;
 }
 
-// per-cluster fixed-order reduction of one value per thread; fin(total) runs
-// in thread 0 of the cluster's last block.
-template <class Fin>
-SGP_DEV void cluster_reduce(double v, int b, int inst, const BlockTab &tab, double *part, unsigned *tickets,
-                            double *sh, int *flag, Fin fin)
+// First stage of every reduction: the block's sum of one value per thread in
+// a fixed order, stored as the block's partial.  The second stage is k_fin
+// (one block per cluster, partials summed in block order), launched after the
+// producer: the kernel boundary orders the two, so no fences or atomics.
+SGP_DEV void block_partial(double v, int b, double *part, double *sh)
 {
     double s = block_sum_256(v, sh);
     if (threadIdx.x == 0) part[b] = s;
-    if (!last_block(&tickets[inst], (unsigned)tab.inb[inst], flag)) return;
-    double tot = sum_partials(part + tab.ifirst[inst], tab.inb[inst], sh);
-    if (threadIdx.x == 0) fin(tot);
 }
 
-// ---------------------------------------------------------------- SpMV
+enum { FIN_ALPHA, FIN_RR, FIN_BETA, FIN_RHO, FIN_INIT, FIN_TRUE, FIN_NORM2 };
 
-// G lanes per block row; lane l takes the row's blocks l, l+G, ...; a fixed
-// butterfly sums the G lanes.  mode 1 adds p.q for alpha (PCG).
-template <int G, class T>
-__global__ __launch_bounds__(256) void k_spmv(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ bcol,
-                                              const T *__restrict__ val, const T *__restrict__ x,
-                                              T *__restrict__ y, int64_t n, BlockTab tab, PcgScalars *S,
-                                              double *part, unsigned *tickets, int mode)
+// fixed-order sum of n partials by 256 threads: thread t owns the interleaved
+// sequence t, t+256, ...; four running sums (positions mod 4 of that
+// sequence) let four loads be in flight, then they are added in a fixed order
+SGP_DEV double sum_partials4(const double *part, int n, double *sh)
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int k = threadIdx.x;
+    for (; k + 3 * 256 < n; k += 4 * 256) {
+        double v0 = part[k], v1 = part[k + 256], v2 = part[k + 512], v3 = part[k + 768];
+        a0 = a0 + v0;
+        a1 = a1 + v1;
+        a2 = a2 + v2;
+        a3 = a3 + v3;
+    }
+    for (; k < n; k += 256) a0 = a0 + part[k];
+    return block_sum_256((a0 + a1) + (a2 + a3), sh);
+}
+
+// Second stage: cluster k = blockIdx.x sums its partials (np values per block,
+// stored as np arrays of stride nblk) and updates its scalars.
+__global__ __launch_bounds__(256) void k_fin(int op, const double *part, int nblk, const int32_t *ifirst,
+                                             const int32_t *inb, PcgScalars *S)
 {
     __shared__ double sh[256];
-    __shared__ int flag;
-    const int b = blockIdx.x;
-    const int inst = tab.inst ? tab.inst[b] : 0;
-    if (S && S[inst].done) return;
-    const int64_t r0 = tab.row0 ? tab.row0[b] : (int64_t)b * (256 / G);
-    const int64_t r1 = tab.row1 ? tab.row1[b] : std::min<int64_t>(r0 + 256 / G, n);
-    const int64_t row = r0 + threadIdx.x / G;
-    const int lane = threadIdx.x % G;
-    const bool ok = row < r1;
-    T a0 = 0, a1 = 0, a2 = 0;
-    if (ok) {
-        const int32_t kb = rowptr[row], ke = rowptr[row + 1];
-        for (int32_t k = kb + lane; k < ke; k += G) {
-            const T *B = val + 9 * (int64_t)k;
-            const int64_t j = bcol[k];
-            const T x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
-            a0 += B[0] * x0 + B[1] * x1 + B[2] * x2;
-            a1 += B[3] * x0 + B[4] * x1 + B[5] * x2;
-            a2 += B[6] * x0 + B[7] * x1 + B[8] * x2;
-        }
-    }
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-        a0 += __shfl_xor(a0, o, G);
-        a1 += __shfl_xor(a1, o, G);
-        a2 += __shfl_xor(a2, o, G);
-    }
-    if (ok && lane == 0) {
-        y[3 * row] = a0;
-        y[3 * row + 1] = a1;
-        y[3 * row + 2] = a2;
-    }
-    if (mode == 0) return;
-    double d = 0.0;
-    if (ok && lane == 0)
-        d = (double)x[3 * row] * (double)a0 + (double)x[3 * row + 1] * (double)a1 + (double)x[3 * row + 2] * (double)a2;
-    PcgScalars *Sc = S + inst;
-    cluster_reduce(d, b, inst, tab, part, tickets, sh, &flag, [&](double pq) {
-        Sc->pq = pq;
-        if (!(pq > 0.0) || !isfinite(pq)) {
+    const int k = blockIdx.x;
+    PcgScalars *Sc = S + k;
+    if (op != FIN_INIT && op != FIN_TRUE && op != FIN_NORM2 && Sc->done) return;
+    const int f = ifirst[k], nbk = inb[k];
+    double t0 = sum_partials4(part + f, nbk, sh);
+    double t1 = (op == FIN_INIT || op == FIN_NORM2) ? sum_partials4(part + nblk + f, nbk, sh) : 0.0;
+    double t2 = (op == FIN_INIT) ? sum_partials4(part + 2 * nblk + f, nbk, sh) : 0.0;
+    if (threadIdx.x != 0) return;
+    switch (op) {
+    case FIN_ALPHA:
+        Sc->pq = t0;
+        if (!(t0 > 0.0) || !isfinite(t0)) {
             Sc->status = SGP_EBREAKDOWN;
             Sc->done = 1;
         } else {
-            Sc->alpha = Sc->rho / pq;
+            Sc->alpha = Sc->rho / t0;
         }
-    });
-}
-
-template <class T>
-static int spmv_dispatch(sgp_ctx ctx, int G, const int32_t *rowptr, const int32_t *bcol, const T *val, const T *x,
-                         T *y, int64_t n, BlockTab tab, int32_t nblocks, PcgScalars *S, double *part,
-                         unsigned *tickets, int mode)
-{
-    hipStream_t st = ctx->stream;
-    unsigned grid = tab.row0 ? (unsigned)nblocks : grid_for(n * G, 256);
-#define SPMV_CASE(g)                                                                                      \
-    case g:                                                                                               \
-        k_spmv<g, T><<<grid, 256, 0, st>>>(rowptr, bcol, val, x, y, n, tab, S, part, tickets, mode); \
         break;
-    switch (G) {
-        SPMV_CASE(1)
-        SPMV_CASE(2)
-        SPMV_CASE(4)
-        SPMV_CASE(8)
-        SPMV_CASE(16)
-    default:
-        return set_err(ctx, SGP_EINVAL, "spmv: unsupported lanes per row %d", G);
+    case FIN_RR:
+        Sc->rr = t0;
+        Sc->iter = Sc->iter + 1;
+        Sc->relres2 = t0 / Sc->nF2;
+        if (!isfinite(t0)) {
+            Sc->status = SGP_ENONFINITE;
+            Sc->done = 1;
+        } else if (Sc->fixed) {
+            if (Sc->iter >= Sc->fixed) Sc->done = 1;
+        } else if (Sc->relres2 <= Sc->tol2) {
+            Sc->done = 1;
+        } else if (Sc->iter >= Sc->max_iter) {
+            Sc->status = SGP_ENOCONV;
+            Sc->done = 1;
+        }
+        break;
+    case FIN_BETA:
+        Sc->beta = t0 / Sc->rho;
+        Sc->rho = t0;
+        break;
+    case FIN_RHO:
+        Sc->rho = t0;
+        break;
+    case FIN_INIT:   // t0 = ||F||^2, t1 = ||r||^2, t2 = bad-input count
+        Sc->nF2 = t0;
+        Sc->rr = t1;
+        Sc->iter = 0;
+        Sc->relres2 = t0 > 0.0 ? t1 / t0 : 0.0;
+        if (t2 != 0.0 || !isfinite(t1)) {
+            Sc->status = SGP_ENONFINITE;
+            Sc->done = 1;
+        } else if (t0 == 0.0) {
+            Sc->done = 2;   // zero force: v = 0
+        } else if (!Sc->fixed && Sc->relres2 <= Sc->tol2) {
+            Sc->done = 1;
+        }
+        break;
+    case FIN_TRUE:
+        Sc->rz = t0;
+        break;
+    case FIN_NORM2:
+        Sc->rz = t0;    // ||r||^2
+        Sc->nF2 = t1;   // ||F||^2
+        break;
     }
-#undef SPMV_CASE
-    LAUNCH_CHECK(ctx);
-    return SGP_OK;
-}
-
-static int g_spmv_lanes = 4;   // lanes per block row (tunable through sgp_tune)
-
-extern "C" int sgp_spmv(sgp_ctx ctx, sgp_bsr A, const double *x, double *y)
-{
-    if (!ctx || !A || (A->n > 0 && (!x || !y))) return set_err(ctx, SGP_EINVAL, "spmv: bad arguments");
-    if (A->n == 0) return SGP_OK;
-    BlockTab none = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    return spmv_dispatch<double>(ctx, g_spmv_lanes, (const int32_t *)A->rowptr.p, (const int32_t *)A->bcol.p,
-                                 (const double *)A->val.p, x, y, A->n, none, 0, nullptr, nullptr, nullptr, 0);
 }
 
 // ---------------------------------------------------------------- vector kernels
 
-template <class T>
+// rows of block b of a row table (blocks never straddle clusters)
 SGP_DEV bool block_rows(const BlockTab &tab, int b, int64_t &row, int &inst)
 {
     inst = tab.inst[b];
@@ -190,16 +183,15 @@ SGP_DEV bool block_rows(const BlockTab &tab, int b, int64_t &row, int &inst)
     return row < tab.row1[b];
 }
 
-// r = F - q (q = Gamma x0) or r = F (x = 0); ||F||^2, ||r||^2, finite check
+// r = F - q (q = Gamma x0) or r = F (x = 0); partials of ||F||^2, ||r||^2, #bad
 template <class T>
 __global__ __launch_bounds__(256) void k_init_res(const double *F, const T *q, T *x, T *r, int use_x0, BlockTab tab,
-                                                  PcgScalars *S, double *part, unsigned *tickets)
+                                                  double *part)
 {
     __shared__ double sh[256];
-    __shared__ int flag;
     int b = blockIdx.x, inst;
     int64_t row;
-    bool ok = block_rows<T>(tab, b, row, inst);
+    bool ok = block_rows(tab, b, row, inst);
     double ff = 0.0, rr = 0.0, bad = 0.0;
     if (ok) {
         for (int a = 0; a < 3; a++) {
@@ -218,44 +210,20 @@ __global__ __launch_bounds__(256) void k_init_res(const double *F, const T *q, T
             rr = rr + (double)ri * (double)ri;
         }
     }
-    PcgScalars *Sc = S + inst;
-    double *p2 = part + gridDim.x, *p3 = part + 2 * gridDim.x;
-    double sff = block_sum_256(ff, sh), srr = block_sum_256(rr, sh), sbad = block_sum_256(bad, sh);
-    if (threadIdx.x == 0) {
-        part[b] = sff;
-        p2[b] = srr;
-        p3[b] = sbad;
-    }
-    if (!last_block(&tickets[inst], (unsigned)tab.inb[inst], &flag)) return;
-    double tff = sum_partials(part + tab.ifirst[inst], tab.inb[inst], sh);
-    double trr = sum_partials(p2 + tab.ifirst[inst], tab.inb[inst], sh);
-    double tbad = sum_partials(p3 + tab.ifirst[inst], tab.inb[inst], sh);
-    if (threadIdx.x == 0) {
-        Sc->nF2 = tff;
-        Sc->rr = trr;
-        Sc->iter = 0;
-        Sc->relres2 = tff > 0.0 ? trr / tff : 0.0;
-        if (tbad != 0.0 || !isfinite(trr)) {
-            Sc->status = SGP_ENONFINITE;
-            Sc->done = 1;
-        } else if (tff == 0.0) {
-            Sc->done = 2;   // zero force: the host writes v = 0
-        } else if (!Sc->fixed && Sc->relres2 <= Sc->tol2) {
-            Sc->done = 1;
-        }
-    }
+    block_partial(ff, b, part, sh);
+    block_partial(rr, b, part + gridDim.x, sh);
+    block_partial(bad, b, part + 2 * gridDim.x, sh);
 }
 
-// p = z, rho = r.z
+// p = z; partial of r.z
 template <class T>
-__global__ __launch_bounds__(256) void k_init_p(const T *r, const T *z, T *p, BlockTab tab, PcgScalars *S,
-                                                double *part, unsigned *tickets)
+__global__ __launch_bounds__(256) void k_init_p(const T *r, const T *z, T *p, BlockTab tab, const PcgScalars *S,
+                                                double *part)
 {
     __shared__ double sh[256];
-    __shared__ int flag;
     int b = blockIdx.x, inst;
     int64_t row;
-    bool ok = block_rows<T>(tab, b, row, inst);
+    bool ok = block_rows(tab, b, row, inst);
     if (S[inst].done) return;
     double rz = 0.0;
     if (ok) {
@@ -265,21 +233,19 @@ __global__ __launch_bounds__(256) void k_init_p(const T *r, const T *z, T *p, Bl
             rz = rz + (double)r[3 * row + a] * (double)zi;
         }
     }
-    PcgScalars *Sc = S + inst;
-    cluster_reduce(rz, b, inst, tab, part, tickets, sh, &flag, [&](double t) { Sc->rho = t; });
+    block_partial(rz, b, part, sh);
 }
 
-// x += alpha p; r -= alpha q; ||r||^2; stopping test
+// x += alpha p; r -= alpha q; partial of ||r||^2
 template <class T>
-__global__ __launch_bounds__(256) void k_update_xr(T *x, T *r, const T *p, const T *q, BlockTab tab, PcgScalars *S,
-                                                   double *part, unsigned *tickets)
+__global__ __launch_bounds__(256) void k_update_xr(T *x, T *r, const T *p, const T *q, BlockTab tab,
+                                                   const PcgScalars *S, double *part)
 {
     __shared__ double sh[256];
-    __shared__ int flag;
     int b = blockIdx.x, inst;
     int64_t row;
-    bool ok = block_rows<T>(tab, b, row, inst);
-    PcgScalars *Sc = S + inst;
+    bool ok = block_rows(tab, b, row, inst);
+    const PcgScalars *Sc = S + inst;
     if (Sc->done) return;
     const T alpha = (T)Sc->alpha;
     double rr = 0.0;
@@ -292,43 +258,37 @@ __global__ __launch_bounds__(256) void k_update_xr(T *x, T *r, const T *p, const
             rr = rr + (double)ri * (double)ri;
         }
     }
-    cluster_reduce(rr, b, inst, tab, part, tickets, sh, &flag, [&](double t) {
-        Sc->rr = t;
-        Sc->iter = Sc->iter + 1;
-        Sc->relres2 = t / Sc->nF2;
-        if (!isfinite(t)) {
-            Sc->status = SGP_ENONFINITE;
-            Sc->done = 1;
-        } else if (Sc->fixed) {
-            if (Sc->iter >= Sc->fixed) Sc->done = 1;
-        } else if (Sc->relres2 <= Sc->tol2) {
-            Sc->done = 1;
-        } else if (Sc->iter >= Sc->max_iter) {
-            Sc->status = SGP_ENOCONV;
-            Sc->done = 1;
-        }
-    });
+    block_partial(rr, b, part, sh);
 }
 
-// rho' = r.z, beta = rho'/rho
+// partial of p.q (batched solves: the product itself has no cluster split)
 template <class T>
-__global__ __launch_bounds__(256) void k_rz(const T *r, const T *z, BlockTab tab, PcgScalars *S, double *part,
-                                            unsigned *tickets)
+__global__ __launch_bounds__(256) void k_pq(const T *p, const T *q, BlockTab tab, const PcgScalars *S, double *part)
 {
     __shared__ double sh[256];
-    __shared__ int flag;
     int b = blockIdx.x, inst;
     int64_t row;
-    bool ok = block_rows<T>(tab, b, row, inst);
-    PcgScalars *Sc = S + inst;
-    if (Sc->done) return;
+    bool ok = block_rows(tab, b, row, inst);
+    if (S[inst].done) return;
+    double d = 0.0;
+    if (ok)
+        for (int a = 0; a < 3; a++) d = d + (double)p[3 * row + a] * (double)q[3 * row + a];
+    block_partial(d, b, part, sh);
+}
+
+// partial of r.z
+template <class T>
+__global__ __launch_bounds__(256) void k_rz(const T *r, const T *z, BlockTab tab, const PcgScalars *S, double *part)
+{
+    __shared__ double sh[256];
+    int b = blockIdx.x, inst;
+    int64_t row;
+    bool ok = block_rows(tab, b, row, inst);
+    if (S[inst].done) return;
     double rz = 0.0;
     if (ok)
         for (int a = 0; a < 3; a++) rz = rz + (double)r[3 * row + a] * (double)z[3 * row + a];
-    cluster_reduce(rz, b, inst, tab, part, tickets, sh, &flag, [&](double t) {
-        Sc->beta = t / Sc->rho;
-        Sc->rho = t;
-    });
+    block_partial(rz, b, part, sh);
 }
 
 template <class T>
@@ -336,7 +296,7 @@ __global__ __launch_bounds__(256) void k_update_p(T *p, const T *z, BlockTab tab
 {
     int b = blockIdx.x, inst;
     int64_t row;
-    bool ok = block_rows<T>(tab, b, row, inst);
+    bool ok = block_rows(tab, b, row, inst);
     const PcgScalars *Sc = S + inst;
     if (Sc->done || !ok) return;
     const T beta = (T)Sc->beta;
@@ -346,23 +306,20 @@ __global__ __launch_bounds__(256) void k_update_p(T *p, const T *z, BlockTab tab
     }
 }
 
-// ||F - Gamma x||^2 per cluster (q = Gamma x given), stored in rz
-__global__ __launch_bounds__(256) void k_true_res(const double *F, const double *q, BlockTab tab, PcgScalars *S,
-                                                  double *part, unsigned *tickets)
+// partial of ||F - q||^2 (q = Gamma x)
+__global__ __launch_bounds__(256) void k_true_res(const double *F, const double *q, BlockTab tab, double *part)
 {
     __shared__ double sh[256];
-    __shared__ int flag;
     int b = blockIdx.x, inst;
     int64_t row;
-    bool ok = block_rows<double>(tab, b, row, inst);
+    bool ok = block_rows(tab, b, row, inst);
     double rr = 0.0;
     if (ok)
         for (int a = 0; a < 3; a++) {
             double t = F[3 * row + a] - q[3 * row + a];
             rr = rr + t * t;
         }
-    PcgScalars *Sc = S + inst;
-    cluster_reduce(rr, b, inst, tab, part, tickets, sh, &flag, [&](double t) { Sc->rz = t; });
+    block_partial(rr, b, part, sh);
 }
 
 template <class T>
@@ -370,7 +327,7 @@ __global__ void k_zero_rows(T *x, BlockTab tab, const PcgScalars *S, int want_do
 {
     int b = blockIdx.x, inst;
     int64_t row;
-    bool ok = block_rows<T>(tab, b, row, inst);
+    bool ok = block_rows(tab, b, row, inst);
     if (!ok || S[inst].done != want_done) return;
     x[3 * row] = 0;
     x[3 * row + 1] = 0;
@@ -394,13 +351,37 @@ __global__ void k_any_open(const PcgScalars *S, int64_t K, int32_t *open)
     if (k < K && !S[k].done) atomicAdd(open, 1);
 }
 
+// rowptr at the cluster offsets (block offsets of the clusters)
+__global__ void k_gather_rowptr(const int32_t *rowptr, const int64_t *off, int64_t K1, int32_t *out)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < K1) out[k] = rowptr[off[k]];
+}
+
 // ---------------------------------------------------------------- the solver state
 
 struct PcgWork {
-    std::vector<int32_t> vec_buf, mv_buf;
-    int32_t vec_nb = 0, mv_nb = 0;
-    BlockTab vec, mv;
+    std::vector<int32_t> vec_buf;
+    int32_t vec_nb = 0;
+    BlockTab vec;
+    int32_t mv_nb = 0;                   // product workgroups (one cluster: p.q partials)
+    const int32_t *mv_first = nullptr;   // {0}
+    const int32_t *mv_nb_dev = nullptr;  // {mv_nb}
+    int64_t K = 1;
 };
+
+template <class T>
+static int spmv_t(sgp_ctx ctx, sgp_bsr A, const T *x, T *y, const PcgScalars *S, double *part, int mode);
+template <>
+int spmv_t<double>(sgp_ctx ctx, sgp_bsr A, const double *x, double *y, const PcgScalars *S, double *part, int mode)
+{
+    return spmv_f64(ctx, A, x, y, S, part, mode);
+}
+template <>
+int spmv_t<float>(sgp_ctx ctx, sgp_bsr A, const float *x, float *y, const PcgScalars *S, double *part, int mode)
+{
+    return spmv_f32(ctx, A, x, y, S, part, mode);
+}
 
 static int g_check_every = 8;
 
@@ -409,33 +390,49 @@ struct Vecs {
     T *x, *r, *z, *p, *q;
 };
 
-// PCG iterations on prepared r, z (z = M r already), until every cluster is done.
+static int fin(sgp_ctx ctx, int op, const double *part, int nblk, const int32_t *ifirst, const int32_t *inb,
+               PcgScalars *S, int64_t K)
+{
+    k_fin<<<(unsigned)K, 256, 0, ctx->stream>>>(op, part, nblk, ifirst, inb, S);
+    LAUNCH_CHECK(ctx);
+    return SGP_OK;
+}
+
+// PCG iterations on prepared r, z (z = M r) and p, until every cluster is done.
 template <class T>
-static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const T *val, Vecs<T> v, PcgWork &w, PcgScalars *S,
-                       int64_t K, double *part, unsigned *tickets, int32_t *open, int check_every, int max_iter,
-                       int fixed)
+static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w, PcgScalars *S,
+                       double *part, int32_t *open, int check_every, int max_iter, int fixed)
 {
     hipStream_t st = ctx->stream;
-    const int32_t *rowptr = (const int32_t *)A->rowptr.p, *bcol = (const int32_t *)A->bcol.p;
     int32_t *hopen = (int32_t *)ctx->pinned;
+    const int64_t K = w.K;
     const int limit = fixed > 0 ? fixed : max_iter;
+    // one cluster: the sweeps stop with it; several: every sweep runs
+    PcgScalars *gate = K == 1 ? S : nullptr;
     for (int it = 0; it < limit;) {
         int chunk = std::min(check_every, limit - it);
         for (int c = 0; c < chunk; c++) {
             SGP_TRY(ktimer_begin(ctx));
-            SGP_TRY(spmv_dispatch<T>(ctx, g_spmv_lanes, rowptr, bcol, val, v.p, v.q, A->n, w.mv, w.mv_nb, S, part,
-                                     tickets, 1));
-            SGP_TRY(ktimer_end(ctx));
-            k_update_xr<T><<<w.vec_nb, 256, 0, st>>>(v.x, v.r, v.p, v.q, w.vec, S, part, tickets);
+            if (K == 1) {
+                SGP_TRY(spmv_t<T>(ctx, A, v.p, v.q, S, part, 1));
+                SGP_TRY(ktimer_end(ctx));
+                SGP_TRY(fin(ctx, FIN_ALPHA, part, w.mv_nb, w.mv_first, w.mv_nb_dev, S, 1));
+            } else {
+                SGP_TRY(spmv_t<T>(ctx, A, v.p, v.q, nullptr, nullptr, 0));
+                SGP_TRY(ktimer_end(ctx));
+                k_pq<T><<<w.vec_nb, 256, 0, st>>>(v.p, v.q, w.vec, S, part);
+                SGP_TRY(fin(ctx, FIN_ALPHA, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
+            }
+            k_update_xr<T><<<w.vec_nb, 256, 0, st>>>(v.x, v.r, v.p, v.q, w.vec, S, part);
+            SGP_TRY(fin(ctx, FIN_RR, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
             if (M) {
-                // one cluster: the sweeps stop with it; several: every sweep runs
-                PcgScalars *gate = K == 1 ? S : nullptr;
                 if (sizeof(T) == 8)
                     SGP_TRY(prec_apply_f64(ctx, M, (const double *)v.r, (double *)v.z, gate));
                 else
                     SGP_TRY(prec_apply_f32(ctx, M, (const float *)v.r, (float *)v.z, gate));
             }
-            k_rz<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.z, w.vec, S, part, tickets);
+            k_rz<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.z, w.vec, S, part);
+            SGP_TRY(fin(ctx, FIN_BETA, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
             k_update_p<T><<<w.vec_nb, 256, 0, st>>>(v.p, v.z, w.vec, S);
             LAUNCH_CHECK(ctx);
         }
@@ -453,18 +450,21 @@ static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const T *val, Vecs<T>
 // the sweeps (their z is simply not used any more), only in the vector and
 // matrix kernels, which carry the per-cluster test.
 
-static int prepare_tabs(sgp_ctx ctx, const std::vector<int64_t> &off, PcgWork &w, DevBuf &dev)
+static int prepare_work(sgp_ctx ctx, sgp_bsr A, const std::vector<int64_t> &off, PcgWork &w)
 {
-    int64_t K = (int64_t)off.size() - 1;
+    const int64_t K = (int64_t)off.size() - 1;
+    w.K = K;
     build_tab(off, 256, w.vec_buf, w.vec_nb);
-    build_tab(off, 256 / g_spmv_lanes, w.mv_buf, w.mv_nb);
+    w.mv_nb = spmv_blocks(A);
+    w.vec_buf.push_back(0);
+    w.vec_buf.push_back(w.mv_nb);
     int32_t *d;
-    size_t nv = w.vec_buf.size(), nm = w.mv_buf.size();
-    SGP_TRY(ensure_t(ctx, dev, nv + nm + 2, &d));
+    size_t nv = w.vec_buf.size();
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP6], nv + 2, &d));
     HIP_TRY(ctx, hipMemcpyAsync(d, w.vec_buf.data(), nv * 4, hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(d + nv, w.mv_buf.data(), nm * 4, hipMemcpyHostToDevice, ctx->stream));
     w.vec = tab_ptrs(d, w.vec_nb, K);
-    w.mv = tab_ptrs(d + nv, w.mv_nb, K);
+    w.mv_first = d + nv - 2;
+    w.mv_nb_dev = d + nv - 1;
     return SGP_OK;
 }
 
@@ -474,10 +474,9 @@ static int solve_f64(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<int64
     hipStream_t st = ctx->stream;
     const int64_t n = A->n, K = (int64_t)off.size() - 1;
     PcgWork w;
-    SGP_TRY(prepare_tabs(ctx, off, w, ctx->ws[WS_TMP6]));
+    SGP_TRY(prepare_work(ctx, A, off, w));
     double *r, *z, *p, *q, *part;
     PcgScalars *S;
-    unsigned *tickets;
     int32_t *open;
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP0], 3 * n + 3, &r));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP1], 3 * n + 3, &p));
@@ -487,32 +486,28 @@ static int solve_f64(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<int64
     int32_t nbmax = std::max(w.vec_nb, w.mv_nb);
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_PART], 3 * (size_t)nbmax + 8, &part));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_SCAL], K + 1, &S));
-    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP4], K + 8, &tickets));
-    open = (int32_t *)(tickets + K + 4);
-    SGP_TRY(fill_i32(ctx, (int32_t *)tickets, 0, K + 1));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP4], 8, &open));
     int fixed = std::max(0, o->fixed_iters);
     int max_iter = o->max_iter > 0 ? o->max_iter : 10000;
     k_set_scalars<<<grid_for(K, 256), 256, 0, st>>>(S, K, o->rtol * o->rtol, fixed, max_iter);
     LAUNCH_CHECK(ctx);
-    const int32_t *rowptr = (const int32_t *)A->rowptr.p, *bcol = (const int32_t *)A->bcol.p;
-    const double *val = (const double *)A->val.p;
-    if (o->use_x0)
-        SGP_TRY(spmv_dispatch<double>(ctx, g_spmv_lanes, rowptr, bcol, val, x, q, n, w.mv, w.mv_nb, nullptr, nullptr,
-                                      nullptr, 0));
-    k_init_res<double><<<w.vec_nb, 256, 0, st>>>(F, q, x, r, o->use_x0, w.vec, S, part, tickets);
+    if (o->use_x0) SGP_TRY(spmv_f64(ctx, A, x, q, nullptr, nullptr, 0));
+    k_init_res<double><<<w.vec_nb, 256, 0, st>>>(F, q, x, r, o->use_x0, w.vec, part);
     LAUNCH_CHECK(ctx);
+    SGP_TRY(fin(ctx, FIN_INIT, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
     k_zero_rows<double><<<w.vec_nb, 256, 0, st>>>(x, w.vec, S, 2);
     if (M) SGP_TRY(prec_apply_f64(ctx, M, r, z, nullptr));
-    k_init_p<double><<<w.vec_nb, 256, 0, st>>>(r, z, p, w.vec, S, part, tickets);
+    k_init_p<double><<<w.vec_nb, 256, 0, st>>>(r, z, p, w.vec, S, part);
     LAUNCH_CHECK(ctx);
+    SGP_TRY(fin(ctx, FIN_RHO, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
     Vecs<double> v = {x, r, z, p, q};
     int ce = o->check_every > 0 ? o->check_every : g_check_every;
-    SGP_TRY(pcg_iterate<double>(ctx, A, M, val, v, w, S, K, part, tickets, open, ce, max_iter, fixed));
+    SGP_TRY(pcg_iterate<double>(ctx, A, M, v, w, S, part, open, ce, max_iter, fixed));
     // true residual
-    SGP_TRY(spmv_dispatch<double>(ctx, g_spmv_lanes, rowptr, bcol, val, x, q, n, w.mv, w.mv_nb, nullptr, nullptr,
-                                  nullptr, 0));
-    k_true_res<<<w.vec_nb, 256, 0, st>>>(F, q, w.vec, S, part, tickets);
+    SGP_TRY(spmv_f64(ctx, A, x, q, nullptr, nullptr, 0));
+    k_true_res<<<w.vec_nb, 256, 0, st>>>(F, q, w.vec, part);
     LAUNCH_CHECK(ctx);
+    SGP_TRY(fin(ctx, FIN_TRUE, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
     std::vector<PcgScalars> hs(K);
     SGP_TRY(readback(ctx, hs.data(), S, K * sizeof(PcgScalars)));
     for (int64_t k = 0; k < K; k++) {
@@ -530,12 +525,6 @@ static int solve_f64(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<int64
 
 // ---------------------------------------------------------------- FP32 inside FP64 refinement
 
-__global__ void k_f64_to_f32_vec(int64_t len, const double *a, float *b)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < len) b[i] = (float)a[i];
-}
-
 __global__ void k_res64(int64_t len, const double *F, const double *q, double *r)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -548,34 +537,21 @@ __global__ void k_axpy_f32_into_f64(int64_t len, const float *d, double *x)
     if (i < len) x[i] = x[i] + (double)d[i];
 }
 
-// ||r||^2 / ||F||^2 of the FP64 residual, one cluster
-__global__ __launch_bounds__(256) void k_norm2_pair(const double *a, const double *b, BlockTab tab, PcgScalars *S,
-                                                    double *part, unsigned *tickets)
+// partials of ||a||^2 and ||b||^2
+__global__ __launch_bounds__(256) void k_norm2_pair(const double *a, const double *b, BlockTab tab, double *part)
 {
     __shared__ double sh[256];
-    __shared__ int flag;
     int bl = blockIdx.x, inst;
     int64_t row;
-    bool ok = block_rows<double>(tab, bl, row, inst);
+    bool ok = block_rows(tab, bl, row, inst);
     double sa = 0.0, sb = 0.0;
     if (ok)
         for (int t = 0; t < 3; t++) {
             sa = sa + a[3 * row + t] * a[3 * row + t];
             sb = sb + b[3 * row + t] * b[3 * row + t];
         }
-    double *p2 = part + gridDim.x;
-    double ta = block_sum_256(sa, sh), tb = block_sum_256(sb, sh);
-    if (threadIdx.x == 0) {
-        part[bl] = ta;
-        p2[bl] = tb;
-    }
-    if (!last_block(&tickets[inst], (unsigned)tab.inb[inst], &flag)) return;
-    double A2 = sum_partials(part + tab.ifirst[inst], tab.inb[inst], sh);
-    double B2 = sum_partials(p2 + tab.ifirst[inst], tab.inb[inst], sh);
-    if (threadIdx.x == 0) {
-        S[inst].rz = A2;    // ||r||^2
-        S[inst].nF2 = B2;   // ||F||^2
-    }
+    block_partial(sa, bl, part, sh);
+    block_partial(sb, bl, part + gridDim.x, sh);
 }
 
 static int solve_ir(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const double *F, double *x, const sgp_solve_opts *o,
@@ -588,11 +564,10 @@ static int solve_ir(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const double *F, double 
     SGP_TRY(prec_make32(ctx, M));
     std::vector<int64_t> off = {0, n};
     PcgWork w;
-    SGP_TRY(prepare_tabs(ctx, off, w, ctx->ws[WS_TMP6]));
+    SGP_TRY(prepare_work(ctx, A, off, w));
     double *r64, *q64, *part;
     float *r, *z, *p, *q, *d;
     PcgScalars *S;
-    unsigned *tickets;
     int32_t *open;
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP0], len + 3, &r64));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP1], len + 3, &q64));
@@ -604,33 +579,28 @@ static int solve_ir(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const double *F, double 
     int32_t nbmax = std::max(w.vec_nb, w.mv_nb);
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_PART], 3 * (size_t)nbmax + 8, &part));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_SCAL], 2, &S));
-    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP4], 16, &tickets));
-    open = (int32_t *)(tickets + 8);
-    SGP_TRY(fill_i32(ctx, (int32_t *)tickets, 0, 2));
-    const int32_t *rowptr = (const int32_t *)A->rowptr.p, *bcol = (const int32_t *)A->bcol.p;
-    const double *val = (const double *)A->val.p;
-    const float *val32 = (const float *)A->val32.p;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP4], 8, &open));
     int max_outer = o->max_outer > 0 ? o->max_outer : 50;
     int max_inner = o->max_iter > 0 ? o->max_iter : 10000;
     double inner = o->inner_rtol > 0 ? o->inner_rtol : 1e-5;
     int ce = o->check_every > 0 ? o->check_every : g_check_every;
-    if (!o->use_x0) HIP_TRY(ctx, hipMemsetAsync(x, 0, len * sizeof(double), st));
+    if (!o->use_x0) SGP_TRY(fill_f64(ctx, x, 0.0, len));
     int total_inner = 0, outer = 0, status = SGP_OK;
     double relres = 0.0;
     PcgScalars hs;
     for (;;) {
-        SGP_TRY(spmv_dispatch<double>(ctx, g_spmv_lanes, rowptr, bcol, val, x, q64, n, w.mv, w.mv_nb, nullptr,
-                                      nullptr, nullptr, 0));
+        SGP_TRY(spmv_f64(ctx, A, x, q64, nullptr, nullptr, 0));
         k_res64<<<grid_for(len, 256), 256, 0, st>>>(len, F, q64, r64);
-        k_norm2_pair<<<w.vec_nb, 256, 0, st>>>(r64, F, w.vec, S, part, tickets);
+        k_norm2_pair<<<w.vec_nb, 256, 0, st>>>(r64, F, w.vec, part);
         LAUNCH_CHECK(ctx);
+        SGP_TRY(fin(ctx, FIN_NORM2, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, 1));
         SGP_TRY(readback(ctx, &hs, S, sizeof hs));
         if (!std::isfinite(hs.rz) || !std::isfinite(hs.nF2)) {
             status = SGP_ENONFINITE;
             break;
         }
         if (hs.nF2 == 0.0) {
-            HIP_TRY(ctx, hipMemsetAsync(x, 0, len * sizeof(double), st));
+            SGP_TRY(fill_f64(ctx, x, 0.0, len));
             relres = 0.0;
             break;
         }
@@ -640,14 +610,17 @@ static int solve_ir(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const double *F, double 
             status = SGP_ENOCONV;
             break;
         }
-        // inner FP32 solve of Gamma d = r, relative tolerance `inner`
+        // inner FP32 solve of Gamma d = r to relative tolerance `inner`
         k_set_scalars<<<1, 32, 0, st>>>(S, 1, inner * inner, 0, max_inner - total_inner);
-        k_init_res<float><<<w.vec_nb, 256, 0, st>>>(r64, q, d, r, 0, w.vec, S, part, tickets);
-        SGP_TRY(prec_apply_f32(ctx, M, r, z, nullptr));
-        k_init_p<float><<<w.vec_nb, 256, 0, st>>>(r, z, p, w.vec, S, part, tickets);
+        k_init_res<float><<<w.vec_nb, 256, 0, st>>>(r64, q, d, r, 0, w.vec, part);
         LAUNCH_CHECK(ctx);
+        SGP_TRY(fin(ctx, FIN_INIT, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, 1));
+        SGP_TRY(prec_apply_f32(ctx, M, r, z, nullptr));
+        k_init_p<float><<<w.vec_nb, 256, 0, st>>>(r, z, p, w.vec, S, part);
+        LAUNCH_CHECK(ctx);
+        SGP_TRY(fin(ctx, FIN_RHO, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, 1));
         Vecs<float> v = {d, r, z, p, q};
-        SGP_TRY(pcg_iterate<float>(ctx, A, M, val32, v, w, S, 1, part, tickets, open, ce, max_inner - total_inner, 0));
+        SGP_TRY(pcg_iterate<float>(ctx, A, M, v, w, S, part, open, ce, max_inner - total_inner, 0));
         SGP_TRY(readback(ctx, &hs, S, sizeof hs));
         total_inner += hs.iter;
         if (hs.status == SGP_EBREAKDOWN || hs.status == SGP_ENONFINITE) {
@@ -727,15 +700,14 @@ extern "C" int sgp_pcg_solve_batched(sgp_ctx ctx, sgp_bsr A, sgp_prec M, int64_t
 extern "C" int sgp_tune(sgp_ctx ctx, const char *key, int32_t value)
 {
     if (!key) return set_err(ctx, SGP_EINVAL, "tune: null key");
-    if (!strcmp(key, "spmv_lanes")) {
-        if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
-            return set_err(ctx, SGP_EINVAL, "tune: spmv_lanes must be 1, 2, 4, 8 or 16");
-        g_spmv_lanes = value;
-        return SGP_OK;
-    }
     if (!strcmp(key, "check_every")) {
         if (value < 1) return set_err(ctx, SGP_EINVAL, "tune: check_every must be >= 1");
         g_check_every = value;
+        return SGP_OK;
+    }
+    if (!strcmp(key, "tail_max")) {
+        if (value < 0 || value > 65536) return set_err(ctx, SGP_EINVAL, "tune: tail_max must be in [0, 65536]");
+        g_tail_max = value;
         return SGP_OK;
     }
     return set_err(ctx, SGP_EINVAL, "tune: unknown key '%s'", key);

@@ -61,11 +61,17 @@ struct sgp_graph_ {
     std::vector<int64_t> h_inst_off;
 };
 
+// Gamma in block CSR: rowptr/bcol as usual; the symmetric blocks keep their 6
+// distinct entries in 64-block groups (see spmv.hip for the layout).
 struct sgp_bsr_ {
     int64_t n = 0, nnzb = 0;
     DevBuf rowptr, bcol, val, val32, diagpos;
+    DevBuf wrow;          // first row of every product wave
+    int64_t nwaves = 0;
     bool have32 = false;
 };
+
+inline int64_t sym_group_size(int64_t nnzb) { return ((nnzb + 63) / 64) * 384; }   // values incl. padding
 
 struct sgp_tree_ {
     int64_t n = 0, nt = 0, n_roots = 0;
@@ -83,7 +89,12 @@ struct sgp_prec_ {
     int32_t steps = 0;
     std::vector<int32_t> h_step_ptr;   // [steps+1] elimination-index ranges of each step
     DevBuf elim, pos, up, in_ptr, in_src, F, Dinv, y;   // tree (F: [n][2][9], Dinv: [n][6])
-    DevBuf F32, Dinv32, y32;                            // FP32 copies for the refinement inner solve
+    DevBuf tout, cs;                                    // push slots: in-list position of (q,k); slot values [n_in][3]
+    DevBuf step_ptr;                                    // device copy of h_step_ptr
+    int32_t tail_step = 0;                              // steps >= tail_step run in one workgroup
+    int32_t tail_nt = 0, tail_ni = 0;                   // tail vertices, tail-internal push slots
+    DevBuf tail_iptr, tail_tslot;                       // per tail target: first internal slot; per (q,k): its slot
+    DevBuf F32, Dinv32, y32, cs32;                      // FP32 copies for the refinement inner solve
     bool have32 = false;
     DevBuf jdinv;                                       // Jacobi: [n][6]
 };
@@ -136,11 +147,13 @@ int iota_i32(sgp_ctx ctx, int32_t *p, int64_t n);
 int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScalars *s);
 int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s);
 int prec_make32(sgp_ctx ctx, sgp_prec M);
+extern int g_tail_max;   // vertices at most left for the one-workgroup tail of the tree sweeps
+int tail_setup_attr(sgp_ctx ctx);
 int bsr_make32(sgp_ctx ctx, sgp_bsr A);
-int spmv_launch_f64(sgp_ctx ctx, sgp_bsr A, const double *x, double *y, PcgScalars *s, double *part,
-                    unsigned *ticket, int mode);
-int spmv_launch_f32(sgp_ctx ctx, sgp_bsr A, const float *x, float *y, PcgScalars *s, double *part,
-                    unsigned *ticket, int mode);
+int bsr_prepare(sgp_ctx ctx, sgp_bsr A);
+int spmv_blocks(sgp_bsr A);
+int spmv_f64(sgp_ctx ctx, sgp_bsr A, const double *x, double *y, const PcgScalars *S, double *part, int mode);
+int spmv_f32(sgp_ctx ctx, sgp_bsr A, const float *x, float *y, const PcgScalars *S, double *part, int mode);
 
 // ---------------------------------------------------------------- device helpers
 

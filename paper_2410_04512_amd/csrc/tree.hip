@@ -8,7 +8,12 @@
 //   atomic passes (max of the IEEE bits of w, which order like the values for
 //   w > 0; then min edge id among the edges of that weight); components hook
 //   along their best edges; the only cycles of the hook graph are mutual pairs,
-//   broken toward the smaller component id; pointer jumping relabels.
+//   broken toward the smaller component id; pointer jumping finds each hook
+//   tree's root, and the merged component takes the smallest representative
+//   of its hook tree as its label.  Representatives start as the vertices
+//   themselves, so every component is always labelled by its smallest vertex
+//   -- the root the forest is oriented from.  Edges inside one component are
+//   dropped from the active list after every round.
 //
 // Rooting: every tree is rooted at its smallest cell id.  An Euler tour of the
 // forest (neighbour lists sorted, successor of dart a->b is b->next(a)) is cut
@@ -34,28 +39,31 @@ __global__ void k_bv_clear_best(unsigned long long *bestw, int32_t *beste, int64
     }
 }
 
-__global__ void k_bv_maxw(const int32_t *ei, const int32_t *ej, const double4 *wu, int64_t m,
+__global__ void k_bv_maxw(const int32_t *act, int64_t na, const int32_t *ei, const int32_t *ej, const double4 *wu,
                           const int32_t *comp, unsigned long long *bestw)
 {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= na) return;
+    int32_t e = act[k];
     int32_t a = comp[ei[e]], b = comp[ej[e]];
     if (a == b) return;
     unsigned long long wb = (unsigned long long)__double_as_longlong(wu[e].x);
-    atomicMax(&bestw[a], wb);
-    atomicMax(&bestw[b], wb);
+    // test before the atomic: a component's slot is hot once it is large
+    if (wb > bestw[a]) atomicMax(&bestw[a], wb);
+    if (wb > bestw[b]) atomicMax(&bestw[b], wb);
 }
 
-__global__ void k_bv_mine(const int32_t *ei, const int32_t *ej, const double4 *wu, int64_t m,
+__global__ void k_bv_mine(const int32_t *act, int64_t na, const int32_t *ei, const int32_t *ej, const double4 *wu,
                           const int32_t *comp, const unsigned long long *bestw, int32_t *beste)
 {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= na) return;
+    int32_t e = act[k];
     int32_t a = comp[ei[e]], b = comp[ej[e]];
     if (a == b) return;
     unsigned long long wb = (unsigned long long)__double_as_longlong(wu[e].x);
-    if (wb == bestw[a]) atomicMin(&beste[a], (int32_t)e);
-    if (wb == bestw[b]) atomicMin(&beste[b], (int32_t)e);
+    if (wb == bestw[a] && e < beste[a]) atomicMin(&beste[a], e);
+    if (wb == bestw[b] && e < beste[b]) atomicMin(&beste[b], e);
 }
 
 __global__ void k_bv_hook(const int32_t *ei, const int32_t *ej, int64_t n, const int32_t *comp,
@@ -90,11 +98,36 @@ __global__ void k_bv_jump(int64_t n, const int32_t *comp, const int32_t *nxt_in,
     if (pp != p) *flag = 1;
 }
 
-__global__ void k_bv_relabel(int64_t n, int32_t *comp, const int32_t *nxt)
+// smallest representative of every hook tree, at the tree's root
+__global__ void k_bv_minrep(int64_t n, const int32_t *comp, const int32_t *nxt, int32_t *mr)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n || comp[c] != c) return;
+    int32_t root = nxt[c];
+    if ((int32_t)c < mr[root]) atomicMin(&mr[root], (int32_t)c);
+}
+
+__global__ void k_bv_relabel(int64_t n, int32_t *comp, const int32_t *nxt, const int32_t *mr)
 {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    comp[v] = nxt[comp[v]];
+    comp[v] = mr[nxt[comp[v]]];
+}
+
+// active-edge compaction: keep the edges that still join two components
+__global__ void k_bv_live(const int32_t *act, int64_t na, const int32_t *ei, const int32_t *ej, const int32_t *comp,
+                          int32_t *flag)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= na) return;
+    int32_t e = act[k];
+    flag[k] = comp[ei[e]] != comp[ej[e]] ? 1 : 0;
+}
+
+__global__ void k_bv_pack(const int32_t *act, int64_t na, const int32_t *flag, const int32_t *off, int32_t *out)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < na && flag[k]) out[off[k]] = act[k];
 }
 
 __global__ void k_compact_flags(const int32_t *flag, const int32_t *off, int64_t m, int32_t *out)
@@ -104,12 +137,6 @@ __global__ void k_compact_flags(const int32_t *flag, const int32_t *off, int64_t
 }
 
 // ---------------------------------------------------------------- rooting
-
-__global__ void k_root_min(int64_t n, const int32_t *comp, int32_t *rootmin)
-{
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) atomicMin(&rootmin[comp[v]], (int32_t)v);
-}
 
 __global__ void k_tdeg(const int32_t *tree_edge, int64_t nt, const int32_t *ei, const int32_t *ej, int32_t *deg)
 {
@@ -159,8 +186,7 @@ __global__ void k_tsort(int64_t n, const int32_t *tptr, int32_t *adj, int32_t *a
 
 // twin, Euler successor, cut at the root of each tree
 __global__ void k_tour(int64_t nd, const int32_t *tptr, const int32_t *adj, const int32_t *adje,
-                       const int32_t *comp, const int32_t *rootmin, int32_t *twin, int32_t *succ,
-                       int32_t *rank)
+                       const int32_t *comp, int32_t *twin, int32_t *succ, int32_t *rank)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nd) return;
@@ -172,7 +198,7 @@ __global__ void k_tour(int64_t nd, const int32_t *tptr, const int32_t *adj, cons
     }
     twin[k] = lo;
     int32_t nx = (lo + 1 < tptr[b + 1]) ? lo + 1 : tptr[b];
-    bool is_root = rootmin[comp[b]] == b;
+    bool is_root = comp[b] == b;   // components are labelled by their smallest vertex
     if (is_root && nx == tptr[b]) nx = -1;   // tour of b's tree ends when it returns to b the last time
     succ[k] = nx;
     rank[k] = (nx < 0) ? 0 : 1;
@@ -194,25 +220,24 @@ __global__ void k_rank_jump(int64_t nd, const int32_t *nxt_in, const int32_t *ra
 }
 
 // component tour lengths at the root's index: 2 (size - 1) = rank(first dart) + 1
-__global__ void k_tour_len(int64_t n, const int32_t *tptr, const int32_t *rootmin, const int32_t *comp,
-                           const int32_t *rank, int32_t *len)
+__global__ void k_tour_len(int64_t n, const int32_t *tptr, const int32_t *comp, const int32_t *rank, int32_t *len)
 {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    bool is_root = rootmin[comp[v]] == v;
+    bool is_root = comp[v] == v;
     len[v] = (is_root && tptr[v + 1] > tptr[v]) ? rank[tptr[v]] + 1 : 0;
 }
 
 __global__ void k_orient(int64_t nd, const int32_t *adj, const int32_t *adje, const int32_t *from,
                          const int32_t *twin, const int32_t *rank, const int32_t *tptr, const int32_t *comp,
-                         const int32_t *rootmin, const int32_t *base, int32_t *parent, int32_t *pedge,
+                         const int32_t *base, int32_t *parent, int32_t *pedge,
                          int32_t *wval, int32_t *dpos, int32_t *bad)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nd) return;
     int32_t a = from[k], b = adj[k];
     bool down = rank[k] > rank[twin[k]];
-    int32_t r = rootmin[comp[a]];
+    int32_t r = comp[a];
     int64_t g = (int64_t)base[r] + (rank[tptr[r]] - rank[k]);
     if (g < 0 || g >= nd) {   // only a broken tour could get here
         atomicOr(bad, 1);
@@ -277,29 +302,43 @@ extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP4], m + 2, &is_tree));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP5], 8, &flag));
     int32_t *hflag = (int32_t *)ctx->pinned;
+    int32_t *act, *act2, *lflag, *loff, *mr;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_KEY_A], m + 2, &act));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_KEY_B], m + 2, &act2));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_VAL_A], m + 2, &lflag));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_VAL_B], m + 2, &loff));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_DEG], n + 2, &mr));
     k_bv_reset<<<grid_for(n, 256), 256, 0, st>>>(comp, n);
+    SGP_TRY(iota_i32(ctx, act, m));
     SGP_TRY(fill_i32(ctx, is_tree, 0, m + 1));
-    for (int round = 0; round < 64; round++) {
+    int64_t na = m;
+    for (int round = 0; round < 64 && na > 0; round++) {
         k_bv_clear_best<<<grid_for(n, 256), 256, 0, st>>>(bestw, beste, n);
-        if (m > 0) {
-            k_bv_maxw<<<grid_for(m, 256), 256, 0, st>>>(ei, ej, wu, m, comp, bestw);
-            k_bv_mine<<<grid_for(m, 256), 256, 0, st>>>(ei, ej, wu, m, comp, bestw, beste);
-        }
+        k_bv_maxw<<<grid_for(na, 256), 256, 0, st>>>(act, na, ei, ej, wu, comp, bestw);
+        k_bv_mine<<<grid_for(na, 256), 256, 0, st>>>(act, na, ei, ej, wu, comp, bestw, beste);
         SGP_TRY(fill_i32(ctx, flag, 0, 1));
         k_bv_hook<<<grid_for(n, 256), 256, 0, st>>>(ei, ej, n, comp, beste, nxt, is_tree, flag);
         LAUNCH_CHECK(ctx);
-        SGP_TRY(readback(ctx, hflag, flag, 4));
-        if (!hflag[0]) break;
+        // pointer jumping, two jumps per check (extra jumps are no-ops)
         for (int j = 0; j < 64; j++) {
             SGP_TRY(fill_i32(ctx, flag, 0, 1));
-            k_bv_jump<<<grid_for(n, 256), 256, 0, st>>>(n, comp, nxt, nxt2, flag);
+            k_bv_jump<<<grid_for(n, 256), 256, 0, st>>>(n, comp, nxt, nxt2, flag + 1);
+            k_bv_jump<<<grid_for(n, 256), 256, 0, st>>>(n, comp, nxt2, nxt, flag);
             LAUNCH_CHECK(ctx);
-            std::swap(nxt, nxt2);
             SGP_TRY(readback(ctx, hflag, flag, 4));
             if (!hflag[0]) break;
         }
-        k_bv_relabel<<<grid_for(n, 256), 256, 0, st>>>(n, comp, nxt);
+        SGP_TRY(fill_i32(ctx, mr, INT_MAX, n));
+        k_bv_minrep<<<grid_for(n, 256), 256, 0, st>>>(n, comp, nxt, mr);
+        k_bv_relabel<<<grid_for(n, 256), 256, 0, st>>>(n, comp, nxt, mr);
+        k_bv_live<<<grid_for(na, 256), 256, 0, st>>>(act, na, ei, ej, comp, lflag);
+        SGP_TRY(scan_exclusive(ctx, lflag, loff, na));
+        k_bv_pack<<<grid_for(na, 256), 256, 0, st>>>(act, na, lflag, loff, act2);
         LAUNCH_CHECK(ctx);
+        int32_t hn;
+        SGP_TRY(readback(ctx, &hn, loff + na, 4));
+        std::swap(act, act2);
+        na = hn;
     }
     // tree edges ascending
     int32_t *toff;
@@ -311,10 +350,8 @@ extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
     const int64_t nt = hnt;
     T->nt = nt;
     // ---- rooting
-    int32_t *rootmin = nxt2, *tdeg = nxt, *tptr, *cur = beste;
+    int32_t *tdeg = nxt, *tptr, *cur = beste;
     SGP_TRY(ensure_t(ctx, T->tptr, n + 2, &tptr));
-    SGP_TRY(fill_i32(ctx, rootmin, INT_MAX, n));
-    k_root_min<<<grid_for(n, 256), 256, 0, st>>>(n, comp, rootmin);
     SGP_TRY(fill_i32(ctx, tdeg, 0, n));
     SGP_TRY(fill_i32(ctx, cur, 0, n));
     SGP_TRY(fill_i32(ctx, parent, -1, n));
@@ -335,7 +372,7 @@ extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
     if (nt > 0) {
         k_tfill<<<grid_for(nt, 256), 256, 0, st>>>(te, nt, ei, ej, tptr, cur, adj, adje);
         k_tsort<<<grid_for(n, 256), 256, 0, st>>>(n, tptr, adj, adje, from);
-        k_tour<<<grid_for(nd, 256), 256, 0, st>>>(nd, tptr, adj, adje, comp, rootmin, twin, succ, rank);
+        k_tour<<<grid_for(nd, 256), 256, 0, st>>>(nd, tptr, adj, adje, comp, twin, succ, rank);
         LAUNCH_CHECK(ctx);
         for (int64_t span = 1; span < nd; span *= 2) {
             k_rank_jump<<<grid_for(nd, 256), 256, 0, st>>>(nd, succ, rank, succ2, rank2);
@@ -350,11 +387,11 @@ extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
         SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP8], nd + 1, &wv));
         SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP9], nd + 2, &wex));
         dpos = cur;     // the lengths are consumed by the scan before k_orient writes
-        k_tour_len<<<grid_for(n, 256), 256, 0, st>>>(n, tptr, rootmin, comp, rank, len);
+        k_tour_len<<<grid_for(n, 256), 256, 0, st>>>(n, tptr, comp, rank, len);
         SGP_TRY(scan_exclusive(ctx, len, base, n));
         SGP_TRY(fill_i32(ctx, flag, 0, 3));
         SGP_TRY(fill_i32(ctx, wv, 0, nd));
-        k_orient<<<grid_for(nd, 256), 256, 0, st>>>(nd, adj, adje, from, twin, rank, tptr, comp, rootmin, base,
+        k_orient<<<grid_for(nd, 256), 256, 0, st>>>(nd, adj, adje, from, twin, rank, tptr, comp, base,
                                                    parent, pedge, wv, dpos, flag + 2);
         SGP_TRY(scan_exclusive(ctx, wv, wex, nd));
         k_depth<<<grid_for(n, 256), 256, 0, st>>>(n, parent, dpos, wex, wv, depth, flag);
