@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--schedule", default="contract", choices=["contract", "level"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--kernel-only", choices=["spmv"], default=None,
+                    help="build the system once, then run only the named kernel (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
@@ -96,6 +98,32 @@ def main():
         ctx.build_tree(g, T)
         ctx.factor_tree(g, T, 1.0, 0.1, 1e-3, args.schedule, M)
         _, info = ctx.pcg_solve(A, M, F, v, rtol=1e-8)
+
+    if args.kernel_only == "spmv":
+        # counter-run mode: a plain copy of known size (calibrates FETCH_SIZE /
+        # WRITE_SIZE), then the block-CSR product alone, 20 times
+        ctx.collide(pos, R, 32, g)
+        ctx.assemble_gamma(g, 1.0, 0.1, 1e-3, A)
+        n, _ = g.size()
+        _, nnzb = A.size()
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 512 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        x = torch.ones_like(F)
+        y = torch.empty_like(F)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            ctx.spmv(A, x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 20
+        print(json.dumps({"kernel": "k_spmv_sym", "copy_bytes": 2 * src.numel() * 8, "avg_ms": ms,
+                          "bytes_per_launch": spmv_bytes(n, nnzb),
+                          "GBs": spmv_bytes(n, nnzb) / ms / 1e6}), flush=True)
+        ctx.close()
+        return
 
     for _ in range(args.warmup):
         step()
