@@ -74,6 +74,7 @@ extern "C" void sgp_graph_free(sgp_graph g)
     (void)hipDeviceSynchronize();
     release(g->rowptr); release(g->col); release(g->ent_edge); release(g->ei);
     release(g->ej); release(g->wu); release(g->inst_off); release(g->inst_of);
+    release(g->perm); release(g->inv);
     delete g;
 }
 
@@ -82,7 +83,7 @@ extern "C" void sgp_bsr_free(sgp_bsr A)
     if (!A) return;
     (void)hipDeviceSynchronize();
     release(A->rowptr); release(A->bcol); release(A->val); release(A->val32); release(A->diagpos);
-    release(A->wrow);
+    release(A->wrow); release(A->perm); release(A->inv);
     delete A;
 }
 
@@ -102,6 +103,7 @@ extern "C" void sgp_prec_free(sgp_prec M)
     release(M->elim); release(M->pos); release(M->up); release(M->in_ptr); release(M->in_src);
     release(M->F); release(M->Dinv); release(M->y); release(M->F32); release(M->Dinv32); release(M->y32);
     release(M->tout); release(M->cs); release(M->cs32); release(M->step_ptr);
+    release(M->elim_int); release(M->perm); release(M->inv); release(M->tail_iptr); release(M->tail_tslot);
     release(M->jdinv);
     delete M;
 }

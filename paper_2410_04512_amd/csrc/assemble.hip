@@ -34,9 +34,75 @@ SGP_DEV void put_sym(double *val, int64_t k, const double *B)
     g[320] = B[8];
 }
 
+// internal row i holds caller row perm[i] plus its diagonal block
+__global__ void k_int_degree(int64_t n, const int32_t *rowptr, const int32_t *perm, int32_t *d)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t u = perm[i];
+    d[i] = rowptr[u + 1] - rowptr[u] + 1;
+}
+
+// Gamma in the internal order.  The diagonal block is summed over the caller
+// row in ascending neighbour order (the definition's order); the blocks are
+// then written in ascending internal column order.
 __global__ void k_assemble(int64_t n, const int32_t *rowptr, const int32_t *col, const int32_t *ent_edge,
-                           const double4 *wu, double gpar, double gperp, double gmed, int32_t *brow, int32_t *bcol,
-                           double *val, int32_t *diagpos)
+                           const double4 *wu, const int32_t *perm, const int32_t *inv, double gpar, double gperp,
+                           double gmed, const int32_t *brow, int32_t *bcol, double *val, int32_t *diagpos)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t u = perm[i];
+    const int32_t b = rowptr[u], e = rowptr[u + 1];
+    int32_t jin[64], pin[64];
+    double D[9];
+    for (int t = 0; t < 9; t++) D[t] = (t % 4 == 0) ? gmed : 0.0;
+    int cnt = 0;
+    for (int32_t p = b; p < e; p++) {
+        double4 q = wu[ent_edge[p]];
+        double W[9];
+        friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
+        for (int t = 0; t < 9; t++) D[t] = D[t] + W[t];
+        // insertion by internal column
+        int32_t jj = inv[col[p]];
+        int c = cnt++;
+        while (c > 0 && jin[c - 1] > jj) {
+            jin[c] = jin[c - 1];
+            pin[c] = pin[c - 1];
+            c--;
+        }
+        jin[c] = jj;
+        pin[c] = p;
+    }
+    int64_t k = brow[i];
+    bool placed = false;
+    for (int c = 0; c < cnt; c++) {
+        if (!placed && jin[c] > (int32_t)i) {
+            put_sym(val, k, D);
+            bcol[k] = (int32_t)i;
+            diagpos[i] = (int32_t)k;
+            k++;
+            placed = true;
+        }
+        double4 q = wu[ent_edge[pin[c]]];
+        double W[9], B[9];
+        friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
+        for (int t = 0; t < 9; t++) B[t] = -W[t];
+        put_sym(val, k, B);
+        bcol[k] = jin[c];
+        k++;
+    }
+    if (!placed) {
+        put_sym(val, k, D);
+        bcol[k] = (int32_t)i;
+        diagpos[i] = (int32_t)k;
+    }
+}
+
+// Gamma in the caller's numbering, 9 entries per block (for export)
+__global__ void k_assemble_canon(int64_t n, const int32_t *rowptr, const int32_t *col, const int32_t *ent_edge,
+                                 const double4 *wu, double gpar, double gperp, double gmed, int32_t *brow,
+                                 int32_t *bcol, double *val)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -44,7 +110,7 @@ __global__ void k_assemble(int64_t n, const int32_t *rowptr, const int32_t *col,
     const int64_t base = (int64_t)b + i;
     double D[9];
     for (int t = 0; t < 9; t++) D[t] = (t % 4 == 0) ? gmed : 0.0;
-    int64_t dpos = base + (e - b);   // diagonal last unless a larger column appears
+    int64_t dpos = base + (e - b);
     bool placed = false;
     for (int32_t p = b; p < e; p++) {
         int32_t j = col[p];
@@ -54,20 +120,21 @@ __global__ void k_assemble(int64_t n, const int32_t *rowptr, const int32_t *col,
         }
         int64_t k = base + (p - b) + (placed ? 1 : 0);
         double4 q = wu[ent_edge[p]];
-        double W[9], B[9];
+        double W[9];
         friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
         for (int t = 0; t < 9; t++) {
-            B[t] = -W[t];
+            if (val) val[9 * k + t] = -W[t];
             D[t] = D[t] + W[t];
         }
-        put_sym(val, k, B);
-        bcol[k] = j;
+        if (bcol) bcol[k] = j;
     }
-    put_sym(val, dpos, D);
-    bcol[dpos] = (int32_t)i;
-    brow[i] = (int32_t)base;
-    diagpos[i] = (int32_t)dpos;
-    if (i == n - 1) brow[n] = (int32_t)(e + n);
+    if (val)
+        for (int t = 0; t < 9; t++) val[9 * dpos + t] = D[t];
+    if (bcol) bcol[dpos] = (int32_t)i;
+    if (brow) {
+        brow[i] = (int32_t)base;
+        if (i == n - 1) brow[n] = (int32_t)(e + n);
+    }
 }
 
 extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double g_perp, double g_med, sgp_bsr A)
@@ -81,20 +148,29 @@ extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double
     A->n = n;
     A->nnzb = nnzb;
     A->have32 = false;
-    int32_t *brow, *bcol, *dpos;
+    int32_t *brow, *bcol, *dpos, *deg;
     double *val;
     SGP_TRY(ensure_t(ctx, A->rowptr, n + 1, &brow));
     SGP_TRY(ensure_t(ctx, A->bcol, nnzb + 1, &bcol));
     SGP_TRY(ensure_t(ctx, A->val, sym_group_size(nnzb) + 8, &val));
     SGP_TRY(ensure_t(ctx, A->diagpos, n + 1, &dpos));
+    A->src = g;
+    A->gpar = g_par;
+    A->gperp = g_perp;
+    A->gmed = g_med;
     if (n == 0) {
         A->nwaves = 0;
         return fill_i32(ctx, brow, 0, 1);
     }
+    SGP_TRY(copy_order(ctx, A->perm, A->inv, g->perm, g->inv, n));
     // zero the padding of the last group (read by no row, kept finite)
     SGP_TRY(fill_f64(ctx, val + (sym_group_size(nnzb) - 384), 0.0, 384));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_DEG], n + 1, &deg));
+    k_int_degree<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->rowptr.p, (const int32_t *)g->perm.p, deg);
+    SGP_TRY(scan_exclusive(ctx, deg, brow, n));
     k_assemble<<<grid_for(n, 128), 128, 0, st>>>(n, (const int32_t *)g->rowptr.p, (const int32_t *)g->col.p,
-                                                 (const int32_t *)g->ent_edge.p, (const double4 *)g->wu.p, g_par,
+                                                 (const int32_t *)g->ent_edge.p, (const double4 *)g->wu.p,
+                                                 (const int32_t *)g->perm.p, (const int32_t *)g->inv.p, g_par,
                                                  g_perp, g_med, brow, bcol, val, dpos);
     LAUNCH_CHECK(ctx);
     SGP_TRY(bsr_prepare(ctx, A));
@@ -114,30 +190,21 @@ extern "C" int sgp_bsr_size(sgp_bsr A, int64_t *n, int64_t *nnzb)
     return SGP_OK;
 }
 
-__global__ void k_expand_sym(int64_t nnzb, const double *val, double *out)
-{
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nnzb) return;
-    const double *g = val + (k >> 6) * 384 + (k & 63);
-    double a = g[0], b = g[64], c = g[128], d = g[192], e = g[256], f = g[320];
-    double *o = out + 9 * k;
-    o[0] = a; o[1] = b; o[2] = c;
-    o[3] = b; o[4] = d; o[5] = e;
-    o[6] = c; o[7] = e; o[8] = f;
-}
-
+// The export is Gamma in the caller's numbering, rebuilt from the graph it
+// was assembled from (same arithmetic, so the same values bit for bit).
 extern "C" int sgp_bsr_export(sgp_ctx ctx, sgp_bsr A, int32_t *rowptr, int32_t *bcol, double *val)
 {
     if (!ctx || !A) return set_err(ctx, SGP_EINVAL, "bsr_export: null handle");
-    hipStream_t st = ctx->stream;
-    if (rowptr) HIP_TRY(ctx, hipMemcpyAsync(rowptr, A->rowptr.p, (A->n + 1) * 4, hipMemcpyDeviceToDevice, st));
-    if (A->nnzb > 0) {
-        if (bcol) HIP_TRY(ctx, hipMemcpyAsync(bcol, A->bcol.p, A->nnzb * 4, hipMemcpyDeviceToDevice, st));
-        if (val) {
-            k_expand_sym<<<grid_for(A->nnzb, 256), 256, 0, st>>>(A->nnzb, (const double *)A->val.p, val);
-            LAUNCH_CHECK(ctx);
-        }
+    if (A->n == 0) {
+        if (rowptr) SGP_TRY(fill_i32(ctx, rowptr, 0, 1));
+        return SGP_OK;
     }
+    sgp_graph g = A->src;
+    if (!g || g->n != A->n) return set_err(ctx, SGP_EINVAL, "bsr_export: the source graph changed or was freed");
+    k_assemble_canon<<<grid_for(A->n, 128), 128, 0, ctx->stream>>>(
+        A->n, (const int32_t *)g->rowptr.p, (const int32_t *)g->col.p, (const int32_t *)g->ent_edge.p,
+        (const double4 *)g->wu.p, A->gpar, A->gperp, A->gmed, rowptr, bcol, val);
+    LAUNCH_CHECK(ctx);
     return SGP_OK;
 }
 

@@ -113,6 +113,12 @@ __global__ void k_gather_sorted(const double *pos, const double *R, const int32_
     sp[s] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], R[i]);
 }
 
+__global__ void k_inverse(const int32_t *perm, int64_t n, int32_t *inv)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) inv[perm[i]] = (int32_t)i;
+}
+
 // --------------------------------------------------------------- 3. contacts
 
 // flags[0]: capacity overflow, flags[1]: coincident centres in contact
@@ -323,6 +329,13 @@ static int collide_impl(sgp_ctx ctx, int64_t n, const double *pos, const double 
     double4 *sp;
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP2], n, &sp));
     k_gather_sorted<<<grid_for(n, 256), 256, 0, st>>>(pos, radius, va, n, sp);
+    LAUNCH_CHECK(ctx);
+    // the cell-list order becomes the library's internal vertex order
+    int32_t *gperm, *ginv;
+    SGP_TRY(ensure_t(ctx, g->perm, n + 1, &gperm));
+    SGP_TRY(ensure_t(ctx, g->inv, n + 1, &ginv));
+    HIP_TRY(ctx, hipMemcpyAsync(gperm, va, n * 4, hipMemcpyDeviceToDevice, st));
+    k_inverse<<<grid_for(n, 256), 256, 0, st>>>(va, n, ginv);
     LAUNCH_CHECK(ctx);
     // 3. contacts
     int32_t *slots, *deg, *upc, *flags;

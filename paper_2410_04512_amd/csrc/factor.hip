@@ -169,12 +169,21 @@ __global__ void k_step_bounds(int64_t n, const uint32_t *skey, int32_t S, int32_
     for (int32_t s = lo + 1; s <= hi; s++) sptr[s] = (int32_t)q;
 }
 
-__global__ void k_stepkeys(int64_t n, const int32_t *stepv, uint32_t *key, int32_t *val)
+// keys walked in the internal order: within a step, vertices end up in the
+// internal (spatial) order, which keeps the sweeps' gathers local
+__global__ void k_stepkeys(int64_t n, const int32_t *stepv, const int32_t *perm, uint32_t *key, int32_t *val)
 {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    key[v] = (uint32_t)stepv[v];
-    val[v] = (int32_t)v;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t v = perm[i];
+    key[i] = (uint32_t)stepv[v];
+    val[i] = v;
+}
+
+__global__ void k_map_ids(int64_t n, const int32_t *ids, const int32_t *inv, int32_t *out)
+{
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) out[q] = inv[ids[q]];
 }
 
 __global__ void k_invperm(int64_t n, const int32_t *elim, int32_t *pos)
@@ -358,7 +367,7 @@ __global__ void k_fwd_step(int32_t q0, int32_t q1, const int32_t *elim, const in
                            const PcgScalars *s)
 {
     if (s && s->done) return;
-    int32_t q = q0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    int32_t q = q0 + (int32_t)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
     if (q < q1) fwd_vertex<T>(q, elim, in_ptr, tout, F, Dinv, r, y, cs);
 }
 
@@ -367,7 +376,7 @@ __global__ void k_bwd_step(int32_t q0, int32_t q1, const int32_t *elim, const in
                            const T *Dinv, T *y, T *z, const PcgScalars *s)
 {
     if (s && s->done) return;
-    int32_t q = q0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    int32_t q = q0 + (int32_t)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
     if (q < q1) bwd_vertex<T>(q, elim, upq, F, Dinv, y, z);
 }
 
@@ -531,7 +540,8 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
                        PcgScalars *s)
 {
     hipStream_t st = ctx->stream;
-    const int32_t *elim = (const int32_t *)M->elim.p, *in_ptr = (const int32_t *)M->in_ptr.p;
+    // r and z are in the internal order
+    const int32_t *elim = (const int32_t *)M->elim_int.p, *in_ptr = (const int32_t *)M->in_ptr.p;
     const int32_t *tout = (const int32_t *)M->tout.p, *upq = (const int32_t *)M->up.p;
     const int32_t *dsp = (const int32_t *)M->step_ptr.p;
     const std::vector<int32_t> &sp = M->h_step_ptr;
@@ -718,9 +728,13 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP8], (size_t)S + 2, &sptr));
     int sbits = 1;
     while ((1 << sbits) < S) sbits++;
-    k_stepkeys<<<grid_for(n, 256), 256, 0, st>>>(n, stepv, ka, elim);
+    SGP_TRY(copy_order(ctx, M->perm, M->inv, g->perm, g->inv, n));
+    k_stepkeys<<<grid_for(n, 256), 256, 0, st>>>(n, stepv, (const int32_t *)g->perm.p, ka, elim);
     LAUNCH_CHECK(ctx);
     SGP_TRY(radix_sort_pairs(ctx, ka, elim, kb, vb, n, sbits));
+    int32_t *elim_int;
+    SGP_TRY(ensure_t(ctx, M->elim_int, n + 1, &elim_int));
+    k_map_ids<<<grid_for(n, 256), 256, 0, st>>>(n, elim, (const int32_t *)g->inv.p, elim_int);
     k_invperm<<<grid_for(n, 256), 256, 0, st>>>(n, elim, pos);
     (void)scnt;
     k_step_bounds<<<grid_for(n + 1, 256), 256, 0, st>>>(n, ka, S, sptr);
@@ -816,6 +830,7 @@ extern "C" int sgp_make_jacobi(sgp_ctx ctx, sgp_bsr A, sgp_prec M)
     M->n = A->n;
     M->steps = 0;
     M->have32 = false;
+    SGP_TRY(copy_order(ctx, M->perm, M->inv, A->perm, A->inv, A->n));
     double *dinv;
     int32_t *status;
     SGP_TRY(ensure_t(ctx, M->jdinv, 6 * A->n + 6, &dinv));
@@ -841,6 +856,13 @@ extern "C" int sgp_prec_steps(sgp_prec M, int32_t *steps)
 extern "C" int sgp_prec_apply(sgp_ctx ctx, sgp_prec M, const double *r, double *z)
 {
     if (!ctx || !M) return set_err(ctx, SGP_EINVAL, "prec_apply: null handle");
-    if (M->n == 0) return SGP_OK;
-    return prec_apply_f64(ctx, M, r, z, nullptr);
+    const int64_t n = M->n;
+    if (n == 0) return SGP_OK;
+    double *ri, *zi;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP0], 3 * n + 3, &ri));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP1], 3 * n + 3, &zi));
+    const int32_t *perm = (const int32_t *)M->perm.p;
+    SGP_TRY(permute_rows(ctx, perm, r, ri, n, 0));
+    SGP_TRY(prec_apply_f64(ctx, M, ri, zi, nullptr));
+    return permute_rows(ctx, perm, zi, z, n, 1);
 }

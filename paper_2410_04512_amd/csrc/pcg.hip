@@ -475,9 +475,17 @@ static int solve_f64(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<int64
     const int64_t n = A->n, K = (int64_t)off.size() - 1;
     PcgWork w;
     SGP_TRY(prepare_work(ctx, A, off, w));
-    double *r, *z, *p, *q, *part;
+    double *r, *z, *p, *q, *part, *Fi, *xi;
     PcgScalars *S;
     int32_t *open;
+    const int32_t *perm = (const int32_t *)A->perm.p;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP8], 6 * n + 6, &Fi));
+    xi = Fi + 3 * n + 3;
+    SGP_TRY(permute_rows(ctx, perm, F, Fi, n, 0));
+    if (o->use_x0) SGP_TRY(permute_rows(ctx, perm, x, xi, n, 0));
+    F = Fi;
+    double *xuser = x;
+    x = xi;
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP0], 3 * n + 3, &r));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP1], 3 * n + 3, &p));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP2], 3 * n + 3, &q));
@@ -508,6 +516,7 @@ static int solve_f64(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<int64
     k_true_res<<<w.vec_nb, 256, 0, st>>>(F, q, w.vec, part);
     LAUNCH_CHECK(ctx);
     SGP_TRY(fin(ctx, FIN_TRUE, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
+    SGP_TRY(permute_rows(ctx, perm, x, xuser, n, 1));
     std::vector<PcgScalars> hs(K);
     SGP_TRY(readback(ctx, hs.data(), S, K * sizeof(PcgScalars)));
     for (int64_t k = 0; k < K; k++) {
@@ -565,10 +574,18 @@ static int solve_ir(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const double *F, double 
     std::vector<int64_t> off = {0, n};
     PcgWork w;
     SGP_TRY(prepare_work(ctx, A, off, w));
-    double *r64, *q64, *part;
+    double *r64, *q64, *part, *Fi, *xi;
     float *r, *z, *p, *q, *d;
     PcgScalars *S;
     int32_t *open;
+    const int32_t *perm = (const int32_t *)A->perm.p;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP8], 2 * len + 6, &Fi));
+    xi = Fi + len + 3;
+    SGP_TRY(permute_rows(ctx, perm, F, Fi, n, 0));
+    if (o->use_x0) SGP_TRY(permute_rows(ctx, perm, x, xi, n, 0));
+    F = Fi;
+    double *xuser = x;
+    x = xi;
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP0], len + 3, &r64));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP1], len + 3, &q64));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP2], 5 * len + 16, &r));
@@ -631,6 +648,7 @@ static int solve_ir(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const double *F, double 
         LAUNCH_CHECK(ctx);
         outer++;
     }
+    SGP_TRY(permute_rows(ctx, perm, x, xuser, n, 1));
     memset(info, 0, sizeof *info);
     info->status = status;
     info->iters = total_inner;

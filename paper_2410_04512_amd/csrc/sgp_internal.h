@@ -55,9 +55,15 @@ enum {
     WS_COUNT
 };
 
+// The graph is kept in the caller's numbering (canonical edge ids).  perm/inv
+// give the library's internal vertex order -- the cell-list order of the last
+// collide (cluster-major, then cell, then id) -- in which Gamma, the CG
+// vectors and the tree sweeps' gathers are laid out for locality:
+// internal i <-> caller perm[i], caller u <-> internal inv[u].
 struct sgp_graph_ {
     int64_t n = 0, m = 0, n_inst = 1;
     DevBuf rowptr, col, ent_edge, ei, ej, wu, inst_off, inst_of;
+    DevBuf perm, inv;
     std::vector<int64_t> h_inst_off;
 };
 
@@ -65,7 +71,10 @@ struct sgp_graph_ {
 // distinct entries in 64-block groups (see spmv.hip for the layout).
 struct sgp_bsr_ {
     int64_t n = 0, nnzb = 0;
-    DevBuf rowptr, bcol, val, val32, diagpos;
+    DevBuf rowptr, bcol, val, val32, diagpos;   // internal order
+    DevBuf perm, inv;                           // copy of the graph's order
+    sgp_graph src = nullptr;                    // graph it was assembled from (canonical export)
+    double gpar = 0, gperp = 0, gmed = 0;
     DevBuf wrow;          // first row of every product wave
     int64_t nwaves = 0;
     bool have32 = false;
@@ -89,6 +98,8 @@ struct sgp_prec_ {
     int32_t steps = 0;
     std::vector<int32_t> h_step_ptr;   // [steps+1] elimination-index ranges of each step
     DevBuf elim, pos, up, in_ptr, in_src, F, Dinv, y;   // tree (F: [n][2][9], Dinv: [n][6])
+    DevBuf elim_int;                                    // elim in the internal order
+    DevBuf perm, inv;                                   // copy of the graph's internal order
     DevBuf tout, cs;                                    // push slots: in-list position of (q,k); slot values [n_in][3]
     DevBuf step_ptr;                                    // device copy of h_step_ptr
     int32_t tail_step = 0;                              // steps >= tail_step run in one workgroup
@@ -144,7 +155,10 @@ int fill_f64(sgp_ctx ctx, double *p, double v, int64_t n);
 int iota_i32(sgp_ctx ctx, int32_t *p, int64_t n);
 
 // shared by several translation units
+// r, z in the internal order (used by the CG)
 int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScalars *s);
+int permute_rows(sgp_ctx ctx, const int32_t *idx, const double *src, double *dst, int64_t n, int scatter);
+int copy_order(sgp_ctx ctx, DevBuf &dperm, DevBuf &dinv, const DevBuf &sperm, const DevBuf &sinv, int64_t n);
 int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s);
 int prec_make32(sgp_ctx ctx, sgp_prec M);
 extern int g_tail_max;   // vertices at most left for the one-workgroup tail of the tree sweeps
@@ -203,6 +217,19 @@ SGP_DEV double sum_partials(const double *part, int n, double *sh)
     double v = 0.0;
     for (int k = threadIdx.x; k < n; k += blockDim.x) v = v + part[k];
     return block_sum_256(v, sh);
+}
+
+// XCD-aware block order.  The dispatcher deals workgroups round-robin to the
+// 8 XCDs (each with its own L2), so workgroup b runs on XCD b % 8.  Mapping b
+// to the logical block below gives every XCD one contiguous run of logical
+// blocks, so the neighbours a run gathers stay in that XCD's L2 instead of
+// being fetched by all eight.  A bijection of [0, nb) for any nb.
+constexpr int NUM_XCD = 8;
+SGP_DEV int64_t xcd_block(int64_t b, int64_t nb)
+{
+    const int64_t q = nb / NUM_XCD, r = nb % NUM_XCD;
+    const int64_t x = b % NUM_XCD, i = b / NUM_XCD;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
 // --- 3x3 blocks: full row-major [9]; symmetric packed [6] = (00,01,02,11,12,22)

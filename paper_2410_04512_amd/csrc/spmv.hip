@@ -9,7 +9,8 @@
 // so the 64 lanes of a wave that take 64 consecutive blocks read each entry
 // with one fully coalesced 512-byte load (256 bytes in FP32).
 //
-// Work split: wave w owns the rows whose first block lies in
+// Work split (workgroups in XCD-contiguous order, see xcd_block): wave w owns
+// the rows whose first block lies in
 // [w * WAVE_BLOCKS, (w + 1) * WAVE_BLOCKS); it walks their blocks 64 at a time
 // (one block per lane), multiplies against the gathered x, parks the three
 // products per block in LDS, and then one lane per row adds the row's products
@@ -50,6 +51,15 @@ int bsr_prepare(sgp_ctx ctx, sgp_bsr A)
     return SGP_OK;
 }
 
+// one block's three products, parked in LDS
+template <class T>
+SGP_DEV void block_product(T *a, int s, const T *v, T x0, T x1, T x2)
+{
+    a[3 * s] = v[0] * x0 + v[1] * x1 + v[2] * x2;
+    a[3 * s + 1] = v[1] * x0 + v[3] * x1 + v[4] * x2;
+    a[3 * s + 2] = v[2] * x0 + v[4] * x1 + v[5] * x2;
+}
+
 template <class T>
 __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_sym(const int32_t *__restrict__ rowptr,
                                                               const int32_t *__restrict__ bcol,
@@ -59,12 +69,13 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_sym(const int32_t *__r
                                                               int mode)
 {
     __shared__ T acc[SPMV_WAVES][3 * ACC_SLOTS];
-    __shared__ double sh[64 * SPMV_WAVES];
+    __shared__ double sh[SPMV_WAVES];
     if (S && S->done) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t w = (int64_t)blockIdx.x * SPMV_WAVES + wv;
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);   // contiguous rows per XCD
+    const int64_t w = lb * SPMV_WAVES + wv;
     int32_t r_lo = 0, r_hi = 0, kb = 0, ke = 0;
-    int64_t base = w * WAVE_BLOCKS;
+    const int64_t base = w * WAVE_BLOCKS;
     if (w < nwaves) {
         r_lo = wrow[w];
         r_hi = wrow[w + 1];
@@ -72,17 +83,42 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_sym(const int32_t *__r
         ke = rowptr[r_hi];
     }
     T *a = acc[wv];
-    for (int64_t c = base; c < ke; c += 64) {
+    // the wave's two 64-block groups: all loads first, then the gathers
+    const int64_t k0 = base + lane, k1 = base + 64 + lane;
+    const bool on0 = k0 >= kb && k0 < ke, on1 = k1 >= kb && k1 < ke;
+    T v0[6], v1[6];
+    int64_t j0 = 0, j1 = 0;
+    const T *g0 = val + (base >> 6) * 384 + lane;
+    if (on0) {
+        for (int t = 0; t < 6; t++) v0[t] = g0[64 * t];
+        j0 = bcol[k0];
+    }
+    if (on1) {
+        for (int t = 0; t < 6; t++) v1[t] = g0[384 + 64 * t];
+        j1 = bcol[k1];
+    }
+    T x00 = 0, x01 = 0, x02 = 0, x10 = 0, x11 = 0, x12 = 0;
+    if (on0) {
+        x00 = x[3 * j0];
+        x01 = x[3 * j0 + 1];
+        x02 = x[3 * j0 + 2];
+    }
+    if (on1) {
+        x10 = x[3 * j1];
+        x11 = x[3 * j1 + 1];
+        x12 = x[3 * j1 + 2];
+    }
+    if (on0) block_product(a, lane, v0, x00, x01, x02);
+    if (on1) block_product(a, 64 + lane, v1, x10, x11, x12);
+    // blocks of the last row that run past the two groups
+    for (int64_t c = base + WAVE_BLOCKS; c < ke; c += 64) {
         const int64_t k = c + lane;
-        if (k >= kb && k < ke) {
+        if (k < ke) {
             const T *g = val + (c >> 6) * 384 + lane;
-            const T b00 = g[0], b01 = g[64], b02 = g[128], b11 = g[192], b12 = g[256], b22 = g[320];
+            T v[6];
+            for (int t = 0; t < 6; t++) v[t] = g[64 * t];
             const int64_t j = bcol[k];
-            const T x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
-            const int s = (int)(k - base);
-            a[3 * s] = b00 * x0 + b01 * x1 + b02 * x2;
-            a[3 * s + 1] = b01 * x0 + b11 * x1 + b12 * x2;
-            a[3 * s + 2] = b02 * x0 + b12 * x1 + b22 * x2;
+            block_product(a, (int)(k - base), v, x[3 * j], x[3 * j + 1], x[3 * j + 2]);
         }
     }
     __syncthreads();
@@ -103,14 +139,11 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_sym(const int32_t *__r
                      (double)x[3 * (int64_t)row + 2] * (double)y2);
     }
     if (mode) {
-        // fixed-order workgroup sum of the p.q shares
-        sh[threadIdx.x] = d;
+        // fixed-order sum of the p.q shares: butterfly within each wave, then the waves in order
+        for (int o = 32; o > 0; o >>= 1) d = d + __shfl_xor(d, o, 64);
+        if (lane == 0) sh[wv] = d;
         __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+        if (threadIdx.x == 0) part[lb] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
     }
 }
 
@@ -136,9 +169,17 @@ int spmv_f32(sgp_ctx ctx, sgp_bsr A, const float *x, float *y, const PcgScalars 
     return SGP_OK;
 }
 
+// caller's numbering in and out; the product runs in the internal order
 extern "C" int sgp_spmv(sgp_ctx ctx, sgp_bsr A, const double *x, double *y)
 {
     if (!ctx || !A || (A->n > 0 && (!x || !y))) return set_err(ctx, SGP_EINVAL, "spmv: bad arguments");
-    if (A->n == 0) return SGP_OK;
-    return spmv_f64(ctx, A, x, y, nullptr, nullptr, 0);
+    const int64_t n = A->n;
+    if (n == 0) return SGP_OK;
+    double *xi, *yi;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP0], 3 * n + 3, &xi));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP1], 3 * n + 3, &yi));
+    const int32_t *perm = (const int32_t *)A->perm.p;
+    SGP_TRY(permute_rows(ctx, perm, x, xi, n, 0));
+    SGP_TRY(spmv_f64(ctx, A, xi, yi, nullptr, nullptr, 0));
+    return permute_rows(ctx, perm, yi, y, n, 1);
 }

@@ -259,3 +259,37 @@ int radix_sort_pairs(sgp_ctx ctx, uint32_t *keys, int32_t *vals, uint32_t *ktmp,
     }
     return SGP_OK;
 }
+
+// ---------------------------------------------------------------- permutations
+
+// gather: dst[i] = src[idx[i]]; scatter: dst[idx[i]] = src[i] (3-vectors)
+__global__ void k_permute_rows(const int32_t *idx, const double *src, double *dst, int64_t n, int scatter)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t j = idx[i];
+    int64_t a = scatter ? i : j, b = scatter ? j : i;
+    dst[3 * b] = src[3 * a];
+    dst[3 * b + 1] = src[3 * a + 1];
+    dst[3 * b + 2] = src[3 * a + 2];
+}
+
+int permute_rows(sgp_ctx ctx, const int32_t *idx, const double *src, double *dst, int64_t n, int scatter)
+{
+    if (n <= 0) return SGP_OK;
+    k_permute_rows<<<grid_for(n, 256), 256, 0, ctx->stream>>>(idx, src, dst, n, scatter);
+    LAUNCH_CHECK(ctx);
+    return SGP_OK;
+}
+
+int copy_order(sgp_ctx ctx, DevBuf &dperm, DevBuf &dinv, const DevBuf &sperm, const DevBuf &sinv, int64_t n)
+{
+    int32_t *a, *b;
+    SGP_TRY(ensure_t(ctx, dperm, n + 1, &a));
+    SGP_TRY(ensure_t(ctx, dinv, n + 1, &b));
+    if (n > 0) {
+        HIP_TRY(ctx, hipMemcpyAsync(a, sperm.p, n * 4, hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(b, sinv.p, n * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    return SGP_OK;
+}
