@@ -25,3 +25,21 @@ def gpu_chain(ctx, c, schedule="contract", prec="tree", max_deg=32, **solve):
         M = ctx.make_jacobi(A)
     v, info = ctx.pcg_solve(A, M, F, **solve)
     return {"g": g, "A": A, "T": T, "M": M, "v": v, "info": info, "F": F, "pos": pos, "R": R}
+
+
+def check_velocity(v_gpu, iters_gpu, A, F, factor, x0=None, rtol=1e-8, prec="tree"):
+    """Velocity parity under the same x0, stopping rule and preconditioner.
+
+    Equal iteration counts: compare with the oracle's solution.  Counts one
+    apart (the residual crossed the tolerance within rounding of it): compare
+    with the oracle run for exactly the GPU's iteration count.  Returns the
+    relative error."""
+    from oracle import oracle as O
+    xo, io = O.pcg(A, F, prec, factor, x0=x0)
+    if io.iters != iters_gpu:
+        assert abs(io.iters - iters_gpu) <= 1, (io.iters, iters_gpu)
+        xo, io = O.pcg(A, F, prec, factor, x0=x0, fixed_iters=iters_gpu)
+    den = max(np.linalg.norm(xo), 1e-300)
+    err = np.linalg.norm(v_gpu - xo) / den
+    assert err <= rtol, err
+    return err

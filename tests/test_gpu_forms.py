@@ -1,0 +1,209 @@
+"""GPU parity of the extended forms, through the C ABI, against the oracle:
+FP32-inner iterative refinement, batched independent solves, the dynamics
+kernels, and the full-size workloads (1M and 4M cells) in the launch
+configuration the benchmark times."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from workloads import sphere_cluster, batched_instance, dynamics_noise
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2410_04512_amd")
+from tests.gpu_util import check_velocity, gpu_chain, host, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = P.Context()
+    yield c
+    c.close()
+
+
+# ---------------------------------------------------------------- mixed precision
+
+@pytest.mark.parametrize("n,seed", [(1000, 0), (20000, 3)])
+def test_fp32_refinement_reaches_fp64_tolerance(ctx, n, seed):
+    """FP32 product and sweeps inside FP64 refinement: the FP64 residual (recomputed
+    by the oracle) meets 1e-8; the error against a 1e-13 FP64 oracle solve is
+    stated and bounded by kappa(Gamma) * 1e-8 (kappa <= 2e3 on these systems)."""
+    c = sphere_cluster(n, seed)
+    out = gpu_chain(ctx, c)   # builds graph/Gamma/tree on the GPU
+    v, info = ctx.pcg_solve(out["A"], out["M"], out["F"], precision="f32ir", inner_rtol=1e-4)
+    assert info["status"] == 0 and info["outer_iters"] >= 2
+    og = O.collide(c["pos"], c["radius"])
+    oa = O.assemble(og)
+    vh = host(v)
+    r = c["force"] - O.spmv(oa, vh)
+    relres = np.linalg.norm(r) / np.linalg.norm(c["force"])
+    assert relres <= 1.0001e-8, relres
+    x13, _ = O.pcg(oa, c["force"], "tree", O.tree_factor(og, O.build_tree(og)), tol=1e-13)
+    err = np.linalg.norm(vh - x13) / np.linalg.norm(x13)
+    assert err <= 2e3 * 1e-8, err
+    print(f"f32ir n={n}: inner iters {info['iters']}, outer {info['outer_iters']}, relres {relres:.2e}, "
+          f"error vs FP64 oracle {err:.2e}")
+    # same algorithm in the oracle (FP32 emulated on the CPU): similar work
+    _, oi = O.ir_solve(oa, c["force"], O.tree_factor(og, O.build_tree(og)), tol=1e-8, inner_tol=1e-4)
+    assert oi.outer == info["outer_iters"]
+    assert abs(oi.iters - info["iters"]) <= max(3, 0.05 * oi.iters)
+
+
+# ---------------------------------------------------------------- batched
+
+SIZES = [1000, 300, 2000, 57, 1500, 1, 2]
+
+
+def _batch():
+    parts = [batched_instance(k + 1, n_override=s) for k, s in enumerate(SIZES)]
+    off = np.concatenate([[0], np.cumsum(SIZES)]).astype(np.int64)
+    pos = np.concatenate([p["pos"] for p in parts])
+    R = np.concatenate([p["radius"] for p in parts])
+    F = np.concatenate([p["force"] for p in parts])
+    return parts, off, pos, R, F
+
+
+def test_batched_graph_tree_and_solves(ctx):
+    parts, off, pos, R, F = _batch()
+    g = ctx.collide_batched(off, to_dev(pos), to_dev(R))
+    A = ctx.assemble_gamma(g)
+    T = ctx.build_tree(g)
+    M = ctx.factor_tree(g, T)
+    v, infos = ctx.pcg_solve_batched(A, M, off, to_dev(F))
+    e = {k: host(t) for k, t in ctx.graph_export(g).items()}
+    te = host(ctx.tree_export(T, int(off[-1]))["tree_edge"])
+    vh = host(v)
+    eoff = 0
+    toff = []
+    for k, p in enumerate(parts):
+        og = O.collide(p["pos"], p["radius"])
+        sl = slice(eoff, eoff + og.m)
+        assert np.array_equal(e["ei"][sl] - off[k], og.ei) and np.array_equal(e["ej"][sl] - off[k], og.ej)
+        assert np.array_equal(e["w"][sl], og.w) and np.array_equal(e["u"][sl], og.u)
+        ot = O.build_tree(og)
+        toff.append(ot.tree_edge + eoff)
+        eoff += og.m
+        oa = O.assemble(og)
+        assert infos[k]["status"] == 0
+        check_velocity(vh[off[k]:off[k + 1]], infos[k]["iters"], oa, p["force"], O.tree_factor(og, ot))
+    assert np.array_equal(te, np.concatenate(toff))
+    assert e["ei"].shape[0] == eoff
+
+
+def test_batched_equals_separate_solves(ctx):
+    parts, off, pos, R, F = _batch()
+    g = ctx.collide_batched(off, to_dev(pos), to_dev(R))
+    A = ctx.assemble_gamma(g)
+    M = ctx.factor_tree(g, ctx.build_tree(g))
+    v, infos = ctx.pcg_solve_batched(A, M, off, to_dev(F))
+    for k, p in enumerate(parts):
+        # a batch lays its cells out on one shared grid, so its internal order
+        # (and with it the summation order) differs from a lone solve: equal up
+        # to CG's rounding spread, bounded here by the parity bar
+        single = gpu_chain(ctx, p)
+        assert abs(single["info"]["iters"] - infos[k]["iters"]) <= 1
+        a, b = host(single["v"]), host(v)[off[k]:off[k + 1]]
+        if single["info"]["iters"] == infos[k]["iters"]:
+            assert np.linalg.norm(a - b) <= 1e-8 * max(np.linalg.norm(a), 1e-300)
+
+
+# ---------------------------------------------------------------- dynamics
+
+def test_forces_and_euler_bit_exact(ctx):
+    c = sphere_cluster(20000, 4)
+    noise = dynamics_noise(7, 20000)
+    g = ctx.collide(to_dev(c["pos"]), to_dev(c["radius"]))
+    Fg = host(ctx.forces(g, to_dev(noise), 5.0))
+    og = O.collide(c["pos"], c["radius"])
+    assert np.array_equal(Fg, O.forces(og, noise, 5.0))
+    v = np.random.default_rng(2).normal(size=(20000, 3))
+    pos = to_dev(c["pos"])
+    ctx.euler(pos, to_dev(v), 0.01)
+    assert np.array_equal(host(pos), O.euler(c["pos"], v, 0.01))
+
+
+def test_time_steps_match_oracle_from_same_positions(ctx):
+    """Three overdamped steps; each step is compared from identical input
+    positions (the oracle consumes the GPU's positions), since contact flips make
+    free-running trajectories diverge."""
+    n = 3000
+    c = sphere_cluster(n, 5)
+    pos = to_dev(c["pos"])
+    R = to_dev(c["radius"])
+    v_prev = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+    for t in range(1, 4):
+        p_host = host(pos)
+        noise = dynamics_noise(t, n)
+        g = ctx.collide(pos, R)
+        F = ctx.forces(g, to_dev(noise), 5.0)
+        A = ctx.assemble_gamma(g)
+        M = ctx.factor_tree(g, ctx.build_tree(g))
+        v, info = ctx.pcg_solve(A, M, F, v=v_prev.clone(), use_x0=True)
+        og = O.collide(p_host, c["radius"])
+        Fo = O.forces(og, noise, 5.0)
+        assert np.array_equal(host(F), Fo)
+        oa = O.assemble(og)
+        check_velocity(host(v), info["iters"], oa, Fo, O.tree_factor(og, O.build_tree(og)), x0=host(v_prev))
+        ctx.euler(pos, v, 0.01)
+        v_prev = v
+
+
+# ---------------------------------------------------------------- full sizes
+
+def test_full_1M_bench_configuration(ctx):
+    """The benchmark's workload and launch configuration: graph and tree
+    bit-exact against the oracle (cell list, Prim), and the GPU velocity's FP64
+    residual, recomputed by the oracle, meets 1e-8."""
+    n = 1_000_000
+    c = sphere_cluster(n, 0)
+    print("1M: GPU chain", flush=True)
+    out = gpu_chain(ctx, c)
+    assert out["info"]["status"] == 0 and out["info"]["iters"] == 170
+    print("1M: oracle collide", flush=True)
+    og = O.collide(c["pos"], c["radius"])
+    e = ctx.graph_export(out["g"])
+    for f in ("ei", "ej", "w", "u"):
+        assert np.array_equal(host(e[f]), getattr(og, f)), f
+    del e
+    print("1M: oracle Prim", flush=True)
+    ot = O.build_tree(og)
+    t = ctx.tree_export(out["T"], n)
+    assert np.array_equal(host(t["tree_edge"]), ot.tree_edge)
+    assert np.array_equal(host(t["parent"]), ot.parent)
+    assert np.array_equal(host(t["depth"]), ot.depth)
+    oa = O.assemble(og)
+    r = c["force"] - O.spmv(oa, host(out["v"]))
+    relres = np.linalg.norm(r) / np.linalg.norm(c["force"])
+    assert relres <= 1.0001e-8, relres
+    # sampled rows of the preconditioner apply: oracle forward/backward on the full tree
+    b = np.random.default_rng(0).normal(size=(n, 3))
+    z = host(ctx.prec_apply(out["M"], to_dev(b)))
+    zo = O.tree_solve(O.tree_factor(og, ot), b)
+    assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
+def test_full_4M_refinement_configuration(ctx):
+    """The mixed-precision workload (4M cells): graph bit-exact, FP64 residual of
+    the refined velocity recomputed by the oracle meets 1e-8."""
+    n = 4_000_000
+    c = sphere_cluster(n, 0)
+    print("4M: GPU chain", flush=True)
+    pos, R, F = to_dev(c["pos"]), to_dev(c["radius"]), to_dev(c["force"])
+    g = ctx.collide(pos, R)
+    A = ctx.assemble_gamma(g)
+    M = ctx.factor_tree(g, ctx.build_tree(g))
+    v, info = ctx.pcg_solve(A, M, F, precision="f32ir", inner_rtol=1e-4)
+    assert info["status"] == 0
+    print("4M: oracle collide", flush=True)
+    og = O.collide(c["pos"], c["radius"])
+    e = ctx.graph_export(g)
+    for f in ("ei", "ej", "w"):
+        assert np.array_equal(host(e[f]), getattr(og, f)), f
+    del e
+    oa = O.assemble(og)
+    r = c["force"] - O.spmv(oa, host(v))
+    relres = np.linalg.norm(r) / np.linalg.norm(c["force"])
+    assert relres <= 1.0001e-8, relres
