@@ -59,6 +59,7 @@ typedef struct sgp_graph_ *sgp_graph;
 typedef struct sgp_bsr_ *sgp_bsr;
 typedef struct sgp_tree_ *sgp_tree;
 typedef struct sgp_prec_ *sgp_prec;
+typedef struct sgp_mpnn_ *sgp_mpnn;
 
 /* ---------------------------------------------------------------- context */
 
@@ -237,6 +238,40 @@ int sgp_forces(sgp_ctx ctx, sgp_graph g, double k_rep, const double *noise, doub
 
 /* Forward Euler, Step 5: pos += dt v (device [n][3]). */
 int sgp_euler(sgp_ctx ctx, int64_t n, double dt, const double *v, double *pos);
+
+/* ------------------------------- learned warm start (not in the paper) */
+
+/* A message-passing network over the collision graph that maps (F, v_prev)
+ * to a velocity guess for the CG (the CG to the same tolerance still decides;
+ * the caller falls back to v_prev when the guess has the larger residual).
+ * Hidden width 64, three layers:
+ *   x_i = [F_i/sF, v_prev,i/sV]; e_p = [w_ij/sW, (r_i - r_j)/d_ij] for the
+ *   neighbour entry p = (i, j);  h = relu(x W_in + b_in);
+ *   per layer: m_p = relu(h_i W_a + b_m + h_j W_b + e_p W_c),
+ *              a_i = sum over i's entries of m_p,  h = h + relu([h, a] W_u + b_u);
+ *   v_hat = sV (h W_out + b_out).
+ * Parameters: one flat FP32 vector in the order W_in(6x64) b_in(64), then per
+ * layer W_a(64x64) W_b(64x64) W_c(4x64) b_m(64) W_u(128x64) b_u(64), then
+ * W_out(64x3) b_out(3), all row-major.  Products run on BF16 MFMA with FP32
+ * accumulation; the loss is the mean squared error of v_hat/sV against v/sV. */
+int sgp_mpnn_param_count(int64_t *count);
+int sgp_mpnn_create(sgp_ctx ctx, sgp_mpnn *out);
+void sgp_mpnn_free(sgp_mpnn M);
+/* theta: device FP32 [param_count]; copied.  Resets the Adam state.  The
+ * scales must be positive. */
+int sgp_mpnn_set_params(sgp_ctx ctx, sgp_mpnn M, const float *theta, double sF, double sV, double sW);
+int sgp_mpnn_get_params(sgp_ctx ctx, sgp_mpnn M, float *theta);
+/* v_hat [n][3] FP64 (device) from F, v_prev [n][3] FP64 (device) on graph g. */
+int sgp_mpnn_forward(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, const double *F, const double *vprev,
+                     double *vhat);
+/* Loss and its gradient in the parameter layout (device FP32) against the
+ * target v; loss is a host pointer (may be NULL).  Synchronises. */
+int sgp_mpnn_grad(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, const double *F, const double *vprev,
+                  const double *v, float *grad, double *loss);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) at learning rate lr on one
+ * sample; loss as above.  Synchronises. */
+int sgp_mpnn_train_step(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, const double *F, const double *vprev,
+                        const double *v, double lr, double *loss);
 
 /* Launch-shape knobs of this process (chosen by the autotuner):
  *  "spmv_lanes"   lanes per block row of the block-CSR product: 1, 2, 4, 8, 16

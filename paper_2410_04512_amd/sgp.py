@@ -81,6 +81,14 @@ _SIGS = {
     "sgp_phase_times": (C.c_int, [_vp, C.POINTER(_dbl)]),
     "sgp_tune": (C.c_int, [_vp, C.c_char_p, _i32]),
     "sgp_kernel_timing": (C.c_int, [_vp, _i32]),
+    "sgp_mpnn_param_count": (C.c_int, [C.POINTER(_i64)]),
+    "sgp_mpnn_create": (C.c_int, [_vp, C.POINTER(_vp)]),
+    "sgp_mpnn_free": (None, [_vp]),
+    "sgp_mpnn_set_params": (C.c_int, [_vp, _vp, _vp, _dbl, _dbl, _dbl]),
+    "sgp_mpnn_get_params": (C.c_int, [_vp, _vp, _vp]),
+    "sgp_mpnn_forward": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "sgp_mpnn_grad": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_dbl)]),
+    "sgp_mpnn_train_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _dbl, C.POINTER(_dbl)]),
     "sgp_kernel_stats": (C.c_int, [_vp, C.POINTER(_dbl), C.POINTER(_i64)]),
 }
 
@@ -176,6 +184,53 @@ class Prec(_Handle):
         s = C.c_int32()
         lib().sgp_prec_steps(self.h, C.byref(s))
         return s.value
+
+
+class Mpnn(_Handle):
+    """Learned warm start network (parameters live on the device)."""
+    _free = "sgp_mpnn_free"
+
+    def __init__(self, ctx):
+        super().__init__(ctx, "sgp_mpnn_create")
+
+    @staticmethod
+    def param_count():
+        c = C.c_int64()
+        lib().sgp_mpnn_param_count(C.byref(c))
+        return c.value
+
+    def set_params(self, theta, sF, sV, sW):
+        t = torch.as_tensor(theta, dtype=torch.float32).to(self.ctx.dev()).contiguous()
+        if t.numel() != self.param_count():
+            raise SgpError(EINVAL, "wrong parameter count")
+        self.ctx._check(lib().sgp_mpnn_set_params(self.ctx.h, self.h, _ptr(t), sF, sV, sW), "sgp_mpnn_set_params")
+
+    def get_params(self):
+        t = torch.empty(self.param_count(), dtype=torch.float32, device=self.ctx.dev())
+        self.ctx._check(lib().sgp_mpnn_get_params(self.ctx.h, self.h, _ptr(t)), "sgp_mpnn_get_params")
+        return t
+
+    def forward(self, g, F, vprev, out=None):
+        out = torch.empty_like(F) if out is None else out
+        self.ctx._check(lib().sgp_mpnn_forward(self.ctx.h, self.h, g.h, _ptr(F, torch.float64, "F"),
+                                               _ptr(vprev, torch.float64, "vprev"), _ptr(out, torch.float64, "vhat")),
+                        "sgp_mpnn_forward")
+        return out
+
+    def grad(self, g, F, vprev, v):
+        gr = torch.empty(self.param_count(), dtype=torch.float32, device=self.ctx.dev())
+        loss = C.c_double()
+        self.ctx._check(lib().sgp_mpnn_grad(self.ctx.h, self.h, g.h, _ptr(F, torch.float64, "F"),
+                                            _ptr(vprev, torch.float64, "vprev"), _ptr(v, torch.float64, "v"),
+                                            _ptr(gr), C.byref(loss)), "sgp_mpnn_grad")
+        return loss.value, gr
+
+    def train_step(self, g, F, vprev, v, lr):
+        loss = C.c_double()
+        self.ctx._check(lib().sgp_mpnn_train_step(self.ctx.h, self.h, g.h, _ptr(F, torch.float64, "F"),
+                                                  _ptr(vprev, torch.float64, "vprev"), _ptr(v, torch.float64, "v"),
+                                                  lr, C.byref(loss)), "sgp_mpnn_train_step")
+        return loss.value
 
 
 class Context:

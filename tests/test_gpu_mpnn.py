@@ -1,0 +1,90 @@
+"""GPU parity of the learned warm start network (BF16 MFMA, FP32 accumulation)
+against the FP64 oracle evaluated with the same BF16-rounded weights.
+
+Tolerance: the GPU rounds every GEMM input activation to BF16 (8 bits of
+mantissa, relative spacing 2^-8 = 3.9e-3); through three layers the outputs
+and gradients carry a few such roundings, so blocks are compared in relative
+norm at 3e-2 and in direction (cosine >= 0.999)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mpnn as N
+from oracle import oracle as O
+from workloads import sphere_cluster
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2410_04512_amd")
+from tests.gpu_util import host, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = P.Context()
+    yield c
+    c.close()
+
+
+def _sample(n=3000, seed=2):
+    c = sphere_cluster(n, seed)
+    og = O.collide(c["pos"], c["radius"])
+    oa = O.assemble(og)
+    ot = O.build_tree(og)
+    v, _ = O.pcg(oa, c["force"], "tree", O.tree_factor(og, ot))
+    vprev = v + 0.3 * np.random.default_rng(seed).normal(size=v.shape) * v.std()
+    return c, og, vprev, v
+
+
+def _oracle(theta, c, og, vprev, v, scales):
+    ee = N.entry_edges(og.rowptr, og.col, og.ei, og.ej)
+    rows, e = N.edge_features(og.rowptr, og.col, og.ei, og.ej, og.w, og.u, ee, scales[2])
+    return N.loss_grad(theta, c["force"], vprev, v, og.rowptr, og.col, e, rows, scales)
+
+
+def test_forward_and_gradients_match_oracle(ctx):
+    c, og, vprev, v = _sample()
+    scales = (float(c["force"].std()), float(v.std()), 0.1)
+    theta = N.init_params(4) + 0.02 * np.random.default_rng(1).normal(size=N.param_count())
+    theta_b = N.bf16_round(theta)
+    M = P.Mpnn(ctx)
+    M.set_params(theta, *scales)
+    g = ctx.collide(to_dev(c["pos"]), to_dev(c["radius"]))
+    F, Vp, V = to_dev(c["force"]), to_dev(vprev), to_dev(v)
+    vh = host(M.forward(g, F, Vp))
+    L, grad, out = _oracle(theta_b, c, og, vprev, v, scales)
+    vo = out * scales[1]
+    assert np.linalg.norm(vh - vo) <= 3e-2 * np.linalg.norm(vo)
+    lg, gg = M.grad(g, F, Vp, V)
+    gg = host(gg).astype(np.float64)
+    assert abs(lg - L) <= 3e-2 * L
+    pg, po = N.unpack(gg), N.unpack(grad)
+    for name, _ in N.LAYOUT:
+        a, b = pg[name].ravel(), po[name].ravel()
+        nb = np.linalg.norm(b)
+        assert np.linalg.norm(a - b) <= 3e-2 * nb + 1e-12, name
+        if nb > 0:
+            assert a @ b / (np.linalg.norm(a) * nb) >= 0.999, name
+
+
+def test_gradient_is_deterministic(ctx):
+    c, og, vprev, v = _sample(2000, 3)
+    M = P.Mpnn(ctx)
+    M.set_params(N.init_params(2), 1.0, float(v.std()), 0.1)
+    g = ctx.collide(to_dev(c["pos"]), to_dev(c["radius"]))
+    args = (g, to_dev(c["force"]), to_dev(vprev), to_dev(v))
+    l1, g1 = M.grad(*args)
+    l2, g2 = M.grad(*args)
+    assert l1 == l2 and torch.equal(g1, g2)
+
+
+def test_training_lowers_the_loss(ctx):
+    c, og, vprev, v = _sample(4000, 5)
+    M = P.Mpnn(ctx)
+    M.set_params(N.init_params(0), float(c["force"].std()), float(v.std()), 0.1)
+    g = ctx.collide(to_dev(c["pos"]), to_dev(c["radius"]))
+    args = (g, to_dev(c["force"]), to_dev(vprev), to_dev(v))
+    losses = [M.train_step(*args, 1e-3) for _ in range(60)]
+    assert losses[-1] < 0.5 * losses[0], losses[::10]
