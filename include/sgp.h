@@ -229,6 +229,10 @@ int sgp_pcg_solve_batched(sgp_ctx ctx, sgp_bsr A, sgp_prec M, int64_t n_inst,
                           const int64_t *offsets, const double *F, double *v,
                           const sgp_solve_opts *opts, sgp_solve_info *info);
 
+/* ||F - Gamma x|| / ||F|| in FP64 (host output; F, x device [n][3]).
+ * Synchronises.  Used to pick the better of two initial guesses. */
+int sgp_residual_norm(sgp_ctx ctx, sgp_bsr A, const double *F, const double *x, double *relres);
+
 /* ------------------------------------- Section 2, Steps 2 and 5 (dynamics) */
 
 /* F_i = noise_i + sum over contacts j of k_rep w_ij (r_i - r_j) / d_ij: pairwise
@@ -243,8 +247,8 @@ int sgp_euler(sgp_ctx ctx, int64_t n, double dt, const double *v, double *pos);
 
 /* A message-passing network over the collision graph that maps (F, v_prev)
  * to a velocity guess for the CG (the CG to the same tolerance still decides;
- * the caller falls back to v_prev when the guess has the larger residual).
- * Hidden width 64, three layers:
+ * v_prev is the fallback, see sgp_mpnn_warm_start).  Hidden width 64, three
+ * layers:
  *   x_i = [F_i/sF, v_prev,i/sV]; e_p = [w_ij/sW, (r_i - r_j)/d_ij] for the
  *   neighbour entry p = (i, j);  h = relu(x W_in + b_in);
  *   per layer: m_p = relu(h_i W_a + b_m + h_j W_b + e_p W_c),
@@ -253,7 +257,12 @@ int sgp_euler(sgp_ctx ctx, int64_t n, double dt, const double *v, double *pos);
  * Parameters: one flat FP32 vector in the order W_in(6x64) b_in(64), then per
  * layer W_a(64x64) W_b(64x64) W_c(4x64) b_m(64) W_u(128x64) b_u(64), then
  * W_out(64x3) b_out(3), all row-major.  Products run on BF16 MFMA with FP32
- * accumulation; the loss is the mean squared error of v_hat/sV against v/sV. */
+ * accumulation.  Two losses:
+ *   Gamma given (energy):  (v_hat' G v_hat - 2 v_hat' F + v' F) / (v' F), which
+ *       is ||v_hat - v||^2_G / ||v||^2_G when G v = F: the error norm that
+ *       CG's convergence depends on; its gradient needs only G v_hat - F;
+ *   Gamma NULL (MSE):      mean over i, components of (v_hat/sV - v/sV)^2.
+ * Gamma must be the matrix assembled from the same graph g. */
 int sgp_mpnn_param_count(int64_t *count);
 int sgp_mpnn_create(sgp_ctx ctx, sgp_mpnn *out);
 void sgp_mpnn_free(sgp_mpnn M);
@@ -265,19 +274,32 @@ int sgp_mpnn_get_params(sgp_ctx ctx, sgp_mpnn M, float *theta);
 int sgp_mpnn_forward(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, const double *F, const double *vprev,
                      double *vhat);
 /* Loss and its gradient in the parameter layout (device FP32) against the
- * target v; loss is a host pointer (may be NULL).  Synchronises. */
-int sgp_mpnn_grad(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, const double *F, const double *vprev,
+ * solved velocity v; Gamma selects the loss (above, may be NULL); loss is a
+ * host pointer (may be NULL).  Synchronises. */
+int sgp_mpnn_grad(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, const double *F, const double *vprev,
                   const double *v, float *grad, double *loss);
 /* One Adam step (beta 0.9, 0.999, eps 1e-8) at learning rate lr on one
  * sample; loss as above.  Synchronises. */
-int sgp_mpnn_train_step(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, const double *F, const double *vprev,
-                        const double *v, double lr, double *loss);
+int sgp_mpnn_train_step(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, const double *F,
+                        const double *vprev, const double *v, double lr, double *loss);
+/* Initial guess for the CG: x0 = the network's v_hat if its energy
+ * 0.5 x' Gamma x - x' F is lower than that of v_prev, else v_prev (the lower
+ * energy is the smaller Gamma-norm error).  x0 device [n][3], may alias vprev.
+ * used_net, energy_net, energy_prev: host outputs (may be NULL).
+ * Synchronises. */
+int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, const double *F,
+                        const double *vprev, double *x0, int32_t *used_net, double *energy_net,
+                        double *energy_prev);
 
 /* Launch-shape knobs of this process (chosen by the autotuner):
- *  "spmv_lanes"   lanes per block row of the block-CSR product: 1, 2, 4, 8, 16
- *  "check_every"  CG iterations between the host's convergence reads (>= 1)
- * Unknown keys or values give SGP_EINVAL.  Results do not depend on
- * check_every; spmv_lanes changes only the rounding order of each row sum. */
+ *  "check_every"  CG iterations between the host's convergence reads (>= 1);
+ *                 0 iterations of extra work either way: converged solves stop
+ *                 on the device and the host only polls
+ *  "tail_max"     the largest number of tree vertices whose last elimination
+ *                 steps run as one LDS-resident workgroup in the tree sweeps
+ *                 (0..65536, 0 disables; used by factors built afterwards)
+ * Unknown keys or values out of range give SGP_EINVAL.  Results do not
+ * depend on either knob. */
 int sgp_tune(sgp_ctx ctx, const char *key, int32_t value);
 
 /* Per-launch timing of the CG's block-CSR product: when enabled, every

@@ -16,7 +16,13 @@ The network (hidden width 64, three message-passing layers):
      U    = [h, a] W_u + b_u
      h    = h + relu(U)
   out   = h W_out + b_out;   v_hat = sV * out
-  loss  = mean over i and components of (out_i - v_i / sV)^2
+  loss  = mean over i and components of (out_i - v_i / sV)^2        (MSE), or
+  loss  = ||v_hat - v||^2_Gamma / ||v||^2_Gamma                       (energy)
+
+The energy loss is the Gamma-norm error that CG's convergence depends on.
+With Gamma v = F it equals (v_hat' Gamma v_hat - 2 v_hat' F + v' F) / (v' F),
+written in that form so that its gradient is exactly 2 sV (Gamma v_hat - F) /
+(v' F) with respect to `out`: it needs the residual of the guess, not v.
 
 `forward` keeps what the manual `backward` needs; gradients are pinned by
 central finite differences in the tests.
@@ -125,6 +131,15 @@ def loss_and_dout(out, v, sV):
     return L, 2.0 * d / d.size
 
 
+def energy_loss_and_dout(out, v, F, gamma_mv, sV):
+    """Energy loss and its gradient with respect to `out`; gamma_mv(x) = Gamma x."""
+    vh = sV * out
+    q = gamma_mv(vh)
+    c = float(np.sum(v * F))
+    L = (float(np.sum(vh * q)) - 2.0 * float(np.sum(vh * F)) + c) / c
+    return L, 2.0 * sV * (q - F) / c
+
+
 def backward(theta, dout, cache, rowptr, col, e, rows):
     p = unpack(theta)
     g = {name: np.zeros(shape) for name, shape in LAYOUT}
@@ -160,9 +175,13 @@ def backward(theta, dout, cache, rowptr, col, e, rows):
     return pack(g)
 
 
-def loss_grad(theta, F, vprev, v, rowptr, col, e, rows, scales):
+def loss_grad(theta, F, vprev, v, rowptr, col, e, rows, scales, gamma_mv=None):
+    """Loss, gradient and output; the energy loss when gamma_mv is given, else MSE."""
     out, cache = forward(theta, F, vprev, rowptr, col, e, rows, scales)
-    L, dout = loss_and_dout(out, v, scales[1])
+    if gamma_mv is None:
+        L, dout = loss_and_dout(out, v, scales[1])
+    else:
+        L, dout = energy_loss_and_dout(out, v, F, gamma_mv, scales[1])
     return L, backward(theta, dout, cache, rowptr, col, e, rows), out
 
 

@@ -97,7 +97,7 @@ struct sgp_mpnn_ {
     Layout L = make_layout();
     Packed PK = make_packed();
     DevBuf theta, m1, m2, grad, wbf, wrow;   // wrow: BF16-rounded master weights as FP32 (edge arithmetic)
-    DevBuf act, efeat, part;
+    DevBuf act, efeat, part, red, sum, vq;   // vq: v_hat and Gamma v_hat (FP64, canonical order)
     double sF = 1, sV = 1, sW = 1;
     int64_t adam_t = 0;
     int64_t cap_n = 0, cap_e = 0;
@@ -152,124 +152,152 @@ __global__ void k_pack(const float *theta, Layout L, Packed P, unsigned short *w
 // ---------------------------------------------------------------- MFMA GEMM
 //
 // C[M x N] (=|+=) A[M x K] B[K x N] (+ bias): A FP32 row-major (lda), B BF16
-// row-major K x N, K and N multiples of 16 (<= 128).  A workgroup of 4 waves
-// takes 64 rows; wave w takes rows [16w, 16w+16) and every 16-wide column
-// tile.  v_mfma_f32_16x16x16_bf16 lane layout (wave64): lane l holds
+// row-major K x N, K = 16 KT and N multiples of 16 (<= 128).
+// v_mfma_f32_16x16x16_bf16 lane layout (wave64): lane l holds
 //   A[l % 16][4 (l / 16) + t], B[4 (l / 16) + t][l % 16], D[4 (l / 16) + t][l % 16], t = 0..3.
+// B is staged in LDS in fragment order (a lane's four k-values adjacent, one
+// 8-byte read); a wave converts the A fragments of its 16-row tile to BF16
+// once and reuses them for every column tile.  A workgroup (4 waves) covers
+// GEMM_ROWS rows.
+constexpr int GEMM_ROWS = 256;
 
+template <int KT>
 __global__ __launch_bounds__(256) void k_gemm(const float *A, int64_t lda, const unsigned short *B, float *C,
-                                              int64_t ldc, int64_t M, int K, int N, const float *bias,
-                                              int accumulate)
+                                              int64_t ldc, int64_t M, int N, const float *bias, int accumulate)
 {
-    __shared__ unsigned short sB[128 * 128];
-    for (int t = threadIdx.x; t < K * N; t += 256) sB[t] = B[t];
+    __shared__ bf16x4 sB[KT * 8 * 64];
+    const int NT = N >> 4;
+    for (int e = threadIdx.x; e < KT * NT * 64; e += 256) {
+        const int ln = e & 63, tile = e >> 6, kt = tile / NT, nt = tile % NT;
+        bf16x4 b;
+        for (int t = 0; t < 4; t++) b[t] = (short)B[(16 * kt + 4 * (ln >> 4) + t) * N + 16 * nt + (ln & 15)];
+        sB[e] = b;
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t r0 = (int64_t)blockIdx.x * 64 + 16 * wv;
     const int lr = lane & 15, lg = lane >> 4;
-    const int64_t arow = r0 + lr;
-    const bool arow_ok = arow < M;
-    for (int n0 = 0; n0 < N; n0 += 16) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            bf16x4 a, b;
-            for (int t = 0; t < 4; t++) {
-                float av = arow_ok ? A[arow * lda + k0 + 4 * lg + t] : 0.f;
-                a[t] = (short)f2bf(av);
-                b[t] = (short)sB[(k0 + 4 * lg + t) * N + n0 + lr];
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    for (int it = 0; it < GEMM_ROWS / 64; it++) {
+        const int64_t r0 = (int64_t)blockIdx.x * GEMM_ROWS + 64 * it + 16 * wv;
+        if (r0 >= M) break;
+        const int64_t arow = r0 + lr;
+        bf16x4 a[KT];
+#pragma unroll
+        for (int kt = 0; kt < KT; kt++) {
+            float4 v = arow < M ? *(const float4 *)(A + arow * lda + 16 * kt + 4 * lg) : make_float4(0.f, 0.f, 0.f, 0.f);
+            a[kt][0] = (short)f2bf(v.x);
+            a[kt][1] = (short)f2bf(v.y);
+            a[kt][2] = (short)f2bf(v.z);
+            a[kt][3] = (short)f2bf(v.w);
         }
-        for (int t = 0; t < 4; t++) {
-            const int64_t row = r0 + 4 * lg + t;
-            if (row >= M) continue;
-            float v = acc[t];
-            if (bias) v += bias[n0 + lr];
-            float *c = C + row * ldc + n0 + lr;
-            *c = accumulate ? *c + v : v;
+        for (int nt = 0; nt < NT; nt++) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kt = 0; kt < KT; kt++)
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[kt], sB[(kt * NT + nt) * 64 + lane], acc, 0, 0, 0);
+            const float bv = bias ? bias[16 * nt + lr] : 0.f;
+            for (int t = 0; t < 4; t++) {
+                const int64_t row = r0 + 4 * lg + t;
+                if (row >= M) continue;
+                float *c = C + row * ldc + 16 * nt + lr;
+                const float v = acc[t] + bv;
+                *c = accumulate ? *c + v : v;
+            }
         }
     }
 }
 
-// Weight gradient G[K x N] = A^T D over M rows, split into chunks of CH rows:
-// partial p holds the chunk's product (MFMA, reduction dimension = rows);
-// k_sum_parts adds the partials in chunk order.
-constexpr int CH = 2048;
+// Weight-gradient partials over chunks of AT_ROWS rows: part[g] holds the
+// chunk's A^T D (K x N, MFMA with the row index as the reduction dimension)
+// followed by the chunk's column sums of D (N values, FP32).  A 64-row slab is
+// staged in LDS transposed and in BF16, so a lane's four reduction-index
+// values are adjacent; wave w owns the output tiles w, w + 4, ...  Every sum
+// has a fixed order.
+constexpr int AT_ROWS = 512;
 
-__global__ __launch_bounds__(256) void k_gemm_at(const float *A, int64_t lda, const float *D, int64_t ldd, int64_t M,
-                                                 int K, int N, float *part)
+template <int KT>
+__global__ __launch_bounds__(256) void k_gemm_at(const float *A, int64_t lda, const float *D, int64_t ldd, int N,
+                                                 int64_t M, float *part)
 {
-    __shared__ float sA[16][128];
-    __shared__ float sD[16][128];
+    constexpr int K = 16 * KT;
+    __shared__ __attribute__((aligned(16))) unsigned short sAT[K][68];
+    __shared__ __attribute__((aligned(16))) unsigned short sDT[128][68];
+    __shared__ float scs[256];
+    const int NT = N >> 4, tiles = KT * NT;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int lr = lane & 15, lg = lane >> 4;
-    const int64_t m0 = (int64_t)blockIdx.x * CH;
-    const int tiles = (K / 16) * (N / 16);
+    const int64_t m0 = (int64_t)blockIdx.x * AT_ROWS;
+    const int64_t m1 = m0 + AT_ROWS < M ? m0 + AT_ROWS : M;
     f32x4 acc[8];
     for (int q = 0; q < 8; q++) acc[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int64_t rs = m0; rs < m0 + CH && rs < M; rs += 16) {
+    float cs = 0.f;   // column threadIdx.x % N (256 is a multiple of N)
+    for (int64_t rs = m0; rs < m1; rs += 64) {
         __syncthreads();
-        for (int t = threadIdx.x; t < 16 * K; t += 256) {
-            int r = t / K, c = t % K;
-            sA[r][c] = (rs + r < M) ? A[(rs + r) * lda + c] : 0.f;
+        for (int t = threadIdx.x; t < 64 * K; t += 256) {
+            const int r = t / K, c = t % K;
+            sAT[c][r] = f2bf(rs + r < m1 ? A[(rs + r) * lda + c] : 0.f);
         }
-        for (int t = threadIdx.x; t < 16 * N; t += 256) {
-            int r = t / N, c = t % N;
-            sD[r][c] = (rs + r < M) ? D[(rs + r) * ldd + c] : 0.f;
+        for (int t = threadIdx.x; t < 64 * N; t += 256) {
+            const int r = t / N, c = t % N;
+            const float v = rs + r < m1 ? D[(rs + r) * ldd + c] : 0.f;
+            cs += v;
+            sDT[c][r] = f2bf(v);
         }
         __syncthreads();
-        for (int q = 0; q < 8; q++) {
-            int tile = wv + 4 * q;
-            if (tile >= tiles) break;
-            int kt = tile / (N / 16), nt = tile % (N / 16);
-            bf16x4 a, b;
-            for (int t = 0; t < 4; t++) {
-                a[t] = (short)f2bf(sA[4 * lg + t][16 * kt + lr]);   // (A^T)[row][k] = A[k][row]
-                b[t] = (short)f2bf(sD[4 * lg + t][16 * nt + lr]);
+        for (int sub = 0; sub < 4; sub++) {
+            for (int q = 0; q < 8; q++) {
+                const int tile = wv + 4 * q;
+                if (tile >= tiles) break;
+                const int kt = tile / NT, nt = tile % NT;
+                const bf16x4 a = *(const bf16x4 *)&sAT[16 * kt + lr][16 * sub + 4 * lg];
+                const bf16x4 b = *(const bf16x4 *)&sDT[16 * nt + lr][16 * sub + 4 * lg];
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[q], 0, 0, 0);
             }
-            acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[q], 0, 0, 0);
         }
     }
-    float *P = part + (int64_t)blockIdx.x * K * N;
+    float *P = part + (int64_t)blockIdx.x * (K * N + N);
     for (int q = 0; q < 8; q++) {
-        int tile = wv + 4 * q;
+        const int tile = wv + 4 * q;
         if (tile >= tiles) break;
-        int kt = tile / (N / 16), nt = tile % (N / 16);
+        const int kt = tile / NT, nt = tile % NT;
         for (int t = 0; t < 4; t++) P[(16 * kt + 4 * lg + t) * N + 16 * nt + lr] = acc[q][t];
     }
+    scs[threadIdx.x] = cs;
+    __syncthreads();
+    if (threadIdx.x < N) {
+        float s = 0.f;
+        for (int k = threadIdx.x; k < 256; k += N) s += scs[k];
+        P[K * N + threadIdx.x] = s;
+    }
 }
 
-// out[r][c] (in the flat gradient, with row stride ld and column window
-// [c0, c1)) = sum over chunks of part[chunk][r][c]
-__global__ void k_sum_parts(const float *part, int nparts, int K, int N, int r1, int c0, int c1, float *out,
-                            int64_t ld)
+// Fixed-order reduction of G partial vectors of length L: stage 1 sums a
+// contiguous run of `per` partials per segment, stage 2 the segments in order.
+__global__ void k_red1(const float *part, int G, int L, int per, float *tmp)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= L) return;
+    const int p0 = blockIdx.y * per, p1 = p0 + per < G ? p0 + per : G;
+    float acc = 0.f;
+    for (int p = p0; p < p1; p++) acc += part[(int64_t)p * L + c];
+    tmp[(int64_t)blockIdx.y * L + c] = acc;
+}
+
+__global__ void k_red2(const float *tmp, int S, int L, float *out)
+{
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= L) return;
+    float acc = 0.f;
+    for (int s = 0; s < S; s++) acc += tmp[(int64_t)s * L + c];
+    out[c] = acc;
+}
+
+// out[r * ld + (c - c0)] = red[off + r * N + c] for r < r1, c0 <= c < c1
+__global__ void k_window(const float *red, int off, int N, int r1, int c0, int c1, float *out, int64_t ld)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= r1 * (c1 - c0)) return;
-    int r = t / (c1 - c0), c = c0 + t % (c1 - c0);
-    float s = 0.f;
-    for (int p = 0; p < nparts; p++) s += part[(int64_t)p * K * N + r * N + c];
-    out[(int64_t)r * ld + (c - c0)] = s;
-}
-
-// column sums of A[M x N] (first nc columns) in chunks of CH rows, then in chunk order
-__global__ void k_colsum_part(const float *A, int64_t lda, int64_t M, int nc, float *part)
-{
-    int c = threadIdx.x;
-    if (c >= nc) return;
-    int64_t m0 = (int64_t)blockIdx.x * CH;
-    float s = 0.f;
-    for (int64_t r = m0; r < m0 + CH && r < M; r++) s += A[r * lda + c];
-    part[(int64_t)blockIdx.x * nc + c] = s;
-}
-
-__global__ void k_colsum_final(const float *part, int nparts, int nc, float *out)
-{
-    int c = threadIdx.x;
-    if (c >= nc) return;
-    float s = 0.f;
-    for (int p = 0; p < nparts; p++) s += part[(int64_t)p * nc + c];
-    out[c] = s;
+    const int r = t / (c1 - c0), c = c0 + t % (c1 - c0);
+    out[(int64_t)r * ld + (c - c0)] = red[off + r * N + c];
 }
 
 // ---------------------------------------------------------------- elementwise
@@ -350,7 +378,11 @@ __global__ __launch_bounds__(256) void k_msg_fwd(int64_t n, const int32_t *rowpt
     agg[i * 64 + f] = acc;
 }
 
-// dP_i = sum over row i of dz_p, dz_p = da_i [z_p > 0]; per-workgroup partials of e_p^T dz_p
+// dP_i = sum over row i of dz_p, dz_p = da_i [z_p > 0]; per-workgroup partials
+// of e_p^T dz_p (4 x 64).  The grid is fixed (at most MSG_BWD_GRID workgroups);
+// workgroup b walks the 4-row blocks b, b + grid, ... in order.
+constexpr int MSG_BWD_GRID = 1024;
+
 __global__ __launch_bounds__(256) void k_msg_bwd_p(int64_t n, const int32_t *rowptr, const int32_t *col,
                                                    const float4 *ef, const float *PQ, const float *bm,
                                                    const float *Wc, const float *da, int64_t ldda, float *dPQ,
@@ -358,11 +390,13 @@ __global__ __launch_bounds__(256) void k_msg_bwd_p(int64_t n, const int32_t *row
 {
     __shared__ float sw[4][256];
     const int wv = threadIdx.x >> 6, f = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+    const float w0 = Wc[f], w1 = Wc[64 + f], w2 = Wc[128 + f], w3 = Wc[192 + f];
+    const float bmf = bm[f];
     float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
-    if (i < n) {
-        const float Pi = PQ[i * 128 + f] + bm[f];
-        const float w0 = Wc[f], w1 = Wc[64 + f], w2 = Wc[128 + f], w3 = Wc[192 + f];
+    for (int64_t blk = blockIdx.x; blk * 4 < n; blk += gridDim.x) {
+        const int64_t i = blk * 4 + wv;
+        if (i >= n) continue;
+        const float Pi = PQ[i * 128 + f] + bmf;
         const float dai = da[i * ldda + f];
         float dp = 0.f;
         for (int32_t p = rowptr[i]; p < rowptr[i + 1]; p++) {
@@ -428,6 +462,59 @@ __global__ __launch_bounds__(256) void k_loss(int64_t n, const float *out16, con
     }
     s = block_sum_256(s, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// energy loss sums per block: (v_hat . Gamma v_hat, v_hat . F, v . F); v == nullptr
+// leaves the third at zero (the warm-start energies need only the first two)
+__global__ __launch_bounds__(256) void k_energy_parts(int64_t len, const double *vh, const double *q, const double *F,
+                                                      const double *v, double *part)
+{
+    __shared__ double sh[256];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) {
+        a += vh[t] * q[t];
+        b += vh[t] * F[t];
+        if (v) c += v[t] * F[t];
+    }
+    a = block_sum_256(a, sh);
+    b = block_sum_256(b, sh);
+    c = block_sum_256(c, sh);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = a;
+        part[3 * blockIdx.x + 1] = b;
+        part[3 * blockIdx.x + 2] = c;
+    }
+}
+
+// s[k] = sum over blocks of part[3 b + k], in block order
+__global__ void k_sum3(const double *part, int np, double *s)
+{
+    __shared__ double sh[256];
+    for (int k = 0; k < 3; k++) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < np; b += 256) a += part[3 * b + k];
+        a = block_sum_256(a, sh);
+        if (threadIdx.x == 0) s[k] = a;
+    }
+}
+
+// d loss / d out = 2 sV (Gamma v_hat - F) / (v . F) in columns 0..2
+__global__ void k_energy_dout(int64_t n, const double *q, const double *F, double sV, const double *s, float *dout16)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double scale = 2.0 * sV / s[2];
+    for (int a = 0; a < 16; a++)
+        dout16[16 * i + a] = a < 3 ? (float)(scale * (q[3 * i + a] - F[3 * i + a])) : 0.f;
+}
+
+// x0 = the guess with the lower energy 0.5 x' Gamma x - x' F (ties keep v_prev)
+__global__ void k_pick(int64_t len, const double *s_net, const double *s_prev, const double *guess, double *x0)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= len) return;
+    const double en = 0.5 * s_net[0] - s_net[1], ep = 0.5 * s_prev[0] - s_prev[1];
+    if (en < ep) x0[t] = guess[t];
 }
 
 __global__ void k_sum_double(const double *part, int np, double *out)
@@ -503,33 +590,57 @@ int gemm(sgp_ctx ctx, const float *A, int64_t lda, const unsigned short *B, floa
          int N, const float *bias, int acc)
 {
     if (M <= 0) return SGP_OK;
-    k_gemm<<<grid_for(M, 64), 256, 0, ctx->stream>>>(A, lda, B, C, ldc, M, K, N, bias, acc);
+    const int64_t nb = grid_for(M, GEMM_ROWS);
+    hipStream_t st = ctx->stream;
+    switch (K) {
+    case 16: k_gemm<1><<<nb, 256, 0, st>>>(A, lda, B, C, ldc, M, N, bias, acc); break;
+    case 64: k_gemm<4><<<nb, 256, 0, st>>>(A, lda, B, C, ldc, M, N, bias, acc); break;
+    case 128: k_gemm<8><<<nb, 256, 0, st>>>(A, lda, B, C, ldc, M, N, bias, acc); break;
+    default: return set_err(ctx, SGP_EINVAL, "mpnn gemm: unsupported K");
+    }
     LAUNCH_CHECK(ctx);
     return SGP_OK;
 }
 
-// out (flat gradient at off, row stride ld) = A^T D restricted to rows [0, r1), columns [c0, c1)
-int gemm_at(sgp_ctx ctx, sgp_mpnn M, const float *A, int64_t lda, const float *D, int64_t ldd, int64_t m, int K, int N,
-            int r1, int c0, int c1, float *out, int64_t ld)
+// out[0, L) = fixed-order sum of the G partial vectors part[g][0, L)
+int reduce_parts(sgp_ctx ctx, sgp_mpnn M, const float *part, int G, int L, float *out)
 {
-    int nparts = (int)((m + CH - 1) / CH);
-    if (nparts == 0) nparts = 1;
-    float *part;
-    SGP_TRY(ensure_t(ctx, M->part, (size_t)nparts * K * N + 64, &part));
-    k_gemm_at<<<nparts, 256, 0, ctx->stream>>>(A, lda, D, ldd, m, K, N, part);
-    k_sum_parts<<<grid_for(r1 * (c1 - c0), 256), 256, 0, ctx->stream>>>(part, nparts, K, N, r1, c0, c1, out, ld);
+    const int S = G < 32 ? G : 32;
+    const int per = (G + S - 1) / S;
+    const int segs = (G + per - 1) / per;
+    float *tmp;
+    SGP_TRY(ensure_t(ctx, M->red, (size_t)segs * L + 64, &tmp));
+    k_red1<<<dim3((unsigned)grid_for(L, 256), (unsigned)segs), 256, 0, ctx->stream>>>(part, G, L, per, tmp);
+    k_red2<<<grid_for(L, 256), 256, 0, ctx->stream>>>(tmp, segs, L, out);
     LAUNCH_CHECK(ctx);
     return SGP_OK;
 }
 
-int colsum(sgp_ctx ctx, sgp_mpnn M, const float *A, int64_t lda, int64_t m, int nc, float *out)
+// A^T D (K x N) followed by the column sums of D (N), summed over all m rows,
+// into M->sum; the caller copies windows of it into the gradient.
+int gemm_at(sgp_ctx ctx, sgp_mpnn M, const float *A, int64_t lda, int K, const float *D, int64_t ldd, int N,
+            int64_t m, float **sum)
 {
-    int nparts = (int)((m + CH - 1) / CH);
-    if (nparts == 0) nparts = 1;
-    float *part;
-    SGP_TRY(ensure_t(ctx, M->part, (size_t)nparts * nc + 64, &part));
-    k_colsum_part<<<nparts, 128, 0, ctx->stream>>>(A, lda, m, nc, part);
-    k_colsum_final<<<1, 128, 0, ctx->stream>>>(part, nparts, nc, out);
+    const int G = m > 0 ? (int)((m + AT_ROWS - 1) / AT_ROWS) : 1;
+    const int L = K * N + N;
+    float *part, *out;
+    SGP_TRY(ensure_t(ctx, M->part, (size_t)G * L + 64, &part));
+    SGP_TRY(ensure_t(ctx, M->sum, (size_t)L + 64, &out));
+    hipStream_t st = ctx->stream;
+    switch (K) {
+    case 16: k_gemm_at<1><<<G, 256, 0, st>>>(A, lda, D, ldd, N, m, part); break;
+    case 64: k_gemm_at<4><<<G, 256, 0, st>>>(A, lda, D, ldd, N, m, part); break;
+    default: return set_err(ctx, SGP_EINVAL, "mpnn gemm_at: unsupported K");
+    }
+    LAUNCH_CHECK(ctx);
+    SGP_TRY(reduce_parts(ctx, M, part, G, L, out));
+    *sum = out;
+    return SGP_OK;
+}
+
+int window(sgp_ctx ctx, const float *red, int off, int N, int r1, int c0, int c1, float *out, int64_t ld)
+{
+    k_window<<<grid_for((int64_t)r1 * (c1 - c0), 256), 256, 0, ctx->stream>>>(red, off, N, r1, c0, c1, out, ld);
     LAUNCH_CHECK(ctx);
     return SGP_OK;
 }
@@ -588,30 +699,36 @@ int backward(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, Act &A)
     float *G = (float *)M->grad.p;
     const int32_t *rowptr = (const int32_t *)g->rowptr.p, *col = (const int32_t *)g->col.p;
     const float4 *ef = (const float4 *)M->efeat.p;
-    // output layer
-    SGP_TRY(gemm_at(ctx, M, A.h[NL], 64, A.dout16, 16, n, 64, 16, 64, 0, 3, G + L.W_out, 3));
-    SGP_TRY(colsum(ctx, M, A.dout16, 16, n, 3, G + L.b_out));
+    float *S;
+    // output layer: W_out rows 0..63 x columns 0..2 of h^T dout, b_out = column sums
+    SGP_TRY(gemm_at(ctx, M, A.h[NL], 64, 64, A.dout16, 16, 16, n, &S));
+    SGP_TRY(window(ctx, S, 0, 16, 64, 0, 3, G + L.W_out, 3));
+    SGP_TRY(window(ctx, S, 64 * 16, 16, 1, 0, 3, G + L.b_out, 3));
     SGP_TRY(gemm(ctx, A.dout16, 16, W + PK.out16T, A.dh, 64, n, 16, 64, nullptr, 0));
     for (int l = NL - 1; l >= 0; l--) {
         k_mask<<<grid_for(64 * n, 256), 256, 0, st>>>(64 * n, A.dh, A.U[l], A.dU);
-        SGP_TRY(gemm_at(ctx, M, A.h[l], 64, A.dU, 64, n, 64, 64, 64, 0, 64, G + L.W_u[l], 64));
-        SGP_TRY(gemm_at(ctx, M, A.a[l], 64, A.dU, 64, n, 64, 64, 64, 0, 64, G + L.W_u[l] + 64 * 64, 64));
-        SGP_TRY(colsum(ctx, M, A.dU, 64, n, 64, G + L.b_u[l]));
+        SGP_TRY(gemm_at(ctx, M, A.h[l], 64, 64, A.dU, 64, 64, n, &S));
+        SGP_TRY(window(ctx, S, 0, 64, 64, 0, 64, G + L.W_u[l], 64));
+        SGP_TRY(window(ctx, S, 64 * 64, 64, 1, 0, 64, G + L.b_u[l], 64));
+        SGP_TRY(gemm_at(ctx, M, A.a[l], 64, 64, A.dU, 64, 64, n, &S));
+        SGP_TRY(window(ctx, S, 0, 64, 64, 0, 64, G + L.W_u[l] + 64 * 64, 64));
         SGP_TRY(gemm(ctx, A.dU, 64, W + PK.uT[l], A.dcat, 128, n, 64, 128, nullptr, 0));   // [dh part | da]
         // messages: recompute PQ of this layer from h[l]
         SGP_TRY(gemm(ctx, A.h[l], 64, W + PK.ab[l], A.PQ, 128, n, 64, 128, nullptr, 0));
-        int nb = (int)grid_for(n, 4);
+        const int nb = (int)std::min<int64_t>(grid_for(n, 4), MSG_BWD_GRID);
         float *wcp;
         SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP9], (size_t)nb * 256 + 64, &wcp));
         k_msg_bwd_p<<<nb, 256, 0, st>>>(n, rowptr, col, ef, A.PQ, wr + L.b_m[l], wr + L.W_c[l], A.dcat + 64, 128,
                                         A.dPQ, wcp);
-        k_msg_bwd_q<<<nb, 256, 0, st>>>(n, rowptr, col, ef, A.PQ, wr + L.b_m[l], wr + L.W_c[l], A.dcat + 64, 128,
-                                        A.dPQ);
-        k_colsum_final<<<1, 256, 0, st>>>(wcp, nb, 256, G + L.W_c[l]);   // partials in block order
+        k_msg_bwd_q<<<grid_for(n, 4), 256, 0, st>>>(n, rowptr, col, ef, A.PQ, wr + L.b_m[l], wr + L.W_c[l],
+                                                    A.dcat + 64, 128, A.dPQ);
         LAUNCH_CHECK(ctx);
-        SGP_TRY(colsum(ctx, M, A.dPQ, 128, n, 64, G + L.b_m[l]));
-        SGP_TRY(gemm_at(ctx, M, A.h[l], 64, A.dPQ, 128, n, 64, 128, 64, 0, 64, G + L.W_a[l], 64));
-        SGP_TRY(gemm_at(ctx, M, A.h[l], 64, A.dPQ, 128, n, 64, 128, 64, 64, 128, G + L.W_b[l], 64));
+        SGP_TRY(reduce_parts(ctx, M, wcp, nb, 256, G + L.W_c[l]));   // W_c is 4 x 64 row-major
+        // W_a, W_b = h^T dP, h^T dQ; b_m = column sums of dP
+        SGP_TRY(gemm_at(ctx, M, A.h[l], 64, 64, A.dPQ, 128, 128, n, &S));
+        SGP_TRY(window(ctx, S, 0, 128, 64, 0, 64, G + L.W_a[l], 64));
+        SGP_TRY(window(ctx, S, 0, 128, 64, 64, 128, G + L.W_b[l], 64));
+        SGP_TRY(window(ctx, S, 64 * 128, 128, 1, 0, 64, G + L.b_m[l], 64));
         // dh_l = dh (residual) + dcat[:, :64] + dPQ W_ab^T
         k_add64<<<grid_for(64 * n, 256), 256, 0, st>>>(n, A.dh, 64, A.dcat, 128, A.tmp, 64);
         LAUNCH_CHECK(ctx);
@@ -619,8 +736,9 @@ int backward(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, Act &A)
         std::swap(A.dh, A.tmp);
     }
     k_mask<<<grid_for(64 * n, 256), 256, 0, st>>>(64 * n, A.dh, A.pre0, A.dU);
-    SGP_TRY(gemm_at(ctx, M, A.x16, 16, A.dU, 64, n, 16, 64, 6, 0, 64, G + L.W_in, 64));
-    SGP_TRY(colsum(ctx, M, A.dU, 64, n, 64, G + L.b_in));
+    SGP_TRY(gemm_at(ctx, M, A.x16, 16, 16, A.dU, 64, 64, n, &S));
+    SGP_TRY(window(ctx, S, 0, 64, 6, 0, 64, G + L.W_in, 64));
+    SGP_TRY(window(ctx, S, 16 * 64, 64, 1, 0, 64, G + L.b_in, 64));
     return SGP_OK;
 }
 
@@ -711,42 +829,82 @@ extern "C" int sgp_mpnn_forward(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, const doub
     return SGP_OK;
 }
 
-static int loss_grad(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, const double *F, const double *vprev, const double *v,
-                     double *loss)
+// sums (x . Gamma x, x . F, v . F) of a canonical-order x into s[0..2]; q
+// receives Gamma x.  Uses the library's product (workspaces of sgp_spmv).
+static int energy_sums(sgp_ctx ctx, sgp_mpnn M, sgp_bsr A, const double *x, double *q, const double *F,
+                       const double *v, double *s)
+{
+    const int64_t n = A->n;
+    SGP_TRY(sgp_spmv(ctx, A, x, q));
+    const int nb = (int)std::min<int64_t>(grid_for(3 * n, 256), 1024);
+    double *part;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_PART], (size_t)3 * nb + 8, &part));
+    k_energy_parts<<<nb, 256, 0, ctx->stream>>>(3 * n, x, q, F, v, part);
+    k_sum3<<<1, 256, 0, ctx->stream>>>(part, nb, s);
+    LAUNCH_CHECK(ctx);
+    return SGP_OK;
+}
+
+static int loss_grad(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gm, const double *F, const double *vprev,
+                     const double *v, double *loss)
 {
     Act A;
     const int64_t n = g->n;
     SGP_TRY(prepare(ctx, M, g, F, vprev, A));
     SGP_TRY(forward(ctx, M, g, A));
-    double *part;
-    int nb = (int)grid_for(n, 256);
-    SGP_TRY(ensure_t(ctx, ctx->ws[WS_PART], (size_t)nb + 8, &part));
-    k_loss<<<nb, 256, 0, ctx->stream>>>(n, A.out16, v, (float)M->sV, A.dout16, part);
-    k_sum_double<<<1, 256, 0, ctx->stream>>>(part, nb, part + nb);
+    double s[3];
+    if (!Gm) {
+        double *part;
+        const int nb = (int)grid_for(n, 256);
+        SGP_TRY(ensure_t(ctx, ctx->ws[WS_PART], (size_t)nb + 8, &part));
+        k_loss<<<nb, 256, 0, ctx->stream>>>(n, A.out16, v, (float)M->sV, A.dout16, part);
+        k_sum_double<<<1, 256, 0, ctx->stream>>>(part, nb, part + nb);
+        LAUNCH_CHECK(ctx);
+        SGP_TRY(backward(ctx, M, g, A));
+        SGP_TRY(readback(ctx, s, part + nb, sizeof(double)));
+        if (loss) *loss = s[0] / (3.0 * (double)n);
+        return SGP_OK;
+    }
+    // energy loss (v_hat' G v_hat - 2 v_hat' F + v' F) / (v' F)
+    double *vh, *ds;
+    SGP_TRY(ensure_t(ctx, M->vq, (size_t)6 * n + 8, &vh));
+    double *q = vh + 3 * n, *sd = vh + 6 * n;
+    ds = sd;
+    k_output<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, A.out16, M->sV, vh);
+    LAUNCH_CHECK(ctx);
+    SGP_TRY(energy_sums(ctx, M, Gm, vh, q, F, v, ds));
+    k_energy_dout<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, q, F, M->sV, ds, A.dout16);
     LAUNCH_CHECK(ctx);
     SGP_TRY(backward(ctx, M, g, A));
-    double s;
-    SGP_TRY(readback(ctx, &s, part + nb, sizeof s));
-    if (loss) *loss = s / (3.0 * (double)n);
+    SGP_TRY(readback(ctx, s, ds, sizeof s));
+    if (loss) *loss = (s[0] - 2.0 * s[1] + s[2]) / s[2];
     return SGP_OK;
 }
 
-extern "C" int sgp_mpnn_grad(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, const double *F, const double *vprev,
+static int check_gamma(sgp_ctx ctx, sgp_graph g, sgp_bsr Gm)
+{
+    if (Gm && Gm->n != g->n) return set_err(ctx, SGP_EINVAL, "mpnn: Gamma and graph sizes differ");
+    return SGP_OK;
+}
+
+extern "C" int sgp_mpnn_grad(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gm, const double *F, const double *vprev,
                              const double *v, float *grad, double *loss)
 {
     SGP_TRY(check_common(ctx, M, g, F, vprev));
     if (!v || !grad || g->n == 0) return set_err(ctx, SGP_EINVAL, "mpnn_grad: bad arguments");
-    SGP_TRY(loss_grad(ctx, M, g, F, vprev, v, loss));
+    SGP_TRY(check_gamma(ctx, g, Gm));
+    SGP_TRY(loss_grad(ctx, M, g, Gm, F, vprev, v, loss));
     HIP_TRY(ctx, hipMemcpyAsync(grad, M->grad.p, M->L.total * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream));
     return SGP_OK;
 }
 
-extern "C" int sgp_mpnn_train_step(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, const double *F, const double *vprev,
-                                   const double *v, double lr, double *loss)
+extern "C" int sgp_mpnn_train_step(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gm, const double *F,
+                                   const double *vprev, const double *v, double lr, double *loss)
 {
     SGP_TRY(check_common(ctx, M, g, F, vprev));
     if (!v || g->n == 0 || !(lr > 0)) return set_err(ctx, SGP_EINVAL, "mpnn_train_step: bad arguments");
-    SGP_TRY(loss_grad(ctx, M, g, F, vprev, v, loss));
+    SGP_TRY(check_gamma(ctx, g, Gm));
+    SGP_TRY(loss_grad(ctx, M, g, Gm, F, vprev, v, loss));
     M->adam_t++;
     const float b1 = 0.9f, b2 = 0.999f;
     float c1 = 1.f - powf(b1, (float)M->adam_t), c2 = 1.f - powf(b2, (float)M->adam_t);
@@ -755,4 +913,41 @@ extern "C" int sgp_mpnn_train_step(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, const d
                                                               1e-8f, c1, c2);
     LAUNCH_CHECK(ctx);
     return repack(ctx, M);
+}
+
+extern "C" int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gm, const double *F,
+                                   const double *vprev, double *x0, int32_t *used_net, double *energy_net,
+                                   double *energy_prev)
+{
+    SGP_TRY(check_common(ctx, M, g, F, vprev));
+    if (!Gm || (g->n > 0 && !x0)) return set_err(ctx, SGP_EINVAL, "mpnn_warm_start: bad arguments");
+    SGP_TRY(check_gamma(ctx, g, Gm));
+    const int64_t n = g->n;
+    if (n == 0) {
+        if (used_net) *used_net = 0;
+        if (energy_net) *energy_net = 0.0;
+        if (energy_prev) *energy_prev = 0.0;
+        return SGP_OK;
+    }
+    Act A;
+    SGP_TRY(prepare(ctx, M, g, F, vprev, A));
+    SGP_TRY(forward(ctx, M, g, A));
+    double *vh;
+    SGP_TRY(ensure_t(ctx, M->vq, (size_t)6 * n + 8, &vh));
+    double *q = vh + 3 * n, *s = vh + 6 * n;   // s: 3 sums of the guess, 3 of v_prev (8 doubles reserved)
+    k_output<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, A.out16, M->sV, vh);
+    LAUNCH_CHECK(ctx);
+    SGP_TRY(energy_sums(ctx, M, Gm, vh, q, F, nullptr, s));
+    SGP_TRY(energy_sums(ctx, M, Gm, vprev, q, F, nullptr, s + 3));
+    if (x0 != vprev)
+        HIP_TRY(ctx, hipMemcpyAsync(x0, vprev, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    k_pick<<<grid_for(3 * n, 256), 256, 0, ctx->stream>>>(3 * n, s, s + 3, vh, x0);
+    LAUNCH_CHECK(ctx);
+    double hs[6];
+    SGP_TRY(readback(ctx, hs, s, sizeof hs));
+    const double en = 0.5 * hs[0] - hs[1], ep = 0.5 * hs[3] - hs[4];
+    if (used_net) *used_net = en < ep ? 1 : 0;
+    if (energy_net) *energy_net = en;
+    if (energy_prev) *energy_prev = ep;
+    return SGP_OK;
 }

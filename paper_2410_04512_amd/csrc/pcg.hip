@@ -715,6 +715,38 @@ extern "C" int sgp_pcg_solve_batched(sgp_ctx ctx, sgp_bsr A, sgp_prec M, int64_t
     return solve_common(ctx, A, M, off, F, v, opts, info);
 }
 
+extern "C" int sgp_residual_norm(sgp_ctx ctx, sgp_bsr A, const double *F, const double *x, double *relres)
+{
+    if (!ctx || !A || !relres || (A->n > 0 && (!F || !x))) return set_err(ctx, SGP_EINVAL, "residual_norm: bad arguments");
+    const int64_t n = A->n;
+    if (n == 0) {
+        *relres = 0.0;
+        return SGP_OK;
+    }
+    std::vector<int64_t> off = {0, n};
+    PcgWork w;
+    SGP_TRY(prepare_work(ctx, A, off, w));
+    double *Fi, *xi, *q, *part;
+    PcgScalars *S;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP8], 9 * n + 9, &Fi));
+    xi = Fi + 3 * n + 3;
+    q = xi + 3 * n + 3;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_PART], 3 * (size_t)std::max(w.vec_nb, w.mv_nb) + 8, &part));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_SCAL], 2, &S));
+    const int32_t *perm = (const int32_t *)A->perm.p;
+    SGP_TRY(permute_rows(ctx, perm, F, Fi, n, 0));
+    SGP_TRY(permute_rows(ctx, perm, x, xi, n, 0));
+    SGP_TRY(spmv_f64(ctx, A, xi, q, nullptr, nullptr, 0));
+    k_res64<<<grid_for(3 * n, 256), 256, 0, ctx->stream>>>(3 * n, Fi, q, q);
+    k_norm2_pair<<<w.vec_nb, 256, 0, ctx->stream>>>(q, Fi, w.vec, part);
+    LAUNCH_CHECK(ctx);
+    SGP_TRY(fin(ctx, FIN_NORM2, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, 1));
+    PcgScalars hs;
+    SGP_TRY(readback(ctx, &hs, S, sizeof hs));
+    *relres = hs.nF2 > 0 ? sqrt(hs.rz / hs.nF2) : 0.0;
+    return SGP_OK;
+}
+
 extern "C" int sgp_tune(sgp_ctx ctx, const char *key, int32_t value)
 {
     if (!key) return set_err(ctx, SGP_EINVAL, "tune: null key");

@@ -81,14 +81,17 @@ _SIGS = {
     "sgp_phase_times": (C.c_int, [_vp, C.POINTER(_dbl)]),
     "sgp_tune": (C.c_int, [_vp, C.c_char_p, _i32]),
     "sgp_kernel_timing": (C.c_int, [_vp, _i32]),
+    "sgp_residual_norm": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(_dbl)]),
     "sgp_mpnn_param_count": (C.c_int, [C.POINTER(_i64)]),
     "sgp_mpnn_create": (C.c_int, [_vp, C.POINTER(_vp)]),
     "sgp_mpnn_free": (None, [_vp]),
     "sgp_mpnn_set_params": (C.c_int, [_vp, _vp, _vp, _dbl, _dbl, _dbl]),
     "sgp_mpnn_get_params": (C.c_int, [_vp, _vp, _vp]),
     "sgp_mpnn_forward": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
-    "sgp_mpnn_grad": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_dbl)]),
-    "sgp_mpnn_train_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _dbl, C.POINTER(_dbl)]),
+    "sgp_mpnn_grad": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_dbl)]),
+    "sgp_mpnn_train_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, C.POINTER(_dbl)]),
+    "sgp_mpnn_warm_start": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i32), C.POINTER(_dbl),
+                                      C.POINTER(_dbl)]),
     "sgp_kernel_stats": (C.c_int, [_vp, C.POINTER(_dbl), C.POINTER(_i64)]),
 }
 
@@ -217,20 +220,33 @@ class Mpnn(_Handle):
                         "sgp_mpnn_forward")
         return out
 
-    def grad(self, g, F, vprev, v):
+    def grad(self, g, F, vprev, v, A: "Bsr | None" = None):
+        """Loss and gradient; energy loss when Gamma (A) is given, else MSE."""
         gr = torch.empty(self.param_count(), dtype=torch.float32, device=self.ctx.dev())
         loss = C.c_double()
-        self.ctx._check(lib().sgp_mpnn_grad(self.ctx.h, self.h, g.h, _ptr(F, torch.float64, "F"),
-                                            _ptr(vprev, torch.float64, "vprev"), _ptr(v, torch.float64, "v"),
-                                            _ptr(gr), C.byref(loss)), "sgp_mpnn_grad")
+        self.ctx._check(lib().sgp_mpnn_grad(self.ctx.h, self.h, g.h, A.h if A is not None else None,
+                                            _ptr(F, torch.float64, "F"), _ptr(vprev, torch.float64, "vprev"),
+                                            _ptr(v, torch.float64, "v"), _ptr(gr), C.byref(loss)), "sgp_mpnn_grad")
         return loss.value, gr
 
-    def train_step(self, g, F, vprev, v, lr):
+    def train_step(self, g, F, vprev, v, lr, A: "Bsr | None" = None):
         loss = C.c_double()
-        self.ctx._check(lib().sgp_mpnn_train_step(self.ctx.h, self.h, g.h, _ptr(F, torch.float64, "F"),
-                                                  _ptr(vprev, torch.float64, "vprev"), _ptr(v, torch.float64, "v"),
-                                                  lr, C.byref(loss)), "sgp_mpnn_train_step")
+        self.ctx._check(lib().sgp_mpnn_train_step(self.ctx.h, self.h, g.h, A.h if A is not None else None,
+                                                  _ptr(F, torch.float64, "F"), _ptr(vprev, torch.float64, "vprev"),
+                                                  _ptr(v, torch.float64, "v"), lr, C.byref(loss)),
+                        "sgp_mpnn_train_step")
         return loss.value
+
+    def warm_start(self, g, A, F, vprev, x0=None):
+        """Initial guess: the network's v_hat or v_prev, whichever has the lower
+        energy under Gamma.  Returns (x0, {"used_net", "energy_net", "energy_prev"})."""
+        x0 = torch.empty_like(vprev) if x0 is None else x0
+        used = C.c_int32()
+        en, ep = C.c_double(), C.c_double()
+        self.ctx._check(lib().sgp_mpnn_warm_start(self.ctx.h, self.h, g.h, A.h, _ptr(F, torch.float64, "F"),
+                                                  _ptr(vprev, torch.float64, "vprev"), _ptr(x0, torch.float64, "x0"),
+                                                  C.byref(used), C.byref(en), C.byref(ep)), "sgp_mpnn_warm_start")
+        return x0, {"used_net": bool(used.value), "energy_net": en.value, "energy_prev": ep.value}
 
 
 class Context:
@@ -393,6 +409,12 @@ class Context:
         if check and st != OK:
             self._check(st, "sgp_pcg_solve_batched")
         return v, [infos[i].as_dict() for i in range(k)]
+
+    def residual_norm(self, A: Bsr, F, x):
+        r = C.c_double()
+        self._check(lib().sgp_residual_norm(self.h, A.h, _ptr(F, torch.float64, "F"), _ptr(x, torch.float64, "x"),
+                                            C.byref(r)), "sgp_residual_norm")
+        return r.value
 
     # ---------------------------------------------------------------- dynamics
     def forces(self, g: Graph, noise, k_rep=5.0, F=None):

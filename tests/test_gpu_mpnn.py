@@ -88,3 +88,66 @@ def test_training_lowers_the_loss(ctx):
     args = (g, to_dev(c["force"]), to_dev(vprev), to_dev(v))
     losses = [M.train_step(*args, 1e-3) for _ in range(60)]
     assert losses[-1] < 0.5 * losses[0], losses[::10]
+
+
+def test_energy_gradients_match_oracle(ctx):
+    """Energy loss ||v_hat - v||^2_Gamma / ||v||^2_Gamma: value and gradient
+    against the oracle (Gamma from the oracle's assembly), same tolerance."""
+    c, og, vprev, v = _sample(3000, 6)
+    oa = O.assemble(og)
+    scales = (float(c["force"].std()), float(v.std()), 0.1)
+    theta = N.init_params(8) + 0.02 * np.random.default_rng(3).normal(size=N.param_count())
+    theta_b = N.bf16_round(theta)
+    M = P.Mpnn(ctx)
+    M.set_params(theta, *scales)
+    g = ctx.collide(to_dev(c["pos"]), to_dev(c["radius"]))
+    A = ctx.assemble_gamma(g)
+    lg, gg = M.grad(g, to_dev(c["force"]), to_dev(vprev), to_dev(v), A)
+    L, grad, _ = _oracle_energy(theta_b, c, og, oa, vprev, v, scales)
+    assert abs(lg - L) <= 3e-2 * abs(L), (lg, L)
+    pg, po = N.unpack(host(gg).astype(np.float64)), N.unpack(grad)
+    for name, _ in N.LAYOUT:
+        a, b = pg[name].ravel(), po[name].ravel()
+        nb = np.linalg.norm(b)
+        assert np.linalg.norm(a - b) <= 3e-2 * nb + 1e-12, name
+        if nb > 0:
+            assert a @ b / (np.linalg.norm(a) * nb) >= 0.999, name
+
+
+def _oracle_energy(theta, c, og, oa, vprev, v, scales):
+    ee = N.entry_edges(og.rowptr, og.col, og.ei, og.ej)
+    rows, e = N.edge_features(og.rowptr, og.col, og.ei, og.ej, og.w, og.u, ee, scales[2])
+    return N.loss_grad(theta, c["force"], vprev, v, og.rowptr, og.col, e, rows, scales, lambda x: O.spmv(oa, x))
+
+
+def test_warm_start_picks_the_lower_energy(ctx):
+    """x0 is the network's guess exactly when its energy 0.5 x'Gx - x'F (checked
+    against the oracle's product) is below v_prev's; both branches exercised."""
+    c, og, vprev, v = _sample(2000, 7)
+    oa = O.assemble(og)
+    F = c["force"]
+
+    def energy(x):
+        a, b = 0.5 * np.sum(x * O.spmv(oa, x)), np.sum(x * F)
+        return a - b, abs(a) + abs(b)
+
+    g = ctx.collide(to_dev(c["pos"]), to_dev(c["radius"]))
+    A = ctx.assemble_gamma(g)
+    garbage = 50.0 * np.random.default_rng(9).normal(size=v.shape)
+    # a zero network guesses 0 (energy 0): it beats a garbage v_prev and loses
+    # to the solution itself (the lowest energy)
+    cases = [(N.init_params(1), vprev, None), (np.zeros(N.param_count()), garbage, True),
+             (N.init_params(1), v, False)]
+    for theta, vp, expect in cases:
+        M = P.Mpnn(ctx)
+        M.set_params(theta, float(F.std()), float(v.std()), 0.1)
+        vh = host(M.forward(g, to_dev(F), to_dev(vp)))
+        x0, info = M.warm_start(g, A, to_dev(F), to_dev(vp))
+        en, sn = energy(vh)
+        ep, sp = energy(vp)
+        assert abs(info["energy_net"] - en) <= 1e-10 * sn
+        assert abs(info["energy_prev"] - ep) <= 1e-10 * sp
+        assert info["used_net"] == (en < ep)
+        if expect is not None:
+            assert info["used_net"] == expect
+        assert np.array_equal(host(x0), vh if info["used_net"] else vp)

@@ -100,3 +100,46 @@ def test_bf16_rounding():
     assert r[6] == 1.0 + 2 ** -7                # 1/4 of a spacing: down
     assert abs(r[3] + 3.140625) < 1e-12
     assert r[4] == 0.0
+
+
+def _gamma(g):
+    A = O.assemble(g).dense()
+    return A, (lambda x: (A @ x.reshape(-1)).reshape(-1, 3))
+
+
+def test_energy_loss_is_the_gamma_norm_error():
+    """With v the exact solution (dense solve), the energy loss equals
+    ||v_hat - v||^2_Gamma / ||v||^2_Gamma computed from the dense matrix, is 0
+    at v_hat = v and 1 at v_hat = 0."""
+    g, rows, e, F, vprev, _ = _setup(60, 3)
+    A, mv = _gamma(g)
+    v = np.linalg.solve(A, F.reshape(-1)).reshape(-1, 3)
+    sV = 0.7
+    out = np.random.default_rng(2).normal(size=v.shape)
+    L, _ = N.energy_loss_and_dout(out, v, F, mv, sV)
+    d = (sV * out - v).reshape(-1)
+    ref = d @ A @ d / (v.reshape(-1) @ A @ v.reshape(-1))
+    assert abs(L - ref) <= 1e-10 * ref
+    assert abs(N.energy_loss_and_dout(v / sV, v, F, mv, sV)[0]) <= 1e-10
+    assert abs(N.energy_loss_and_dout(np.zeros_like(v), v, F, mv, sV)[0] - 1.0) <= 1e-12
+
+
+def test_energy_gradients_match_central_differences():
+    g, rows, e, F, vprev, _ = _setup()
+    A, mv = _gamma(g)
+    v = np.linalg.solve(A, F.reshape(-1)).reshape(-1, 3)
+    theta = N.init_params(5) + 0.05 * np.random.default_rng(3).normal(size=N.param_count())
+    scales = (1.0, float(v.std()), 0.1)
+    L, grad, _ = N.loss_grad(theta, F, vprev, v, g.rowptr, g.col, e, rows, scales, mv)
+    rng = np.random.default_rng(4)
+    idx = rng.choice(theta.size, size=300, replace=False)
+    h = 1e-6
+    num = np.empty(idx.size)
+    for k, i in enumerate(idx):
+        tp = theta.copy(); tp[i] += h
+        tm = theta.copy(); tm[i] -= h
+        Lp = N.loss_grad(tp, F, vprev, v, g.rowptr, g.col, e, rows, scales, mv)[0]
+        Lm = N.loss_grad(tm, F, vprev, v, g.rowptr, g.col, e, rows, scales, mv)[0]
+        num[k] = (Lp - Lm) / (2 * h)
+    err = np.abs(num - grad[idx])
+    assert np.all(err <= 1e-6 * np.abs(grad[idx]).max() + 1e-7 * np.abs(num)), err.max()
