@@ -14,8 +14,12 @@ Prints ONE JSON line.  Besides the headline value it carries:
   cpu_baseline  the FP64 CPU oracle timed on this host's cores on a bounded
                 sample of the same workload (setup + a fixed number of CG
                 iterations, extrapolated to the GPU's iteration count);
-  extra         phase times, block-Jacobi PCG and FP32-inner refinement on the
-                same system (iterations and solve time), for comparison.
+  extra         the other workloads, each bounded to seconds of GPU time:
+                block-Jacobi PCG on the same 1M system; the 1k-cell solve's
+                latency with and without hipGraph replay; FP32-inner refinement
+                against plain FP64 at 4M cells; 256 independent spheroids in
+                one batched pipeline with autotuned knobs; the learned warm
+                start over 200 time steps of a 200k-cell spheroid.
 """
 from __future__ import annotations
 
@@ -53,11 +57,175 @@ def cpu_baseline(c, gpu_iters: int, sample_iters: int = 10):
     t2 = time.perf_counter()
     per_iter = (t2 - t1) / sample_iters
     est = (t1 - t0) + per_iter * gpu_iters
+    import platform
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": 1.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "host_cores_visible": os.cpu_count(), "host_cpu": model,
             "sample": f"1M-cell workload: collide+assemble+Prim+root+TreeLDLT in full ({t1 - t0:.1f} s) "
                       f"plus {sample_iters} tree-PCG iterations ({t2 - t1:.1f} s), "
                       f"extrapolated to {gpu_iters} iterations; single-threaded C, -O2",
             "setup_s": t1 - t0, "per_iter_s": per_iter}
+
+
+def _sync_time(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, r
+
+
+def extra_jacobi(ctx, A, M, F):
+    """Block-Jacobi PCG against tree-PCG on the same 1M system (solve only)."""
+    import torch
+    MJ = ctx.make_jacobi(A)
+    tj, (_, ij) = _sync_time(lambda: ctx.pcg_solve(A, MJ, F, torch.zeros_like(F), rtol=1e-8))
+    tt, (_, it) = _sync_time(lambda: ctx.pcg_solve(A, M, F, torch.zeros_like(F), rtol=1e-8))
+    return {"jacobi_pcg": {"iters": ij["iters"], "solve_ms": 1e3 * tj},
+            "tree_pcg": {"iters": it["iters"], "solve_ms": 1e3 * tt}}
+
+
+def extra_small(P, dev, reps=30):
+    """1000-cell workload (seed 0): latency of one solve and of the whole
+    pipeline, eager launches against hipGraph replay of the CG chunks."""
+    import numpy as np
+    from workloads import sphere_cluster
+    c = sphere_cluster(1000, 0)
+    pos, R, F = dev(c["pos"]), dev(c["radius"]), dev(c["force"])
+    ctx = P.Context()
+    out = {"workload": "jittered FCC ball, 1000 spheres, seed 0"}
+    for graph in (0, 1):
+        ctx.tune("graph", graph)
+        for ce in (8, 32):
+            ctx.tune("check_every", ce)
+            ts, tp, iters = [], [], 0
+            for r in range(reps + 2):
+                t_all, (A, M, ts_) = _sync_time(lambda: _pipeline(ctx, pos, R, F))
+                if r >= 2:
+                    tp.append(t_all)
+                    ts.append(ts_[0])
+                    iters = ts_[1]
+            out[f"graph{graph}_check{ce}"] = {"solve_us": 1e6 * float(np.median(ts)),
+                                             "pipeline_us": 1e6 * float(np.median(tp)), "iters": iters}
+    ctx.close()
+    return out
+
+
+def _pipeline(ctx, pos, R, F, schedule="contract"):
+    import torch
+    g = ctx.collide(pos, R)
+    A = ctx.assemble_gamma(g)
+    M = ctx.factor_tree(g, ctx.build_tree(g), schedule=schedule)
+    ts, (_, info) = _sync_time(lambda: ctx.pcg_solve(A, M, F, torch.zeros_like(F), rtol=1e-8))
+    return A, M, (ts, info["iters"])
+
+
+def extra_mixed(P, dev, n=4_000_000):
+    """4M cells (seed 0): FP32 product and sweeps inside FP64 refinement against
+    plain FP64 tree-PCG on the same system; both solutions are compared with an
+    FP64 solve to relres 1e-13 on the GPU (the oracle's parity with that path
+    is tested separately)."""
+    import torch
+    from workloads import sphere_cluster
+    c = sphere_cluster(n, 0)
+    pos, R, F = dev(c["pos"]), dev(c["radius"]), dev(c["force"])
+    del c
+    ctx = P.Context()
+    g = ctx.collide(pos, R)
+    A = ctx.assemble_gamma(g)
+    M = ctx.factor_tree(g, ctx.build_tree(g))
+    ref, _ = ctx.pcg_solve(A, M, F, rtol=1e-13, max_iter=20000)
+    out = {"workload": f"jittered FCC ball, {n} spheres, seed 0; solve only, relres 1e-8"}
+    for name, kw in (("f64", {}), ("f32ir", {"precision": "f32ir", "inner_rtol": 1e-4})):
+        ctx.pcg_solve(A, M, F, rtol=1e-8, **kw)   # warm-up (FP32 copies built once)
+        ts = []
+        for _ in range(3):
+            t, (v, info) = _sync_time(lambda: ctx.pcg_solve(A, M, F, rtol=1e-8, **kw))
+            ts.append(t)
+        err = float(torch.linalg.vector_norm(v - ref) / torch.linalg.vector_norm(ref))
+        out[name] = {"solve_ms": 1e3 * min(ts), "iters": info["iters"], "outer": info["outer_iters"],
+                     "relres_true": info["relres_true"], "err_vs_fp64_1e-13": err}
+    out["wall_ratio_f32ir_vs_f64"] = out["f32ir"]["solve_ms"] / out["f64"]["solve_ms"]
+    out["iter_ratio_f32ir_vs_f64"] = out["f32ir"]["iters"] / out["f64"]["iters"]
+    ctx.close()
+    return out
+
+
+def extra_batched(P, dev, n_inst=256, steps=3, log=None):
+    """256 spheroids, sizes log-uniform in [1e3, 2e5], seeds 1..256: one batched
+    pipeline (collide -> assemble -> tree -> factor -> PCG over all instances at
+    once), knobs chosen by the autotuner on this batch."""
+    import numpy as np
+    import torch
+    from paper_2410_04512_amd import autotune
+    from workloads import batched_instance
+    parts = [batched_instance(k + 1) for k in range(n_inst)]
+    sizes = np.array([p["pos"].shape[0] for p in parts])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = dev(np.concatenate([p["pos"] for p in parts]))
+    R = dev(np.concatenate([p["radius"] for p in parts]))
+    F = dev(np.concatenate([p["force"] for p in parts]))
+    del parts
+    ctx = P.Context()
+    g = ctx.collide_batched(off, pos, R)
+    A = ctx.assemble_gamma(g)
+    T = ctx.build_tree(g)
+    tuned = autotune.tune(ctx, g, T, A, F, offsets=off, log=log)
+    sched = tuned["schedule"]
+    del g, A, T, tuned["prec"]
+
+    def step():
+        g = ctx.collide_batched(off, pos, R)
+        A = ctx.assemble_gamma(g)
+        M = ctx.factor_tree(g, ctx.build_tree(g), schedule=sched)
+        ts, (v, infos) = _sync_time(lambda: ctx.pcg_solve_batched(A, M, off, F, rtol=1e-8))
+        return ts, infos
+
+    step()
+    times, solve_t = [], []
+    for _ in range(steps):
+        t, (ts, infos) = _sync_time(step)
+        times.append(t)
+        solve_t.append(ts)
+    it = np.array([i["iters"] for i in infos])
+    rel = np.array([i["relres_true"] for i in infos])
+    st = np.array([i["status"] for i in infos])
+    ms = 1e3 * float(np.median(times))
+    return {"workload": f"{n_inst} spheroids, sizes log-uniform [1e3, 2e5] (sum {int(off[-1])} cells), seeds 1..{n_inst}",
+            "solves_per_s": n_inst / (ms * 1e-3), "ms_per_step": ms, "solve_ms": 1e3 * float(np.median(solve_t)),
+            "iters_min": int(it.min()), "iters_mean": float(it.mean()), "iters_max": int(it.max()),
+            "max_relres_true": float(rel.max()), "all_converged": bool((st == 0).all()),
+            "tuned": {k: v for k, v in tuned.items() if k not in ("prec", "table", "defaults")},
+            "tune_table_ms": {k: 1e3 * v for k, v in tuned["table"].items()}}
+
+
+def extra_learned(P, dev, log=None):
+    """200k-cell spheroid (seed 0), 200 overdamped steps (dt 0.01, repulsion
+    5 w n plus N(0, 0.1^2) active force); the network trains on steps 1-100 and
+    warm-starts steps 101-200; iterations and wall time to relres 1e-8 against
+    the previous-step and the zero start."""
+    import torch
+    from paper_2410_04512_amd import warmstart as W
+    from workloads import sphere_cluster, dynamics_noise
+    c = sphere_cluster(200_000, 0)
+    ctx = P.Context()
+    pos, R = dev(c["pos"]), dev(c["radius"])
+    res = W.run(ctx, pos, R, dynamics_noise, n_steps=200, n_train=100, epochs=30, lr=3e-3, log=log)
+    s = W.summary(res)
+    s["workload"] = "200k-cell spheroid, seed 0, 200 steps; train 1-100, test 101-200"
+    del res
+    ctx.close()
+    torch.cuda.synchronize()
+    return s
 
 
 def main():
@@ -69,6 +237,8 @@ def main():
     ap.add_argument("--schedule", default="contract", choices=["contract", "level"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--extras", default="jacobi,small,mixed,batched,learned",
+                    help="comma list of extra workloads to run after the headline")
     ap.add_argument("--kernel-only", choices=["spmv"], default=None,
                     help="build the system once, then run only the named kernel (for counter runs)")
     args = ap.parse_args()
@@ -173,21 +343,24 @@ def main():
     }
     if not args.no_extra:
         ex = {}
-        MJ = ctx.make_jacobi(A)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        _, ij = ctx.pcg_solve(A, MJ, F, torch.zeros_like(F), rtol=1e-8)
-        torch.cuda.synchronize()
-        ex["jacobi_pcg"] = {"iters": ij["iters"], "solve_ms": 1e3 * (time.perf_counter() - ta)}
-        ta = time.perf_counter()
-        _, it = ctx.pcg_solve(A, M, F, torch.zeros_like(F), rtol=1e-8)
-        torch.cuda.synchronize()
-        ex["tree_pcg"] = {"iters": it["iters"], "solve_ms": 1e3 * (time.perf_counter() - ta)}
-        ta = time.perf_counter()
-        _, ii = ctx.pcg_solve(A, M, F, torch.zeros_like(F), rtol=1e-8, precision="f32ir", inner_rtol=1e-4)
-        torch.cuda.synchronize()
-        ex["tree_pcg_f32ir"] = {"iters": ii["iters"], "outer": ii["outer_iters"], "relres": ii["relres_rec"],
-                                "solve_ms": 1e3 * (time.perf_counter() - ta)}
+        wanted = [e for e in args.extras.split(",") if e]
+        log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+        for name in wanted:
+            log(f"extra: {name}")
+            t_x = time.perf_counter()
+            if name == "jacobi":
+                ex.update(extra_jacobi(ctx, A, M, F))
+            elif name == "small":
+                ex["small_1k"] = extra_small(P, dev)
+            elif name == "mixed":
+                ex["mixed_4M"] = extra_mixed(P, dev)
+            elif name == "batched":
+                ex["batched_256"] = extra_batched(P, dev, log=log)
+            elif name == "learned":
+                ex["learned_200k"] = extra_learned(P, dev, log=log)
+            else:
+                raise SystemExit(f"unknown extra '{name}'")
+            log(f"extra: {name} done in {time.perf_counter() - t_x:.1f} s")
         out["extra"] = ex
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, int(info.get("iters") or 170))

@@ -291,16 +291,24 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
                         const double *vprev, double *x0, int32_t *used_net, double *energy_net,
                         double *energy_prev);
 
-/* Launch-shape knobs of this process (chosen by the autotuner):
- *  "check_every"  CG iterations between the host's convergence reads (>= 1);
- *                 0 iterations of extra work either way: converged solves stop
- *                 on the device and the host only polls
+/* Launch-shape knobs of this context (chosen by the autotuner):
+ *  "check_every"  CG iterations between the host's convergence reads
+ *                 (1..1024, default 8); iterations issued past convergence
+ *                 are no-ops on the device
  *  "tail_max"     the largest number of tree vertices whose last elimination
  *                 steps run as one LDS-resident workgroup in the tree sweeps
- *                 (0..65536, 0 disables; used by factors built afterwards)
- * Unknown keys or values out of range give SGP_EINVAL.  Results do not
- * depend on either knob. */
+ *                 (0..65536, 0 disables, default 2200; used by factors built
+ *                 afterwards)
+ *  "graph"        1: each chunk of check_every CG iterations is captured once
+ *                 per solve into a hipGraph and replayed (default 0)
+ *  "spmv_waves"   waves per workgroup of the block-CSR product: 2, 4 or 8
+ *                 (default 4)
+ * Unknown keys or values out of range give SGP_EINVAL.  check_every, tail_max
+ * and graph leave every result bitwise unchanged; spmv_waves changes only the
+ * summation order of the p.q dot product. */
 int sgp_tune(sgp_ctx ctx, const char *key, int32_t value);
+/* Current value of a knob (host output). */
+int sgp_tune_get(sgp_ctx ctx, const char *key, int32_t *value);
 
 /* Per-launch timing of the CG's block-CSR product: when enabled, every
  * product launched by sgp_pcg_solve* is bracketed by HIP events on the

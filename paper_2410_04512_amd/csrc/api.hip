@@ -30,6 +30,7 @@ extern "C" void sgp_destroy(sgp_ctx c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
     for (auto &b : c->ws) release(b);
     if (c->tickets) (void)hipFree(c->tickets);

@@ -392,7 +392,6 @@ __global__ void k_bwd_step(int32_t q0, int32_t q1, const int32_t *elim, const in
 // x only from LDS.  x is also written to y (global) for the earlier steps.
 constexpr int TAIL_THREADS = 1024;
 constexpr int TAIL_LDS_BYTES = 160 * 1024;
-int g_tail_max = 2200;
 
 template <class T>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, int32_t Qt, int32_t nt, int32_t ni,
@@ -744,10 +743,10 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     int32_t *dsp;
     SGP_TRY(ensure_t(ctx, M->step_ptr, (size_t)S + 2, &dsp));
     HIP_TRY(ctx, hipMemcpyAsync(dsp, sptr, (S + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-    // steps from tail_step on hold at most g_tail_max vertices in all (each
+    // steps from tail_step on hold at most ctx->tail_max vertices in all (each
     // has at most two pushes, so 3 g_tail_max slots of LDS always suffice)
     M->tail_step = S;
-    int tmax = std::min(g_tail_max, TAIL_LDS_BYTES / (9 * 8));
+    int tmax = std::min(ctx->tail_max, TAIL_LDS_BYTES / (9 * 8));
     while (M->tail_step > 0 && n - M->h_step_ptr[M->tail_step - 1] <= tmax) M->tail_step--;
     // up links and in-lists
     int32_t *upq, *icnt, *in_ptr, *in_src;

@@ -383,7 +383,6 @@ int spmv_t<float>(sgp_ctx ctx, sgp_bsr A, const float *x, float *y, const PcgSca
     return spmv_f32(ctx, A, x, y, S, part, mode);
 }
 
-static int g_check_every = 8;
 
 template <class T>
 struct Vecs {
@@ -399,6 +398,83 @@ static int fin(sgp_ctx ctx, int op, const double *part, int nblk, const int32_t 
 }
 
 // PCG iterations on prepared r, z (z = M r) and p, until every cluster is done.
+// `count` CG iterations, launched on ctx->stream (no host synchronisation,
+// allocation or memset inside, so the sequence can be captured into a graph).
+// Every kernel returns at once for a converged cluster, so iterations issued
+// past convergence change nothing.
+template <class T>
+static int pcg_chunk(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w, PcgScalars *S, double *part,
+                     int count)
+{
+    hipStream_t st = ctx->stream;
+    const int64_t K = w.K;
+    // one cluster: the sweeps stop with it; several: every sweep runs
+    PcgScalars *gate = K == 1 ? S : nullptr;
+    for (int c = 0; c < count; c++) {
+        SGP_TRY(ktimer_begin(ctx));
+        if (K == 1) {
+            SGP_TRY(spmv_t<T>(ctx, A, v.p, v.q, S, part, 1));
+            SGP_TRY(ktimer_end(ctx));
+            SGP_TRY(fin(ctx, FIN_ALPHA, part, w.mv_nb, w.mv_first, w.mv_nb_dev, S, 1));
+        } else {
+            SGP_TRY(spmv_t<T>(ctx, A, v.p, v.q, nullptr, nullptr, 0));
+            SGP_TRY(ktimer_end(ctx));
+            k_pq<T><<<w.vec_nb, 256, 0, st>>>(v.p, v.q, w.vec, S, part);
+            SGP_TRY(fin(ctx, FIN_ALPHA, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
+        }
+        k_update_xr<T><<<w.vec_nb, 256, 0, st>>>(v.x, v.r, v.p, v.q, w.vec, S, part);
+        SGP_TRY(fin(ctx, FIN_RR, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
+        if (M) {
+            if (sizeof(T) == 8)
+                SGP_TRY(prec_apply_f64(ctx, M, (const double *)v.r, (double *)v.z, gate));
+            else
+                SGP_TRY(prec_apply_f32(ctx, M, (const float *)v.r, (float *)v.z, gate));
+        }
+        k_rz<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.z, w.vec, S, part);
+        SGP_TRY(fin(ctx, FIN_BETA, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
+        k_update_p<T><<<w.vec_nb, 256, 0, st>>>(v.p, v.z, w.vec, S);
+        LAUNCH_CHECK(ctx);
+    }
+    return SGP_OK;
+}
+
+// an instantiated graph of one chunk, destroyed with the solve
+struct ChunkGraph {
+    hipGraphExec_t exec = nullptr;
+    ~ChunkGraph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+
+// capture `count` iterations on the context's private stream (capture only
+// records; nothing runs until the graph is launched on ctx->stream)
+template <class T>
+static int capture_chunk(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w, PcgScalars *S, double *part,
+                         int count, ChunkGraph &g)
+{
+    if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    hipStream_t saved = ctx->stream;
+    ctx->stream = ctx->cap_stream;
+    hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+    int rc = e == hipSuccess ? pcg_chunk<T>(ctx, A, M, v, w, S, part, count) : SGP_EHIP;
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(ctx->cap_stream, &graph) : e;
+    ctx->stream = saved;
+    if (rc != SGP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e2 != hipSuccess) return set_err(ctx, SGP_EHIP, "graph capture failed: %s", hipGetErrorString(e2));
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        g.exec = nullptr;
+        return set_err(ctx, SGP_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    return SGP_OK;
+}
+
 template <class T>
 static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w, PcgScalars *S,
                        double *part, int32_t *open, int check_every, int max_iter, int fixed)
@@ -407,34 +483,16 @@ static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w
     int32_t *hopen = (int32_t *)ctx->pinned;
     const int64_t K = w.K;
     const int limit = fixed > 0 ? fixed : max_iter;
-    // one cluster: the sweeps stop with it; several: every sweep runs
-    PcgScalars *gate = K == 1 ? S : nullptr;
+    // graph replay of whole chunks (not while per-launch timing records events)
+    const bool graph = ctx->use_graph && !ctx->ktiming;
+    ChunkGraph cg;
     for (int it = 0; it < limit;) {
         int chunk = std::min(check_every, limit - it);
-        for (int c = 0; c < chunk; c++) {
-            SGP_TRY(ktimer_begin(ctx));
-            if (K == 1) {
-                SGP_TRY(spmv_t<T>(ctx, A, v.p, v.q, S, part, 1));
-                SGP_TRY(ktimer_end(ctx));
-                SGP_TRY(fin(ctx, FIN_ALPHA, part, w.mv_nb, w.mv_first, w.mv_nb_dev, S, 1));
-            } else {
-                SGP_TRY(spmv_t<T>(ctx, A, v.p, v.q, nullptr, nullptr, 0));
-                SGP_TRY(ktimer_end(ctx));
-                k_pq<T><<<w.vec_nb, 256, 0, st>>>(v.p, v.q, w.vec, S, part);
-                SGP_TRY(fin(ctx, FIN_ALPHA, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
-            }
-            k_update_xr<T><<<w.vec_nb, 256, 0, st>>>(v.x, v.r, v.p, v.q, w.vec, S, part);
-            SGP_TRY(fin(ctx, FIN_RR, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
-            if (M) {
-                if (sizeof(T) == 8)
-                    SGP_TRY(prec_apply_f64(ctx, M, (const double *)v.r, (double *)v.z, gate));
-                else
-                    SGP_TRY(prec_apply_f32(ctx, M, (const float *)v.r, (float *)v.z, gate));
-            }
-            k_rz<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.z, w.vec, S, part);
-            SGP_TRY(fin(ctx, FIN_BETA, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
-            k_update_p<T><<<w.vec_nb, 256, 0, st>>>(v.p, v.z, w.vec, S);
-            LAUNCH_CHECK(ctx);
+        if (graph && chunk == check_every) {
+            if (!cg.exec) SGP_TRY(capture_chunk<T>(ctx, A, M, v, w, S, part, chunk, cg));
+            HIP_TRY(ctx, hipGraphLaunch(cg.exec, st));
+        } else {
+            SGP_TRY(pcg_chunk<T>(ctx, A, M, v, w, S, part, chunk));
         }
         it += chunk;
         SGP_TRY(fill_i32(ctx, open, 0, 1));
@@ -455,7 +513,7 @@ static int prepare_work(sgp_ctx ctx, sgp_bsr A, const std::vector<int64_t> &off,
     const int64_t K = (int64_t)off.size() - 1;
     w.K = K;
     build_tab(off, 256, w.vec_buf, w.vec_nb);
-    w.mv_nb = spmv_blocks(A);
+    w.mv_nb = spmv_blocks(ctx, A);
     w.vec_buf.push_back(0);
     w.vec_buf.push_back(w.mv_nb);
     int32_t *d;
@@ -509,7 +567,7 @@ static int solve_f64(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<int64
     LAUNCH_CHECK(ctx);
     SGP_TRY(fin(ctx, FIN_RHO, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
     Vecs<double> v = {x, r, z, p, q};
-    int ce = o->check_every > 0 ? o->check_every : g_check_every;
+    int ce = o->check_every > 0 ? o->check_every : ctx->check_every;
     SGP_TRY(pcg_iterate<double>(ctx, A, M, v, w, S, part, open, ce, max_iter, fixed));
     // true residual
     SGP_TRY(spmv_f64(ctx, A, x, q, nullptr, nullptr, 0));
@@ -600,7 +658,7 @@ static int solve_ir(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const double *F, double 
     int max_outer = o->max_outer > 0 ? o->max_outer : 50;
     int max_inner = o->max_iter > 0 ? o->max_iter : 10000;
     double inner = o->inner_rtol > 0 ? o->inner_rtol : 1e-5;
-    int ce = o->check_every > 0 ? o->check_every : g_check_every;
+    int ce = o->check_every > 0 ? o->check_every : ctx->check_every;
     if (!o->use_x0) SGP_TRY(fill_f64(ctx, x, 0.0, len));
     int total_inner = 0, outer = 0, status = SGP_OK;
     double relres = 0.0;
@@ -749,16 +807,38 @@ extern "C" int sgp_residual_norm(sgp_ctx ctx, sgp_bsr A, const double *F, const 
 
 extern "C" int sgp_tune(sgp_ctx ctx, const char *key, int32_t value)
 {
+    if (!ctx) return SGP_EINVAL;
     if (!key) return set_err(ctx, SGP_EINVAL, "tune: null key");
     if (!strcmp(key, "check_every")) {
-        if (value < 1) return set_err(ctx, SGP_EINVAL, "tune: check_every must be >= 1");
-        g_check_every = value;
+        if (value < 1 || value > 1024) return set_err(ctx, SGP_EINVAL, "tune: check_every must be in [1, 1024]");
+        ctx->check_every = value;
         return SGP_OK;
     }
     if (!strcmp(key, "tail_max")) {
         if (value < 0 || value > 65536) return set_err(ctx, SGP_EINVAL, "tune: tail_max must be in [0, 65536]");
-        g_tail_max = value;
+        ctx->tail_max = value;
+        return SGP_OK;
+    }
+    if (!strcmp(key, "graph")) {
+        if (value != 0 && value != 1) return set_err(ctx, SGP_EINVAL, "tune: graph must be 0 or 1");
+        ctx->use_graph = value;
+        return SGP_OK;
+    }
+    if (!strcmp(key, "spmv_waves")) {
+        if (value != 2 && value != 4 && value != 8) return set_err(ctx, SGP_EINVAL, "tune: spmv_waves must be 2, 4 or 8");
+        ctx->spmv_waves = value;
         return SGP_OK;
     }
     return set_err(ctx, SGP_EINVAL, "tune: unknown key '%s'", key);
+}
+
+extern "C" int sgp_tune_get(sgp_ctx ctx, const char *key, int32_t *value)
+{
+    if (!ctx || !key || !value) return set_err(ctx, SGP_EINVAL, "tune_get: bad arguments");
+    if (!strcmp(key, "check_every")) *value = ctx->check_every;
+    else if (!strcmp(key, "tail_max")) *value = ctx->tail_max;
+    else if (!strcmp(key, "graph")) *value = ctx->use_graph;
+    else if (!strcmp(key, "spmv_waves")) *value = ctx->spmv_waves;
+    else return set_err(ctx, SGP_EINVAL, "tune_get: unknown key '%s'", key);
+    return SGP_OK;
 }

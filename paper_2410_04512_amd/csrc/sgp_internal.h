@@ -41,6 +41,12 @@ struct sgp_ctx_ {
     int kev_used = 0;
     double ktime_ms = 0.0;
     int64_t klaunches = 0;
+    // launch-shape knobs (sgp_tune); none changes a result beyond rounding order
+    int check_every = 8;           // CG iterations between the host's convergence reads
+    int tail_max = 2200;           // vertices at most left for the one-workgroup tail of the tree sweeps
+    int use_graph = 0;             // replay a captured chunk of CG iterations as one hipGraph
+    int spmv_waves = 4;            // waves per workgroup of the block-CSR product (2, 4 or 8)
+    hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)
 };
 
 // event pair around one timed launch (no-op unless timing is on)
@@ -161,11 +167,10 @@ int permute_rows(sgp_ctx ctx, const int32_t *idx, const double *src, double *dst
 int copy_order(sgp_ctx ctx, DevBuf &dperm, DevBuf &dinv, const DevBuf &sperm, const DevBuf &sinv, int64_t n);
 int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s);
 int prec_make32(sgp_ctx ctx, sgp_prec M);
-extern int g_tail_max;   // vertices at most left for the one-workgroup tail of the tree sweeps
 int tail_setup_attr(sgp_ctx ctx);
 int bsr_make32(sgp_ctx ctx, sgp_bsr A);
 int bsr_prepare(sgp_ctx ctx, sgp_bsr A);
-int spmv_blocks(sgp_bsr A);
+int spmv_blocks(sgp_ctx ctx, sgp_bsr A);
 int spmv_f64(sgp_ctx ctx, sgp_bsr A, const double *x, double *y, const PcgScalars *S, double *part, int mode);
 int spmv_f32(sgp_ctx ctx, sgp_bsr A, const float *x, float *y, const PcgScalars *S, double *part, int mode);
 

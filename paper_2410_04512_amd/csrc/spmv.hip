@@ -20,7 +20,6 @@
 
 constexpr int WAVE_GROUPS = 2;                       // 64-block groups per wave
 constexpr int WAVE_BLOCKS = 64 * WAVE_GROUPS;
-constexpr int SPMV_WAVES = 4;                        // waves per workgroup
 constexpr int ROW_MAX = 65;                          // blocks per row at most (max_deg 64 + diagonal)
 constexpr int ACC_SLOTS = WAVE_BLOCKS + ROW_MAX;     // product slots per wave
 
@@ -60,7 +59,7 @@ SGP_DEV void block_product(T *a, int s, const T *v, T x0, T x1, T x2)
     a[3 * s + 2] = v[2] * x0 + v[4] * x1 + v[5] * x2;
 }
 
-template <class T>
+template <class T, int SPMV_WAVES>
 __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_sym(const int32_t *__restrict__ rowptr,
                                                               const int32_t *__restrict__ bcol,
                                                               const T *__restrict__ val, const T *__restrict__ x,
@@ -143,30 +142,41 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_sym(const int32_t *__r
         for (int o = 32; o > 0; o >>= 1) d = d + __shfl_xor(d, o, 64);
         if (lane == 0) sh[wv] = d;
         __syncthreads();
-        if (threadIdx.x == 0) part[lb] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+        if (threadIdx.x == 0) {
+            double t = sh[0];
+            for (int k = 1; k < SPMV_WAVES; k++) t = t + sh[k];
+            part[lb] = t;
+        }
     }
 }
 
-int spmv_blocks(sgp_bsr A) { return (int)((A->nwaves + SPMV_WAVES - 1) / SPMV_WAVES); }
+int spmv_blocks(sgp_ctx ctx, sgp_bsr A) { return (int)((A->nwaves + ctx->spmv_waves - 1) / ctx->spmv_waves); }
+
+template <class T>
+static int spmv_launch(sgp_ctx ctx, sgp_bsr A, const T *val, const T *x, T *y, const PcgScalars *S, double *part,
+                       int mode)
+{
+    if (A->nwaves == 0) return SGP_OK;
+    const int nb = spmv_blocks(ctx, A);
+    const int32_t *rp = (const int32_t *)A->rowptr.p, *bc = (const int32_t *)A->bcol.p, *wr = (const int32_t *)A->wrow.p;
+    switch (ctx->spmv_waves) {
+    case 2: k_spmv_sym<T, 2><<<nb, 128, 0, ctx->stream>>>(rp, bc, val, x, y, wr, A->nwaves, S, part, mode); break;
+    case 4: k_spmv_sym<T, 4><<<nb, 256, 0, ctx->stream>>>(rp, bc, val, x, y, wr, A->nwaves, S, part, mode); break;
+    case 8: k_spmv_sym<T, 8><<<nb, 512, 0, ctx->stream>>>(rp, bc, val, x, y, wr, A->nwaves, S, part, mode); break;
+    default: return set_err(ctx, SGP_EINVAL, "spmv: unsupported waves per workgroup %d", ctx->spmv_waves);
+    }
+    LAUNCH_CHECK(ctx);
+    return SGP_OK;
+}
 
 int spmv_f64(sgp_ctx ctx, sgp_bsr A, const double *x, double *y, const PcgScalars *S, double *part, int mode)
 {
-    if (A->nwaves == 0) return SGP_OK;
-    k_spmv_sym<double><<<spmv_blocks(A), 64 * SPMV_WAVES, 0, ctx->stream>>>(
-        (const int32_t *)A->rowptr.p, (const int32_t *)A->bcol.p, (const double *)A->val.p, x, y,
-        (const int32_t *)A->wrow.p, A->nwaves, S, part, mode);
-    LAUNCH_CHECK(ctx);
-    return SGP_OK;
+    return spmv_launch<double>(ctx, A, (const double *)A->val.p, x, y, S, part, mode);
 }
 
 int spmv_f32(sgp_ctx ctx, sgp_bsr A, const float *x, float *y, const PcgScalars *S, double *part, int mode)
 {
-    if (A->nwaves == 0) return SGP_OK;
-    k_spmv_sym<float><<<spmv_blocks(A), 64 * SPMV_WAVES, 0, ctx->stream>>>(
-        (const int32_t *)A->rowptr.p, (const int32_t *)A->bcol.p, (const float *)A->val32.p, x, y,
-        (const int32_t *)A->wrow.p, A->nwaves, S, part, mode);
-    LAUNCH_CHECK(ctx);
-    return SGP_OK;
+    return spmv_launch<float>(ctx, A, (const float *)A->val32.p, x, y, S, part, mode);
 }
 
 // caller's numbering in and out; the product runs in the internal order

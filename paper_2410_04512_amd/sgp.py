@@ -80,6 +80,7 @@ _SIGS = {
     "sgp_euler": (C.c_int, [_vp, _i64, _dbl, _vp, _vp]),
     "sgp_phase_times": (C.c_int, [_vp, C.POINTER(_dbl)]),
     "sgp_tune": (C.c_int, [_vp, C.c_char_p, _i32]),
+    "sgp_tune_get": (C.c_int, [_vp, C.c_char_p, C.POINTER(_i32)]),
     "sgp_kernel_timing": (C.c_int, [_vp, _i32]),
     "sgp_residual_norm": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(_dbl)]),
     "sgp_mpnn_param_count": (C.c_int, [C.POINTER(_i64)]),
@@ -443,3 +444,8 @@ class Context:
 
     def tune(self, key: str, value: int):
         self._check(lib().sgp_tune(self.h, key.encode(), int(value)), "sgp_tune")
+
+    def tune_get(self, key: str) -> int:
+        v = C.c_int32()
+        self._check(lib().sgp_tune_get(self.h, key.encode(), C.byref(v)), "sgp_tune_get")
+        return v.value

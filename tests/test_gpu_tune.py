@@ -1,0 +1,136 @@
+"""Launch-shape knobs and the autotuner, through the C ABI.
+
+check_every, tail_max and hipGraph replay must leave results bitwise
+unchanged (they change when and how kernels are issued, never what they
+compute); spmv_waves changes only the summation order of p.q, so results
+agree to CG's rounding spread.  Graph replays are checked against eager
+solves several times, with other eager work and synchronisations between
+them."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from workloads import sphere_cluster, batched_instance
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2410_04512_amd")
+from tests.gpu_util import check_velocity, host, to_dev  # noqa: E402
+
+
+@pytest.fixture()
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = P.Context()
+    yield c
+    c.close()
+
+
+def _system(ctx, n=20000, seed=11):
+    c = sphere_cluster(n, seed)
+    g = ctx.collide(to_dev(c["pos"]), to_dev(c["radius"]))
+    A = ctx.assemble_gamma(g)
+    T = ctx.build_tree(g)
+    return c, g, A, T
+
+
+def test_defaults_and_rejections(ctx):
+    assert ctx.tune_get("check_every") == 8 and ctx.tune_get("tail_max") == 2200
+    assert ctx.tune_get("graph") == 0 and ctx.tune_get("spmv_waves") == 4
+    for key, bad in (("check_every", 0), ("tail_max", -1), ("graph", 2), ("spmv_waves", 3), ("nope", 1)):
+        with pytest.raises(P.SgpError):
+            ctx.tune(key, bad)
+
+
+def test_graph_replay_is_bitwise_eager(ctx):
+    c, g, A, T = _system(ctx)
+    M = ctx.factor_tree(g, T)
+    F = to_dev(c["force"])
+    ctx.tune("check_every", 4)
+    v0, i0 = ctx.pcg_solve(A, M, F)
+    ctx.tune("graph", 1)
+    for rep in range(3):
+        v1, i1 = ctx.pcg_solve(A, M, F)
+        assert i1["iters"] == i0["iters"] and torch.equal(v0, v1), rep
+        # eager work and a synchronisation between replays
+        ctx.tune("graph", 0)
+        v2, _ = ctx.pcg_solve(A, M, F, fixed_iters=5)
+        torch.cuda.synchronize()
+        ctx.tune("graph", 1)
+    # FP32-inner refinement runs its inner CG through the same path
+    ctx.tune("graph", 0)
+    w0, j0 = ctx.pcg_solve(A, M, F, precision="f32ir", inner_rtol=1e-4)
+    ctx.tune("graph", 1)
+    w1, j1 = ctx.pcg_solve(A, M, F, precision="f32ir", inner_rtol=1e-4)
+    assert j0["iters"] == j1["iters"] and torch.equal(w0, w1)
+    og = O.collide(c["pos"], c["radius"])
+    check_velocity(host(v1), i1["iters"], O.assemble(og), c["force"], O.tree_factor(og, O.build_tree(og)))
+
+
+def test_graph_replay_batched(ctx):
+    sizes = [3000, 500, 12000, 40]
+    parts = [batched_instance(k + 1, n_override=s) for k, s in enumerate(sizes)]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = to_dev(np.concatenate([p["pos"] for p in parts]))
+    R = to_dev(np.concatenate([p["radius"] for p in parts]))
+    F = to_dev(np.concatenate([p["force"] for p in parts]))
+    g = ctx.collide_batched(off, pos, R)
+    A = ctx.assemble_gamma(g)
+    M = ctx.factor_tree(g, ctx.build_tree(g))
+    ctx.tune("check_every", 4)
+    v0, i0 = ctx.pcg_solve_batched(A, M, off, F)
+    ctx.tune("graph", 1)
+    for _ in range(2):
+        v1, i1 = ctx.pcg_solve_batched(A, M, off, F)
+        assert [a["iters"] for a in i0] == [b["iters"] for b in i1]
+        assert torch.equal(v0, v1)
+
+
+def test_check_every_and_tail_max_are_bitwise_neutral(ctx):
+    c, g, A, T = _system(ctx, 30000, 12)
+    F = to_dev(c["force"])
+    M = ctx.factor_tree(g, T)
+    ref, iref = ctx.pcg_solve(A, M, F)
+    for ce in (1, 3, 32):
+        ctx.tune("check_every", ce)
+        v, i = ctx.pcg_solve(A, M, F)
+        assert i["iters"] == iref["iters"] and torch.equal(v, ref), ce
+    ctx.tune("check_every", 8)
+    for tm in (0, 300):
+        ctx.tune("tail_max", tm)
+        M2 = ctx.factor_tree(g, T)
+        v, i = ctx.pcg_solve(A, M2, F)
+        assert i["iters"] == iref["iters"] and torch.equal(v, ref), tm
+        b = torch.randn_like(F)
+        assert torch.equal(ctx.prec_apply(M2, b), ctx.prec_apply(M, b)), tm
+
+
+def test_spmv_waves_change_rounding_only(ctx):
+    c, g, A, T = _system(ctx, 30000, 13)
+    F = to_dev(c["force"])
+    M = ctx.factor_tree(g, T)
+    x = torch.randn_like(F)
+    q4 = ctx.spmv(A, x)
+    ref, iref = ctx.pcg_solve(A, M, F)
+    for wv in (2, 8):
+        ctx.tune("spmv_waves", wv)
+        assert torch.equal(ctx.spmv(A, x), q4), wv    # the product itself is unchanged
+        v, i = ctx.pcg_solve(A, M, F)
+        assert abs(i["iters"] - iref["iters"]) <= 1
+        if i["iters"] == iref["iters"]:
+            assert float(torch.linalg.vector_norm(v - ref) / torch.linalg.vector_norm(ref)) <= 1e-8
+
+
+def test_autotuner_choice_solves(ctx):
+    from paper_2410_04512_amd import autotune
+    c, g, A, T = _system(ctx, 20000, 14)
+    F = to_dev(c["force"])
+    res = autotune.tune(ctx, g, T, A, F, fixed_iters=10, repeats=1)
+    assert res["schedule"] in autotune.SCHEDULES and res["tail_max"] in autotune.TAIL_MAX
+    assert ctx.tune_get("spmv_waves") == res["spmv_waves"] and ctx.tune_get("graph") == res["graph"]
+    assert ctx.tune_get("check_every") == res["check_every"]
+    v, info = ctx.pcg_solve(A, res["prec"], F)
+    assert info["status"] == 0 and info["relres_true"] <= 1.0001e-8
+    print({k: v_ for k, v_ in res.items() if k not in ("prec",)})
