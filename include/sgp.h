@@ -182,6 +182,11 @@ int sgp_make_jacobi(sgp_ctx ctx, sgp_bsr A, sgp_prec M);
 
 /* Number of parallel elimination steps of a tree preconditioner (host). */
 int sgp_prec_steps(sgp_prec M, int32_t *steps);
+/* Shape of a tree factor's elimination schedule (host outputs, each may be
+ * NULL): the number of steps, the first step run by the one-workgroup tail
+ * (== steps when there is none), the number of leading light steps, and the
+ * number of vertices of every step (step_sizes: `steps` entries). */
+int sgp_prec_info(sgp_prec M, int32_t *steps, int32_t *tail_step, int32_t *light_steps, int32_t *step_sizes);
 
 /* z = M^{-1} r (device [n][3] FP64; r and z must not overlap).  For the tree
  * this is ForwardSolve, DiagSolve and BackwardSolve of Appendix B.1. */
@@ -303,9 +308,17 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
  *                 per solve into a hipGraph and replayed (default 0)
  *  "spmv_waves"   waves per workgroup of the block-CSR product: 2, 4 or 8
  *                 (default 4)
+ *  "light_height" CONTRACT schedule: the first light_height rounds remove
+ *                 leaves only; the subtrees they remove are swept by one
+ *                 workgroup each, in one launch per sweep (0..1024, 0 = plain
+ *                 rake-and-compress, default 0; used by factors built
+ *                 afterwards)
+ *  "light_cap"    vertices of such subtrees packed into one workgroup
+ *                 (1..2^20, default 512)
  * Unknown keys or values out of range give SGP_EINVAL.  check_every, tail_max
  * and graph leave every result bitwise unchanged; spmv_waves changes only the
- * summation order of the p.q dot product. */
+ * summation order of the p.q dot product; light_height and light_cap change
+ * the elimination order of the tree factor, so results agree to rounding. */
 int sgp_tune(sgp_ctx ctx, const char *key, int32_t value);
 /* Current value of a knob (host output). */
 int sgp_tune_get(sgp_ctx ctx, const char *key, int32_t *value);

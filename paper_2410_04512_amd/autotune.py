@@ -1,13 +1,14 @@
 """Autotuner for the launch-shape knobs of a solve (orchestration only).
 
 The knobs (see sgp_tune in include/sgp.h) and the elimination schedule of the
-tree factor change launch shapes, never the method: check_every, tail_max,
-graph and the schedule leave every result bitwise unchanged, and spmv_waves
-changes only the summation order of one dot product.  So the autotuner can
-pick them by time alone, on the caller's own workload:
+tree factor change launch shapes, never the method: check_every, tail_max
+and graph leave every result bitwise unchanged; spmv_waves, light_height and
+the schedule change only the order of roundings.  So the autotuner can pick
+them by time alone, on the caller's own workload:
 
-  1. schedule x tail_max: a factor per pair, timed by fixed-iteration solves
-     (the sweeps are the only part that differs);
+  1. schedule x light_height x tail_max: a factor per combination (the level
+     schedule has no light phase), timed by fixed-iteration solves (the
+     sweeps are the only part that differs);
   2. spmv_waves: fixed-iteration solves with the chosen factor;
   3. graph x check_every: full solves to the tolerance (the polling cadence
      and the launch path only show in the whole solve).
@@ -24,6 +25,7 @@ import torch
 
 SCHEDULES = ("contract", "level")
 TAIL_MAX = (0, 1024, 2200)
+LIGHT_HEIGHT = (0, 16, 32, 64)
 SPMV_WAVES = (2, 4, 8)
 CHECK_EVERY = (4, 8, 16, 32)
 GRAPH = (0, 1)
@@ -44,9 +46,9 @@ def _timed(ctx, fn, repeats):
 def tune(ctx, g, T, A, F, offsets=None, fixed_iters=20, repeats=3, rtol=1e-8, log=None):
     """Choose the knobs for solving Gamma v = F on (g, T, A); F on the device,
     `offsets` (host int64) for a batch.  Applies the choice to ctx and returns
-    {"schedule", "tail_max", "spmv_waves", "check_every", "graph", "prec",
-    "table"}: `prec` is the factor built with the chosen schedule and
-    tail_max, `table` every timing (seconds)."""
+    {"schedule", "light_height", "tail_max", "spmv_waves", "check_every",
+    "graph", "prec", "table"}: `prec` is the factor built with the chosen
+    schedule, light_height and tail_max, `table` every timing (seconds)."""
     table = {}
 
     def solve(M, fixed):
@@ -54,20 +56,24 @@ def tune(ctx, g, T, A, F, offsets=None, fixed_iters=20, repeats=3, rtol=1e-8, lo
             return ctx.pcg_solve(A, M, F, rtol=rtol, fixed_iters=fixed)
         return ctx.pcg_solve_batched(A, M, offsets, F, rtol=rtol, fixed_iters=fixed)
 
-    start = {k: ctx.tune_get(k) for k in ("check_every", "tail_max", "graph", "spmv_waves")}
+    start = {k: ctx.tune_get(k) for k in ("check_every", "tail_max", "graph", "spmv_waves", "light_height")}
     ctx.tune("graph", 0)
     best = None
     for sched in SCHEDULES:
-        for tm in TAIL_MAX:
-            ctx.tune("tail_max", tm)
-            M = ctx.factor_tree(g, T, schedule=sched)
-            t = _timed(ctx, lambda: solve(M, fixed_iters), repeats)
-            table[f"schedule={sched},tail_max={tm}"] = t
-            if log:
-                log(f"autotune: schedule {sched} tail_max {tm}: {t * 1e3:.2f} ms / {fixed_iters} iterations")
-            if best is None or t < best[0]:
-                best = (t, sched, tm, M)
-    _, sched, tm, M = best
+        for lh in (LIGHT_HEIGHT if sched == "contract" else (0,)):
+            ctx.tune("light_height", lh)
+            for tm in TAIL_MAX:
+                ctx.tune("tail_max", tm)
+                M = ctx.factor_tree(g, T, schedule=sched)
+                t = _timed(ctx, lambda: solve(M, fixed_iters), repeats)
+                table[f"schedule={sched},light_height={lh},tail_max={tm}"] = t
+                if log:
+                    log(f"autotune: schedule {sched} light_height {lh} tail_max {tm}: "
+                        f"{t * 1e3:.2f} ms / {fixed_iters} iterations")
+                if best is None or t < best[0]:
+                    best = (t, sched, lh, tm, M)
+    _, sched, lh, tm, M = best
+    ctx.tune("light_height", lh)
     ctx.tune("tail_max", tm)
     best_w = None
     for wv in SPMV_WAVES:
@@ -92,5 +98,5 @@ def tune(ctx, g, T, A, F, offsets=None, fixed_iters=20, repeats=3, rtol=1e-8, lo
                 best_c = (t, gr, ce)
     ctx.tune("graph", best_c[1])
     ctx.tune("check_every", best_c[2])
-    return {"schedule": sched, "tail_max": tm, "spmv_waves": best_w[1], "graph": best_c[1],
+    return {"schedule": sched, "light_height": lh, "tail_max": tm, "spmv_waves": best_w[1], "graph": best_c[1],
             "check_every": best_c[2], "prec": M, "table": table, "defaults": start}

@@ -8,7 +8,9 @@
 // With the vertices renumbered in elimination order q, P = L D L^T where row
 // q of L^T has the blocks L_{up_k(q), q} = A_{up_k, q} D_q^{-1}.  We store
 //    Dinv[q]   = D_q^{-1}            (symmetric, packed 6)
-//    F[q][k]   = A_{up_k(q), q}      (full 3x3, the coupling at elimination)
+//    F[k][q]   = A_{up_k(q), q}      (full 3x3, the coupling at elimination; two
+//                                   planes of n blocks, so the many vertices
+//                                   with one up-link never fetch a second block)
 // and solve P x = b as
 //    forward   y_q = D_q^{-1} (b_q - sum_{(u,k): up_k(u) = q} F[u][k] y_u)
 //    backward  x_q = y_q - D_q^{-1} sum_k F[q][k]^T x_{up_k(q)}
@@ -159,24 +161,110 @@ __global__ void k_contract_apply(int64_t n, int32_t s, const int32_t *stepv, con
     atomicAdd(cnt, 1);
 }
 
-// step boundaries from the keys sorted by step: sptr[s] = first q of step s
-__global__ void k_step_bounds(int64_t n, const uint32_t *skey, int32_t S, int32_t *sptr)
+// ---- light subtrees (CONTRACT with a rake-only start)
+//
+// The first rounds eliminate only leaves (rake), so after H rounds the
+// eliminated vertices are exactly those of height < H: whole subtrees hanging
+// off the remaining tree.  Each such subtree is handed to one workgroup of the
+// sweeps (several subtrees per workgroup, packed in the internal order up to
+// light_cap vertices), which walks the H steps with a barrier between them:
+// one launch per sweep instead of H.
+
+__global__ void k_rake_select(int64_t n, int32_t s, const int32_t *par, const int32_t *nch, int32_t *stepv,
+                              int32_t *up0, int32_t *up1)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n || stepv[v] >= 0 || nch[v] != 0) return;
+    stepv[v] = s;
+    up0[v] = par[v];
+    up1[v] = -1;
+}
+
+// jr[v]: v's parent if v and its parent are light, v itself for the root of a
+// light subtree, -1 for a vertex that is not light
+__global__ void k_light_init(int64_t n, const int32_t *parent, const int32_t *stepv, int32_t *jr)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    if (stepv[v] < 0) {
+        jr[v] = -1;
+        return;
+    }
+    const int32_t p = parent[v];
+    jr[v] = (p >= 0 && stepv[p] >= 0) ? p : (int32_t)v;
+}
+
+__global__ void k_light_jump(int64_t n, const int32_t *a, int32_t *b)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t j = a[v];
+    b[v] = j >= 0 ? a[j] : -1;
+}
+
+__global__ void k_light_count(int64_t n, const int32_t *jr, int32_t *cnt)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    if (jr[v] >= 0) atomicAdd(&cnt[jr[v]], 1);
+}
+
+// subtree sizes of the light roots, walked in the internal order
+__global__ void k_light_vals(int64_t n, const int32_t *perm, const int32_t *jr, const int32_t *cnt, int32_t *val)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = perm[i];
+    val[i] = jr[v] == v ? cnt[v] : 0;
+}
+
+// workgroup of a light root: its first vertex's rank among all light vertices / cap
+__global__ void k_light_rootwg(int64_t n, const int32_t *perm, const int32_t *jr, const int32_t *start, int32_t cap,
+                               int32_t *wgr)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = perm[i];
+    if (jr[v] == v) wgr[v] = start[i] / cap;
+}
+
+__global__ void k_light_wg(int64_t n, const int32_t *jr, const int32_t *wgr, int32_t *wgv)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    wgv[v] = jr[v] >= 0 ? wgr[jr[v]] : 0;
+}
+
+// first q of every (light step, workgroup) key below lim; keys sorted
+__global__ void k_light_ptr(int64_t n, const uint32_t *key, int64_t lim, int32_t *wptr)
 {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q > n) return;
-    int32_t lo = q == 0 ? -1 : (int32_t)skey[q - 1];
-    int32_t hi = q == n ? S : (int32_t)skey[q];
+    const int64_t lo = q == 0 ? -1 : (int64_t)key[q - 1];
+    int64_t hi = q == n ? lim : (int64_t)key[q];
+    if (hi > lim) hi = lim;
+    for (int64_t k = lo + 1; k <= hi; k++) wptr[k] = (int32_t)q;
+}
+
+// step boundaries from the keys sorted by step: sptr[s] = first q of step s
+__global__ void k_step_bounds(int64_t n, const uint32_t *skey, uint32_t div, int32_t S, int32_t *sptr)
+{
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > n) return;
+    int32_t lo = q == 0 ? -1 : (int32_t)(skey[q - 1] / div);
+    int32_t hi = q == n ? S : (int32_t)(skey[q] / div);
     for (int32_t s = lo + 1; s <= hi; s++) sptr[s] = (int32_t)q;
 }
 
 // keys walked in the internal order: within a step, vertices end up in the
 // internal (spatial) order, which keeps the sweeps' gathers local
-__global__ void k_stepkeys(int64_t n, const int32_t *stepv, const int32_t *perm, uint32_t *key, int32_t *val)
+__global__ void k_stepkeys(int64_t n, const int32_t *stepv, const int32_t *wgv, uint32_t nwg, const int32_t *perm,
+                           uint32_t *key, int32_t *val)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t v = perm[i];
-    key[i] = (uint32_t)stepv[v];
+    key[i] = (uint32_t)stepv[v] * nwg + (wgv ? (uint32_t)wgv[v] : 0u);
     val[i] = v;
 }
 
@@ -217,7 +305,7 @@ __global__ void k_uplinks(int64_t n, const int32_t *elim, const int32_t *pos, co
 // their Schur contributions C[slot] (symmetric packed) to the vertices above.
 __global__ void k_factor_step(int32_t q0, int32_t q1, const int32_t *elim, const int32_t *upq,
                               const int32_t *in_ptr, const int32_t *in_src, const double *Pd, double *E,
-                              double *C, double *F, double *Dinv, int32_t *status)
+                              double *C, double *F, int64_t fs, double *Dinv, int32_t *status)
 {
     int32_t q = q0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
     if (q >= q1) return;
@@ -243,7 +331,7 @@ __global__ void k_factor_step(int32_t q0, int32_t q1, const int32_t *elim, const
     if (qa >= 0) {
         double E0[9];
         for (int t = 0; t < 9; t++) E0[t] = E[9 * (int64_t)q + t];   // A_{p,v}
-        for (int t = 0; t < 9; t++) F[18 * (int64_t)q + t] = E0[t];
+        for (int t = 0; t < 9; t++) F[9 * (int64_t)q + t] = E0[t];
         mm3(E0, Di, T0);                                                // A_{p,v} D^{-1}
         double *c = C + 6 * (2 * (int64_t)q);
         // A_{p,v} D^{-1} A_{v,p}: upper triangle of T0 E0^T
@@ -259,7 +347,7 @@ __global__ void k_factor_step(int32_t q0, int32_t q1, const int32_t *elim, const
         for (int t = 0; t < 9; t++) E1[t] = E[9 * (int64_t)qb + t];   // A_{v,c}
         for (int a = 0; a < 3; a++)
             for (int b = 0; b < 3; b++) E1t[3 * a + b] = E1[3 * b + a];
-        for (int t = 0; t < 9; t++) F[18 * (int64_t)q + 9 + t] = E1t[t];   // A_{c,v}
+        for (int t = 0; t < 9; t++) F[fs + 9 * (int64_t)q + t] = E1t[t];   // A_{c,v}
         mm3(E1t, Di, T1);                                                   // A_{c,v} D^{-1}
         double *c = C + 6 * (2 * (int64_t)q + 1);
         // A_{c,v} D^{-1} A_{v,c}: upper triangle of T1 E1
@@ -299,7 +387,7 @@ __global__ void k_permute9(int64_t n, const int32_t *elim, const double *src, do
 // push of its contributions to the vertices above it
 template <class T>
 SGP_DEV void fwd_vertex(int32_t q, const int32_t *elim, const int32_t *in_ptr, const int32_t *tout, const T *F,
-                        const T *Dinv, const T *r, T *y, T *cs)
+                        int64_t fs, const T *Dinv, const T *r, T *y, T *cs)
 {
     int64_t v = elim[q];
     T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
@@ -327,7 +415,7 @@ SGP_DEV void fwd_vertex(int32_t q, const int32_t *elim, const int32_t *in_ptr, c
     for (int k = 0; k < 2; k++) {
         int32_t to = tout[2 * q + k];
         if (to < 0) continue;
-        const T *Fm = F + 9 * (2 * (int64_t)q + k);
+        const T *Fm = F + k * fs + 9 * (int64_t)q;
         T *c = cs + 3 * (int64_t)to;
         c[0] = Fm[0] * o0 + Fm[1] * o1 + Fm[2] * o2;
         c[1] = Fm[3] * o0 + Fm[4] * o1 + Fm[5] * o2;
@@ -337,13 +425,14 @@ SGP_DEV void fwd_vertex(int32_t q, const int32_t *elim, const int32_t *in_ptr, c
 
 // backward substitution of one vertex q; y holds x for the vertices above
 template <class T>
-SGP_DEV void bwd_vertex(int32_t q, const int32_t *elim, const int32_t *upq, const T *F, const T *Dinv, T *y, T *z)
+SGP_DEV void bwd_vertex(int32_t q, const int32_t *elim, const int32_t *upq, const T *F, int64_t fs, const T *Dinv,
+                        T *y, T *z)
 {
     T a0 = 0, a1 = 0, a2 = 0;
     for (int k = 0; k < 2; k++) {
         int32_t w = upq[2 * q + k];
         if (w < 0) continue;
-        const T *Fm = F + 9 * (2 * (int64_t)q + k);
+        const T *Fm = F + k * fs + 9 * (int64_t)q;
         T x0 = y[3 * (int64_t)w], x1 = y[3 * (int64_t)w + 1], x2 = y[3 * (int64_t)w + 2];
         a0 = a0 + (Fm[0] * x0 + Fm[3] * x1 + Fm[6] * x2);
         a1 = a1 + (Fm[1] * x0 + Fm[4] * x1 + Fm[7] * x2);
@@ -363,21 +452,58 @@ SGP_DEV void bwd_vertex(int32_t q, const int32_t *elim, const int32_t *upq, cons
 
 template <class T>
 __global__ void k_fwd_step(int32_t q0, int32_t q1, const int32_t *elim, const int32_t *in_ptr,
-                           const int32_t *tout, const T *F, const T *Dinv, const T *r, T *y, T *cs,
+                           const int32_t *tout, const T *F, int64_t fs, const T *Dinv, const T *r, T *y, T *cs,
                            const PcgScalars *s)
 {
     if (s && s->done) return;
     int32_t q = q0 + (int32_t)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
-    if (q < q1) fwd_vertex<T>(q, elim, in_ptr, tout, F, Dinv, r, y, cs);
+    if (q < q1) fwd_vertex<T>(q, elim, in_ptr, tout, F, fs, Dinv, r, y, cs);
 }
 
 template <class T>
 __global__ void k_bwd_step(int32_t q0, int32_t q1, const int32_t *elim, const int32_t *upq, const T *F,
-                           const T *Dinv, T *y, T *z, const PcgScalars *s)
+                           int64_t fs, const T *Dinv, T *y, T *z, const PcgScalars *s)
 {
     if (s && s->done) return;
     int32_t q = q0 + (int32_t)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
-    if (q < q1) bwd_vertex<T>(q, elim, upq, F, Dinv, y, z);
+    if (q < q1) bwd_vertex<T>(q, elim, upq, F, fs, Dinv, y, z);
+}
+
+// The light steps of both sweeps: workgroup w owns the light subtrees packed
+// into it and walks steps 0..L-1 (forward) or L-1..0 (backward) over its own
+// vertices, wptr[s * nwg + w] .. wptr[s * nwg + w + 1], with a barrier between
+// steps.  A light vertex's pushes go to its parent, which is in the same
+// workgroup (read after the barrier) or above the light steps (read by a
+// later launch); backward, a light vertex reads x of its parent the same way.
+template <class T>
+__global__ __launch_bounds__(256) void k_fwd_light(int32_t L, int32_t nwg, const int32_t *wptr, const int32_t *elim,
+                                                   const int32_t *in_ptr, const int32_t *tout, const T *F,
+                                                   int64_t fs, const T *Dinv, const T *r, T *y, T *cs,
+                                                   const PcgScalars *s)
+{
+    if (s && s->done) return;
+    const int32_t w = (int32_t)xcd_block(blockIdx.x, gridDim.x);
+    for (int32_t k = 0; k < L; k++) {
+        const int32_t q1 = wptr[(int64_t)k * nwg + w + 1];
+        for (int32_t q = wptr[(int64_t)k * nwg + w] + (int32_t)threadIdx.x; q < q1; q += 256)
+            fwd_vertex<T>(q, elim, in_ptr, tout, F, fs, Dinv, r, y, cs);
+        __syncthreads();
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_bwd_light(int32_t L, int32_t nwg, const int32_t *wptr, const int32_t *elim,
+                                                   const int32_t *upq, const T *F, int64_t fs, const T *Dinv,
+                                                   T *y, T *z, const PcgScalars *s)
+{
+    if (s && s->done) return;
+    const int32_t w = (int32_t)xcd_block(blockIdx.x, gridDim.x);
+    for (int32_t k = L - 1; k >= 0; k--) {
+        const int32_t q1 = wptr[(int64_t)k * nwg + w + 1];
+        for (int32_t q = wptr[(int64_t)k * nwg + w] + (int32_t)threadIdx.x; q < q1; q += 256)
+            bwd_vertex<T>(q, elim, upq, F, fs, Dinv, y, z);
+        __syncthreads();
+    }
 }
 
 // The last, small steps of both sweeps in one workgroup.  The tail vertices
@@ -390,23 +516,76 @@ __global__ void k_bwd_step(int32_t q0, int32_t q1, const int32_t *elim, const in
 // for all tail vertices in parallel.  A barrier separates two steps; all
 // up-links of tail vertices point into the tail, so the backward steps read
 // x only from LDS.  x is also written to y (global) for the earlier steps.
+// Threads exchange data through LDS only (global reads are of inputs this
+// kernel never writes, global writes are never read back here), so the steps
+// are separated by LDS-only barriers: the next step's prefetched loads stay
+// in flight across them.
 constexpr int TAIL_THREADS = 1024;
 constexpr int TAIL_LDS_BYTES = 160 * 1024;
 
+// LDS of the tail: right-hand sides and internal push slots (3 values each),
+// and the step bounds of its steps
+static size_t tail_lds_bytes(size_t elem, int64_t nt, int64_t ni, int64_t nsteps)
+{
+    return 3 * elem * (size_t)(nt + ni) + 4 * (size_t)(nsteps + 1);
+}
+
+// tail vertices at most: every vertex pushes to at most two others and a step
+// holds at least one vertex, so 3 * 8 * 3 nt + 4 (nt + 1) bytes always suffice
+constexpr int TAIL_MAX_VERTICES = (TAIL_LDS_BYTES - 4) / 76;
+
+// the per-vertex constants of one tail vertex, loaded a step ahead
+template <class T>
+struct TailPre {
+    T d[6], f0[9], f1[9];
+    int32_t a0, a1;   // forward: push slots; backward: up-links (elimination index)
+    int32_t b0, b1;   // forward: first and end internal in-slot; backward: vertex id
+};
+
+template <class T>
+SGP_DEV void tail_load(TailPre<T> &p, int32_t q, const int32_t *links, const int32_t *ip, const int32_t *elim,
+                       const T *F, int64_t fs, const T *Dinv)
+{
+    for (int t = 0; t < 6; t++) p.d[t] = Dinv[6 * (int64_t)q + t];
+    p.a0 = links[0];
+    p.a1 = links[1];
+    if (ip) {
+        p.b0 = ip[0];
+        p.b1 = ip[1];
+    } else {
+        p.b0 = elim[q];
+    }
+    for (int t = 0; t < 9; t++) p.f0[t] = F[9 * (int64_t)q + t];
+    if (p.a1 >= 0)
+        for (int t = 0; t < 9; t++) p.f1[t] = F[fs + 9 * (int64_t)q + t];
+}
+
 template <class T>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, int32_t Qt, int32_t nt, int32_t ni,
-                                                       const int32_t *sp, const int32_t *elim, const int32_t *in_ptr,
+                                                       const int32_t *sp_g, const int32_t *elim, const int32_t *in_ptr,
                                                        const int32_t *iptr, const int32_t *tslot, const int32_t *upq,
-                                                       const T *F, const T *Dinv, const T *r, const T *cs, T *y,
-                                                       T *z, const PcgScalars *s)
+                                                       const T *F, int64_t fs, const T *Dinv, const T *r,
+                                                       const T *cs, T *y, T *z, const PcgScalars *s)
 {
     extern __shared__ unsigned char lds_raw[];
     T *sv = (T *)lds_raw;
     T *slot = sv + 3 * nt;
+    // step bounds of the tail steps, sp[k] for k = s0..S, kept in LDS
+    int32_t *ssp = (int32_t *)(slot + 3 * ni) - s0;
     if (s && s->done) return;
-    (void)ni;
+    const int tid = threadIdx.x;
+    for (int32_t k = s0 + tid; k <= S; k += TAIL_THREADS) ssp[k] = sp_g[k];
+    const int32_t *sp = ssp;
+    // a thread's first vertex of a step is prefetched while the step before
+    // it runs (its loads do not depend on the sweep), so a step waits on LDS
+    // and the barrier rather than on memory
+    TailPre<T> pa, pb;
+    {
+        const int32_t q = sp_g[s0] + tid;
+        if (q < sp_g[s0 + 1]) tail_load(pa, q, tslot + 2 * (q - Qt), iptr + (q - Qt), elim, F, fs, Dinv);
+    }
     // pre-tail contributions
-    for (int32_t i = threadIdx.x; i < nt; i += TAIL_THREADS) {
+    for (int32_t i = tid; i < nt; i += TAIL_THREADS) {
         const int32_t q = Qt + i;
         const int64_t v = elim[q];
         T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
@@ -420,50 +599,75 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
         sv[3 * i + 1] = b1;
         sv[3 * i + 2] = b2;
     }
-    __syncthreads();
-    // forward steps
-    for (int32_t k = s0; k < S; k++) {
-        for (int32_t q = sp[k] + threadIdx.x; q < sp[k + 1]; q += TAIL_THREADS) {
+    lds_barrier();
+    // forward steps; the two prefetch buffers swap roles every step (the
+    // loop is unrolled by two so that no buffer is copied)
+    auto fstep = [&](int32_t k, TailPre<T> &cur, TailPre<T> &nxt) {
+        if (k + 1 < S) {
+            const int32_t q = sp[k + 1] + tid;
+            if (q < sp[k + 2]) tail_load(nxt, q, tslot + 2 * (q - Qt), iptr + (q - Qt), elim, F, fs, Dinv);
+        }
+        for (int32_t q = sp[k] + tid; q < sp[k + 1]; q += TAIL_THREADS) {
+            if (q != sp[k] + tid) tail_load(cur, q, tslot + 2 * (q - Qt), iptr + (q - Qt), elim, F, fs, Dinv);
             const int32_t i = q - Qt;
             T b0 = sv[3 * i], b1 = sv[3 * i + 1], b2 = sv[3 * i + 2];
-            for (int32_t j = iptr[i]; j < iptr[i + 1]; j++) {
+            for (int32_t j = cur.b0; j < cur.b1; j++) {
                 b0 = b0 - slot[3 * j];
                 b1 = b1 - slot[3 * j + 1];
                 b2 = b2 - slot[3 * j + 2];
             }
             T o0, o1, o2;
-            sym_mv(Dinv + 6 * (int64_t)q, b0, b1, b2, o0, o1, o2);
+            sym_mv(cur.d, b0, b1, b2, o0, o1, o2);
             sv[3 * i] = o0;
             sv[3 * i + 1] = o1;
             sv[3 * i + 2] = o2;
-            for (int kk = 0; kk < 2; kk++) {
-                const int32_t d = tslot[2 * i + kk];
-                if (d < 0) continue;
-                const T *Fm = F + 9 * (2 * (int64_t)q + kk);
-                slot[3 * d] = Fm[0] * o0 + Fm[1] * o1 + Fm[2] * o2;
-                slot[3 * d + 1] = Fm[3] * o0 + Fm[4] * o1 + Fm[5] * o2;
-                slot[3 * d + 2] = Fm[6] * o0 + Fm[7] * o1 + Fm[8] * o2;
+            if (cur.a0 >= 0) {
+                const T *Fm = cur.f0;
+                slot[3 * cur.a0] = Fm[0] * o0 + Fm[1] * o1 + Fm[2] * o2;
+                slot[3 * cur.a0 + 1] = Fm[3] * o0 + Fm[4] * o1 + Fm[5] * o2;
+                slot[3 * cur.a0 + 2] = Fm[6] * o0 + Fm[7] * o1 + Fm[8] * o2;
+            }
+            if (cur.a1 >= 0) {
+                const T *Fm = cur.f1;
+                slot[3 * cur.a1] = Fm[0] * o0 + Fm[1] * o1 + Fm[2] * o2;
+                slot[3 * cur.a1 + 1] = Fm[3] * o0 + Fm[4] * o1 + Fm[5] * o2;
+                slot[3 * cur.a1 + 2] = Fm[6] * o0 + Fm[7] * o1 + Fm[8] * o2;
             }
         }
-        __syncthreads();
+        lds_barrier();
+    };
+    for (int32_t k = s0; k < S; k += 2) {
+        fstep(k, pa, pb);
+        if (k + 1 < S) fstep(k + 1, pb, pa);
     }
     // backward steps
-    for (int32_t k = S - 1; k >= s0; k--) {
-        for (int32_t q = sp[k] + threadIdx.x; q < sp[k + 1]; q += TAIL_THREADS) {
+    auto bstep = [&](int32_t k, TailPre<T> &cur, TailPre<T> &nxt) {
+        if (k - 1 >= s0) {
+            const int32_t q = sp[k - 1] + tid;
+            if (q < sp[k]) tail_load(nxt, q, upq + 2 * q, (const int32_t *)nullptr, elim, F, fs, Dinv);
+        }
+        for (int32_t q = sp[k] + tid; q < sp[k + 1]; q += TAIL_THREADS) {
+            if (q != sp[k] + tid) tail_load(cur, q, upq + 2 * q, (const int32_t *)nullptr, elim, F, fs, Dinv);
             const int32_t i = q - Qt;
             T a0 = 0, a1 = 0, a2 = 0;
-            for (int kk = 0; kk < 2; kk++) {
-                const int32_t w = upq[2 * q + kk];
-                if (w < 0) continue;
-                const T *Fm = F + 9 * (2 * (int64_t)q + kk);
-                const int32_t wi = w - Qt;
+            if (cur.a0 >= 0) {
+                const T *Fm = cur.f0;
+                const int32_t wi = cur.a0 - Qt;
+                const T x0 = sv[3 * wi], x1 = sv[3 * wi + 1], x2 = sv[3 * wi + 2];
+                a0 = a0 + (Fm[0] * x0 + Fm[3] * x1 + Fm[6] * x2);
+                a1 = a1 + (Fm[1] * x0 + Fm[4] * x1 + Fm[7] * x2);
+                a2 = a2 + (Fm[2] * x0 + Fm[5] * x1 + Fm[8] * x2);
+            }
+            if (cur.a1 >= 0) {
+                const T *Fm = cur.f1;
+                const int32_t wi = cur.a1 - Qt;
                 const T x0 = sv[3 * wi], x1 = sv[3 * wi + 1], x2 = sv[3 * wi + 2];
                 a0 = a0 + (Fm[0] * x0 + Fm[3] * x1 + Fm[6] * x2);
                 a1 = a1 + (Fm[1] * x0 + Fm[4] * x1 + Fm[7] * x2);
                 a2 = a2 + (Fm[2] * x0 + Fm[5] * x1 + Fm[8] * x2);
             }
             T d0, d1, d2;
-            sym_mv(Dinv + 6 * (int64_t)q, a0, a1, a2, d0, d1, d2);
+            sym_mv(cur.d, a0, a1, a2, d0, d1, d2);
             const T x0 = sv[3 * i] - d0, x1 = sv[3 * i + 1] - d1, x2 = sv[3 * i + 2] - d2;
             sv[3 * i] = x0;
             sv[3 * i + 1] = x1;
@@ -471,12 +675,20 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
             y[3 * (int64_t)q] = x0;
             y[3 * (int64_t)q + 1] = x1;
             y[3 * (int64_t)q + 2] = x2;
-            const int64_t v = elim[q];
+            const int64_t v = cur.b0;
             z[3 * v] = x0;
             z[3 * v + 1] = x1;
             z[3 * v + 2] = x2;
         }
-        __syncthreads();
+        lds_barrier();
+    };
+    {
+        const int32_t q = sp[S - 1] + tid;
+        if (q < sp[S]) tail_load(pa, q, upq + 2 * q, (const int32_t *)nullptr, elim, F, fs, Dinv);
+    }
+    for (int32_t k = S - 1; k >= s0; k -= 2) {
+        bstep(k, pa, pb);
+        if (k - 1 >= s0) bstep(k - 1, pb, pa);
     }
 }
 
@@ -544,23 +756,31 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
     const int32_t *tout = (const int32_t *)M->tout.p, *upq = (const int32_t *)M->up.p;
     const int32_t *dsp = (const int32_t *)M->step_ptr.p;
     const std::vector<int32_t> &sp = M->h_step_ptr;
-    const int32_t S = M->steps, ts = M->tail_step;
-    for (int k = 0; k < ts; k++) {
+    const int32_t S = M->steps, ts = M->tail_step, L = M->light_steps;
+    const int64_t fs = 9 * M->n;   // second plane of F
+    const int32_t *wptr = (const int32_t *)M->light_ptr.p;
+    if (L > 0)
+        k_fwd_light<T><<<M->light_nwg, 256, 0, st>>>(L, M->light_nwg, wptr, elim, in_ptr, tout, F, fs, Dinv, r, y,
+                                                    cs, s);
+    for (int k = L; k < ts; k++) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
         if (q1 > q0)
-            k_fwd_step<T><<<grid_for(q1 - q0, 256), 256, 0, st>>>(q0, q1, elim, in_ptr, tout, F, Dinv, r, y, cs, s);
+            k_fwd_step<T><<<grid_for(q1 - q0, 256), 256, 0, st>>>(q0, q1, elim, in_ptr, tout, F, fs, Dinv, r, y, cs,
+                                                                  s);
     }
     if (ts < S) {
-        size_t lds = (size_t)3 * sizeof(T) * (M->tail_nt + M->tail_ni);
+        size_t lds = tail_lds_bytes(sizeof(T), M->tail_nt, M->tail_ni, S - ts);
         k_tail<T><<<1, TAIL_THREADS, lds, st>>>(ts, S, sp[ts], M->tail_nt, M->tail_ni, dsp, elim, in_ptr,
                                                (const int32_t *)M->tail_iptr.p, (const int32_t *)M->tail_tslot.p,
-                                               upq, F, Dinv, r, cs, y, z, s);
+                                               upq, F, fs, Dinv, r, cs, y, z, s);
     }
-    for (int k = ts - 1; k >= 0; k--) {
+    for (int k = ts - 1; k >= L; k--) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
         if (q1 > q0)
-            k_bwd_step<T><<<grid_for(q1 - q0, 256), 256, 0, st>>>(q0, q1, elim, upq, F, Dinv, y, z, s);
+            k_bwd_step<T><<<grid_for(q1 - q0, 256), 256, 0, st>>>(q0, q1, elim, upq, F, fs, Dinv, y, z, s);
     }
+    if (L > 0)
+        k_bwd_light<T><<<M->light_nwg, 256, 0, st>>>(L, M->light_nwg, wptr, elim, upq, F, fs, Dinv, y, z, s);
     LAUNCH_CHECK(ctx);
     return SGP_OK;
 }
@@ -652,7 +872,7 @@ static int tail_tables(sgp_ctx ctx, sgp_prec M, int64_t n, const int32_t *in_ptr
     SGP_TRY(readback(ctx, &ni, rank + (t1 - t0), 4));
     M->tail_nt = nt;
     M->tail_ni = ni;
-    if ((size_t)3 * 8 * (nt + ni) > (size_t)TAIL_LDS_BYTES)
+    if (tail_lds_bytes(8, nt, ni, M->steps - M->tail_step) > (size_t)TAIL_LDS_BYTES)
         return set_err(ctx, SGP_EINVAL, "factor_tree: tail does not fit in LDS (%d + %d)", nt, ni);
     return SGP_OK;
 }
@@ -675,6 +895,8 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     M->n = n;
     M->schedule = schedule;
     M->have32 = false;
+    M->light_steps = 0;
+    M->light_nwg = 0;
     if (n == 0) {
         M->steps = 0;
         M->h_step_ptr.assign(1, 0);
@@ -686,6 +908,8 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP2], n + 1, &up1));
     const int32_t *parent = (const int32_t *)T->parent.p;
     int32_t S = 0;
+    int32_t light = 0, nwg = 1;   // light steps and their workgroups (CONTRACT only)
+    int32_t *wgv = nullptr;       // workgroup of every light vertex
     if (schedule == SGP_SCHED_LEVEL) {
         k_sched_level<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)T->depth.p, parent, T->max_depth, stepv,
                                                       up0, up1);
@@ -703,6 +927,45 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
         k_contract_init<<<grid_for(n, 256), 256, 0, st>>>(n, parent, par, nch, xch, stepv);
         LAUNCH_CHECK(ctx);
         int64_t done = 0;
+        // rake-only rounds: the light subtrees
+        while (done < n && S < ctx->light_height) {
+            k_rake_select<<<grid_for(n, 256), 256, 0, st>>>(n, S, par, nch, stepv, up0, up1);
+            k_contract_apply<<<grid_for(n, 256), 256, 0, st>>>(n, S, stepv, up0, up1, par, nch, xch, cnt);
+            LAUNCH_CHECK(ctx);
+            S++;
+            SGP_TRY(readback(ctx, hbuf, cnt, 4));
+            if (hbuf[0] <= done) return set_err(ctx, SGP_EINVAL, "factor_tree: raking made no progress");
+            done = hbuf[0];
+        }
+        // a tree raked away completely runs as ordinary steps
+        if (S > 0 && done < n) {
+            light = S;
+            int32_t *ja, *jb, *lcnt, *lstart, *wgr;
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_VAL_A], n + 1, &ja));
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_VAL_B], n + 1, &jb));
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP7], n + 1, &lcnt));
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP8], n + 2, &lstart));
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_KEY_B], n + 1, &wgr));
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP9], n + 1, &wgv));
+            k_light_init<<<grid_for(n, 256), 256, 0, st>>>(n, parent, stepv, ja);
+            // a light vertex is at most `light` - 1 links below its root
+            for (int span = 1; span < light; span *= 2) {
+                k_light_jump<<<grid_for(n, 256), 256, 0, st>>>(n, ja, jb);
+                std::swap(ja, jb);
+            }
+            SGP_TRY(fill_i32(ctx, lcnt, 0, n));
+            k_light_count<<<grid_for(n, 256), 256, 0, st>>>(n, ja, lcnt);
+            k_light_vals<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->perm.p, ja, lcnt, jb);
+            LAUNCH_CHECK(ctx);
+            SGP_TRY(scan_exclusive(ctx, jb, lstart, n));
+            int32_t total;
+            SGP_TRY(readback(ctx, &total, lstart + n, 4));
+            const int32_t cap = std::max(ctx->light_cap, 1);
+            nwg = (total + cap - 1) / cap;
+            k_light_rootwg<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->perm.p, ja, lstart, cap, wgr);
+            k_light_wg<<<grid_for(n, 256), 256, 0, st>>>(n, ja, wgr, wgv);
+            LAUNCH_CHECK(ctx);
+        }
         while (done < n) {
             if (S > 100000) return set_err(ctx, SGP_EINVAL, "factor_tree: contraction did not finish");
             k_contract_select<<<grid_for(n, 256), 256, 0, st>>>(n, S, par, nch, xch, stepv, up0, up1);
@@ -725,10 +988,14 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     SGP_TRY(ensure_t(ctx, M->pos, n + 1, &pos));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP7], (size_t)S + 2, &scnt));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP8], (size_t)S + 2, &sptr));
+    // keys (step, light workgroup); the sort is stable, so the vertices of one
+    // key stay in the internal order
+    if ((int64_t)S * nwg >= ((int64_t)1 << 31)) return set_err(ctx, SGP_EINVAL, "factor_tree: schedule too large");
     int sbits = 1;
-    while ((1 << sbits) < S) sbits++;
+    while (((int64_t)1 << sbits) < (int64_t)S * nwg) sbits++;
     SGP_TRY(copy_order(ctx, M->perm, M->inv, g->perm, g->inv, n));
-    k_stepkeys<<<grid_for(n, 256), 256, 0, st>>>(n, stepv, (const int32_t *)g->perm.p, ka, elim);
+    k_stepkeys<<<grid_for(n, 256), 256, 0, st>>>(n, stepv, light ? wgv : nullptr, (uint32_t)nwg,
+                                               (const int32_t *)g->perm.p, ka, elim);
     LAUNCH_CHECK(ctx);
     SGP_TRY(radix_sort_pairs(ctx, ka, elim, kb, vb, n, sbits));
     int32_t *elim_int;
@@ -736,18 +1003,27 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     k_map_ids<<<grid_for(n, 256), 256, 0, st>>>(n, elim, (const int32_t *)g->inv.p, elim_int);
     k_invperm<<<grid_for(n, 256), 256, 0, st>>>(n, elim, pos);
     (void)scnt;
-    k_step_bounds<<<grid_for(n + 1, 256), 256, 0, st>>>(n, ka, S, sptr);
+    k_step_bounds<<<grid_for(n + 1, 256), 256, 0, st>>>(n, ka, (uint32_t)nwg, S, sptr);
     LAUNCH_CHECK(ctx);
+    M->light_steps = light;
+    M->light_nwg = light ? nwg : 0;
+    if (light) {
+        int32_t *wptr;
+        const int64_t lim = (int64_t)light * nwg;
+        SGP_TRY(ensure_t(ctx, M->light_ptr, (size_t)lim + 2, &wptr));
+        k_light_ptr<<<grid_for(n + 1, 256), 256, 0, st>>>(n, ka, lim, wptr);
+        LAUNCH_CHECK(ctx);
+    }
     M->h_step_ptr.resize(S + 1);
     SGP_TRY(readback(ctx, M->h_step_ptr.data(), sptr, (S + 1) * sizeof(int32_t)));
     int32_t *dsp;
     SGP_TRY(ensure_t(ctx, M->step_ptr, (size_t)S + 2, &dsp));
     HIP_TRY(ctx, hipMemcpyAsync(dsp, sptr, (S + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-    // steps from tail_step on hold at most ctx->tail_max vertices in all (each
-    // has at most two pushes, so 3 g_tail_max slots of LDS always suffice)
+    // steps from tail_step on hold at most ctx->tail_max vertices in all (and
+    // never more than fit in LDS, TAIL_MAX_VERTICES)
     M->tail_step = S;
-    int tmax = std::min(ctx->tail_max, TAIL_LDS_BYTES / (9 * 8));
-    while (M->tail_step > 0 && n - M->h_step_ptr[M->tail_step - 1] <= tmax) M->tail_step--;
+    int tmax = std::min(ctx->tail_max, TAIL_MAX_VERTICES);
+    while (M->tail_step > light && n - M->h_step_ptr[M->tail_step - 1] <= tmax) M->tail_step--;
     // up links and in-lists
     int32_t *upq, *icnt, *in_ptr, *in_src;
     SGP_TRY(ensure_t(ctx, M->up, 2 * n + 2, &upq));
@@ -784,7 +1060,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
         int32_t q0 = M->h_step_ptr[k], q1 = M->h_step_ptr[k + 1];
         if (q1 > q0)
             k_factor_step<<<grid_for(q1 - q0, 128), 128, 0, st>>>(q0, q1, elim, upq, in_ptr, in_src, Pd, E, C, F,
-                                                                  Dinv, status);
+                                                                  9 * n, Dinv, status);
     }
     LAUNCH_CHECK(ctx);
     // push slots of the forward sweep: in-list position of every (q, k)
@@ -842,6 +1118,18 @@ extern "C" int sgp_make_jacobi(sgp_ctx ctx, sgp_bsr A, sgp_prec M)
     int32_t *h = (int32_t *)ctx->pinned;
     SGP_TRY(readback(ctx, h, status, 4));
     if (h[0]) return set_err(ctx, SGP_ENOTSPD, "make_jacobi: a diagonal block is not positive definite");
+    return SGP_OK;
+}
+
+extern "C" int sgp_prec_info(sgp_prec M, int32_t *steps, int32_t *tail_step, int32_t *light_steps,
+                             int32_t *step_sizes)
+{
+    if (!M) return SGP_EINVAL;
+    if (steps) *steps = M->steps;
+    if (tail_step) *tail_step = M->tail_step;
+    if (light_steps) *light_steps = M->light_steps;
+    if (step_sizes && M->kind == PREC_TREE)
+        for (int32_t k = 0; k < M->steps; k++) step_sizes[k] = M->h_step_ptr[k + 1] - M->h_step_ptr[k];
     return SGP_OK;
 }
 

@@ -84,37 +84,55 @@ SGP_DEV void block_partial(double v, int b, double *part, double *sh)
 
 enum { FIN_ALPHA, FIN_RR, FIN_BETA, FIN_RHO, FIN_INIT, FIN_TRUE, FIN_NORM2 };
 
-// fixed-order sum of n partials by 256 threads: thread t owns the interleaved
-// sequence t, t+256, ...; four running sums (positions mod 4 of that
-// sequence) let four loads be in flight, then they are added in a fixed order
-SGP_DEV double sum_partials4(const double *part, int n, double *sh)
+// fixed-order sum of n partials by the FIN_THREADS threads of k_fin: thread t
+// owns the interleaved sequence t, t+FIN_THREADS, ...; eight running sums
+// (positions mod 8 of that sequence) keep eight loads in flight; each wave
+// then folds its lanes by a butterfly and thread 0 adds the waves in order.
+// Result valid in thread 0.
+constexpr int FIN_THREADS = 1024;
+
+SGP_DEV double sum_partials8(const double *part, int n, double *sh)
 {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0, a6 = 0.0, a7 = 0.0;
     int k = threadIdx.x;
-    for (; k + 3 * 256 < n; k += 4 * 256) {
-        double v0 = part[k], v1 = part[k + 256], v2 = part[k + 512], v3 = part[k + 768];
+    constexpr int B = FIN_THREADS;
+    for (; k + 7 * B < n; k += 8 * B) {
+        const double v0 = part[k], v1 = part[k + B], v2 = part[k + 2 * B], v3 = part[k + 3 * B];
+        const double v4 = part[k + 4 * B], v5 = part[k + 5 * B], v6 = part[k + 6 * B], v7 = part[k + 7 * B];
         a0 = a0 + v0;
         a1 = a1 + v1;
         a2 = a2 + v2;
         a3 = a3 + v3;
+        a4 = a4 + v4;
+        a5 = a5 + v5;
+        a6 = a6 + v6;
+        a7 = a7 + v7;
     }
-    for (; k < n; k += 256) a0 = a0 + part[k];
-    return block_sum_256((a0 + a1) + (a2 + a3), sh);
+    for (; k < n; k += B) a0 = a0 + part[k];
+    double v = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
+    for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < FIN_THREADS / 64; w++) r = r + sh[w];
+    __syncthreads();
+    return r;
 }
 
 // Second stage: cluster k = blockIdx.x sums its partials (np values per block,
 // stored as np arrays of stride nblk) and updates its scalars.
-__global__ __launch_bounds__(256) void k_fin(int op, const double *part, int nblk, const int32_t *ifirst,
-                                             const int32_t *inb, PcgScalars *S)
+__global__ __launch_bounds__(FIN_THREADS) void k_fin(int op, const double *part, int nblk, const int32_t *ifirst,
+                                                     const int32_t *inb, PcgScalars *S)
 {
-    __shared__ double sh[256];
+    __shared__ double sh[FIN_THREADS / 64];
     const int k = blockIdx.x;
     PcgScalars *Sc = S + k;
     if (op != FIN_INIT && op != FIN_TRUE && op != FIN_NORM2 && Sc->done) return;
     const int f = ifirst[k], nbk = inb[k];
-    double t0 = sum_partials4(part + f, nbk, sh);
-    double t1 = (op == FIN_INIT || op == FIN_NORM2) ? sum_partials4(part + nblk + f, nbk, sh) : 0.0;
-    double t2 = (op == FIN_INIT) ? sum_partials4(part + 2 * nblk + f, nbk, sh) : 0.0;
+    double t0 = sum_partials8(part + f, nbk, sh);
+    double t1 = (op == FIN_INIT || op == FIN_NORM2) ? sum_partials8(part + nblk + f, nbk, sh) : 0.0;
+    double t2 = (op == FIN_INIT) ? sum_partials8(part + 2 * nblk + f, nbk, sh) : 0.0;
     if (threadIdx.x != 0) return;
     switch (op) {
     case FIN_ALPHA:
@@ -392,7 +410,7 @@ struct Vecs {
 static int fin(sgp_ctx ctx, int op, const double *part, int nblk, const int32_t *ifirst, const int32_t *inb,
                PcgScalars *S, int64_t K)
 {
-    k_fin<<<(unsigned)K, 256, 0, ctx->stream>>>(op, part, nblk, ifirst, inb, S);
+    k_fin<<<(unsigned)K, FIN_THREADS, 0, ctx->stream>>>(op, part, nblk, ifirst, inb, S);
     LAUNCH_CHECK(ctx);
     return SGP_OK;
 }
@@ -829,6 +847,16 @@ extern "C" int sgp_tune(sgp_ctx ctx, const char *key, int32_t value)
         ctx->spmv_waves = value;
         return SGP_OK;
     }
+    if (!strcmp(key, "light_height")) {
+        if (value < 0 || value > 1024) return set_err(ctx, SGP_EINVAL, "tune: light_height must be in [0, 1024]");
+        ctx->light_height = value;
+        return SGP_OK;
+    }
+    if (!strcmp(key, "light_cap")) {
+        if (value < 1 || value > (1 << 20)) return set_err(ctx, SGP_EINVAL, "tune: light_cap must be in [1, 2^20]");
+        ctx->light_cap = value;
+        return SGP_OK;
+    }
     return set_err(ctx, SGP_EINVAL, "tune: unknown key '%s'", key);
 }
 
@@ -839,6 +867,8 @@ extern "C" int sgp_tune_get(sgp_ctx ctx, const char *key, int32_t *value)
     else if (!strcmp(key, "tail_max")) *value = ctx->tail_max;
     else if (!strcmp(key, "graph")) *value = ctx->use_graph;
     else if (!strcmp(key, "spmv_waves")) *value = ctx->spmv_waves;
+    else if (!strcmp(key, "light_height")) *value = ctx->light_height;
+    else if (!strcmp(key, "light_cap")) *value = ctx->light_cap;
     else return set_err(ctx, SGP_EINVAL, "tune_get: unknown key '%s'", key);
     return SGP_OK;
 }

@@ -46,6 +46,8 @@ struct sgp_ctx_ {
     int tail_max = 2200;           // vertices at most left for the one-workgroup tail of the tree sweeps
     int use_graph = 0;             // replay a captured chunk of CG iterations as one hipGraph
     int spmv_waves = 4;            // waves per workgroup of the block-CSR product (2, 4 or 8)
+    int light_height = 0;          // rake rounds whose subtrees the sweeps handle one workgroup each (0: off)
+    int light_cap = 512;           // vertices of such subtrees packed into one workgroup
     hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)
 };
 
@@ -108,6 +110,8 @@ struct sgp_prec_ {
     DevBuf perm, inv;                                   // copy of the graph's internal order
     DevBuf tout, cs;                                    // push slots: in-list position of (q,k); slot values [n_in][3]
     DevBuf step_ptr;                                    // device copy of h_step_ptr
+    int32_t light_steps = 0, light_nwg = 0;             // steps < light_steps: subtrees, one workgroup each
+    DevBuf light_ptr;                                   // [light_steps * light_nwg + 1] first q of (step, workgroup)
     int32_t tail_step = 0;                              // steps >= tail_step run in one workgroup
     int32_t tail_nt = 0, tail_ni = 0;                   // tail vertices, tail-internal push slots
     DevBuf tail_iptr, tail_tslot;                       // per tail target: first internal slot; per (q,k): its slot
@@ -180,6 +184,17 @@ int spmv_f32(sgp_ctx ctx, sgp_bsr A, const float *x, float *y, const PcgScalars 
 
 constexpr int RED_BLOCKS = 512;     // fixed grid of the deterministic reductions
 constexpr int RED_THREADS = 256;
+
+// Workgroup barrier that orders LDS only: waits for the wave's LDS accesses,
+// not for its global loads, so loads whose results are not needed yet stay
+// in flight across it.  For code whose threads exchange data through LDS
+// alone (global memory written before it is not read after it by others).
+SGP_DEV void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // Sum over a 256-thread block in a fixed order; result valid in thread 0.
 SGP_DEV double block_sum_256(double v, double *sh)

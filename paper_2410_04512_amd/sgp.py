@@ -80,6 +80,7 @@ _SIGS = {
     "sgp_euler": (C.c_int, [_vp, _i64, _dbl, _vp, _vp]),
     "sgp_phase_times": (C.c_int, [_vp, C.POINTER(_dbl)]),
     "sgp_tune": (C.c_int, [_vp, C.c_char_p, _i32]),
+    "sgp_prec_info": (C.c_int, [_vp, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), _vp]),
     "sgp_tune_get": (C.c_int, [_vp, C.c_char_p, C.POINTER(_i32)]),
     "sgp_kernel_timing": (C.c_int, [_vp, _i32]),
     "sgp_residual_norm": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(_dbl)]),
@@ -188,6 +189,15 @@ class Prec(_Handle):
         s = C.c_int32()
         lib().sgp_prec_steps(self.h, C.byref(s))
         return s.value
+
+    def info(self):
+        """{"steps", "tail_step", "light_steps", "step_sizes"} of the schedule."""
+        s, t, lt = C.c_int32(), C.c_int32(), C.c_int32()
+        lib().sgp_prec_info(self.h, C.byref(s), C.byref(t), C.byref(lt), None)
+        sizes = (C.c_int32 * max(s.value, 1))()
+        lib().sgp_prec_info(self.h, C.byref(s), C.byref(t), C.byref(lt), sizes)
+        return {"steps": s.value, "tail_step": t.value, "light_steps": lt.value,
+                "step_sizes": [sizes[k] for k in range(s.value)]}
 
 
 class Mpnn(_Handle):

@@ -39,7 +39,9 @@ def _system(ctx, n=20000, seed=11):
 def test_defaults_and_rejections(ctx):
     assert ctx.tune_get("check_every") == 8 and ctx.tune_get("tail_max") == 2200
     assert ctx.tune_get("graph") == 0 and ctx.tune_get("spmv_waves") == 4
-    for key, bad in (("check_every", 0), ("tail_max", -1), ("graph", 2), ("spmv_waves", 3), ("nope", 1)):
+    assert ctx.tune_get("light_height") == 0 and ctx.tune_get("light_cap") == 512
+    for key, bad in (("check_every", 0), ("tail_max", -1), ("graph", 2), ("spmv_waves", 3), ("nope", 1),
+                     ("light_height", -1), ("light_cap", 0)):
         with pytest.raises(P.SgpError):
             ctx.tune(key, bad)
 
@@ -134,3 +136,46 @@ def test_autotuner_choice_solves(ctx):
     v, info = ctx.pcg_solve(A, res["prec"], F)
     assert info["status"] == 0 and info["relres_true"] <= 1.0001e-8
     print({k: v_ for k, v_ in res.items() if k not in ("prec",)})
+
+
+@pytest.mark.parametrize("lh,cap", [(0, 512), (4, 1), (32, 64), (32, 512), (1000, 512)])
+def test_light_subtree_sweeps_match_oracle(ctx, lh, cap):
+    """The rake-only start with its one-workgroup-per-subtree sweeps (and the
+    extremes: off, one vertex per workgroup, a tree raked away completely):
+    the tree solve against the oracle's, FP64 and FP32, and a converged CG."""
+    c, g, A, T = _system(ctx, 6000, 15)
+    ctx.tune("light_height", lh)
+    ctx.tune("light_cap", cap)
+    M = ctx.factor_tree(g, T)
+    og = O.collide(c["pos"], c["radius"])
+    fo = O.tree_factor(og, O.build_tree(og))
+    b = np.random.default_rng(lh).normal(size=(6000, 3))
+    zo = O.tree_solve(fo, b)
+    z = host(ctx.prec_apply(M, to_dev(b)))
+    assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+    F = to_dev(c["force"])
+    v, info = ctx.pcg_solve(A, M, F)
+    assert info["status"] == 0 and info["relres_true"] <= 1.0001e-8
+    check_velocity(host(v), info["iters"], O.assemble(og), c["force"], fo)
+    w, i32 = ctx.pcg_solve(A, M, F, precision="f32ir", inner_rtol=1e-4)
+    assert i32["status"] == 0 and i32["relres_true"] <= 1.0001e-8
+
+
+def test_light_subtrees_batched(ctx):
+    """A batch of separate trees (several of them raked away completely)."""
+    sizes = [3000, 20, 9000, 1, 700]
+    parts = [batched_instance(k + 3, n_override=s) for k, s in enumerate(sizes)]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = to_dev(np.concatenate([p["pos"] for p in parts]))
+    R = to_dev(np.concatenate([p["radius"] for p in parts]))
+    F = np.concatenate([p["force"] for p in parts])
+    g = ctx.collide_batched(off, pos, R)
+    A = ctx.assemble_gamma(g)
+    M = ctx.factor_tree(g, ctx.build_tree(g))
+    v, infos = ctx.pcg_solve_batched(A, M, off, to_dev(F))
+    vh = host(v)
+    for k, p in enumerate(parts):
+        og = O.collide(p["pos"], p["radius"])
+        assert infos[k]["status"] == 0
+        check_velocity(vh[off[k]:off[k + 1]], infos[k]["iters"], O.assemble(og), p["force"],
+                       O.tree_factor(og, O.build_tree(og)))
