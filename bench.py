@@ -34,6 +34,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
+# HBM bytes per launch of the block-CSR product (4 waves per workgroup) on the
+# 1M-cell workload, from two rocprofv3 counter runs of `--kernel-only spmv`:
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a 512 MiB copy
+# read and write 512 MiB (summary and commands under profiles/).  Must be
+# re-measured, or set to None, whenever that kernel changes.
+SPMV_TRAFFIC_1M = 700.8e6
+
 
 def spmv_bytes(n: int, nnzb: int, val_bytes: int = 48) -> int:
     """Algorithmic bytes of one block-CSR product y = Gamma x as the library
@@ -336,7 +343,9 @@ def main():
                    "relres_true": info.get("relres_true")},
         "roofline": {"bound": "hbm", "kernel": "k_spmv (block-CSR product in CG)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": SPMV_TRAFFIC_1M if (args.n == 1_000_000 and ctx.tune_get("spmv_waves") == 4) else None,
+                     "traffic_unit": "B/launch (counters)",
                      "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_spmv_ms,
                      "launches": spmv_launches},
         "phase_ms": {k: v_ / args.steps for k, v_ in phase.items()},

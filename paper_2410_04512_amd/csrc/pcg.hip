@@ -254,29 +254,38 @@ __global__ __launch_bounds__(256) void k_init_p(const T *r, const T *z, T *p, Bl
     block_partial(rz, b, part, sh);
 }
 
+// Element range of a block: the 3 (row1 - row0) values of its rows, walked
+// flat (thread t takes elements t, t + 256, t + 512 of the range), so every
+// load instruction of a wave reads 512 contiguous bytes.
+SGP_DEV int block_elems(const BlockTab &tab, int b, int64_t &e0, int &inst)
+{
+    inst = tab.inst[b];
+    e0 = 3 * (int64_t)tab.row0[b];
+    return 3 * (tab.row1[b] - tab.row0[b]);
+}
+
 // x += alpha p; r -= alpha q; partial of ||r||^2
 template <class T>
 __global__ __launch_bounds__(256) void k_update_xr(T *x, T *r, const T *p, const T *q, BlockTab tab,
                                                    const PcgScalars *S, double *part)
 {
     __shared__ double sh[256];
-    int b = blockIdx.x, inst;
-    int64_t row;
-    bool ok = block_rows(tab, b, row, inst);
+    int inst;
+    int64_t e0;
+    const int ne = block_elems(tab, blockIdx.x, e0, inst);
     const PcgScalars *Sc = S + inst;
     if (Sc->done) return;
     const T alpha = (T)Sc->alpha;
     double rr = 0.0;
-    if (ok) {
-        for (int a = 0; a < 3; a++) {
-            int64_t i = 3 * row + a;
-            x[i] = x[i] + alpha * p[i];
-            T ri = r[i] - alpha * q[i];
-            r[i] = ri;
-            rr = rr + (double)ri * (double)ri;
-        }
+    for (int t = threadIdx.x; t < ne; t += 256) {
+        const int64_t i = e0 + t;
+        const T xi = x[i], pi = p[i], rv = r[i], qi = q[i];
+        x[i] = xi + alpha * pi;
+        const T ri = rv - alpha * qi;
+        r[i] = ri;
+        rr = rr + (double)ri * (double)ri;
     }
-    block_partial(rr, b, part, sh);
+    block_partial(rr, blockIdx.x, part, sh);
 }
 
 // partial of p.q (batched solves: the product itself has no cluster split)
@@ -284,14 +293,13 @@ template <class T>
 __global__ __launch_bounds__(256) void k_pq(const T *p, const T *q, BlockTab tab, const PcgScalars *S, double *part)
 {
     __shared__ double sh[256];
-    int b = blockIdx.x, inst;
-    int64_t row;
-    bool ok = block_rows(tab, b, row, inst);
+    int inst;
+    int64_t e0;
+    const int ne = block_elems(tab, blockIdx.x, e0, inst);
     if (S[inst].done) return;
     double d = 0.0;
-    if (ok)
-        for (int a = 0; a < 3; a++) d = d + (double)p[3 * row + a] * (double)q[3 * row + a];
-    block_partial(d, b, part, sh);
+    for (int t = threadIdx.x; t < ne; t += 256) d = d + (double)p[e0 + t] * (double)q[e0 + t];
+    block_partial(d, blockIdx.x, part, sh);
 }
 
 // partial of r.z
@@ -299,27 +307,26 @@ template <class T>
 __global__ __launch_bounds__(256) void k_rz(const T *r, const T *z, BlockTab tab, const PcgScalars *S, double *part)
 {
     __shared__ double sh[256];
-    int b = blockIdx.x, inst;
-    int64_t row;
-    bool ok = block_rows(tab, b, row, inst);
+    int inst;
+    int64_t e0;
+    const int ne = block_elems(tab, blockIdx.x, e0, inst);
     if (S[inst].done) return;
     double rz = 0.0;
-    if (ok)
-        for (int a = 0; a < 3; a++) rz = rz + (double)r[3 * row + a] * (double)z[3 * row + a];
-    block_partial(rz, b, part, sh);
+    for (int t = threadIdx.x; t < ne; t += 256) rz = rz + (double)r[e0 + t] * (double)z[e0 + t];
+    block_partial(rz, blockIdx.x, part, sh);
 }
 
 template <class T>
 __global__ __launch_bounds__(256) void k_update_p(T *p, const T *z, BlockTab tab, const PcgScalars *S)
 {
-    int b = blockIdx.x, inst;
-    int64_t row;
-    bool ok = block_rows(tab, b, row, inst);
+    int inst;
+    int64_t e0;
+    const int ne = block_elems(tab, blockIdx.x, e0, inst);
     const PcgScalars *Sc = S + inst;
-    if (Sc->done || !ok) return;
+    if (Sc->done) return;
     const T beta = (T)Sc->beta;
-    for (int a = 0; a < 3; a++) {
-        int64_t i = 3 * row + a;
+    for (int t = threadIdx.x; t < ne; t += 256) {
+        const int64_t i = e0 + t;
         p[i] = z[i] + beta * p[i];
     }
 }
