@@ -520,7 +520,7 @@ __global__ __launch_bounds__(256) void k_bwd_light(int32_t L, int32_t nwg, const
 // kernel never writes, global writes are never read back here), so the steps
 // are separated by LDS-only barriers: the next step's prefetched loads stay
 // in flight across them.
-constexpr int TAIL_THREADS = 1024;
+constexpr int TAIL_THREADS = 512;
 constexpr int TAIL_LDS_BYTES = 160 * 1024;
 
 // LDS of the tail: right-hand sides and internal push slots (3 values each),
@@ -534,6 +534,33 @@ static size_t tail_lds_bytes(size_t elem, int64_t nt, int64_t ni, int64_t nsteps
 // holds at least one vertex, so 3 * 8 * 3 nt + 4 (nt + 1) bytes always suffice
 constexpr int TAIL_MAX_VERTICES = (TAIL_LDS_BYTES - 4) / 76;
 
+// The tail's right-hand sides before its first step: r minus the pushes from
+// vertices eliminated before the tail (all finished by the launch boundary).
+// Many small workgroups, one tail vertex per thread, so the dependent loads
+// of different vertices overlap across CUs instead of queueing in the tail's
+// single workgroup.
+template <class T>
+__global__ __launch_bounds__(64) void k_tail_pre(int32_t Qt, int32_t nt, const int32_t *elim, const int32_t *in_ptr,
+                                                 const int32_t *iptr, const T *r, const T *cs, T *tb,
+                                                 const PcgScalars *s)
+{
+    if (s && s->done) return;
+    const int32_t i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= nt) return;
+    const int32_t q = Qt + i;
+    const int64_t v = elim[q];
+    T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
+    const int32_t te = in_ptr[q + 1] - (iptr[i + 1] - iptr[i]);
+    for (int32_t t = in_ptr[q]; t < te; t++) {
+        b0 = b0 - cs[3 * (int64_t)t];
+        b1 = b1 - cs[3 * (int64_t)t + 1];
+        b2 = b2 - cs[3 * (int64_t)t + 2];
+    }
+    tb[3 * (int64_t)i] = b0;
+    tb[3 * (int64_t)i + 1] = b1;
+    tb[3 * (int64_t)i + 2] = b2;
+}
+
 // the per-vertex constants of one tail vertex, loaded a step ahead
 template <class T>
 struct TailPre {
@@ -542,30 +569,46 @@ struct TailPre {
     int32_t b0, b1;   // forward: first and end internal in-slot; backward: vertex id
 };
 
+// The loaders never branch on a value they load: a branch would wait for
+// every load issued before it and turn the prefetch into a stall.  Both F
+// planes are read (the second is zero where there is no second link).
 template <class T>
-SGP_DEV void tail_load(TailPre<T> &p, int32_t q, const int32_t *links, const int32_t *ip, const int32_t *elim,
-                       const T *F, int64_t fs, const T *Dinv)
+SGP_DEV void tail_load_common(TailPre<T> &p, int32_t q, const T *F, int64_t fs, const T *Dinv)
 {
     for (int t = 0; t < 6; t++) p.d[t] = Dinv[6 * (int64_t)q + t];
-    p.a0 = links[0];
-    p.a1 = links[1];
-    if (ip) {
-        p.b0 = ip[0];
-        p.b1 = ip[1];
-    } else {
-        p.b0 = elim[q];
-    }
     for (int t = 0; t < 9; t++) p.f0[t] = F[9 * (int64_t)q + t];
-    if (p.a1 >= 0)
-        for (int t = 0; t < 9; t++) p.f1[t] = F[fs + 9 * (int64_t)q + t];
+    for (int t = 0; t < 9; t++) p.f1[t] = F[fs + 9 * (int64_t)q + t];
+}
+
+// forward: push slots and the internal in-slot range
+template <class T>
+SGP_DEV void tail_load_fwd(TailPre<T> &p, int32_t q, int32_t i, const int32_t *tslot, const int32_t *iptr,
+                           const T *F, int64_t fs, const T *Dinv)
+{
+    p.a0 = tslot[2 * i];
+    p.a1 = tslot[2 * i + 1];
+    p.b0 = iptr[i];
+    p.b1 = iptr[i + 1];
+    tail_load_common(p, q, F, fs, Dinv);
+}
+
+// backward: up-links and the vertex id
+template <class T>
+SGP_DEV void tail_load_bwd(TailPre<T> &p, int32_t q, const int32_t *upq, const int32_t *elim, const T *F,
+                           int64_t fs, const T *Dinv)
+{
+    p.a0 = upq[2 * q];
+    p.a1 = upq[2 * q + 1];
+    p.b0 = elim[q];
+    tail_load_common(p, q, F, fs, Dinv);
 }
 
 template <class T>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, int32_t Qt, int32_t nt, int32_t ni,
                                                        const int32_t *sp_g, const int32_t *elim, const int32_t *in_ptr,
                                                        const int32_t *iptr, const int32_t *tslot, const int32_t *upq,
-                                                       const T *F, int64_t fs, const T *Dinv, const T *r,
-                                                       const T *cs, T *y, T *z, const PcgScalars *s)
+                                                       const T *F, int64_t fs, const T *Dinv, const T *tb, T *y,
+                                                       T *z, const PcgScalars *s)
 {
     extern __shared__ unsigned char lds_raw[];
     T *sv = (T *)lds_raw;
@@ -581,58 +624,59 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
     // and the barrier rather than on memory
     TailPre<T> pa, pb;
     {
-        const int32_t q = sp_g[s0] + tid;
-        if (q < sp_g[s0 + 1]) tail_load(pa, q, tslot + 2 * (q - Qt), iptr + (q - Qt), elim, F, fs, Dinv);
+        const int32_t qe = sp_g[s0 + 1] - 1;
+        const int32_t q = sp_g[s0] + tid < qe ? sp_g[s0] + tid : qe;
+        tail_load_fwd(pa, q, q - Qt, tslot, iptr, F, fs, Dinv);
     }
-    // pre-tail contributions
-    for (int32_t i = tid; i < nt; i += TAIL_THREADS) {
-        const int32_t q = Qt + i;
-        const int64_t v = elim[q];
-        T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
-        const int32_t te = in_ptr[q + 1] - (iptr[i + 1] - iptr[i]);
-        for (int32_t t = in_ptr[q]; t < te; t++) {
-            b0 = b0 - cs[3 * (int64_t)t];
-            b1 = b1 - cs[3 * (int64_t)t + 1];
-            b2 = b2 - cs[3 * (int64_t)t + 2];
-        }
-        sv[3 * i] = b0;
-        sv[3 * i + 1] = b1;
-        sv[3 * i + 2] = b2;
-    }
+    // right-hand sides with the pre-tail contributions (k_tail_pre)
+    for (int32_t i = tid; i < 3 * nt; i += TAIL_THREADS) sv[i] = tb[i];
     lds_barrier();
     // forward steps; the two prefetch buffers swap roles every step (the
-    // loop is unrolled by two so that no buffer is copied)
-    auto fstep = [&](int32_t k, TailPre<T> &cur, TailPre<T> &nxt) {
-        if (k + 1 < S) {
-            const int32_t q = sp[k + 1] + tid;
-            if (q < sp[k + 2]) tail_load(nxt, q, tslot + 2 * (q - Qt), iptr + (q - Qt), elim, F, fs, Dinv);
+    // loop is unrolled by two so that no buffer is copied).  A thread's first
+    // vertex of a step uses the prefetched buffer; further vertices of a big
+    // step load into their own buffer.
+    auto fwd_one = [&](int32_t q, const TailPre<T> &c) {
+        const int32_t i = q - Qt;
+        T b0 = sv[3 * i], b1 = sv[3 * i + 1], b2 = sv[3 * i + 2];
+        for (int32_t j = c.b0; j < c.b1; j++) {
+            b0 = b0 - slot[3 * j];
+            b1 = b1 - slot[3 * j + 1];
+            b2 = b2 - slot[3 * j + 2];
         }
-        for (int32_t q = sp[k] + tid; q < sp[k + 1]; q += TAIL_THREADS) {
-            if (q != sp[k] + tid) tail_load(cur, q, tslot + 2 * (q - Qt), iptr + (q - Qt), elim, F, fs, Dinv);
-            const int32_t i = q - Qt;
-            T b0 = sv[3 * i], b1 = sv[3 * i + 1], b2 = sv[3 * i + 2];
-            for (int32_t j = cur.b0; j < cur.b1; j++) {
-                b0 = b0 - slot[3 * j];
-                b1 = b1 - slot[3 * j + 1];
-                b2 = b2 - slot[3 * j + 2];
-            }
-            T o0, o1, o2;
-            sym_mv(cur.d, b0, b1, b2, o0, o1, o2);
-            sv[3 * i] = o0;
-            sv[3 * i + 1] = o1;
-            sv[3 * i + 2] = o2;
-            if (cur.a0 >= 0) {
-                const T *Fm = cur.f0;
-                slot[3 * cur.a0] = Fm[0] * o0 + Fm[1] * o1 + Fm[2] * o2;
-                slot[3 * cur.a0 + 1] = Fm[3] * o0 + Fm[4] * o1 + Fm[5] * o2;
-                slot[3 * cur.a0 + 2] = Fm[6] * o0 + Fm[7] * o1 + Fm[8] * o2;
-            }
-            if (cur.a1 >= 0) {
-                const T *Fm = cur.f1;
-                slot[3 * cur.a1] = Fm[0] * o0 + Fm[1] * o1 + Fm[2] * o2;
-                slot[3 * cur.a1 + 1] = Fm[3] * o0 + Fm[4] * o1 + Fm[5] * o2;
-                slot[3 * cur.a1 + 2] = Fm[6] * o0 + Fm[7] * o1 + Fm[8] * o2;
-            }
+        T o0, o1, o2;
+        sym_mv(c.d, b0, b1, b2, o0, o1, o2);
+        sv[3 * i] = o0;
+        sv[3 * i + 1] = o1;
+        sv[3 * i + 2] = o2;
+        if (c.a0 >= 0) {
+            slot[3 * c.a0] = c.f0[0] * o0 + c.f0[1] * o1 + c.f0[2] * o2;
+            slot[3 * c.a0 + 1] = c.f0[3] * o0 + c.f0[4] * o1 + c.f0[5] * o2;
+            slot[3 * c.a0 + 2] = c.f0[6] * o0 + c.f0[7] * o1 + c.f0[8] * o2;
+        }
+        if (c.a1 >= 0) {
+            slot[3 * c.a1] = c.f1[0] * o0 + c.f1[1] * o1 + c.f1[2] * o2;
+            slot[3 * c.a1 + 1] = c.f1[3] * o0 + c.f1[4] * o1 + c.f1[5] * o2;
+            slot[3 * c.a1 + 2] = c.f1[6] * o0 + c.f1[7] * o1 + c.f1[8] * o2;
+        }
+    };
+    // The prefetch is issued on every path (a thread without a vertex in the
+    // next step loads the step's last one, the last step reloads its own), so
+    // every path leaves the same loads in flight and the compiler's wait
+    // counts stay partial instead of falling back to waiting for all.
+    auto fstep = [&](int32_t k, TailPre<T> &cur, TailPre<T> &nxt) {
+        {
+            const int32_t kk = k + 1 < S ? k + 1 : k;
+            const int32_t qe = sp[kk + 1] - 1;
+            const int32_t q = sp[kk] + tid < qe ? sp[kk] + tid : qe;
+            tail_load_fwd(nxt, q, q - Qt, tslot, iptr, F, fs, Dinv);
+        }
+        const int32_t q1 = sp[k + 1];
+        int32_t q = sp[k] + tid;
+        if (q < q1) fwd_one(q, cur);
+        for (q += TAIL_THREADS; q < q1; q += TAIL_THREADS) {
+            TailPre<T> extra;
+            tail_load_fwd(extra, q, q - Qt, tslot, iptr, F, fs, Dinv);
+            fwd_one(q, extra);
         }
         lds_barrier();
     };
@@ -641,50 +685,58 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
         if (k + 1 < S) fstep(k + 1, pb, pa);
     }
     // backward steps
-    auto bstep = [&](int32_t k, TailPre<T> &cur, TailPre<T> &nxt) {
-        if (k - 1 >= s0) {
-            const int32_t q = sp[k - 1] + tid;
-            if (q < sp[k]) tail_load(nxt, q, upq + 2 * q, (const int32_t *)nullptr, elim, F, fs, Dinv);
+    auto bwd_one = [&](int32_t q, const TailPre<T> &c) {
+        const int32_t i = q - Qt;
+        T a0 = 0, a1 = 0, a2 = 0;
+        if (c.a0 >= 0) {
+            const int32_t wi = c.a0 - Qt;
+            const T x0 = sv[3 * wi], x1 = sv[3 * wi + 1], x2 = sv[3 * wi + 2];
+            a0 = a0 + (c.f0[0] * x0 + c.f0[3] * x1 + c.f0[6] * x2);
+            a1 = a1 + (c.f0[1] * x0 + c.f0[4] * x1 + c.f0[7] * x2);
+            a2 = a2 + (c.f0[2] * x0 + c.f0[5] * x1 + c.f0[8] * x2);
         }
-        for (int32_t q = sp[k] + tid; q < sp[k + 1]; q += TAIL_THREADS) {
-            if (q != sp[k] + tid) tail_load(cur, q, upq + 2 * q, (const int32_t *)nullptr, elim, F, fs, Dinv);
-            const int32_t i = q - Qt;
-            T a0 = 0, a1 = 0, a2 = 0;
-            if (cur.a0 >= 0) {
-                const T *Fm = cur.f0;
-                const int32_t wi = cur.a0 - Qt;
-                const T x0 = sv[3 * wi], x1 = sv[3 * wi + 1], x2 = sv[3 * wi + 2];
-                a0 = a0 + (Fm[0] * x0 + Fm[3] * x1 + Fm[6] * x2);
-                a1 = a1 + (Fm[1] * x0 + Fm[4] * x1 + Fm[7] * x2);
-                a2 = a2 + (Fm[2] * x0 + Fm[5] * x1 + Fm[8] * x2);
-            }
-            if (cur.a1 >= 0) {
-                const T *Fm = cur.f1;
-                const int32_t wi = cur.a1 - Qt;
-                const T x0 = sv[3 * wi], x1 = sv[3 * wi + 1], x2 = sv[3 * wi + 2];
-                a0 = a0 + (Fm[0] * x0 + Fm[3] * x1 + Fm[6] * x2);
-                a1 = a1 + (Fm[1] * x0 + Fm[4] * x1 + Fm[7] * x2);
-                a2 = a2 + (Fm[2] * x0 + Fm[5] * x1 + Fm[8] * x2);
-            }
-            T d0, d1, d2;
-            sym_mv(cur.d, a0, a1, a2, d0, d1, d2);
-            const T x0 = sv[3 * i] - d0, x1 = sv[3 * i + 1] - d1, x2 = sv[3 * i + 2] - d2;
-            sv[3 * i] = x0;
-            sv[3 * i + 1] = x1;
-            sv[3 * i + 2] = x2;
-            y[3 * (int64_t)q] = x0;
-            y[3 * (int64_t)q + 1] = x1;
-            y[3 * (int64_t)q + 2] = x2;
-            const int64_t v = cur.b0;
-            z[3 * v] = x0;
-            z[3 * v + 1] = x1;
-            z[3 * v + 2] = x2;
+        if (c.a1 >= 0) {
+            const int32_t wi = c.a1 - Qt;
+            const T x0 = sv[3 * wi], x1 = sv[3 * wi + 1], x2 = sv[3 * wi + 2];
+            a0 = a0 + (c.f1[0] * x0 + c.f1[3] * x1 + c.f1[6] * x2);
+            a1 = a1 + (c.f1[1] * x0 + c.f1[4] * x1 + c.f1[7] * x2);
+            a2 = a2 + (c.f1[2] * x0 + c.f1[5] * x1 + c.f1[8] * x2);
+        }
+        T d0, d1, d2;
+        sym_mv(c.d, a0, a1, a2, d0, d1, d2);
+        const T x0 = sv[3 * i] - d0, x1 = sv[3 * i + 1] - d1, x2 = sv[3 * i + 2] - d2;
+        sv[3 * i] = x0;
+        sv[3 * i + 1] = x1;
+        sv[3 * i + 2] = x2;
+        y[3 * (int64_t)q] = x0;
+        y[3 * (int64_t)q + 1] = x1;
+        y[3 * (int64_t)q + 2] = x2;
+        const int64_t v = c.b0;
+        z[3 * v] = x0;
+        z[3 * v + 1] = x1;
+        z[3 * v + 2] = x2;
+    };
+    auto bstep = [&](int32_t k, TailPre<T> &cur, TailPre<T> &nxt) {
+        {
+            const int32_t kk = k - 1 >= s0 ? k - 1 : k;
+            const int32_t qe = sp[kk + 1] - 1;
+            const int32_t q = sp[kk] + tid < qe ? sp[kk] + tid : qe;
+            tail_load_bwd(nxt, q, upq, elim, F, fs, Dinv);
+        }
+        const int32_t q1 = sp[k + 1];
+        int32_t q = sp[k] + tid;
+        if (q < q1) bwd_one(q, cur);
+        for (q += TAIL_THREADS; q < q1; q += TAIL_THREADS) {
+            TailPre<T> extra;
+            tail_load_bwd(extra, q, upq, elim, F, fs, Dinv);
+            bwd_one(q, extra);
         }
         lds_barrier();
     };
     {
-        const int32_t q = sp[S - 1] + tid;
-        if (q < sp[S]) tail_load(pa, q, upq + 2 * q, (const int32_t *)nullptr, elim, F, fs, Dinv);
+        const int32_t qe = sp[S] - 1;
+        const int32_t q = sp[S - 1] + tid < qe ? sp[S - 1] + tid : qe;
+        tail_load_bwd(pa, q, upq, elim, F, fs, Dinv);
     }
     for (int32_t k = S - 1; k >= s0; k -= 2) {
         bstep(k, pa, pb);
@@ -770,9 +822,13 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
     }
     if (ts < S) {
         size_t lds = tail_lds_bytes(sizeof(T), M->tail_nt, M->tail_ni, S - ts);
-        k_tail<T><<<1, TAIL_THREADS, lds, st>>>(ts, S, sp[ts], M->tail_nt, M->tail_ni, dsp, elim, in_ptr,
+        const int32_t nt = M->tail_nt;
+        T *tb = (T *)M->tail_b.p;
+        k_tail_pre<T><<<(nt + 63) / 64, 64, 0, st>>>(sp[ts], nt, elim, in_ptr, (const int32_t *)M->tail_iptr.p, r, cs,
+                                                    tb, s);
+        k_tail<T><<<1, TAIL_THREADS, lds, st>>>(ts, S, sp[ts], nt, M->tail_ni, dsp, elim, in_ptr,
                                                (const int32_t *)M->tail_iptr.p, (const int32_t *)M->tail_tslot.p,
-                                               upq, F, fs, Dinv, r, cs, y, z, s);
+                                               upq, F, fs, Dinv, tb, y, z, s);
     }
     for (int k = ts - 1; k >= L; k--) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
@@ -864,6 +920,8 @@ static int tail_tables(sgp_ctx ctx, sgp_prec M, int64_t n, const int32_t *in_ptr
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP7], (size_t)(t1 - t0) + 2, &rank));
     SGP_TRY(ensure_t(ctx, M->tail_iptr, (size_t)nt + 2, &iptr));
     SGP_TRY(ensure_t(ctx, M->tail_tslot, 2 * (size_t)nt + 2, &tslot));
+    double *tb;
+    SGP_TRY(ensure_t(ctx, M->tail_b, 3 * (size_t)nt + 3, &tb));   // FP64 or FP32 sweeps
     if (t1 > t0) k_tail_flags<<<grid_for(t1 - t0, 256), 256, 0, st>>>(t0, t1, in_src, Qt, flag);
     SGP_TRY(scan_exclusive(ctx, flag, rank, t1 - t0));
     k_tail_tables<<<grid_for(nt + 1, 256), 256, 0, st>>>(Qt, nt, t0, in_ptr, tout, rank, iptr, tslot);

@@ -777,7 +777,7 @@ extern "C" void sgp_mpnn_free(sgp_mpnn M)
     if (!M) return;
     (void)hipDeviceSynchronize();
     release(M->theta); release(M->m1); release(M->m2); release(M->grad); release(M->wbf); release(M->wrow);
-    release(M->act); release(M->efeat); release(M->part);
+    release(M->act); release(M->efeat); release(M->part); release(M->red); release(M->sum); release(M->vq);
     delete M;
 }
 

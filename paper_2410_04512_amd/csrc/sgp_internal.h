@@ -115,6 +115,7 @@ struct sgp_prec_ {
     int32_t tail_step = 0;                              // steps >= tail_step run in one workgroup
     int32_t tail_nt = 0, tail_ni = 0;                   // tail vertices, tail-internal push slots
     DevBuf tail_iptr, tail_tslot;                       // per tail target: first internal slot; per (q,k): its slot
+    DevBuf tail_b;                                      // [tail_nt][3] right-hand sides entering the tail
     DevBuf F32, Dinv32, y32, cs32;                      // FP32 copies for the refinement inner solve
     bool have32 = false;
     DevBuf jdinv;                                       // Jacobi: [n][6]
