@@ -389,10 +389,16 @@ template <class T>
 SGP_DEV void fwd_vertex(int32_t q, const int32_t *elim, const int32_t *in_ptr, const int32_t *tout, const T *F,
                         int64_t fs, const T *Dinv, const T *r, T *y, T *cs)
 {
-    int64_t v = elim[q];
-    T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
+    // every load that does not depend on another is issued first, so the
+    // vertex waits for memory twice (ids, then values) rather than three times
+    const int64_t v = elim[q];
     int32_t t = in_ptr[q];
     const int32_t te = in_ptr[q + 1];
+    const int32_t to0 = tout[2 * q], to1 = tout[2 * q + 1];
+    T d[6], f0[9];
+    for (int k = 0; k < 6; k++) d[k] = Dinv[6 * (int64_t)q + k];
+    for (int k = 0; k < 9; k++) f0[k] = F[9 * (int64_t)q + k];
+    T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
     // slots are independent loads: fetch four at a time, add in order
     for (; t + 4 <= te; t += 4) {
         const T *c = cs + 3 * (int64_t)t;
@@ -408,15 +414,19 @@ SGP_DEV void fwd_vertex(int32_t q, const int32_t *elim, const int32_t *in_ptr, c
         b0 = b0 - c[0]; b1 = b1 - c[1]; b2 = b2 - c[2];
     }
     T o0, o1, o2;
-    sym_mv(Dinv + 6 * (int64_t)q, b0, b1, b2, o0, o1, o2);
+    sym_mv(d, b0, b1, b2, o0, o1, o2);
     y[3 * (int64_t)q] = o0;
     y[3 * (int64_t)q + 1] = o1;
     y[3 * (int64_t)q + 2] = o2;
-    for (int k = 0; k < 2; k++) {
-        int32_t to = tout[2 * q + k];
-        if (to < 0) continue;
-        const T *Fm = F + k * fs + 9 * (int64_t)q;
-        T *c = cs + 3 * (int64_t)to;
+    if (to0 >= 0) {
+        T *c = cs + 3 * (int64_t)to0;
+        c[0] = f0[0] * o0 + f0[1] * o1 + f0[2] * o2;
+        c[1] = f0[3] * o0 + f0[4] * o1 + f0[5] * o2;
+        c[2] = f0[6] * o0 + f0[7] * o1 + f0[8] * o2;
+    }
+    if (to1 >= 0) {
+        const T *Fm = F + fs + 9 * (int64_t)q;
+        T *c = cs + 3 * (int64_t)to1;
         c[0] = Fm[0] * o0 + Fm[1] * o1 + Fm[2] * o2;
         c[1] = Fm[3] * o0 + Fm[4] * o1 + Fm[5] * o2;
         c[2] = Fm[6] * o0 + Fm[7] * o1 + Fm[8] * o2;
@@ -428,23 +438,32 @@ template <class T>
 SGP_DEV void bwd_vertex(int32_t q, const int32_t *elim, const int32_t *upq, const T *F, int64_t fs, const T *Dinv,
                         T *y, T *z)
 {
+    const int32_t w0 = upq[2 * q], w1 = upq[2 * q + 1];
+    const int64_t v = elim[q];
+    T d[6], f0[9];
+    for (int k = 0; k < 6; k++) d[k] = Dinv[6 * (int64_t)q + k];
+    for (int k = 0; k < 9; k++) f0[k] = F[9 * (int64_t)q + k];
+    const T y0 = y[3 * (int64_t)q], y1 = y[3 * (int64_t)q + 1], y2 = y[3 * (int64_t)q + 2];
     T a0 = 0, a1 = 0, a2 = 0;
-    for (int k = 0; k < 2; k++) {
-        int32_t w = upq[2 * q + k];
-        if (w < 0) continue;
-        const T *Fm = F + k * fs + 9 * (int64_t)q;
-        T x0 = y[3 * (int64_t)w], x1 = y[3 * (int64_t)w + 1], x2 = y[3 * (int64_t)w + 2];
+    if (w0 >= 0) {
+        const T x0 = y[3 * (int64_t)w0], x1 = y[3 * (int64_t)w0 + 1], x2 = y[3 * (int64_t)w0 + 2];
+        a0 = a0 + (f0[0] * x0 + f0[3] * x1 + f0[6] * x2);
+        a1 = a1 + (f0[1] * x0 + f0[4] * x1 + f0[7] * x2);
+        a2 = a2 + (f0[2] * x0 + f0[5] * x1 + f0[8] * x2);
+    }
+    if (w1 >= 0) {
+        const T *Fm = F + fs + 9 * (int64_t)q;
+        const T x0 = y[3 * (int64_t)w1], x1 = y[3 * (int64_t)w1 + 1], x2 = y[3 * (int64_t)w1 + 2];
         a0 = a0 + (Fm[0] * x0 + Fm[3] * x1 + Fm[6] * x2);
         a1 = a1 + (Fm[1] * x0 + Fm[4] * x1 + Fm[7] * x2);
         a2 = a2 + (Fm[2] * x0 + Fm[5] * x1 + Fm[8] * x2);
     }
     T d0, d1, d2;
-    sym_mv(Dinv + 6 * (int64_t)q, a0, a1, a2, d0, d1, d2);
-    T x0 = y[3 * (int64_t)q] - d0, x1 = y[3 * (int64_t)q + 1] - d1, x2 = y[3 * (int64_t)q + 2] - d2;
+    sym_mv(d, a0, a1, a2, d0, d1, d2);
+    const T x0 = y0 - d0, x1 = y1 - d1, x2 = y2 - d2;
     y[3 * (int64_t)q] = x0;
     y[3 * (int64_t)q + 1] = x1;
     y[3 * (int64_t)q + 2] = x2;
-    int64_t v = elim[q];
     z[3 * v] = x0;
     z[3 * v + 1] = x1;
     z[3 * v + 2] = x2;
