@@ -255,6 +255,7 @@ static int collide_impl(sgp_ctx ctx, int64_t n, const double *pos, const double 
     if (n >= (int64_t)1 << 30) return set_err(ctx, SGP_EINVAL, "collide: n too large");
     hipStream_t st = ctx->stream;
     g->n = n;
+    g->version = next_graph_version();
     g->n_inst = n_inst;
     g->h_inst_off.assign(h_off, h_off + n_inst + 1);
     int32_t *rowptr;

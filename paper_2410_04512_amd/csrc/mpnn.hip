@@ -14,6 +14,12 @@
 // contractions run on MFMA and the per-edge part stays a bandwidth-bound
 // gather instead of a 2m x 132 GEMM.
 //
+// Order: the network runs in the graph's internal (cell-list) vertex order,
+// so a row's neighbours sit close in memory and the per-edge gathers mostly
+// hit in L2; inputs are gathered and outputs scattered through the graph's
+// permutation at the boundary.  The network is permutation-equivariant, so
+// this changes only the order of roundings in its sums.
+//
 // Precision: FP32 master weights; every GEMM takes BF16 weights and BF16
 // activations with FP32 accumulation (v_mfma_f32_16x16x16_bf16); the per-edge
 // arithmetic uses the BF16-rounded W_c and b_m in FP32.  All reductions (row
@@ -98,6 +104,10 @@ struct sgp_mpnn_ {
     Packed PK = make_packed();
     DevBuf theta, m1, m2, grad, wbf, wrow;   // wrow: BF16-rounded master weights as FP32 (edge arithmetic)
     DevBuf act, efeat, part, red, sum, vq;   // vq: v_hat and Gamma v_hat (FP64, canonical order)
+    DevBuf irow, icol;                      // neighbour lists in the internal order (with efeat)
+    const void *lists_of = nullptr;         // graph and version they were built for
+    uint64_t lists_version = 0;
+    double lists_sW = 0;
     double sF = 1, sV = 1, sW = 1;
     int64_t adam_t = 0;
     int64_t cap_n = 0, cap_e = 0;
@@ -302,28 +312,48 @@ __global__ void k_window(const float *red, int off, int N, int r1, int c0, int c
 
 // ---------------------------------------------------------------- elementwise
 
-__global__ void k_input(int64_t n, const double *F, const double *vp, float sF, float sV, float *x16)
+// node features of internal vertex i = graph vertex perm[i]
+__global__ void k_input(int64_t n, const int32_t *perm, const double *F, const double *vp, float sF, float sV,
+                        float *x16)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int64_t u = perm[i];
     float *x = x16 + 16 * i;
     for (int a = 0; a < 3; a++) {
-        x[a] = (float)(F[3 * i + a] / sF);
-        x[3 + a] = (float)(vp[3 * i + a] / sV);
+        x[a] = (float)(F[3 * u + a] / sF);
+        x[3 + a] = (float)(vp[3 * u + a] / sV);
     }
     for (int a = 6; a < 16; a++) x[a] = 0.f;
 }
 
-// e_p = [w/sW, n], n = (r_i - r_j)/d = -u_e for i < j, +u_e otherwise
-__global__ void k_edge_feat(int64_t n, const int32_t *rowptr, const int32_t *col, const int32_t *ent_edge,
-                            const double4 *wu, float sW, float4 *ef)
+// neighbour count of internal row i
+__global__ void k_int_deg(int64_t n, const int32_t *perm, const int32_t *rowptr, int32_t *deg)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    for (int32_t p = rowptr[i]; p < rowptr[i + 1]; p++) {
-        double4 q = wu[ent_edge[p]];
-        float s = (i < col[p]) ? -1.f : 1.f;
-        ef[p] = make_float4((float)(q.x / sW), s * (float)q.y, s * (float)q.z, s * (float)q.w);
+    const int32_t u = perm[i];
+    deg[i] = rowptr[u + 1] - rowptr[u];
+}
+
+// internal neighbour lists (the graph's row order kept within a row) and the
+// edge features e_p = [w/sW, n], n = (r_i - r_j)/d = -u_e when i < j in the
+// graph's numbering, +u_e otherwise.  16 threads per row, one entry each.
+__global__ void k_int_entries(int64_t n, const int32_t *perm, const int32_t *inv, const int32_t *rowptr,
+                              const int32_t *col, const int32_t *ent_edge, const double4 *wu, float sW,
+                              const int32_t *irow, int32_t *icol, float4 *ef)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t >> 4;
+    if (i >= n) return;
+    const int32_t u = perm[i];
+    const int32_t b = rowptr[u], e = rowptr[u + 1], k0 = irow[i];
+    for (int32_t c = (int32_t)(t & 15); c < e - b; c += 16) {
+        const int32_t j = col[b + c];
+        const double4 q = wu[ent_edge[b + c]];
+        const float sg = (u < j) ? -1.f : 1.f;
+        icol[k0 + c] = inv[j];
+        ef[k0 + c] = make_float4((float)(q.x / sW), sg * (float)q.y, sg * (float)q.z, sg * (float)q.w);
     }
 }
 
@@ -359,28 +389,52 @@ __global__ void k_add64(int64_t n, const float *a, int64_t lda, const float *b, 
 
 // ---------------------------------------------------------------- messages (one wave per row, lane = feature)
 
+// A row's entries are taken MSG_BATCH at a time: their column ids and edge
+// features first, then all their neighbour gathers, then the arithmetic in
+// entry order -- so a wave waits for memory twice per batch instead of twice
+// per entry.  The summation order is the entry order, as in a plain loop.
+constexpr int MSG_BATCH = 8;
+
 __global__ __launch_bounds__(256) void k_msg_fwd(int64_t n, const int32_t *rowptr, const int32_t *col,
                                                  const float4 *ef, const float *PQ, const float *bm,
                                                  const float *Wc, float *agg)
 {
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     const int f = threadIdx.x & 63;
     if (i >= n) return;
     const float Pi = PQ[i * 128 + f] + bm[f];
     const float w0 = Wc[f], w1 = Wc[64 + f], w2 = Wc[128 + f], w3 = Wc[192 + f];
     float acc = 0.f;
-    for (int32_t p = rowptr[i]; p < rowptr[i + 1]; p++) {
-        const int64_t j = col[p];
-        const float4 e = ef[p];
-        const float z = Pi + PQ[j * 128 + 64 + f] + (e.x * w0 + e.y * w1 + e.z * w2 + e.w * w3);
-        acc += fmaxf(z, 0.f);
+    const int32_t re = rowptr[i + 1];
+    for (int32_t p = rowptr[i]; p < re; p += MSG_BATCH) {
+        const int cnt = re - p < MSG_BATCH ? re - p : MSG_BATCH;
+        int64_t jj[MSG_BATCH];
+        float4 ee[MSG_BATCH];
+        float qv[MSG_BATCH];
+#pragma unroll
+        for (int u = 0; u < MSG_BATCH; u++)
+            if (u < cnt) {
+                jj[u] = col[p + u];
+                ee[u] = ef[p + u];
+            }
+#pragma unroll
+        for (int u = 0; u < MSG_BATCH; u++)
+            if (u < cnt) qv[u] = PQ[jj[u] * 128 + 64 + f];
+#pragma unroll
+        for (int u = 0; u < MSG_BATCH; u++)
+            if (u < cnt) {
+                const float4 e = ee[u];
+                const float z = Pi + qv[u] + (e.x * w0 + e.y * w1 + e.z * w2 + e.w * w3);
+                acc += fmaxf(z, 0.f);
+            }
     }
     agg[i * 64 + f] = acc;
 }
 
 // dP_i = sum over row i of dz_p, dz_p = da_i [z_p > 0]; per-workgroup partials
 // of e_p^T dz_p (4 x 64).  The grid is fixed (at most MSG_BWD_GRID workgroups);
-// workgroup b walks the 4-row blocks b, b + grid, ... in order.
+// workgroup b (in XCD-contiguous order) walks its own contiguous run of 4-row
+// blocks in order.
 constexpr int MSG_BWD_GRID = 1024;
 
 __global__ __launch_bounds__(256) void k_msg_bwd_p(int64_t n, const int32_t *rowptr, const int32_t *col,
@@ -393,22 +447,42 @@ __global__ __launch_bounds__(256) void k_msg_bwd_p(int64_t n, const int32_t *row
     const float w0 = Wc[f], w1 = Wc[64 + f], w2 = Wc[128 + f], w3 = Wc[192 + f];
     const float bmf = bm[f];
     float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
-    for (int64_t blk = blockIdx.x; blk * 4 < n; blk += gridDim.x) {
+    const int64_t nblk = (n + 3) / 4, per = (nblk + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * per;
+    const int64_t b1 = b0 + per < nblk ? b0 + per : nblk;
+    for (int64_t blk = b0; blk < b1; blk++) {
         const int64_t i = blk * 4 + wv;
         if (i >= n) continue;
         const float Pi = PQ[i * 128 + f] + bmf;
         const float dai = da[i * ldda + f];
         float dp = 0.f;
-        for (int32_t p = rowptr[i]; p < rowptr[i + 1]; p++) {
-            const int64_t j = col[p];
-            const float4 e = ef[p];
-            const float z = Pi + PQ[j * 128 + 64 + f] + (e.x * w0 + e.y * w1 + e.z * w2 + e.w * w3);
-            const float dz = z > 0.f ? dai : 0.f;
-            dp += dz;
-            g0 += e.x * dz;
-            g1 += e.y * dz;
-            g2 += e.z * dz;
-            g3 += e.w * dz;
+        const int32_t re = rowptr[i + 1];
+        for (int32_t p = rowptr[i]; p < re; p += MSG_BATCH) {
+            const int cnt = re - p < MSG_BATCH ? re - p : MSG_BATCH;
+            int64_t jj[MSG_BATCH];
+            float4 ee[MSG_BATCH];
+            float qv[MSG_BATCH];
+#pragma unroll
+            for (int u = 0; u < MSG_BATCH; u++)
+                if (u < cnt) {
+                    jj[u] = col[p + u];
+                    ee[u] = ef[p + u];
+                }
+#pragma unroll
+            for (int u = 0; u < MSG_BATCH; u++)
+                if (u < cnt) qv[u] = PQ[jj[u] * 128 + 64 + f];
+#pragma unroll
+            for (int u = 0; u < MSG_BATCH; u++)
+                if (u < cnt) {
+                    const float4 e = ee[u];
+                    const float z = Pi + qv[u] + (e.x * w0 + e.y * w1 + e.z * w2 + e.w * w3);
+                    const float dz = z > 0.f ? dai : 0.f;
+                    dp += dz;
+                    g0 += e.x * dz;
+                    g1 += e.y * dz;
+                    g2 += e.z * dz;
+                    g3 += e.w * dz;
+                }
         }
         dPQ[i * 128 + f] = dp;
     }
@@ -427,24 +501,45 @@ __global__ __launch_bounds__(256) void k_msg_bwd_q(int64_t n, const int32_t *row
                                                    const float4 *ef, const float *PQ, const float *bm,
                                                    const float *Wc, const float *da, int64_t ldda, float *dPQ)
 {
-    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t j = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     const int f = threadIdx.x & 63;
     if (j >= n) return;
     const float Qj = PQ[j * 128 + 64 + f];
     const float w0 = Wc[f], w1 = Wc[64 + f], w2 = Wc[128 + f], w3 = Wc[192 + f];
+    const float bmf = bm[f];
     float dq = 0.f;
-    for (int32_t p = rowptr[j]; p < rowptr[j + 1]; p++) {
-        const int64_t i = col[p];
-        const float4 e = ef[p];
-        const float z = (PQ[i * 128 + f] + bm[f]) + Qj + (e.x * w0 - e.y * w1 - e.z * w2 - e.w * w3);
-        dq += z > 0.f ? da[i * ldda + f] : 0.f;
+    const int32_t re = rowptr[j + 1];
+    for (int32_t p = rowptr[j]; p < re; p += MSG_BATCH) {
+        const int cnt = re - p < MSG_BATCH ? re - p : MSG_BATCH;
+        int64_t ii[MSG_BATCH];
+        float4 ee[MSG_BATCH];
+        float pv[MSG_BATCH], dv[MSG_BATCH];
+#pragma unroll
+        for (int u = 0; u < MSG_BATCH; u++)
+            if (u < cnt) {
+                ii[u] = col[p + u];
+                ee[u] = ef[p + u];
+            }
+#pragma unroll
+        for (int u = 0; u < MSG_BATCH; u++)
+            if (u < cnt) {
+                pv[u] = PQ[ii[u] * 128 + f];
+                dv[u] = da[ii[u] * ldda + f];
+            }
+#pragma unroll
+        for (int u = 0; u < MSG_BATCH; u++)
+            if (u < cnt) {
+                const float4 e = ee[u];
+                const float z = (pv[u] + bmf) + Qj + (e.x * w0 - e.y * w1 - e.z * w2 - e.w * w3);
+                dq += z > 0.f ? dv[u] : 0.f;
+            }
     }
     dPQ[j * 128 + 64 + f] = dq;
 }
 
 // loss = mean (out - v/sV)^2 over 3n values; dout16 = 2 (out - v/sV)/(3n) in columns 0..2
-__global__ __launch_bounds__(256) void k_loss(int64_t n, const float *out16, const double *v, float sV, float *dout16,
-                                              double *part)
+__global__ __launch_bounds__(256) void k_loss(int64_t n, const int32_t *perm, const float *out16, const double *v,
+                                              float sV, float *dout16, double *part)
 {
     __shared__ double sh[256];
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -453,7 +548,7 @@ __global__ __launch_bounds__(256) void k_loss(int64_t n, const float *out16, con
         for (int a = 0; a < 16; a++) {
             float d = 0.f;
             if (a < 3) {
-                d = out16[16 * i + a] - (float)(v[3 * i + a] / sV);
+                d = out16[16 * i + a] - (float)(v[3 * (int64_t)perm[i] + a] / sV);
                 s += (double)d * (double)d;
                 d = 2.f * d / (float)(3 * n);
             }
@@ -499,13 +594,15 @@ __global__ void k_sum3(const double *part, int np, double *s)
 }
 
 // d loss / d out = 2 sV (Gamma v_hat - F) / (v . F) in columns 0..2
-__global__ void k_energy_dout(int64_t n, const double *q, const double *F, double sV, const double *s, float *dout16)
+__global__ void k_energy_dout(int64_t n, const int32_t *perm, const double *q, const double *F, double sV,
+                              const double *s, float *dout16)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int64_t u = perm[i];
     const double scale = 2.0 * sV / s[2];
     for (int a = 0; a < 16; a++)
-        dout16[16 * i + a] = a < 3 ? (float)(scale * (q[3 * i + a] - F[3 * i + a])) : 0.f;
+        dout16[16 * i + a] = a < 3 ? (float)(scale * (q[3 * u + a] - F[3 * u + a])) : 0.f;
 }
 
 // x0 = the guess with the lower energy 0.5 x' Gamma x - x' F (ties keep v_prev)
@@ -526,11 +623,12 @@ __global__ void k_sum_double(const double *part, int np, double *out)
     if (threadIdx.x == 0) *out = s;
 }
 
-__global__ void k_output(int64_t n, const float *out16, double sV, double *vhat)
+__global__ void k_output(int64_t n, const int32_t *perm, const float *out16, double sV, double *vhat)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    for (int a = 0; a < 3; a++) vhat[3 * i + a] = sV * (double)out16[16 * i + a];
+    const int64_t u = perm[i];
+    for (int a = 0; a < 3; a++) vhat[3 * u + a] = sV * (double)out16[16 * i + a];
 }
 
 __global__ void k_adam(int64_t np, float *theta, const float *g, float *m1, float *m2, float lr, float b1, float b2,
@@ -650,15 +748,32 @@ int prepare(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, const double *F, const double 
     const int64_t n = g->n, ne = 2 * g->m;
     float *base;
     float4 *ef;
+    int32_t *irow, *icol, *deg;
     SGP_TRY(ensure_t(ctx, M->act, (size_t)act_floats(n) + 64, &base));
     SGP_TRY(ensure_t(ctx, M->efeat, (size_t)ne + 1, &ef));
+    SGP_TRY(ensure_t(ctx, M->irow, (size_t)n + 2, &irow));
+    SGP_TRY(ensure_t(ctx, M->icol, (size_t)ne + 1, &icol));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_DEG], (size_t)n + 2, &deg));
     A = carve(base, n);
     hipStream_t st = ctx->stream;
-    k_input<<<grid_for(n, 256), 256, 0, st>>>(n, F, vp, (float)M->sF, (float)M->sV, A.x16);
-    k_edge_feat<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->rowptr.p, (const int32_t *)g->col.p,
-                                                  (const int32_t *)g->ent_edge.p, (const double4 *)g->wu.p,
-                                                  (float)M->sW, ef);
+    const int32_t *perm = (const int32_t *)g->perm.p;
+    k_input<<<grid_for(n, 256), 256, 0, st>>>(n, perm, F, vp, (float)M->sF, (float)M->sV, A.x16);
     LAUNCH_CHECK(ctx);
+    // the internal neighbour lists depend only on the graph and sW: rebuilt
+    // when either changed since the last call
+    if (M->lists_of != g || M->lists_version != g->version || M->lists_sW != M->sW) {
+        k_int_deg<<<grid_for(n, 256), 256, 0, st>>>(n, perm, (const int32_t *)g->rowptr.p, deg);
+        LAUNCH_CHECK(ctx);
+        SGP_TRY(scan_exclusive(ctx, deg, irow, n));
+        k_int_entries<<<grid_for(16 * n, 256), 256, 0, st>>>(n, perm, (const int32_t *)g->inv.p,
+                                                             (const int32_t *)g->rowptr.p, (const int32_t *)g->col.p,
+                                                             (const int32_t *)g->ent_edge.p, (const double4 *)g->wu.p,
+                                                             (float)M->sW, irow, icol, ef);
+        LAUNCH_CHECK(ctx);
+        M->lists_of = g;
+        M->lists_version = g->version;
+        M->lists_sW = M->sW;
+    }
     return SGP_OK;
 }
 
@@ -670,7 +785,7 @@ int forward(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, Act &A)
     const float *wr = (const float *)M->wrow.p;
     const Layout &L = M->L;
     const Packed &PK = M->PK;
-    const int32_t *rowptr = (const int32_t *)g->rowptr.p, *col = (const int32_t *)g->col.p;
+    const int32_t *rowptr = (const int32_t *)M->irow.p, *col = (const int32_t *)M->icol.p;   // internal order
     const float4 *ef = (const float4 *)M->efeat.p;
     SGP_TRY(gemm(ctx, A.x16, 16, W + PK.in16, A.pre0, 64, n, 16, 64, wr + L.b_in, 0));
     k_relu<<<grid_for(64 * n, 256), 256, 0, st>>>(64 * n, A.pre0, A.h[0]);
@@ -697,7 +812,7 @@ int backward(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, Act &A)
     const Layout &L = M->L;
     const Packed &PK = M->PK;
     float *G = (float *)M->grad.p;
-    const int32_t *rowptr = (const int32_t *)g->rowptr.p, *col = (const int32_t *)g->col.p;
+    const int32_t *rowptr = (const int32_t *)M->irow.p, *col = (const int32_t *)M->icol.p;   // internal order
     const float4 *ef = (const float4 *)M->efeat.p;
     float *S;
     // output layer: W_out rows 0..63 x columns 0..2 of h^T dout, b_out = column sums
@@ -778,6 +893,7 @@ extern "C" void sgp_mpnn_free(sgp_mpnn M)
     (void)hipDeviceSynchronize();
     release(M->theta); release(M->m1); release(M->m2); release(M->grad); release(M->wbf); release(M->wrow);
     release(M->act); release(M->efeat); release(M->part); release(M->red); release(M->sum); release(M->vq);
+    release(M->irow); release(M->icol);
     delete M;
 }
 
@@ -824,7 +940,7 @@ extern "C" int sgp_mpnn_forward(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, const doub
     Act A;
     SGP_TRY(prepare(ctx, M, g, F, vprev, A));
     SGP_TRY(forward(ctx, M, g, A));
-    k_output<<<grid_for(g->n, 256), 256, 0, ctx->stream>>>(g->n, A.out16, M->sV, vhat);
+    k_output<<<grid_for(g->n, 256), 256, 0, ctx->stream>>>(g->n, (const int32_t *)g->perm.p, A.out16, M->sV, vhat);
     LAUNCH_CHECK(ctx);
     return SGP_OK;
 }
@@ -857,7 +973,7 @@ static int loss_grad(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gm, const dou
         double *part;
         const int nb = (int)grid_for(n, 256);
         SGP_TRY(ensure_t(ctx, ctx->ws[WS_PART], (size_t)nb + 8, &part));
-        k_loss<<<nb, 256, 0, ctx->stream>>>(n, A.out16, v, (float)M->sV, A.dout16, part);
+        k_loss<<<nb, 256, 0, ctx->stream>>>(n, (const int32_t *)g->perm.p, A.out16, v, (float)M->sV, A.dout16, part);
         k_sum_double<<<1, 256, 0, ctx->stream>>>(part, nb, part + nb);
         LAUNCH_CHECK(ctx);
         SGP_TRY(backward(ctx, M, g, A));
@@ -870,10 +986,11 @@ static int loss_grad(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gm, const dou
     SGP_TRY(ensure_t(ctx, M->vq, (size_t)6 * n + 8, &vh));
     double *q = vh + 3 * n, *sd = vh + 6 * n;
     ds = sd;
-    k_output<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, A.out16, M->sV, vh);
+    k_output<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, (const int32_t *)g->perm.p, A.out16, M->sV, vh);
     LAUNCH_CHECK(ctx);
     SGP_TRY(energy_sums(ctx, M, Gm, vh, q, F, v, ds));
-    k_energy_dout<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, q, F, M->sV, ds, A.dout16);
+    k_energy_dout<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, (const int32_t *)g->perm.p, q, F, M->sV, ds,
+                                                            A.dout16);
     LAUNCH_CHECK(ctx);
     SGP_TRY(backward(ctx, M, g, A));
     SGP_TRY(readback(ctx, s, ds, sizeof s));
@@ -935,7 +1052,7 @@ extern "C" int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr
     double *vh;
     SGP_TRY(ensure_t(ctx, M->vq, (size_t)6 * n + 8, &vh));
     double *q = vh + 3 * n, *s = vh + 6 * n;   // s: 3 sums of the guess, 3 of v_prev (8 doubles reserved)
-    k_output<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, A.out16, M->sV, vh);
+    k_output<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, (const int32_t *)g->perm.p, A.out16, M->sV, vh);
     LAUNCH_CHECK(ctx);
     SGP_TRY(energy_sums(ctx, M, Gm, vh, q, F, nullptr, s));
     SGP_TRY(energy_sums(ctx, M, Gm, vprev, q, F, nullptr, s + 3));

@@ -70,6 +70,7 @@ enum {
 // internal i <-> caller perm[i], caller u <-> internal inv[u].
 struct sgp_graph_ {
     int64_t n = 0, m = 0, n_inst = 1;
+    uint64_t version = 0;   // changes whenever a collide rewrites the graph
     DevBuf rowptr, col, ent_edge, ei, ej, wu, inst_off, inst_of;
     DevBuf perm, inv;
     std::vector<int64_t> h_inst_off;
@@ -176,6 +177,7 @@ int tail_setup_attr(sgp_ctx ctx);
 int bsr_make32(sgp_ctx ctx, sgp_bsr A);
 int bsr_prepare(sgp_ctx ctx, sgp_bsr A);
 int spmv_blocks(sgp_ctx ctx, sgp_bsr A);
+uint64_t next_graph_version();   // process-wide, strictly increasing
 int spmv_f64(sgp_ctx ctx, sgp_bsr A, const double *x, double *y, const PcgScalars *S, double *part, int mode);
 int spmv_f32(sgp_ctx ctx, sgp_bsr A, const float *x, float *y, const PcgScalars *S, double *part, int mode);
 

@@ -3,8 +3,16 @@
 // deterministic; no floating-point atomics anywhere.
 #include "sgp_internal.h"
 
+#include <atomic>
+
 #include <algorithm>
 #include <cstring>
+
+uint64_t next_graph_version()
+{
+    static std::atomic<uint64_t> counter{0};
+    return ++counter;
+}
 
 int set_err(sgp_ctx ctx, int code, const char *fmt, ...)
 {
