@@ -4,9 +4,9 @@
 // of the block Laplacian): for a contact e = (i, j) with overlap w and unit
 // vector u, W_e = w (g_par u u^T + g_perp (I - u u^T)) (eq.
 // cell_cell_friction); Gamma_ij = Gamma_ji = -W_e; Gamma_ii = g_med I plus
-// the W_e of i's contacts.  Row i of the block matrix is row i of the
-// neighbour list with the diagonal block inserted in column order, so the
-// block layout needs no sort: block k of row i sits at rowptr[i] + i + k'.
+// the W_e of i's contacts.  In the caller's numbering (the export), row i of
+// the block matrix is row i of the neighbour list with the diagonal block
+// inserted in column order, so block k of row i sits at rowptr[i] + i + k'.
 // The diagonal sum runs over the neighbours in ascending column order, with
 // the same operation order as the definition (no fused multiply-add), so the
 // assembled values are reproducible bit for bit.
@@ -43,56 +43,45 @@ __global__ void k_int_degree(int64_t n, const int32_t *rowptr, const int32_t *pe
     d[i] = rowptr[u + 1] - rowptr[u] + 1;
 }
 
-// Gamma in the internal order.  The diagonal block is summed over the caller
-// row in ascending neighbour order (the definition's order); the blocks are
-// then written in ascending internal column order.
+// Gamma in the internal order.  Row i (caller row perm[i]) holds the
+// off-diagonal blocks -W_e in the caller row's neighbour order, then the
+// diagonal block, summed over the same neighbours in the same (the
+// definition's) order.  Any fixed block order within a row serves the
+// product, which sums a row's blocks in storage order; this one needs no
+// per-row sort.  ASM_LANES threads share a row, one block each, so a wave's
+// stores land in runs of consecutive blocks; the row's first thread also
+// forms the diagonal block.
+constexpr int ASM_LANES = 16;
+
 __global__ void k_assemble(int64_t n, const int32_t *rowptr, const int32_t *col, const int32_t *ent_edge,
                            const double4 *wu, const int32_t *perm, const int32_t *inv, double gpar, double gperp,
                            double gmed, const int32_t *brow, int32_t *bcol, double *val, int32_t *diagpos)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / ASM_LANES;
+    const int c0 = (int)(t % ASM_LANES);
     if (i >= n) return;
     const int32_t u = perm[i];
     const int32_t b = rowptr[u], e = rowptr[u + 1];
-    int32_t jin[64], pin[64];
-    double D[9];
-    for (int t = 0; t < 9; t++) D[t] = (t % 4 == 0) ? gmed : 0.0;
-    int cnt = 0;
-    for (int32_t p = b; p < e; p++) {
-        double4 q = wu[ent_edge[p]];
-        double W[9];
-        friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
-        for (int t = 0; t < 9; t++) D[t] = D[t] + W[t];
-        // insertion by internal column
-        int32_t jj = inv[col[p]];
-        int c = cnt++;
-        while (c > 0 && jin[c - 1] > jj) {
-            jin[c] = jin[c - 1];
-            pin[c] = pin[c - 1];
-            c--;
-        }
-        jin[c] = jj;
-        pin[c] = p;
-    }
-    int64_t k = brow[i];
-    bool placed = false;
-    for (int c = 0; c < cnt; c++) {
-        if (!placed && jin[c] > (int32_t)i) {
-            put_sym(val, k, D);
-            bcol[k] = (int32_t)i;
-            diagpos[i] = (int32_t)k;
-            k++;
-            placed = true;
-        }
-        double4 q = wu[ent_edge[pin[c]]];
+    const int64_t k0 = brow[i];
+    for (int32_t c = c0; c < e - b; c += ASM_LANES) {
+        const double4 q = wu[ent_edge[b + c]];
         double W[9], B[9];
         friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
-        for (int t = 0; t < 9; t++) B[t] = -W[t];
-        put_sym(val, k, B);
-        bcol[k] = jin[c];
-        k++;
+        for (int x = 0; x < 9; x++) B[x] = -W[x];
+        put_sym(val, k0 + c, B);
+        bcol[k0 + c] = inv[col[b + c]];
     }
-    if (!placed) {
+    if (c0 == 0) {
+        double D[9];
+        for (int x = 0; x < 9; x++) D[x] = (x % 4 == 0) ? gmed : 0.0;
+        for (int32_t p = b; p < e; p++) {
+            const double4 q = wu[ent_edge[p]];
+            double W[9];
+            friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
+            for (int x = 0; x < 9; x++) D[x] = D[x] + W[x];
+        }
+        const int64_t k = k0 + (e - b);
         put_sym(val, k, D);
         bcol[k] = (int32_t)i;
         diagpos[i] = (int32_t)k;
@@ -168,7 +157,7 @@ extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_DEG], n + 1, &deg));
     k_int_degree<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->rowptr.p, (const int32_t *)g->perm.p, deg);
     SGP_TRY(scan_exclusive(ctx, deg, brow, n));
-    k_assemble<<<grid_for(n, 128), 128, 0, st>>>(n, (const int32_t *)g->rowptr.p, (const int32_t *)g->col.p,
+    k_assemble<<<grid_for(ASM_LANES * n, 256), 256, 0, st>>>(n, (const int32_t *)g->rowptr.p, (const int32_t *)g->col.p,
                                                  (const int32_t *)g->ent_edge.p, (const double4 *)g->wu.p,
                                                  (const int32_t *)g->perm.p, (const int32_t *)g->inv.p, g_par,
                                                  g_perp, g_med, brow, bcol, val, dpos);

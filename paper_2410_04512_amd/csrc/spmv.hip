@@ -14,7 +14,7 @@
 // [w * WAVE_BLOCKS, (w + 1) * WAVE_BLOCKS); it walks their blocks 64 at a time
 // (one block per lane), multiplies against the gathered x, parks the three
 // products per block in LDS, and then one lane per row adds the row's products
-// in column order.  A row is never split between waves, so every row sum has
+// in storage order.  A row is never split between waves, so every row sum has
 // one fixed order and the product is bitwise reproducible.
 #include "sgp_internal.h"
 
@@ -120,7 +120,11 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_sym(const int32_t *__r
             block_product(a, (int)(k - base), v, x[3 * j], x[3 * j + 1], x[3 * j + 2]);
         }
     }
-    __syncthreads();
+    // a wave reads back only what it wrote itself: a wave-scope LDS fence
+    // suffices (the other waves of the workgroup need not wait)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
     double d = 0.0;
     for (int32_t row = r_lo + lane; row < r_hi; row += 64) {
         const int s0 = (int)(rowptr[row] - base), s1 = (int)(rowptr[row + 1] - base);

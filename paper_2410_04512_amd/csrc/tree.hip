@@ -39,18 +39,48 @@ __global__ void k_bv_clear_best(unsigned long long *bestw, int32_t *beste, int64
     }
 }
 
+// atomicMax of val into slot[key] for the lanes with ok set.  Lanes of a wave
+// that share a key are combined first (up to four keys, each led by the lowest
+// pending lane); the rest use their own atomic.  Late rounds send most edges
+// of a wave to one or two large components, whose slots would otherwise take
+// one atomic per edge.  Must be called by every lane of the wave.
+SGP_DEV void wave_max_by_key(unsigned long long *slot, int32_t key, unsigned long long val, bool ok)
+{
+    const int lane = threadIdx.x & 63;
+    bool pending = ok;
+    for (int it = 0; it < 4; it++) {
+        const unsigned long long mask = __ballot(pending);
+        if (mask == 0ull) return;
+        const int leader = __ffsll((long long)mask) - 1;
+        const int32_t k = __shfl(key, leader, 64);
+        const bool mine = pending && key == k;
+        unsigned long long v = mine ? val : 0ull;
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long w = __shfl_xor(v, o, 64);
+            v = v > w ? v : w;
+        }
+        if (lane == leader && v > slot[k]) atomicMax(&slot[k], v);
+        pending = pending && !mine;
+    }
+    if (pending && val > slot[key]) atomicMax(&slot[key], val);
+}
+
 __global__ void k_bv_maxw(const int32_t *act, int64_t na, const int32_t *ei, const int32_t *ej, const double4 *wu,
                           const int32_t *comp, unsigned long long *bestw)
 {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= na) return;
-    int32_t e = act[k];
-    int32_t a = comp[ei[e]], b = comp[ej[e]];
-    if (a == b) return;
-    unsigned long long wb = (unsigned long long)__double_as_longlong(wu[e].x);
-    // test before the atomic: a component's slot is hot once it is large
-    if (wb > bestw[a]) atomicMax(&bestw[a], wb);
-    if (wb > bestw[b]) atomicMax(&bestw[b], wb);
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t a = 0, b = 0;
+    unsigned long long wb = 0ull;
+    bool ok = false;
+    if (k < na) {
+        const int32_t e = act[k];
+        a = comp[ei[e]];
+        b = comp[ej[e]];
+        ok = a != b;
+        wb = (unsigned long long)__double_as_longlong(wu[e].x);
+    }
+    wave_max_by_key(bestw, a, wb, ok);
+    wave_max_by_key(bestw, b, wb, ok);
 }
 
 __global__ void k_bv_mine(const int32_t *act, int64_t na, const int32_t *ei, const int32_t *ej, const double4 *wu,
