@@ -34,20 +34,24 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
-# HBM bytes per launch of the block-CSR product (4 waves per workgroup) on the
-# 1M-cell workload, from two rocprofv3 counter runs of `--kernel-only spmv`:
+# HBM bytes per launch of the product (4 waves per workgroup) on the 1M-cell
+# workload, per form, from two rocprofv3 counter runs of `--kernel-only spmv`:
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a 512 MiB copy
 # read and write 512 MiB (summary and commands under profiles/).  Must be
 # re-measured, or set to None, whenever that kernel changes.
-SPMV_TRAFFIC_1M = 700.8e6
+SPMV_TRAFFIC_1M = {0: 700.8e6, 1: None}
 
 
-def spmv_bytes(n: int, nnzb: int, val_bytes: int = 48) -> int:
-    """Algorithmic bytes of one block-CSR product y = Gamma x as the library
-    stores Gamma: every block's 6 distinct entries (the blocks are symmetric,
-    48 B in FP64) and its column index once, the row pointers once, x once,
-    y once."""
-    return nnzb * (val_bytes + 4) + 4 * (n + 1) + 24 * n + 24 * n
+def spmv_bytes(n: int, nnzb: int, form: int = 1, val_bytes: int = 48) -> int:
+    """Algorithmic bytes of one product y = Gamma x as the library forms it.
+    Blocks (form 0): every block's 6 distinct entries (the blocks are
+    symmetric, 48 B in FP64) and its column index once.  Edge form (form 1):
+    every off-diagonal entry's (w, u) (32 B) and column once, every diagonal
+    block's 6 entries once.  Both: the row pointers once, x once, y once."""
+    if form == 0:
+        return nnzb * (val_bytes + 4) + 4 * (n + 1) + 24 * n + 24 * n
+    ne = nnzb - n
+    return ne * (32 + 4) + n * 48 + 4 * (n + 1) + 24 * n + 24 * n
 
 
 def cpu_baseline(c, gpu_iters: int, sample_iters: int = 10):
@@ -246,6 +250,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--extras", default="jacobi,small,mixed,batched,learned",
                     help="comma list of extra workloads to run after the headline")
+    ap.add_argument("--spmv-form", type=int, choices=[0, 1], default=None,
+                    help="product form: 0 stored 3x3 blocks, 1 contacts' (w, u) (the library default)")
     ap.add_argument("--kernel-only", choices=["spmv"], default=None,
                     help="build the system once, then run only the named kernel (for counter runs)")
     args = ap.parse_args()
@@ -264,6 +270,8 @@ def main():
     dev = lambda a: torch.as_tensor(a).to("cuda")  # noqa: E731
     pos, R, F = dev(c["pos"]), dev(c["radius"]), dev(c["force"])
     ctx = P.Context()
+    if args.spmv_form is not None:
+        ctx.tune("spmv_form", args.spmv_form)
     g, A, T, M = P.Graph(ctx), P.Bsr(ctx), P.Tree(ctx), P.Prec(ctx)
     v = torch.zeros_like(F)
     info = {}
@@ -296,8 +304,9 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 20
-        print(json.dumps({"kernel": "k_spmv_sym", "copy_bytes": 2 * src.numel() * 8, "api_call_avg_ms": ms,
-                          "bytes_per_launch": spmv_bytes(n, nnzb),
+        print(json.dumps({"kernel": "k_spmv_edge" if ctx.tune_get("spmv_form") else "k_spmv_sym",
+                          "copy_bytes": 2 * src.numel() * 8, "api_call_avg_ms": ms,
+                          "bytes_per_launch": spmv_bytes(n, nnzb, ctx.tune_get("spmv_form")),
                           "note": "api_call_avg_ms includes the two permutations of sgp_spmv; the kernel alone is in the trace"}), flush=True)
         ctx.close()
         return
@@ -322,7 +331,8 @@ def main():
     _, nnzb = A.size()
     nt, n_roots, max_depth = T.size()
     avg_spmv_ms = spmv_ms / max(spmv_launches, 1)
-    bytes_spmv = spmv_bytes(n, nnzb)
+    form = ctx.tune_get("spmv_form")
+    bytes_spmv = spmv_bytes(n, nnzb, form)
     achieved = bytes_spmv / (avg_spmv_ms * 1e-3) / 1e9
     out = {
         "metric": "Gamma v=F solves/s @1M cells, relres 1e-8 (tree-PCG, FP64)",
@@ -341,10 +351,11 @@ def main():
                    "n_cells": n, "contacts": m, "nnzb": nnzb, "tree_depth": max_depth, "trees": n_roots,
                    "schedule": args.schedule, "elim_steps": M.steps(), "cg_iters": info.get("iters"),
                    "relres_true": info.get("relres_true")},
-        "roofline": {"bound": "hbm", "kernel": "k_spmv (block-CSR product in CG)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_spmv_edge (Gamma p from contacts, in CG)" if form else "k_spmv_sym (block-CSR product, in CG)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": SPMV_TRAFFIC_1M if (args.n == 1_000_000 and ctx.tune_get("spmv_waves") == 4) else None,
+                     "traffic": SPMV_TRAFFIC_1M[form] if (args.n == 1_000_000 and ctx.tune_get("spmv_waves") == 4) else None,
                      "traffic_unit": "B/launch (counters)",
                      "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_spmv_ms,
                      "launches": spmv_launches},

@@ -306,8 +306,11 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
  *                 afterwards)
  *  "graph"        1: each chunk of check_every CG iterations is captured once
  *                 per solve into a hipGraph and replayed (default 0)
- *  "spmv_waves"   waves per workgroup of the block-CSR product: 2, 4 or 8
- *                 (default 4)
+ *  "spmv_waves"   waves per workgroup of the product: 2, 4 or 8 (default 4)
+ *  "spmv_form"    how the CG forms Gamma p: 0 from the stored 3x3 blocks,
+ *                 1 from the contacts, D_i p_i - sum_j W_ij p_j with
+ *                 W_ij p = w (g_perp p + (g_par - g_perp)(u.p) u) (default 1;
+ *                 fewer bytes per product; sgp_spmv uses it too)
  *  "light_height" CONTRACT schedule: the first light_height rounds remove
  *                 leaves only; the subtrees they remove are swept by one
  *                 workgroup each, in one launch per sweep (0..1024, 0 = plain
@@ -317,8 +320,8 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
  *                 (1..2^20, default 512)
  * Unknown keys or values out of range give SGP_EINVAL.  check_every, tail_max
  * and graph leave every result bitwise unchanged; spmv_waves changes only the
- * summation order of the p.q dot product; light_height and light_cap change
- * the elimination order of the tree factor, so results agree to rounding. */
+ * summation order of the p.q dot product; spmv_form, light_height and
+ * light_cap change the order of roundings, so results agree to rounding. */
 int sgp_tune(sgp_ctx ctx, const char *key, int32_t value);
 /* Current value of a knob (host output). */
 int sgp_tune_get(sgp_ctx ctx, const char *key, int32_t *value);

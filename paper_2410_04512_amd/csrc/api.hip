@@ -85,6 +85,7 @@ extern "C" void sgp_bsr_free(sgp_bsr A)
     (void)hipDeviceSynchronize();
     release(A->rowptr); release(A->bcol); release(A->val); release(A->val32); release(A->diagpos);
     release(A->wrow); release(A->perm); release(A->inv);
+    release(A->ecol); release(A->ew); release(A->dg); release(A->ew32); release(A->dg32); release(A->ewrow);
     delete A;
 }
 

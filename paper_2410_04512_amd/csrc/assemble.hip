@@ -55,7 +55,8 @@ constexpr int ASM_LANES = 16;
 
 __global__ void k_assemble(int64_t n, const int32_t *rowptr, const int32_t *col, const int32_t *ent_edge,
                            const double4 *wu, const int32_t *perm, const int32_t *inv, double gpar, double gperp,
-                           double gmed, const int32_t *brow, int32_t *bcol, double *val, int32_t *diagpos)
+                           double gmed, const int32_t *brow, int32_t *bcol, double *val, int32_t *diagpos,
+                           int32_t *ecol, double *ew, double *dg)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = t / ASM_LANES;
@@ -70,7 +71,16 @@ __global__ void k_assemble(int64_t n, const int32_t *rowptr, const int32_t *col,
         friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
         for (int x = 0; x < 9; x++) B[x] = -W[x];
         put_sym(val, k0 + c, B);
-        bcol[k0 + c] = inv[col[b + c]];
+        const int32_t jc = inv[col[b + c]];
+        bcol[k0 + c] = jc;
+        // edge form: entry k0 + c - i
+        const int64_t ke = k0 + c - i;
+        double *g = ew + (ke >> 6) * 256 + (ke & 63);
+        g[0] = q.x;
+        g[64] = q.y;
+        g[128] = q.z;
+        g[192] = q.w;
+        ecol[ke] = jc;
     }
     if (c0 == 0) {
         double D[9];
@@ -83,6 +93,7 @@ __global__ void k_assemble(int64_t n, const int32_t *rowptr, const int32_t *col,
         }
         const int64_t k = k0 + (e - b);
         put_sym(val, k, D);
+        put_sym(dg, i, D);
         bcol[k] = (int32_t)i;
         diagpos[i] = (int32_t)k;
     }
@@ -137,12 +148,16 @@ extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double
     A->n = n;
     A->nnzb = nnzb;
     A->have32 = false;
-    int32_t *brow, *bcol, *dpos, *deg;
-    double *val;
+    int32_t *brow, *bcol, *dpos, *deg, *ecol;
+    double *val, *ew, *dg;
+    const int64_t ne = 2 * g->m;
     SGP_TRY(ensure_t(ctx, A->rowptr, n + 1, &brow));
     SGP_TRY(ensure_t(ctx, A->bcol, nnzb + 1, &bcol));
     SGP_TRY(ensure_t(ctx, A->val, sym_group_size(nnzb) + 8, &val));
     SGP_TRY(ensure_t(ctx, A->diagpos, n + 1, &dpos));
+    SGP_TRY(ensure_t(ctx, A->ecol, ne + 1, &ecol));
+    SGP_TRY(ensure_t(ctx, A->ew, edge_group_size(ne) + 8, &ew));
+    SGP_TRY(ensure_t(ctx, A->dg, sym_group_size(n) + 8, &dg));
     A->src = g;
     A->gpar = g_par;
     A->gperp = g_perp;
@@ -152,15 +167,17 @@ extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double
         return fill_i32(ctx, brow, 0, 1);
     }
     SGP_TRY(copy_order(ctx, A->perm, A->inv, g->perm, g->inv, n));
-    // zero the padding of the last group (read by no row, kept finite)
+    // zero the padding of the last groups (read by no row, kept finite)
     SGP_TRY(fill_f64(ctx, val + (sym_group_size(nnzb) - 384), 0.0, 384));
+    SGP_TRY(fill_f64(ctx, dg + (sym_group_size(n) - 384), 0.0, 384));
+    if (ne > 0) SGP_TRY(fill_f64(ctx, ew + (edge_group_size(ne) - 256), 0.0, 256));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_DEG], n + 1, &deg));
     k_int_degree<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->rowptr.p, (const int32_t *)g->perm.p, deg);
     SGP_TRY(scan_exclusive(ctx, deg, brow, n));
     k_assemble<<<grid_for(ASM_LANES * n, 256), 256, 0, st>>>(n, (const int32_t *)g->rowptr.p, (const int32_t *)g->col.p,
                                                  (const int32_t *)g->ent_edge.p, (const double4 *)g->wu.p,
                                                  (const int32_t *)g->perm.p, (const int32_t *)g->inv.p, g_par,
-                                                 g_perp, g_med, brow, bcol, val, dpos);
+                                                 g_perp, g_med, brow, bcol, val, dpos, ecol, ew, dg);
     LAUNCH_CHECK(ctx);
     SGP_TRY(bsr_prepare(ctx, A));
     if (ctx->ev[3]) {
@@ -212,6 +229,13 @@ int bsr_make32(sgp_ctx ctx, sgp_bsr A)
     int64_t len = sym_group_size(A->nnzb);
     SGP_TRY(ensure_t(ctx, A->val32, len + 8, &v32));
     if (A->nnzb > 0) k_round32<<<grid_for(len, 256), 256, 0, ctx->stream>>>(len, (const double *)A->val.p, v32);
+    // the edge form: (w, u) and the diagonal blocks, rounded once
+    float *e32, *d32;
+    const int64_t elen = edge_group_size(A->nnzb - A->n), dlen = sym_group_size(A->n);
+    SGP_TRY(ensure_t(ctx, A->ew32, elen + 8, &e32));
+    SGP_TRY(ensure_t(ctx, A->dg32, dlen + 8, &d32));
+    if (elen > 0) k_round32<<<grid_for(elen, 256), 256, 0, ctx->stream>>>(elen, (const double *)A->ew.p, e32);
+    if (A->n > 0) k_round32<<<grid_for(dlen, 256), 256, 0, ctx->stream>>>(dlen, (const double *)A->dg.p, d32);
     LAUNCH_CHECK(ctx);
     A->have32 = true;
     return SGP_OK;

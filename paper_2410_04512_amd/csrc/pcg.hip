@@ -854,6 +854,11 @@ extern "C" int sgp_tune(sgp_ctx ctx, const char *key, int32_t value)
         ctx->spmv_waves = value;
         return SGP_OK;
     }
+    if (!strcmp(key, "spmv_form")) {
+        if (value != 0 && value != 1) return set_err(ctx, SGP_EINVAL, "tune: spmv_form must be 0 or 1");
+        ctx->spmv_form = value;
+        return SGP_OK;
+    }
     if (!strcmp(key, "light_height")) {
         if (value < 0 || value > 1024) return set_err(ctx, SGP_EINVAL, "tune: light_height must be in [0, 1024]");
         ctx->light_height = value;
@@ -875,6 +880,7 @@ extern "C" int sgp_tune_get(sgp_ctx ctx, const char *key, int32_t *value)
     else if (!strcmp(key, "graph")) *value = ctx->use_graph;
     else if (!strcmp(key, "spmv_waves")) *value = ctx->spmv_waves;
     else if (!strcmp(key, "light_height")) *value = ctx->light_height;
+    else if (!strcmp(key, "spmv_form")) *value = ctx->spmv_form;
     else if (!strcmp(key, "light_cap")) *value = ctx->light_cap;
     else return set_err(ctx, SGP_EINVAL, "tune_get: unknown key '%s'", key);
     return SGP_OK;

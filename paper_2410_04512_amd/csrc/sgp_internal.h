@@ -46,6 +46,7 @@ struct sgp_ctx_ {
     int tail_max = 2200;           // vertices at most left for the one-workgroup tail of the tree sweeps
     int use_graph = 0;             // replay a captured chunk of CG iterations as one hipGraph
     int spmv_waves = 4;            // waves per workgroup of the block-CSR product (2, 4 or 8)
+    int spmv_form = 1;             // product from the 3x3 blocks (0) or from the contacts' (w, u) (1)
     int light_height = 0;          // rake rounds whose subtrees the sweeps handle one workgroup each (0: off)
     int light_cap = 512;           // vertices of such subtrees packed into one workgroup
     hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)
@@ -85,11 +86,18 @@ struct sgp_bsr_ {
     sgp_graph src = nullptr;                    // graph it was assembled from (canonical export)
     double gpar = 0, gperp = 0, gmed = 0;
     DevBuf wrow;          // first row of every product wave
+    // edge form of the same matrix (internal order): the off-diagonal entries
+    // of row i are rowptr[i] - i + c (c < degree; the diagonal block is the
+    // last of every block row); per entry its column and (w, u) in 64-entry
+    // groups of 4 planes; the diagonal blocks as 64-row groups of 6 planes
+    DevBuf ecol, ew, dg, ew32, dg32, ewrow;
+    int64_t enwaves = 0;
     int64_t nwaves = 0;
     bool have32 = false;
 };
 
 inline int64_t sym_group_size(int64_t nnzb) { return ((nnzb + 63) / 64) * 384; }   // values incl. padding
+inline int64_t edge_group_size(int64_t ne) { return ((ne + 63) / 64) * 256; }     // (w, u) incl. padding
 
 struct sgp_tree_ {
     int64_t n = 0, nt = 0, n_roots = 0;

@@ -16,12 +16,24 @@
 // products per block in LDS, and then one lane per row adds the row's products
 // in storage order.  A row is never split between waves, so every row sum has
 // one fixed order and the product is bitwise reproducible.
+//
+// Edge form (the default for the CG): the same product from the contacts
+// themselves, q_i = D_i p_i - sum_j W_ij p_j with
+// W_ij p = w (g_perp p + (g_par - g_perp) (u . p) u) (eq. cell_cell_friction),
+// so an off-diagonal entry costs its (w, u) and column (36 bytes) instead of a
+// 6-entry block and column (52 bytes); the diagonal blocks D_i sit in their
+// own 64-row groups.  Same work split and fixed row-sum order as above; the
+// rows' first entries decide the wave (one extra wave owns trailing rows
+// without entries).
 #include "sgp_internal.h"
 
 constexpr int WAVE_GROUPS = 2;                       // 64-block groups per wave
 constexpr int WAVE_BLOCKS = 64 * WAVE_GROUPS;
 constexpr int ROW_MAX = 65;                          // blocks per row at most (max_deg 64 + diagonal)
 constexpr int ACC_SLOTS = WAVE_BLOCKS + ROW_MAX;     // product slots per wave
+constexpr int EDGE_GROUPS = 4;                       // 64-entry groups per wave, edge form
+constexpr int EDGE_BLOCKS = 64 * EDGE_GROUPS;
+constexpr int EDGE_SLOTS = EDGE_BLOCKS + ROW_MAX;
 
 // first row of every wave: wrow[w] = first row whose first block is >= w * WAVE_BLOCKS
 __global__ void k_wave_rows(const int32_t *rowptr, int64_t n, int64_t nwaves, int32_t *wrow)
@@ -37,14 +49,35 @@ __global__ void k_wave_rows(const int32_t *rowptr, int64_t n, int64_t nwaves, in
     wrow[w] = (int32_t)lo;
 }
 
+// the same for the edge form: row i's first entry is rowptr[i] - i
+__global__ void k_wave_rows_edge(const int32_t *rowptr, int64_t n, int64_t nwaves, int32_t *wrow)
+{
+    int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w > nwaves) return;
+    int64_t b0 = w * EDGE_BLOCKS;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)rowptr[mid] - mid < b0) lo = mid + 1; else hi = mid;
+    }
+    wrow[w] = (int32_t)lo;
+}
+
 int bsr_prepare(sgp_ctx ctx, sgp_bsr A)
 {
     int64_t nw = (A->nnzb + WAVE_BLOCKS - 1) / WAVE_BLOCKS;
     int32_t *wrow;
     SGP_TRY(ensure_t(ctx, A->wrow, nw + 2, &wrow));
     A->nwaves = nw;
+    const int64_t ne = A->nnzb - A->n;
+    const int64_t enw = ne / EDGE_BLOCKS + 1;   // the last wave also owns rows whose first entry is ne
+    int32_t *ewrow;
+    SGP_TRY(ensure_t(ctx, A->ewrow, enw + 2, &ewrow));
+    A->enwaves = A->n > 0 ? enw : 0;
     if (A->n > 0) {
         k_wave_rows<<<grid_for(nw + 1, 256), 256, 0, ctx->stream>>>((const int32_t *)A->rowptr.p, A->n, nw, wrow);
+        k_wave_rows_edge<<<grid_for(enw + 1, 256), 256, 0, ctx->stream>>>((const int32_t *)A->rowptr.p, A->n, enw,
+                                                                         ewrow);
         LAUNCH_CHECK(ctx);
     }
     return SGP_OK;
@@ -154,20 +187,154 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_sym(const int32_t *__r
     }
 }
 
-int spmv_blocks(sgp_ctx ctx, sgp_bsr A) { return (int)((A->nwaves + ctx->spmv_waves - 1) / ctx->spmv_waves); }
+template <class T>
+SGP_DEV void edge_product(T *a, int s, const T *e, T x0, T x1, T x2, T gpar, T gperp)
+{
+    const T w = e[0], u0 = e[1], u1 = e[2], u2 = e[3];
+    const T c = (gpar - gperp) * ((u0 * x0 + u1 * x1) + u2 * x2);
+    a[3 * s] = w * (gperp * x0 + c * u0);
+    a[3 * s + 1] = w * (gperp * x1 + c * u1);
+    a[3 * s + 2] = w * (gperp * x2 + c * u2);
+}
+
+template <class T, int SPMV_WAVES>
+__global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_edge(const int32_t *__restrict__ rowptr,
+                                                               const int32_t *__restrict__ ecol,
+                                                               const T *__restrict__ ew, const T *__restrict__ dg,
+                                                               T gpar, T gperp, const T *__restrict__ x,
+                                                               T *__restrict__ y, const int32_t *__restrict__ wrow,
+                                                               int64_t nwaves, const PcgScalars *S, double *part,
+                                                               int mode)
+{
+    __shared__ T acc[SPMV_WAVES][3 * EDGE_SLOTS];
+    __shared__ double sh[SPMV_WAVES];
+    if (S && S->done) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t w = lb * SPMV_WAVES + wv;
+    int32_t r_lo = 0, r_hi = 0;
+    int64_t kb = 0, ke = 0;
+    const int64_t base = w * EDGE_BLOCKS;
+    if (w < nwaves) {
+        r_lo = wrow[w];
+        r_hi = wrow[w + 1];
+        kb = (int64_t)rowptr[r_lo] - r_lo;
+        ke = (int64_t)rowptr[r_hi] - r_hi;
+    }
+    T *a = acc[wv];
+    // a lane's first row: its diagonal block and x, loaded before anything
+    // waits (rows past the first 64 of a wave load theirs in the row loop)
+    const int32_t row0 = r_lo + lane;
+    const bool has_row = row0 < r_hi;
+    T dr[6], pr[3];
+    if (has_row) {
+        const T *dgr = dg + ((int64_t)row0 >> 6) * 384 + (row0 & 63);
+        for (int t = 0; t < 6; t++) dr[t] = dgr[64 * t];
+        for (int t = 0; t < 3; t++) pr[t] = x[3 * (int64_t)row0 + t];
+    }
+    // the wave's 64-entry groups: all (w, u) and columns first, then the
+    // gathers, then the products
+    const T *gb = ew + (base >> 6) * 256 + lane;
+    bool on[EDGE_GROUPS];
+    T e[EDGE_GROUPS][4], xv[EDGE_GROUPS][3];
+    int64_t j[EDGE_GROUPS];
+#pragma unroll
+    for (int q = 0; q < EDGE_GROUPS; q++) {
+        const int64_t k = base + 64 * q + lane;
+        on[q] = k >= kb && k < ke;
+        j[q] = 0;
+        if (on[q]) {
+            for (int t = 0; t < 4; t++) e[q][t] = gb[256 * q + 64 * t];
+            j[q] = ecol[k];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < EDGE_GROUPS; q++)
+        if (on[q])
+            for (int t = 0; t < 3; t++) xv[q][t] = x[3 * j[q] + t];
+#pragma unroll
+    for (int q = 0; q < EDGE_GROUPS; q++)
+        if (on[q]) edge_product(a, 64 * q + lane, e[q], xv[q][0], xv[q][1], xv[q][2], gpar, gperp);
+    // entries of the last row that run past the groups
+    for (int64_t c = base + EDGE_BLOCKS; c < ke; c += 64) {
+        const int64_t k = c + lane;
+        if (k < ke) {
+            const T *g = ew + (c >> 6) * 256 + lane;
+            T ee[4];
+            for (int t = 0; t < 4; t++) ee[t] = g[64 * t];
+            const int64_t jj = ecol[k];
+            edge_product(a, (int)(k - base), ee, x[3 * jj], x[3 * jj + 1], x[3 * jj + 2], gpar, gperp);
+        }
+    }
+    // a wave reads back only what it wrote itself
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    double d = 0.0;
+    for (int32_t row = row0; row < r_hi; row += 64) {
+        const int s0 = (int)((int64_t)rowptr[row] - row - base), s1 = (int)((int64_t)rowptr[row + 1] - (row + 1) - base);
+        if (row != row0) {
+            const T *dgr = dg + ((int64_t)row >> 6) * 384 + (row & 63);
+            for (int t = 0; t < 6; t++) dr[t] = dgr[64 * t];
+            for (int t = 0; t < 3; t++) pr[t] = x[3 * (int64_t)row + t];
+        }
+        const T p0 = pr[0], p1 = pr[1], p2 = pr[2];
+        T y0 = dr[0] * p0 + dr[1] * p1 + dr[2] * p2;
+        T y1 = dr[1] * p0 + dr[3] * p1 + dr[4] * p2;
+        T y2 = dr[2] * p0 + dr[4] * p1 + dr[5] * p2;
+        for (int s = s0; s < s1; s++) {
+            y0 -= a[3 * s];
+            y1 -= a[3 * s + 1];
+            y2 -= a[3 * s + 2];
+        }
+        y[3 * (int64_t)row] = y0;
+        y[3 * (int64_t)row + 1] = y1;
+        y[3 * (int64_t)row + 2] = y2;
+        if (mode) d = d + ((double)p0 * (double)y0 + (double)p1 * (double)y1 + (double)p2 * (double)y2);
+    }
+    if (mode) {
+        for (int o = 32; o > 0; o >>= 1) d = d + __shfl_xor(d, o, 64);
+        if (lane == 0) sh[wv] = d;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = sh[0];
+            for (int k = 1; k < SPMV_WAVES; k++) t = t + sh[k];
+            part[lb] = t;
+        }
+    }
+}
+
+int spmv_blocks(sgp_ctx ctx, sgp_bsr A)
+{
+    const int64_t nw = ctx->spmv_form ? A->enwaves : A->nwaves;
+    return (int)((nw + ctx->spmv_waves - 1) / ctx->spmv_waves);
+}
 
 template <class T>
-static int spmv_launch(sgp_ctx ctx, sgp_bsr A, const T *val, const T *x, T *y, const PcgScalars *S, double *part,
-                       int mode)
+static int spmv_launch(sgp_ctx ctx, sgp_bsr A, const T *val, const T *ew, const T *dg, const T *x, T *y,
+                       const PcgScalars *S, double *part, int mode)
 {
-    if (A->nwaves == 0) return SGP_OK;
+    const int64_t nw = ctx->spmv_form ? A->enwaves : A->nwaves;
+    if (nw == 0) return SGP_OK;
     const int nb = spmv_blocks(ctx, A);
+    hipStream_t st = ctx->stream;
     const int32_t *rp = (const int32_t *)A->rowptr.p, *bc = (const int32_t *)A->bcol.p, *wr = (const int32_t *)A->wrow.p;
-    switch (ctx->spmv_waves) {
-    case 2: k_spmv_sym<T, 2><<<nb, 128, 0, ctx->stream>>>(rp, bc, val, x, y, wr, A->nwaves, S, part, mode); break;
-    case 4: k_spmv_sym<T, 4><<<nb, 256, 0, ctx->stream>>>(rp, bc, val, x, y, wr, A->nwaves, S, part, mode); break;
-    case 8: k_spmv_sym<T, 8><<<nb, 512, 0, ctx->stream>>>(rp, bc, val, x, y, wr, A->nwaves, S, part, mode); break;
-    default: return set_err(ctx, SGP_EINVAL, "spmv: unsupported waves per workgroup %d", ctx->spmv_waves);
+    if (ctx->spmv_form) {
+        const int32_t *ec = (const int32_t *)A->ecol.p, *ewr = (const int32_t *)A->ewrow.p;
+        const T gp = (T)A->gpar, gq = (T)A->gperp;
+        switch (ctx->spmv_waves) {
+        case 2: k_spmv_edge<T, 2><<<nb, 128, 0, st>>>(rp, ec, ew, dg, gp, gq, x, y, ewr, nw, S, part, mode); break;
+        case 4: k_spmv_edge<T, 4><<<nb, 256, 0, st>>>(rp, ec, ew, dg, gp, gq, x, y, ewr, nw, S, part, mode); break;
+        case 8: k_spmv_edge<T, 8><<<nb, 512, 0, st>>>(rp, ec, ew, dg, gp, gq, x, y, ewr, nw, S, part, mode); break;
+        default: return set_err(ctx, SGP_EINVAL, "spmv: unsupported waves per workgroup %d", ctx->spmv_waves);
+        }
+    } else {
+        switch (ctx->spmv_waves) {
+        case 2: k_spmv_sym<T, 2><<<nb, 128, 0, st>>>(rp, bc, val, x, y, wr, nw, S, part, mode); break;
+        case 4: k_spmv_sym<T, 4><<<nb, 256, 0, st>>>(rp, bc, val, x, y, wr, nw, S, part, mode); break;
+        case 8: k_spmv_sym<T, 8><<<nb, 512, 0, st>>>(rp, bc, val, x, y, wr, nw, S, part, mode); break;
+        default: return set_err(ctx, SGP_EINVAL, "spmv: unsupported waves per workgroup %d", ctx->spmv_waves);
+        }
     }
     LAUNCH_CHECK(ctx);
     return SGP_OK;
@@ -175,12 +342,14 @@ static int spmv_launch(sgp_ctx ctx, sgp_bsr A, const T *val, const T *x, T *y, c
 
 int spmv_f64(sgp_ctx ctx, sgp_bsr A, const double *x, double *y, const PcgScalars *S, double *part, int mode)
 {
-    return spmv_launch<double>(ctx, A, (const double *)A->val.p, x, y, S, part, mode);
+    return spmv_launch<double>(ctx, A, (const double *)A->val.p, (const double *)A->ew.p, (const double *)A->dg.p,
+                               x, y, S, part, mode);
 }
 
 int spmv_f32(sgp_ctx ctx, sgp_bsr A, const float *x, float *y, const PcgScalars *S, double *part, int mode)
 {
-    return spmv_launch<float>(ctx, A, (const float *)A->val32.p, x, y, S, part, mode);
+    return spmv_launch<float>(ctx, A, (const float *)A->val32.p, (const float *)A->ew32.p, (const float *)A->dg32.p,
+                              x, y, S, part, mode);
 }
 
 // caller's numbering in and out; the product runs in the internal order

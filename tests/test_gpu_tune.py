@@ -40,8 +40,9 @@ def test_defaults_and_rejections(ctx):
     assert ctx.tune_get("check_every") == 8 and ctx.tune_get("tail_max") == 2200
     assert ctx.tune_get("graph") == 0 and ctx.tune_get("spmv_waves") == 4
     assert ctx.tune_get("light_height") == 0 and ctx.tune_get("light_cap") == 512
+    assert ctx.tune_get("spmv_form") == 1
     for key, bad in (("check_every", 0), ("tail_max", -1), ("graph", 2), ("spmv_waves", 3), ("nope", 1),
-                     ("light_height", -1), ("light_cap", 0)):
+                     ("light_height", -1), ("light_cap", 0), ("spmv_form", 2)):
         with pytest.raises(P.SgpError):
             ctx.tune(key, bad)
 
@@ -179,3 +180,52 @@ def test_light_subtrees_batched(ctx):
         assert infos[k]["status"] == 0
         check_velocity(vh[off[k]:off[k + 1]], infos[k]["iters"], O.assemble(og), p["force"],
                        O.tree_factor(og, O.build_tree(og)))
+
+
+@pytest.mark.parametrize("n,seed", [(6000, 16), (30000, 17)])
+def test_edge_form_product_and_solve(ctx, n, seed):
+    """The product from the contacts' (w, u) against the stored blocks and the
+    oracle's assembled Gamma (FP64 rounding only), and CG with either form."""
+    c, g, A, T = _system(ctx, n, seed)
+    og = O.collide(c["pos"], c["radius"])
+    oa = O.assemble(og)
+    x = np.random.default_rng(seed).normal(size=(n, 3))
+    ref = O.spmv(oa, x)
+    ctx.tune("spmv_form", 0)
+    q0 = host(ctx.spmv(A, to_dev(x)))
+    ctx.tune("spmv_form", 1)
+    q1 = host(ctx.spmv(A, to_dev(x)))
+    for q in (q0, q1):
+        assert np.linalg.norm(q - ref) <= 1e-14 * np.linalg.norm(ref)
+    M = ctx.factor_tree(g, T)
+    fo = O.tree_factor(og, O.build_tree(og))
+    F = to_dev(c["force"])
+    for form in (0, 1):
+        ctx.tune("spmv_form", form)
+        v, info = ctx.pcg_solve(A, M, F)
+        assert info["status"] == 0 and info["relres_true"] <= 1.0001e-8
+        check_velocity(host(v), info["iters"], oa, c["force"], fo)
+        w, i32 = ctx.pcg_solve(A, M, F, precision="f32ir", inner_rtol=1e-4)
+        assert i32["status"] == 0 and i32["relres_true"] <= 1.0001e-8
+
+
+def test_edge_form_with_isolated_cells(ctx):
+    """Rows without contacts (isolated cells, a batch of singletons) are owned
+    by the product's last wave: q_i = g_med p_i for them."""
+    sizes = [1, 1, 500, 1, 64, 1, 1]
+    parts = [batched_instance(k + 9, n_override=s) for k, s in enumerate(sizes)]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = np.concatenate([p["pos"] + 100.0 * k for k, p in enumerate(parts)])
+    R = np.concatenate([p["radius"] for p in parts])
+    g = ctx.collide_batched(off, to_dev(pos), to_dev(R))
+    A = ctx.assemble_gamma(g)
+    x = np.random.default_rng(3).normal(size=(pos.shape[0], 3))
+    ctx.tune("spmv_form", 0)
+    q0 = host(ctx.spmv(A, to_dev(x)))
+    ctx.tune("spmv_form", 1)
+    q1 = host(ctx.spmv(A, to_dev(x)))
+    assert np.linalg.norm(q1 - q0) <= 1e-14 * np.linalg.norm(q0)
+    for k, s in enumerate(sizes):
+        if s == 1:
+            i = off[k]
+            assert np.allclose(q1[i], 1e-3 * x[i], rtol=1e-15, atol=0)
