@@ -59,10 +59,12 @@ def train(model: Mpnn, samples, epochs, lr, seed=0, log=None):
 
 
 def run(ctx: Context, pos, radius, noise_fn, n_steps=200, n_train=100, dt=0.01, k_rep=5.0,
-        epochs=20, lr=1e-3, rtol=1e-8, seed=0, schedule="contract", log=None):
+        epochs=20, lr=1e-3, rtol=1e-8, seed=0, schedule="contract", log=None, on_test_step=None):
     """Run the protocol.  `pos` (device [n][3] FP64) is advanced in place;
     `noise_fn(step, n)` returns the active force of a step (host or device).
-    Returns per-step records and the training history."""
+    `on_test_step(t, pos, F, x0, v)`, if given, sees every test step's
+    positions (before the update), forces, learned initial guess and solved
+    velocity.  Returns per-step records and the training history."""
     n = pos.shape[0]
     dev = pos.device
     v_prev = torch.zeros((n, 3), dtype=torch.float64, device=dev)
@@ -106,8 +108,11 @@ def run(ctx: Context, pos, radius, noise_fn, n_steps=200, n_train=100, dt=0.01, 
         # learned warm start (network pass + energy pick) and its solve
         t0 = _now(ctx)
         x0, ws = model.warm_start(g, A, F, v_prev)
+        x0_kept = x0.clone() if on_test_step else None
         v_b, ib = ctx.pcg_solve(A, M, F, v=x0, use_x0=True, rtol=rtol)
         ms_b = (_now(ctx) - t0) * 1e3
+        if on_test_step:
+            on_test_step(t, pos, F, x0_kept, v_b)
         # report only: the energy of the solution, E* = -0.5 v' F, scales the
         # energies of the guesses to relative Gamma-norm errors (zero start = 1)
         e_star = -0.5 * float(torch.dot(v_b.reshape(-1), F.reshape(-1)))

@@ -207,3 +207,82 @@ def test_full_4M_refinement_configuration(ctx):
     r = c["force"] - O.spmv(oa, host(v))
     relres = np.linalg.norm(r) / np.linalg.norm(c["force"])
     assert relres <= 1.0001e-8, relres
+
+
+def test_full_batched_256_configuration(ctx):
+    """The benchmark's batched workload (256 spheroids, sizes log-uniform in
+    [1e3, 2e5], seeds 1..256) through its pipeline: every instance converges
+    with the GPU's true relres <= 1e-8; sampled instances (the three smallest,
+    two mid-sized) have the oracle's graph and tree bit for bit and pass the
+    velocity check."""
+    parts = [batched_instance(k + 1) for k in range(256)]
+    sizes = np.array([p["pos"].shape[0] for p in parts])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    print(f"batched: {int(off[-1])} cells", flush=True)
+    from paper_2410_04512_amd import autotune
+    g = ctx.collide_batched(off, to_dev(np.concatenate([p["pos"] for p in parts])),
+                            to_dev(np.concatenate([p["radius"] for p in parts])))
+    A = ctx.assemble_gamma(g)
+    T = ctx.build_tree(g)
+    F = to_dev(np.concatenate([p["force"] for p in parts]))
+    # knobs as the benchmark chooses them (the autotuner on this batch)
+    tuned = autotune.tune(ctx, g, T, A, F, offsets=off, fixed_iters=10, repeats=1)
+    print(f"batched: tuned {({k: v for k, v in tuned.items() if k not in ('prec', 'table', 'defaults')})}", flush=True)
+    M = tuned["prec"]
+    v, infos = ctx.pcg_solve_batched(A, M, off, F)
+    for k, val in tuned["defaults"].items():
+        ctx.tune(k, val)
+    assert all(i["status"] == 0 and i["relres_true"] <= 1.0001e-8 for i in infos)
+    order = np.argsort(sizes)
+    sample = list(order[:3]) + [int(np.argsort(np.abs(sizes - 20000))[0]), int(np.argsort(np.abs(sizes - 8000))[0])]
+    e = {k: host(t) for k, t in ctx.graph_export(g).items()}
+    te = host(ctx.tree_export(T, int(off[-1]))["tree_edge"])
+    # edge ranges of the instances: edges are numbered instance by instance
+    eoff = np.concatenate([[0], np.cumsum([np.searchsorted(e["ei"], off[k + 1]) - np.searchsorted(e["ei"], off[k])
+                                           for k in range(256)])])
+    vh = host(v)
+    for k in sample:
+        p = parts[k]
+        print(f"batched: oracle check of instance {k + 1} ({sizes[k]} cells)", flush=True)
+        og = O.collide(p["pos"], p["radius"])
+        sl = slice(int(eoff[k]), int(eoff[k + 1]))
+        assert np.array_equal(e["ei"][sl] - off[k], og.ei) and np.array_equal(e["ej"][sl] - off[k], og.ej)
+        assert np.array_equal(e["w"][sl], og.w) and np.array_equal(e["u"][sl], og.u)
+        ot = O.build_tree(og)
+        mine = te[(te >= eoff[k]) & (te < eoff[k + 1])] - eoff[k]
+        assert np.array_equal(mine, ot.tree_edge)
+        check_velocity(vh[off[k]:off[k + 1]], infos[k]["iters"], O.assemble(og), p["force"], O.tree_factor(og, ot))
+
+
+def test_full_learned_warm_start_configuration(ctx):
+    """The benchmark's learned warm-start run (200k cells, 200 steps, training
+    on steps 1-100): every solve converges; at sampled test steps the oracle,
+    from the GPU's positions, reproduces the forces bit for bit, its FP64
+    residual of the GPU's velocity meets 1e-8, and the learned initial guess
+    has an energy no higher than the zero start's."""
+    from paper_2410_04512_amd import warmstart as W
+    from workloads import dynamics_noise
+    n = 200_000
+    c = sphere_cluster(n, 0)
+    kept = {}
+
+    def hook(t, pos, F, x0, v):
+        if t in (101, 160):
+            kept[t] = (host(pos), host(F), host(x0), host(v))
+
+    res = W.run(ctx, to_dev(c["pos"]), to_dev(c["radius"]), dynamics_noise, n_steps=200, n_train=100, epochs=30,
+                lr=3e-3, log=lambda s: print(s, flush=True), on_test_step=hook)
+    s = W.summary(res)
+    assert s["all_converged"] and s["max_relres_true"] <= 1.0001e-8
+    assert s["mean_iters_learned"] < s["mean_iters_prev"]
+    for t, (pos, F, x0, v) in kept.items():
+        print(f"learned: oracle check of step {t}", flush=True)
+        og = O.collide(pos, c["radius"])
+        Fo = O.forces(og, dynamics_noise(t, n), 5.0)
+        assert np.array_equal(F, Fo)
+        r = Fo - O.spmv(O.assemble(og), v)
+        relres = np.linalg.norm(r) / np.linalg.norm(Fo)
+        assert relres <= 1.0001e-8, (t, relres)
+        # the learned guess was a better start than zero in the energy norm
+        e0 = 0.5 * x0.ravel() @ O.spmv(O.assemble(og), x0).ravel() - x0.ravel() @ Fo.ravel()
+        assert e0 <= 0.0, (t, e0)
