@@ -383,23 +383,11 @@ __global__ void k_permute9(int64_t n, const int32_t *elim, const double *src, do
 // ---------------------------------------------------------------- sweeps
 
 
-// forward substitution of one vertex q (pivot solve folded in), then the
-// push of its contributions to the vertices above it
+// b -= the slots t..te-1, in slot order; slots are independent loads:
+// fetched four at a time
 template <class T>
-SGP_DEV void fwd_vertex(int32_t q, const int32_t *elim, const int32_t *in_ptr, const int32_t *tout, const T *F,
-                        int64_t fs, const T *Dinv, const T *r, T *y, T *cs)
+SGP_DEV void sum_slots(int32_t t, int32_t te, const T *cs, T &b0, T &b1, T &b2)
 {
-    // every load that does not depend on another is issued first, so the
-    // vertex waits for memory twice (ids, then values) rather than three times
-    const int64_t v = elim[q];
-    int32_t t = in_ptr[q];
-    const int32_t te = in_ptr[q + 1];
-    const int32_t to0 = tout[2 * q], to1 = tout[2 * q + 1];
-    T d[6], f0[9];
-    for (int k = 0; k < 6; k++) d[k] = Dinv[6 * (int64_t)q + k];
-    for (int k = 0; k < 9; k++) f0[k] = F[9 * (int64_t)q + k];
-    T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
-    // slots are independent loads: fetch four at a time, add in order
     for (; t + 4 <= te; t += 4) {
         const T *c = cs + 3 * (int64_t)t;
         T c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5];
@@ -413,6 +401,34 @@ SGP_DEV void fwd_vertex(int32_t q, const int32_t *elim, const int32_t *in_ptr, c
         const T *c = cs + 3 * (int64_t)t;
         b0 = b0 - c[0]; b1 = b1 - c[1]; b2 = b2 - c[2];
     }
+}
+
+// forward substitution of one vertex q (pivot solve folded in), then the
+// push of its contributions to the vertices above it.  The loads come in
+// rounds: what depends on q alone (ids, the pivot, the first coupling
+// plane), then what those ids address (r, the slots, and the second plane
+// for a vertex with a second link).  Every load precedes every store in the
+// source, so the compiler need not order a coupling's load after a push that
+// might alias it.  A finished solve (s->done) skips the stores only, so its
+// flag is awaited together with the loads.
+template <class T>
+SGP_DEV void fwd_vertex(int32_t q, const int32_t *elim, const int32_t *in_ptr, const int32_t *tout, const T *F,
+                        int64_t fs, const T *Dinv, const T *r, T *y, T *cs, const PcgScalars *s)
+{
+    const int32_t dn = done_flag(s);
+    const int64_t v = elim[q];
+    const int32_t t = in_ptr[q];
+    const int32_t te = in_ptr[q + 1];
+    const int32_t to0 = tout[2 * q], to1 = tout[2 * q + 1];
+    T d[6], f0[9], f1[9];
+    for (int k = 0; k < 6; k++) d[k] = Dinv[6 * (int64_t)q + k];
+    for (int k = 0; k < 9; k++) f0[k] = F[9 * (int64_t)q + k];
+    T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
+    sum_slots<T>(t, te, cs, b0, b1, b2);
+    if (to1 >= 0)
+        for (int k = 0; k < 9; k++) f1[k] = F[fs + 9 * (int64_t)q + k];
+    keep_loads_above();
+    if (dn) return;
     T o0, o1, o2;
     sym_mv(d, b0, b1, b2, o0, o1, o2);
     y[3 * (int64_t)q] = o0;
@@ -425,48 +441,55 @@ SGP_DEV void fwd_vertex(int32_t q, const int32_t *elim, const int32_t *in_ptr, c
         c[2] = f0[6] * o0 + f0[7] * o1 + f0[8] * o2;
     }
     if (to1 >= 0) {
-        const T *Fm = F + fs + 9 * (int64_t)q;
         T *c = cs + 3 * (int64_t)to1;
-        c[0] = Fm[0] * o0 + Fm[1] * o1 + Fm[2] * o2;
-        c[1] = Fm[3] * o0 + Fm[4] * o1 + Fm[5] * o2;
-        c[2] = Fm[6] * o0 + Fm[7] * o1 + Fm[8] * o2;
+        c[0] = f1[0] * o0 + f1[1] * o1 + f1[2] * o2;
+        c[1] = f1[3] * o0 + f1[4] * o1 + f1[5] * o2;
+        c[2] = f1[6] * o0 + f1[7] * o1 + f1[8] * o2;
     }
 }
 
-// backward substitution of one vertex q; y holds x for the vertices above
+// backward substitution of one vertex q; y holds x for the vertices above.
+// Two rounds of loads: ids, pivot, own y and the first coupling plane; then
+// x of both up-links (a missing link reads the vertex's own y and is masked)
+// and, for a second link, the second plane.
 template <class T>
 SGP_DEV void bwd_vertex(int32_t q, const int32_t *elim, const int32_t *upq, const T *F, int64_t fs, const T *Dinv,
-                        T *y, T *z)
+                        T *y, T *z, const PcgScalars *s)
 {
+    const int32_t dn = done_flag(s);
     const int32_t w0 = upq[2 * q], w1 = upq[2 * q + 1];
     const int64_t v = elim[q];
-    T d[6], f0[9];
+    T d[6], f0[9], f1[9];
     for (int k = 0; k < 6; k++) d[k] = Dinv[6 * (int64_t)q + k];
     for (int k = 0; k < 9; k++) f0[k] = F[9 * (int64_t)q + k];
     const T y0 = y[3 * (int64_t)q], y1 = y[3 * (int64_t)q + 1], y2 = y[3 * (int64_t)q + 2];
+    const int64_t u0 = w0 >= 0 ? w0 : q, u1 = w1 >= 0 ? w1 : q;
+    const T p0 = y[3 * u0], p1 = y[3 * u0 + 1], p2 = y[3 * u0 + 2];
+    const T x0 = y[3 * u1], x1 = y[3 * u1 + 1], x2 = y[3 * u1 + 2];
+    if (w1 >= 0)
+        for (int k = 0; k < 9; k++) f1[k] = F[fs + 9 * (int64_t)q + k];
+    keep_loads_above();
+    if (dn) return;
     T a0 = 0, a1 = 0, a2 = 0;
     if (w0 >= 0) {
-        const T x0 = y[3 * (int64_t)w0], x1 = y[3 * (int64_t)w0 + 1], x2 = y[3 * (int64_t)w0 + 2];
-        a0 = a0 + (f0[0] * x0 + f0[3] * x1 + f0[6] * x2);
-        a1 = a1 + (f0[1] * x0 + f0[4] * x1 + f0[7] * x2);
-        a2 = a2 + (f0[2] * x0 + f0[5] * x1 + f0[8] * x2);
+        a0 = a0 + (f0[0] * p0 + f0[3] * p1 + f0[6] * p2);
+        a1 = a1 + (f0[1] * p0 + f0[4] * p1 + f0[7] * p2);
+        a2 = a2 + (f0[2] * p0 + f0[5] * p1 + f0[8] * p2);
     }
     if (w1 >= 0) {
-        const T *Fm = F + fs + 9 * (int64_t)q;
-        const T x0 = y[3 * (int64_t)w1], x1 = y[3 * (int64_t)w1 + 1], x2 = y[3 * (int64_t)w1 + 2];
-        a0 = a0 + (Fm[0] * x0 + Fm[3] * x1 + Fm[6] * x2);
-        a1 = a1 + (Fm[1] * x0 + Fm[4] * x1 + Fm[7] * x2);
-        a2 = a2 + (Fm[2] * x0 + Fm[5] * x1 + Fm[8] * x2);
+        a0 = a0 + (f1[0] * x0 + f1[3] * x1 + f1[6] * x2);
+        a1 = a1 + (f1[1] * x0 + f1[4] * x1 + f1[7] * x2);
+        a2 = a2 + (f1[2] * x0 + f1[5] * x1 + f1[8] * x2);
     }
-    T d0, d1, d2;
-    sym_mv(d, a0, a1, a2, d0, d1, d2);
-    const T x0 = y0 - d0, x1 = y1 - d1, x2 = y2 - d2;
-    y[3 * (int64_t)q] = x0;
-    y[3 * (int64_t)q + 1] = x1;
-    y[3 * (int64_t)q + 2] = x2;
-    z[3 * v] = x0;
-    z[3 * v + 1] = x1;
-    z[3 * v + 2] = x2;
+    T e0, e1, e2;
+    sym_mv(d, a0, a1, a2, e0, e1, e2);
+    const T n0 = y0 - e0, n1 = y1 - e1, n2 = y2 - e2;
+    y[3 * (int64_t)q] = n0;
+    y[3 * (int64_t)q + 1] = n1;
+    y[3 * (int64_t)q + 2] = n2;
+    z[3 * v] = n0;
+    z[3 * v + 1] = n1;
+    z[3 * v + 2] = n2;
 }
 
 template <class T>
@@ -474,18 +497,16 @@ __global__ void k_fwd_step(int32_t q0, int32_t q1, const int32_t *elim, const in
                            const int32_t *tout, const T *F, int64_t fs, const T *Dinv, const T *r, T *y, T *cs,
                            const PcgScalars *s)
 {
-    if (s && s->done) return;
     int32_t q = q0 + (int32_t)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
-    if (q < q1) fwd_vertex<T>(q, elim, in_ptr, tout, F, fs, Dinv, r, y, cs);
+    if (q < q1) fwd_vertex<T>(q, elim, in_ptr, tout, F, fs, Dinv, r, y, cs, s);
 }
 
 template <class T>
 __global__ void k_bwd_step(int32_t q0, int32_t q1, const int32_t *elim, const int32_t *upq, const T *F,
                            int64_t fs, const T *Dinv, T *y, T *z, const PcgScalars *s)
 {
-    if (s && s->done) return;
     int32_t q = q0 + (int32_t)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
-    if (q < q1) bwd_vertex<T>(q, elim, upq, F, fs, Dinv, y, z);
+    if (q < q1) bwd_vertex<T>(q, elim, upq, F, fs, Dinv, y, z, s);
 }
 
 // The light steps of both sweeps: workgroup w owns the light subtrees packed
@@ -505,7 +526,7 @@ __global__ __launch_bounds__(256) void k_fwd_light(int32_t L, int32_t nwg, const
     for (int32_t k = 0; k < L; k++) {
         const int32_t q1 = wptr[(int64_t)k * nwg + w + 1];
         for (int32_t q = wptr[(int64_t)k * nwg + w] + (int32_t)threadIdx.x; q < q1; q += 256)
-            fwd_vertex<T>(q, elim, in_ptr, tout, F, fs, Dinv, r, y, cs);
+            fwd_vertex<T>(q, elim, in_ptr, tout, F, fs, Dinv, r, y, cs, nullptr);
         __syncthreads();
     }
 }
@@ -520,7 +541,7 @@ __global__ __launch_bounds__(256) void k_bwd_light(int32_t L, int32_t nwg, const
     for (int32_t k = L - 1; k >= 0; k--) {
         const int32_t q1 = wptr[(int64_t)k * nwg + w + 1];
         for (int32_t q = wptr[(int64_t)k * nwg + w] + (int32_t)threadIdx.x; q < q1; q += 256)
-            bwd_vertex<T>(q, elim, upq, F, fs, Dinv, y, z);
+            bwd_vertex<T>(q, elim, upq, F, fs, Dinv, y, z, nullptr);
         __syncthreads();
     }
 }
@@ -540,6 +561,7 @@ __global__ __launch_bounds__(256) void k_bwd_light(int32_t L, int32_t nwg, const
 // are separated by LDS-only barriers: the next step's prefetched loads stay
 // in flight across them.
 constexpr int TAIL_THREADS = 512;
+constexpr int TAIL_SLOTS = 4;   // LDS reads of in-slots issued together
 constexpr int TAIL_LDS_BYTES = 160 * 1024;
 
 // LDS of the tail: right-hand sides and internal push slots (3 values each),
@@ -563,18 +585,16 @@ __global__ __launch_bounds__(64) void k_tail_pre(int32_t Qt, int32_t nt, const i
                                                  const int32_t *iptr, const T *r, const T *cs, T *tb,
                                                  const PcgScalars *s)
 {
-    if (s && s->done) return;
     const int32_t i = blockIdx.x * 64 + threadIdx.x;
     if (i >= nt) return;
     const int32_t q = Qt + i;
+    const int32_t dn = done_flag(s);
     const int64_t v = elim[q];
     T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
     const int32_t te = in_ptr[q + 1] - (iptr[i + 1] - iptr[i]);
-    for (int32_t t = in_ptr[q]; t < te; t++) {
-        b0 = b0 - cs[3 * (int64_t)t];
-        b1 = b1 - cs[3 * (int64_t)t + 1];
-        b2 = b2 - cs[3 * (int64_t)t + 2];
-    }
+    sum_slots<T>(in_ptr[q], te, cs, b0, b1, b2);
+    keep_loads_above();
+    if (dn) return;
     tb[3 * (int64_t)i] = b0;
     tb[3 * (int64_t)i + 1] = b1;
     tb[3 * (int64_t)i + 2] = b2;
@@ -588,15 +608,24 @@ struct TailPre {
     int32_t b0, b1;   // forward: first and end internal in-slot; backward: vertex id
 };
 
+// the constants of a thread's vertex in the last TAIL_THREADS tail vertices,
+// for both sweeps, loaded once per launch
+template <class T>
+struct TailReg {
+    T d[6], f0[9], f1[9];
+    int32_t slot0, slot1, in0, in1;   // forward: push slots, internal in-slot range
+    int32_t up0, up1, id;             // backward: up-links, vertex id
+};
+
 // The loaders never branch on a value they load: a branch would wait for
 // every load issued before it and turn the prefetch into a stall.  Both F
 // planes are read (the second is zero where there is no second link).
 template <class T>
-SGP_DEV void tail_load_common(TailPre<T> &p, int32_t q, const T *F, int64_t fs, const T *Dinv)
+SGP_DEV void tail_load_common(T *d, T *f0, T *f1, int32_t q, const T *F, int64_t fs, const T *Dinv)
 {
-    for (int t = 0; t < 6; t++) p.d[t] = Dinv[6 * (int64_t)q + t];
-    for (int t = 0; t < 9; t++) p.f0[t] = F[9 * (int64_t)q + t];
-    for (int t = 0; t < 9; t++) p.f1[t] = F[fs + 9 * (int64_t)q + t];
+    for (int t = 0; t < 6; t++) d[t] = Dinv[6 * (int64_t)q + t];
+    for (int t = 0; t < 9; t++) f0[t] = F[9 * (int64_t)q + t];
+    for (int t = 0; t < 9; t++) f1[t] = F[fs + 9 * (int64_t)q + t];
 }
 
 // forward: push slots and the internal in-slot range
@@ -608,7 +637,7 @@ SGP_DEV void tail_load_fwd(TailPre<T> &p, int32_t q, int32_t i, const int32_t *t
     p.a1 = tslot[2 * i + 1];
     p.b0 = iptr[i];
     p.b1 = iptr[i + 1];
-    tail_load_common(p, q, F, fs, Dinv);
+    tail_load_common(p.d, p.f0, p.f1, q, F, fs, Dinv);
 }
 
 // backward: up-links and the vertex id
@@ -619,145 +648,209 @@ SGP_DEV void tail_load_bwd(TailPre<T> &p, int32_t q, const int32_t *upq, const i
     p.a0 = upq[2 * q];
     p.a1 = upq[2 * q + 1];
     p.b0 = elim[q];
-    tail_load_common(p, q, F, fs, Dinv);
+    tail_load_common(p.d, p.f0, p.f1, q, F, fs, Dinv);
 }
 
 template <class T>
-__global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, int32_t Qt, int32_t nt, int32_t ni,
-                                                       const int32_t *sp_g, const int32_t *elim, const int32_t *in_ptr,
-                                                       const int32_t *iptr, const int32_t *tslot, const int32_t *upq,
-                                                       const T *F, int64_t fs, const T *Dinv, const T *tb, T *y,
-                                                       T *z, const PcgScalars *s)
+SGP_DEV void tail_load_reg(TailReg<T> &p, int32_t q, int32_t i, const int32_t *tslot, const int32_t *iptr,
+                           const int32_t *upq, const int32_t *elim, const T *F, int64_t fs, const T *Dinv)
+{
+    p.slot0 = tslot[2 * i];
+    p.slot1 = tslot[2 * i + 1];
+    p.in0 = iptr[i];
+    p.in1 = iptr[i + 1];
+    p.up0 = upq[2 * q];
+    p.up1 = upq[2 * q + 1];
+    p.id = elim[q];
+    tail_load_common(p.d, p.f0, p.f1, q, F, fs, Dinv);
+}
+
+// The tail's steps fall in two parts.  Steps whose vertices all lie in the
+// last TAIL_THREADS tail vertices (the window, from step kw on: usually most
+// of the steps, few vertices each) give vertex base + t to thread t, whose
+// constants are loaded once per launch for both sweeps, so these steps touch
+// no global memory but the backward sweep's stores.  The steps before kw
+// (fewer, larger) give their vertices to threads in order, and a thread's
+// first vertex of the next step is loaded while a step runs.
+template <class T>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, int32_t kw, int32_t Qt, int32_t q1a,
+                                                       int32_t nt, int32_t ni, const int32_t *sp_g, const int32_t *elim,
+                                                       const int32_t *in_ptr, const int32_t *iptr,
+                                                       const int32_t *tslot, const int32_t *upq, const T *F,
+                                                       int64_t fs, const T *Dinv, const T *tb, T *y, T *z,
+                                                       const PcgScalars *s)
 {
     extern __shared__ unsigned char lds_raw[];
     T *sv = (T *)lds_raw;
     T *slot = sv + 3 * nt;
     // step bounds of the tail steps, sp[k] for k = s0..S, kept in LDS
     int32_t *ssp = (int32_t *)(slot + 3 * ni) - s0;
-    if (s && s->done) return;
+    const int32_t dn = done_flag(s);
     const int tid = threadIdx.x;
-    for (int32_t k = s0 + tid; k <= S; k += TAIL_THREADS) ssp[k] = sp_g[k];
-    const int32_t *sp = ssp;
-    // a thread's first vertex of a step is prefetched while the step before
-    // it runs (its loads do not depend on the sweep), so a step waits on LDS
-    // and the barrier rather than on memory
+    // the window's vertex of this thread (clamped: a thread past the end
+    // loads the last vertex and never uses it)
+    const int32_t base = nt > TAIL_THREADS ? nt - TAIL_THREADS : 0;
+    const int32_t ir = base + tid;
+    TailReg<T> R;
+    {
+        const int32_t i = ir < nt ? ir : nt - 1;
+        tail_load_reg(R, Qt + i, i, tslot, iptr, upq, elim, F, fs, Dinv);
+    }
+    // a thread's first vertex of step k, clamped into the step
+    auto vtx = [&](const int32_t *b, int32_t k) {
+        const int32_t qe = b[k + 1] - 1;
+        const int32_t q = b[k] + tid;
+        return q < qe ? q : qe;
+    };
+    // the first step's first vertices (q1a: the end of step s0 when it lies
+    // before the window, else Qt + 1), addressed from the arguments alone
     TailPre<T> pa, pb;
     {
-        const int32_t qe = sp_g[s0 + 1] - 1;
-        const int32_t q = sp_g[s0] + tid < qe ? sp_g[s0] + tid : qe;
+        const int32_t q = Qt + tid < q1a - 1 ? Qt + tid : q1a - 1;
         tail_load_fwd(pa, q, q - Qt, tslot, iptr, F, fs, Dinv);
     }
+    keep_loads_above();
+    if (dn) return;   // uniform: the whole workgroup leaves
+    for (int32_t k = s0 + tid; k <= S; k += TAIL_THREADS) ssp[k] = sp_g[k];
+    const int32_t *sp = ssp;
     // right-hand sides with the pre-tail contributions (k_tail_pre)
     for (int32_t i = tid; i < 3 * nt; i += TAIL_THREADS) sv[i] = tb[i];
     lds_barrier();
-    // forward steps; the two prefetch buffers swap roles every step (the
-    // loop is unrolled by two so that no buffer is copied).  A thread's first
-    // vertex of a step uses the prefetched buffer; further vertices of a big
-    // step load into their own buffer.
-    auto fwd_one = [&](int32_t q, const TailPre<T> &c) {
-        const int32_t i = q - Qt;
-        T b0 = sv[3 * i], b1 = sv[3 * i + 1], b2 = sv[3 * i + 2];
-        for (int32_t j = c.b0; j < c.b1; j++) {
-            b0 = b0 - slot[3 * j];
-            b1 = b1 - slot[3 * j + 1];
-            b2 = b2 - slot[3 * j + 2];
+    // forward: y_q = Dinv_q (b_q - its in-slots), pushes F_q y_q to its
+    // up-links' slots
+    auto fwd_one = [&](int32_t i, const T *d, const T *f0, const T *f1, int32_t a0, int32_t a1, int32_t b0,
+                       int32_t b1) {
+        T c0 = sv[3 * i], c1 = sv[3 * i + 1], c2 = sv[3 * i + 2];
+        // in-slots in slot order, TAIL_SLOTS reads in flight at a time
+        // (clamped addresses, surplus masked)
+        for (int32_t j = b0; j < b1; j += TAIL_SLOTS) {
+            const int32_t last = b1 - 1;
+            T c[3 * TAIL_SLOTS];
+#pragma unroll
+            for (int u = 0; u < TAIL_SLOTS; u++) {
+                const int32_t ju = j + u < last ? j + u : last;
+                c[3 * u] = slot[3 * ju];
+                c[3 * u + 1] = slot[3 * ju + 1];
+                c[3 * u + 2] = slot[3 * ju + 2];
+            }
+#pragma unroll
+            for (int u = 0; u < TAIL_SLOTS; u++) {
+                const bool on = j + u < b1;
+                c0 = on ? c0 - c[3 * u] : c0;
+                c1 = on ? c1 - c[3 * u + 1] : c1;
+                c2 = on ? c2 - c[3 * u + 2] : c2;
+            }
         }
         T o0, o1, o2;
-        sym_mv(c.d, b0, b1, b2, o0, o1, o2);
+        sym_mv(d, c0, c1, c2, o0, o1, o2);
         sv[3 * i] = o0;
         sv[3 * i + 1] = o1;
         sv[3 * i + 2] = o2;
-        if (c.a0 >= 0) {
-            slot[3 * c.a0] = c.f0[0] * o0 + c.f0[1] * o1 + c.f0[2] * o2;
-            slot[3 * c.a0 + 1] = c.f0[3] * o0 + c.f0[4] * o1 + c.f0[5] * o2;
-            slot[3 * c.a0 + 2] = c.f0[6] * o0 + c.f0[7] * o1 + c.f0[8] * o2;
+        if (a0 >= 0) {
+            slot[3 * a0] = f0[0] * o0 + f0[1] * o1 + f0[2] * o2;
+            slot[3 * a0 + 1] = f0[3] * o0 + f0[4] * o1 + f0[5] * o2;
+            slot[3 * a0 + 2] = f0[6] * o0 + f0[7] * o1 + f0[8] * o2;
         }
-        if (c.a1 >= 0) {
-            slot[3 * c.a1] = c.f1[0] * o0 + c.f1[1] * o1 + c.f1[2] * o2;
-            slot[3 * c.a1 + 1] = c.f1[3] * o0 + c.f1[4] * o1 + c.f1[5] * o2;
-            slot[3 * c.a1 + 2] = c.f1[6] * o0 + c.f1[7] * o1 + c.f1[8] * o2;
+        if (a1 >= 0) {
+            slot[3 * a1] = f1[0] * o0 + f1[1] * o1 + f1[2] * o2;
+            slot[3 * a1 + 1] = f1[3] * o0 + f1[4] * o1 + f1[5] * o2;
+            slot[3 * a1 + 2] = f1[6] * o0 + f1[7] * o1 + f1[8] * o2;
         }
     };
-    // The prefetch is issued on every path (a thread without a vertex in the
-    // next step loads the step's last one, the last step reloads its own), so
+    auto fwd_pre = [&](int32_t q, const TailPre<T> &c) {
+        fwd_one(q - Qt, c.d, c.f0, c.f1, c.a0, c.a1, c.b0, c.b1);
+    };
+    // A step before the window: the thread's first vertex from `cur`
+    // (prefetched), further ones loaded here; the next step's first vertex is
+    // prefetched into `nxt` on every path (a thread without a vertex there
+    // loads the step's last one, the last such step reloads its own), so
     // every path leaves the same loads in flight and the compiler's wait
-    // counts stay partial instead of falling back to waiting for all.
+    // counts stay partial.
     auto fstep = [&](int32_t k, TailPre<T> &cur, TailPre<T> &nxt) {
         {
-            const int32_t kk = k + 1 < S ? k + 1 : k;
-            const int32_t qe = sp[kk + 1] - 1;
-            const int32_t q = sp[kk] + tid < qe ? sp[kk] + tid : qe;
+            const int32_t q = vtx(sp, k + 1 < kw ? k + 1 : k);
             tail_load_fwd(nxt, q, q - Qt, tslot, iptr, F, fs, Dinv);
         }
         const int32_t q1 = sp[k + 1];
         int32_t q = sp[k] + tid;
-        if (q < q1) fwd_one(q, cur);
+        if (q < q1) fwd_pre(q, cur);
         for (q += TAIL_THREADS; q < q1; q += TAIL_THREADS) {
             TailPre<T> extra;
             tail_load_fwd(extra, q, q - Qt, tslot, iptr, F, fs, Dinv);
-            fwd_one(q, extra);
+            fwd_pre(q, extra);
         }
         lds_barrier();
     };
-    for (int32_t k = s0; k < S; k += 2) {
+    for (int32_t k = s0; k < kw; k += 2) {
         fstep(k, pa, pb);
-        if (k + 1 < S) fstep(k + 1, pb, pa);
+        if (k + 1 < kw) fstep(k + 1, pb, pa);
     }
-    // backward steps
-    auto bwd_one = [&](int32_t q, const TailPre<T> &c) {
-        const int32_t i = q - Qt;
-        T a0 = 0, a1 = 0, a2 = 0;
-        if (c.a0 >= 0) {
-            const int32_t wi = c.a0 - Qt;
+    for (int32_t k = kw; k < S; k++) {
+        if (ir >= sp[k] - Qt && ir < sp[k + 1] - Qt)
+            fwd_one(ir, R.d, R.f0, R.f1, R.slot0, R.slot1, R.in0, R.in1);
+        lds_barrier();
+    }
+    // backward: x_q = y_q - Dinv_q (sum over up-links of F^T x), also written
+    // to y (global) for the steps before the tail and to z
+    auto bwd_one = [&](int32_t i, const T *d, const T *f0, const T *f1, int32_t a0, int32_t a1, int64_t v) {
+        T c0 = 0, c1 = 0, c2 = 0;
+        if (a0 >= 0) {
+            const int32_t wi = a0 - Qt;
             const T x0 = sv[3 * wi], x1 = sv[3 * wi + 1], x2 = sv[3 * wi + 2];
-            a0 = a0 + (c.f0[0] * x0 + c.f0[3] * x1 + c.f0[6] * x2);
-            a1 = a1 + (c.f0[1] * x0 + c.f0[4] * x1 + c.f0[7] * x2);
-            a2 = a2 + (c.f0[2] * x0 + c.f0[5] * x1 + c.f0[8] * x2);
+            c0 = c0 + (f0[0] * x0 + f0[3] * x1 + f0[6] * x2);
+            c1 = c1 + (f0[1] * x0 + f0[4] * x1 + f0[7] * x2);
+            c2 = c2 + (f0[2] * x0 + f0[5] * x1 + f0[8] * x2);
         }
-        if (c.a1 >= 0) {
-            const int32_t wi = c.a1 - Qt;
+        if (a1 >= 0) {
+            const int32_t wi = a1 - Qt;
             const T x0 = sv[3 * wi], x1 = sv[3 * wi + 1], x2 = sv[3 * wi + 2];
-            a0 = a0 + (c.f1[0] * x0 + c.f1[3] * x1 + c.f1[6] * x2);
-            a1 = a1 + (c.f1[1] * x0 + c.f1[4] * x1 + c.f1[7] * x2);
-            a2 = a2 + (c.f1[2] * x0 + c.f1[5] * x1 + c.f1[8] * x2);
+            c0 = c0 + (f1[0] * x0 + f1[3] * x1 + f1[6] * x2);
+            c1 = c1 + (f1[1] * x0 + f1[4] * x1 + f1[7] * x2);
+            c2 = c2 + (f1[2] * x0 + f1[5] * x1 + f1[8] * x2);
         }
         T d0, d1, d2;
-        sym_mv(c.d, a0, a1, a2, d0, d1, d2);
+        sym_mv(d, c0, c1, c2, d0, d1, d2);
         const T x0 = sv[3 * i] - d0, x1 = sv[3 * i + 1] - d1, x2 = sv[3 * i + 2] - d2;
         sv[3 * i] = x0;
         sv[3 * i + 1] = x1;
         sv[3 * i + 2] = x2;
-        y[3 * (int64_t)q] = x0;
-        y[3 * (int64_t)q + 1] = x1;
-        y[3 * (int64_t)q + 2] = x2;
-        const int64_t v = c.b0;
+        const int64_t q = Qt + i;
+        y[3 * q] = x0;
+        y[3 * q + 1] = x1;
+        y[3 * q + 2] = x2;
         z[3 * v] = x0;
         z[3 * v + 1] = x1;
         z[3 * v + 2] = x2;
     };
+    auto bwd_pre = [&](int32_t q, const TailPre<T> &c) {
+        bwd_one(q - Qt, c.d, c.f0, c.f1, c.a0, c.a1, c.b0);
+    };
+    // the first backward step before the window is loaded now, while the
+    // window's steps run
+    {
+        const int32_t q = vtx(sp, kw > s0 ? kw - 1 : s0);
+        tail_load_bwd(pa, q, upq, elim, F, fs, Dinv);
+    }
+    for (int32_t k = S - 1; k >= kw; k--) {
+        if (ir >= sp[k] - Qt && ir < sp[k + 1] - Qt) bwd_one(ir, R.d, R.f0, R.f1, R.up0, R.up1, R.id);
+        lds_barrier();
+    }
     auto bstep = [&](int32_t k, TailPre<T> &cur, TailPre<T> &nxt) {
         {
-            const int32_t kk = k - 1 >= s0 ? k - 1 : k;
-            const int32_t qe = sp[kk + 1] - 1;
-            const int32_t q = sp[kk] + tid < qe ? sp[kk] + tid : qe;
+            const int32_t q = vtx(sp, k - 1 >= s0 ? k - 1 : k);
             tail_load_bwd(nxt, q, upq, elim, F, fs, Dinv);
         }
         const int32_t q1 = sp[k + 1];
         int32_t q = sp[k] + tid;
-        if (q < q1) bwd_one(q, cur);
+        if (q < q1) bwd_pre(q, cur);
         for (q += TAIL_THREADS; q < q1; q += TAIL_THREADS) {
             TailPre<T> extra;
             tail_load_bwd(extra, q, upq, elim, F, fs, Dinv);
-            bwd_one(q, extra);
+            bwd_pre(q, extra);
         }
         lds_barrier();
     };
-    {
-        const int32_t qe = sp[S] - 1;
-        const int32_t q = sp[S - 1] + tid < qe ? sp[S - 1] + tid : qe;
-        tail_load_bwd(pa, q, upq, elim, F, fs, Dinv);
-    }
-    for (int32_t k = S - 1; k >= s0; k -= 2) {
+    for (int32_t k = kw - 1; k >= s0; k -= 2) {
         bstep(k, pa, pb);
         if (k - 1 >= s0) bstep(k - 1, pb, pa);
     }
@@ -842,10 +935,16 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
     if (ts < S) {
         size_t lds = tail_lds_bytes(sizeof(T), M->tail_nt, M->tail_ni, S - ts);
         const int32_t nt = M->tail_nt;
+        if (nt > TAIL_MAX_VERTICES) return set_err(ctx, SGP_EINVAL, "tree sweeps: tail of %d vertices", nt);
         T *tb = (T *)M->tail_b.p;
         k_tail_pre<T><<<(nt + 63) / 64, 64, 0, st>>>(sp[ts], nt, elim, in_ptr, (const int32_t *)M->tail_iptr.p, r, cs,
                                                     tb, s);
-        k_tail<T><<<1, TAIL_THREADS, lds, st>>>(ts, S, sp[ts], nt, M->tail_ni, dsp, elim, in_ptr,
+        // the first step whose vertices all lie in the last TAIL_THREADS tail vertices
+        const int32_t base = nt > TAIL_THREADS ? nt - TAIL_THREADS : 0;
+        int32_t kw = ts;
+        while (kw < S && sp[kw] - sp[ts] < base) kw++;
+        const int32_t q1a = kw > ts ? sp[ts + 1] : sp[ts] + 1;
+        k_tail<T><<<1, TAIL_THREADS, lds, st>>>(ts, S, kw, sp[ts], q1a, nt, M->tail_ni, dsp, elim, in_ptr,
                                                (const int32_t *)M->tail_iptr.p, (const int32_t *)M->tail_tslot.p,
                                                upq, F, fs, Dinv, tb, y, z, s);
     }

@@ -25,6 +25,20 @@ struct PcgScalars {
     int32_t iter, done, status, fixed, max_iter, pad0;
 };
 
+// The solve's stop flag, or 0 without a solve.  The address is selected
+// rather than branched on, so the load can be issued early and awaited late,
+// together with a kernel's first round of loads.
+static __device__ int32_t k_never_done = 0;   // never written
+__device__ inline int32_t done_flag(const PcgScalars *s)
+{
+    return *(s ? &s->done : &k_never_done);
+}
+
+// A compiler-only fence (no instruction): memory accesses written before it
+// stay before it, so a branch after it cannot pull the loads above it into
+// one of its arms and make them wait for the branch condition.
+__device__ inline void keep_loads_above() { __asm__ __volatile__("" ::: "memory"); }
+
 struct sgp_ctx_ {
     hipStream_t stream = nullptr;
     int device = 0;
