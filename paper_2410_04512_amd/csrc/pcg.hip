@@ -8,6 +8,18 @@
 //           stop if ||r|| / ||F|| <= rtol
 //           z = M^{-1} r; rho' = r.z; p = z + (rho'/rho) p
 //
+// The launches of one iteration: the product (with the partials of p.q);
+// alpha; r -= alpha q (with the partials of ||r||^2); z = M^{-1} r; the
+// partials of r.z; one reduction for both ||r||^2 (the stopping rule) and
+// rho' (beta); then x += alpha p and p = z + beta p in one pass, which reads
+// p once for both.  The same values as the order above, bit for bit: x's
+// update only moves later.  The stopping rule is thus applied after the
+// sweeps of the last iteration instead of before them (one preconditioner
+// application more per solve, for one reduction less per iteration).  A
+// solve that stops normally is marked done = 3 ("finishing"): the last pass
+// still adds alpha p to x but leaves p, and the next alpha reduction turns
+// the mark into done = 1; every other kernel skips on any nonzero mark.
+//
 // Every scalar lives on the device.  Each dot product is a fixed-shape
 // two-stage reduction (per-block partials in a fixed order, the last block of
 // a cluster sums them in a fixed order), so results are bitwise reproducible.
@@ -82,7 +94,7 @@ SGP_DEV void block_partial(double v, int b, double *part, double *sh)
     if (threadIdx.x == 0) part[b] = s;
 }
 
-enum { FIN_ALPHA, FIN_RR, FIN_BETA, FIN_RHO, FIN_INIT, FIN_TRUE, FIN_NORM2 };
+enum { FIN_ALPHA, FIN_RR_BETA, FIN_RHO, FIN_INIT, FIN_TRUE, FIN_NORM2 };
 
 // fixed-order sum of n partials by the FIN_THREADS threads of k_fin: thread t
 // owns the interleaved sequence t, t+FIN_THREADS, ...; eight running sums
@@ -128,10 +140,15 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int op, const double *part,
     __shared__ double sh[FIN_THREADS / 64];
     const int k = blockIdx.x;
     PcgScalars *Sc = S + k;
-    if (op != FIN_INIT && op != FIN_TRUE && op != FIN_NORM2 && Sc->done) return;
+    if (op != FIN_INIT && op != FIN_TRUE && op != FIN_NORM2 && Sc->done) {
+        // a finishing solve (its last x update has run): finished
+        if (op == FIN_ALPHA && Sc->done == 3 && threadIdx.x == 0) Sc->done = 1;
+        return;
+    }
     const int f = ifirst[k], nbk = inb[k];
     double t0 = sum_partials8(part + f, nbk, sh);
-    double t1 = (op == FIN_INIT || op == FIN_NORM2) ? sum_partials8(part + nblk + f, nbk, sh) : 0.0;
+    double t1 = (op == FIN_INIT || op == FIN_NORM2 || op == FIN_RR_BETA) ? sum_partials8(part + nblk + f, nbk, sh)
+                                                                          : 0.0;
     double t2 = (op == FIN_INIT) ? sum_partials8(part + 2 * nblk + f, nbk, sh) : 0.0;
     if (threadIdx.x != 0) return;
     switch (op) {
@@ -144,26 +161,29 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int op, const double *part,
             Sc->alpha = Sc->rho / t0;
         }
         break;
-    case FIN_RR:
+    case FIN_RR_BETA: {   // t0 = ||r||^2, t1 = r.z
         Sc->rr = t0;
         Sc->iter = Sc->iter + 1;
         Sc->relres2 = t0 / Sc->nF2;
         if (!isfinite(t0)) {
             Sc->status = SGP_ENONFINITE;
             Sc->done = 1;
-        } else if (Sc->fixed) {
-            if (Sc->iter >= Sc->fixed) Sc->done = 1;
+            break;
+        }
+        bool stop = false;
+        if (Sc->fixed) {
+            stop = Sc->iter >= Sc->fixed;
         } else if (Sc->relres2 <= Sc->tol2) {
-            Sc->done = 1;
+            stop = true;
         } else if (Sc->iter >= Sc->max_iter) {
             Sc->status = SGP_ENOCONV;
-            Sc->done = 1;
+            stop = true;
         }
+        Sc->beta = t1 / Sc->rho;
+        Sc->rho = t1;
+        if (stop) Sc->done = 3;
         break;
-    case FIN_BETA:
-        Sc->beta = t0 / Sc->rho;
-        Sc->rho = t0;
-        break;
+    }
     case FIN_RHO:
         Sc->rho = t0;
         break;
@@ -264,10 +284,9 @@ SGP_DEV int block_elems(const BlockTab &tab, int b, int64_t &e0, int &inst)
     return 3 * (tab.row1[b] - tab.row0[b]);
 }
 
-// x += alpha p; r -= alpha q; partial of ||r||^2
+// r -= alpha q; partial of ||r||^2
 template <class T>
-__global__ __launch_bounds__(256) void k_update_xr(T *x, T *r, const T *p, const T *q, BlockTab tab,
-                                                   const PcgScalars *S, double *part)
+__global__ __launch_bounds__(256) void k_update_r(T *r, const T *q, BlockTab tab, const PcgScalars *S, double *part)
 {
     __shared__ double sh[256];
     int inst;
@@ -279,9 +298,7 @@ __global__ __launch_bounds__(256) void k_update_xr(T *x, T *r, const T *p, const
     double rr = 0.0;
     for (int t = threadIdx.x; t < ne; t += 256) {
         const int64_t i = e0 + t;
-        const T xi = x[i], pi = p[i], rv = r[i], qi = q[i];
-        x[i] = xi + alpha * pi;
-        const T ri = rv - alpha * qi;
+        const T ri = r[i] - alpha * q[i];
         r[i] = ri;
         rr = rr + (double)ri * (double)ri;
     }
@@ -316,18 +333,30 @@ __global__ __launch_bounds__(256) void k_rz(const T *r, const T *z, BlockTab tab
     block_partial(rz, blockIdx.x, part, sh);
 }
 
+// x += alpha p, then p = z + beta p (p only while the solve goes on)
 template <class T>
-__global__ __launch_bounds__(256) void k_update_p(T *p, const T *z, BlockTab tab, const PcgScalars *S)
+__global__ __launch_bounds__(256) void k_update_xp(T *x, T *p, const T *z, BlockTab tab, const PcgScalars *S)
 {
     int inst;
     int64_t e0;
     const int ne = block_elems(tab, blockIdx.x, e0, inst);
     const PcgScalars *Sc = S + inst;
-    if (Sc->done) return;
+    const int32_t dn = Sc->done;
+    if (dn != 0 && dn != 3) return;
+    const T alpha = (T)Sc->alpha;
+    if (dn == 3) {
+        for (int t = threadIdx.x; t < ne; t += 256) {
+            const int64_t i = e0 + t;
+            x[i] = x[i] + alpha * p[i];
+        }
+        return;
+    }
     const T beta = (T)Sc->beta;
     for (int t = threadIdx.x; t < ne; t += 256) {
         const int64_t i = e0 + t;
-        p[i] = z[i] + beta * p[i];
+        const T pi = p[i];
+        x[i] = x[i] + alpha * pi;
+        p[i] = z[i] + beta * pi;
     }
 }
 
@@ -447,17 +476,17 @@ static int pcg_chunk(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w, 
             k_pq<T><<<w.vec_nb, 256, 0, st>>>(v.p, v.q, w.vec, S, part);
             SGP_TRY(fin(ctx, FIN_ALPHA, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
         }
-        k_update_xr<T><<<w.vec_nb, 256, 0, st>>>(v.x, v.r, v.p, v.q, w.vec, S, part);
-        SGP_TRY(fin(ctx, FIN_RR, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
+        // partials: ||r||^2 in the first nb entries, r.z in the next nb
+        k_update_r<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.q, w.vec, S, part);
         if (M) {
             if (sizeof(T) == 8)
                 SGP_TRY(prec_apply_f64(ctx, M, (const double *)v.r, (double *)v.z, gate));
             else
                 SGP_TRY(prec_apply_f32(ctx, M, (const float *)v.r, (float *)v.z, gate));
         }
-        k_rz<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.z, w.vec, S, part);
-        SGP_TRY(fin(ctx, FIN_BETA, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
-        k_update_p<T><<<w.vec_nb, 256, 0, st>>>(v.p, v.z, w.vec, S);
+        k_rz<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.z, w.vec, S, part + w.vec_nb);
+        SGP_TRY(fin(ctx, FIN_RR_BETA, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
+        k_update_xp<T><<<w.vec_nb, 256, 0, st>>>(v.x, v.p, v.z, w.vec, S);
         LAUNCH_CHECK(ctx);
     }
     return SGP_OK;
