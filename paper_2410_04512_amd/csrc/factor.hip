@@ -161,6 +161,38 @@ __global__ void k_contract_apply(int64_t n, int32_t s, const int32_t *stepv, con
     atomicAdd(cnt, 1);
 }
 
+// The first round's changes, pulled by every surviving vertex from its
+// children in the tree (the same sums as k_contract_apply's atomics: XOR and
+// counts commute, so the state is identical bit for bit).  Before round 0 the
+// children of p are exactly its tree neighbours whose parent is p.
+__global__ void k_contract_pull0(int64_t n, const int32_t *parent, const int32_t *tptr, const int32_t *tadj,
+                                 const int32_t *stepv, const int32_t *up0, const int32_t *up1, int32_t *par,
+                                 int32_t *nch, int32_t *xch, int32_t *cnt)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    if (stepv[p] == 0) {
+        atomicAdd(cnt, 1);
+        return;
+    }
+    int32_t nc = nch[p], xc = xch[p];
+    for (int32_t t = tptr[p]; t < tptr[p + 1]; t++) {
+        const int32_t v = tadj[t];
+        if (parent[v] != (int32_t)p || stepv[v] != 0) continue;
+        const int32_t c = up1[v];
+        if (c < 0) {
+            nc -= 1;
+            xc ^= v;
+        } else {
+            xc ^= v ^ c;
+        }
+    }
+    nch[p] = nc;
+    xch[p] = xc;
+    const int32_t pp = par[p];
+    if (pp >= 0 && stepv[pp] == 0 && up1[pp] == (int32_t)p) par[p] = up0[pp];
+}
+
 // ---- light subtrees (CONTRACT with a rake-only start)
 //
 // The first rounds eliminate only leaves (rake), so after H rounds the
@@ -1096,7 +1128,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
         SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP3], n + 1, &par));
         SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP4], n + 1, &nch));
         SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP5], n + 1, &xch));
-        SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP6], 4, &cnt));
+        SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP6], 16, &cnt));   // cnt[0]: raking total; cnt[4..]: round counts
         SGP_TRY(fill_i32(ctx, nch, 0, n));
         SGP_TRY(fill_i32(ctx, xch, 0, n));
         SGP_TRY(fill_i32(ctx, cnt, 0, 1));
@@ -1142,15 +1174,31 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
             k_light_wg<<<grid_for(n, 256), 256, 0, st>>>(n, ja, wgr, wgv);
             LAUNCH_CHECK(ctx);
         }
+        // rounds in batches of ROUNDS_PER_READ with one readback of their
+        // per-round counts: rounds past the last vertex select nothing
+        constexpr int ROUNDS_PER_READ = 8;
+        int32_t *rcnt = cnt + 4;
         while (done < n) {
             if (S > 100000) return set_err(ctx, SGP_EINVAL, "factor_tree: contraction did not finish");
-            k_contract_select<<<grid_for(n, 256), 256, 0, st>>>(n, S, par, nch, xch, stepv, up0, up1);
-            k_contract_apply<<<grid_for(n, 256), 256, 0, st>>>(n, S, stepv, up0, up1, par, nch, xch, cnt);
+            SGP_TRY(fill_i32(ctx, rcnt, 0, ROUNDS_PER_READ));
+            for (int b = 0; b < ROUNDS_PER_READ; b++) {
+                const int32_t s = S + b;
+                k_contract_select<<<grid_for(n, 256), 256, 0, st>>>(n, s, par, nch, xch, stepv, up0, up1);
+                if (s == 0)
+                    k_contract_pull0<<<grid_for(n, 256), 256, 0, st>>>(n, parent, (const int32_t *)T->tptr.p,
+                                                                      (const int32_t *)T->tadj.p, stepv, up0, up1,
+                                                                      par, nch, xch, rcnt);
+                else
+                    k_contract_apply<<<grid_for(n, 256), 256, 0, st>>>(n, s, stepv, up0, up1, par, nch, xch,
+                                                                      rcnt + b);
+            }
             LAUNCH_CHECK(ctx);
-            S++;
-            SGP_TRY(readback(ctx, hbuf, cnt, 4));
-            if (hbuf[0] <= done) return set_err(ctx, SGP_EINVAL, "factor_tree: contraction made no progress");
-            done = hbuf[0];
+            SGP_TRY(readback(ctx, hbuf, rcnt, 4 * ROUNDS_PER_READ));
+            for (int b = 0; b < ROUNDS_PER_READ && done < n; b++) {
+                if (hbuf[b] <= 0) return set_err(ctx, SGP_EINVAL, "factor_tree: contraction made no progress");
+                done += hbuf[b];
+                S++;
+            }
         }
     }
     M->steps = S;

@@ -349,11 +349,15 @@ extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
         SGP_TRY(fill_i32(ctx, flag, 0, 1));
         k_bv_hook<<<grid_for(n, 256), 256, 0, st>>>(ei, ej, n, comp, beste, nxt, is_tree, flag);
         LAUNCH_CHECK(ctx);
-        // pointer jumping, two jumps per check (extra jumps are no-ops)
+        // pointer jumping: three pairs of jumps before the first check (hook
+        // chains are short: one check usually ends it), then two per check;
+        // jumps past convergence are no-ops
         for (int j = 0; j < 64; j++) {
-            SGP_TRY(fill_i32(ctx, flag, 0, 1));
-            k_bv_jump<<<grid_for(n, 256), 256, 0, st>>>(n, comp, nxt, nxt2, flag + 1);
-            k_bv_jump<<<grid_for(n, 256), 256, 0, st>>>(n, comp, nxt2, nxt, flag);
+            for (int r = 0; r < (j == 0 ? 3 : 1); r++) {
+                if (r == (j == 0 ? 2 : 0)) SGP_TRY(fill_i32(ctx, flag, 0, 1));   // the last pair is checked
+                k_bv_jump<<<grid_for(n, 256), 256, 0, st>>>(n, comp, nxt, nxt2, flag + 1);
+                k_bv_jump<<<grid_for(n, 256), 256, 0, st>>>(n, comp, nxt2, nxt, flag);
+            }
             LAUNCH_CHECK(ctx);
             SGP_TRY(readback(ctx, hflag, flag, 4));
             if (!hflag[0]) break;
