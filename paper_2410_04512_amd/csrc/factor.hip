@@ -483,10 +483,12 @@ SGP_DEV void fwd_vertex(int32_t q, const int32_t *elim, const int32_t *in_ptr, c
 // backward substitution of one vertex q; y holds x for the vertices above.
 // Two rounds of loads: ids, pivot, own y and the first coupling plane; then
 // x of both up-links (a missing link reads the vertex's own y and is masked)
-// and, for a second link, the second plane.
+// and, for a second link, the second plane.  x_q is kept in y only for the
+// vertices below that read it (keep_x: vertices with in-slots; none in the
+// first elimination step).
 template <class T>
 SGP_DEV void bwd_vertex(int32_t q, const int32_t *elim, const int32_t *upq, const T *F, int64_t fs, const T *Dinv,
-                        T *y, T *z, const PcgScalars *s)
+                        T *y, T *z, const PcgScalars *s, bool keep_x = true)
 {
     const int32_t dn = done_flag(s);
     const int32_t w0 = upq[2 * q], w1 = upq[2 * q + 1];
@@ -516,9 +518,11 @@ SGP_DEV void bwd_vertex(int32_t q, const int32_t *elim, const int32_t *upq, cons
     T e0, e1, e2;
     sym_mv(d, a0, a1, a2, e0, e1, e2);
     const T n0 = y0 - e0, n1 = y1 - e1, n2 = y2 - e2;
-    y[3 * (int64_t)q] = n0;
-    y[3 * (int64_t)q + 1] = n1;
-    y[3 * (int64_t)q + 2] = n2;
+    if (keep_x) {
+        y[3 * (int64_t)q] = n0;
+        y[3 * (int64_t)q + 1] = n1;
+        y[3 * (int64_t)q + 2] = n2;
+    }
     z[3 * v] = n0;
     z[3 * v + 1] = n1;
     z[3 * v + 2] = n2;
@@ -533,12 +537,14 @@ __global__ void k_fwd_step(int32_t q0, int32_t q1, const int32_t *elim, const in
     if (q < q1) fwd_vertex<T>(q, elim, in_ptr, tout, F, fs, Dinv, r, y, cs, s);
 }
 
+// keep_x = false for the first elimination step (its vertices have no
+// in-slots, so no vertex reads their x)
 template <class T>
 __global__ void k_bwd_step(int32_t q0, int32_t q1, const int32_t *elim, const int32_t *upq, const T *F,
-                           int64_t fs, const T *Dinv, T *y, T *z, const PcgScalars *s)
+                           int64_t fs, const T *Dinv, T *y, T *z, const PcgScalars *s, int keep_x)
 {
     int32_t q = q0 + (int32_t)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
-    if (q < q1) bwd_vertex<T>(q, elim, upq, F, fs, Dinv, y, z, s);
+    if (q < q1) bwd_vertex<T>(q, elim, upq, F, fs, Dinv, y, z, s, keep_x != 0);
 }
 
 // The light steps of both sweeps: workgroup w owns the light subtrees packed
@@ -983,7 +989,7 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
     for (int k = ts - 1; k >= L; k--) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
         if (q1 > q0)
-            k_bwd_step<T><<<grid_for(q1 - q0, 256), 256, 0, st>>>(q0, q1, elim, upq, F, fs, Dinv, y, z, s);
+            k_bwd_step<T><<<grid_for(q1 - q0, 256), 256, 0, st>>>(q0, q1, elim, upq, F, fs, Dinv, y, z, s, k > 0);
     }
     if (L > 0)
         k_bwd_light<T><<<M->light_nwg, 256, 0, st>>>(L, M->light_nwg, wptr, elim, upq, F, fs, Dinv, y, z, s);
