@@ -358,7 +358,9 @@ def main():
                      "traffic": SPMV_TRAFFIC_1M[form] if (args.n == 1_000_000 and ctx.tune_get("spmv_waves") == 4) else None,
                      "traffic_unit": "B/launch (counters)",
                      "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_spmv_ms,
-                     "launches": spmv_launches},
+                     "launches": spmv_launches,
+                     "timed": f"HIP events around the third product of every {ctx.tune_get('check_every')}-iteration "
+                              "CG chunk of the timed region (products after convergence excluded)"},
         "phase_ms": {k: v_ / args.steps for k, v_ in phase.items()},
     }
     if not args.no_extra:

@@ -326,11 +326,14 @@ int sgp_tune(sgp_ctx ctx, const char *key, int32_t value);
 /* Current value of a knob (host output). */
 int sgp_tune_get(sgp_ctx ctx, const char *key, int32_t *value);
 
-/* Per-launch timing of the CG's block-CSR product: when enabled, every
- * product launched by sgp_pcg_solve* is bracketed by HIP events on the
- * context's stream; sgp_kernel_stats returns the summed duration (ms) and the
- * number of timed launches since timing was enabled (enabling resets them).
- * Launches of converged clusters exit at once and are still counted. */
+/* Per-launch timing of the CG's product: when enabled, one product per
+ * chunk of check_every CG iterations launched by sgp_pcg_solve* (the third
+ * of the chunk, or its last if shorter) is bracketed by HIP events on the
+ * context's stream -- an event pair around every product would itself cost
+ * time.  A single solve's products issued after its last iteration return at
+ * once and are not counted.  sgp_kernel_stats returns the summed duration
+ * (ms) and the number of timed launches since timing was enabled (enabling
+ * resets them).  Graph replay is off while timing is on. */
 int sgp_kernel_timing(sgp_ctx ctx, int32_t enable);
 int sgp_kernel_stats(sgp_ctx ctx, double *total_ms, int64_t *launches);
 

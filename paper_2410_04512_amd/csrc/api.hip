@@ -113,9 +113,11 @@ extern "C" void sgp_prec_free(sgp_prec M)
 
 // ---------------------------------------------------------------- kernel timing
 
-int ktimer_begin(sgp_ctx c)
+int ktimer_begin(sgp_ctx c, int32_t iter)
 {
     if (!c->ktiming) return SGP_OK;
+    if ((int)c->kev_iter.size() <= c->kev_used / 2) c->kev_iter.resize(c->kev_used / 2 + 64);
+    c->kev_iter[c->kev_used / 2] = iter;
     if (c->kev_used + 2 > (int)c->kev.size()) {
         for (int k = 0; k < 64; k++) {
             hipEvent_t e;
@@ -135,11 +137,12 @@ int ktimer_end(sgp_ctx c)
     return SGP_OK;
 }
 
-int ktimer_flush(sgp_ctx c)
+int ktimer_flush(sgp_ctx c, int32_t iters_done)
 {
     if (!c->ktiming || c->kev_used == 0) return SGP_OK;
     HIP_TRY(c, hipEventSynchronize(c->kev[c->kev_used - 1]));
     for (int k = 0; k < c->kev_used; k += 2) {
+        if (c->kev_iter[k / 2] >= iters_done) continue;   // issued past convergence: a no-op launch
         float ms = 0.f;
         HIP_TRY(c, hipEventElapsedTime(&ms, c->kev[k], c->kev[k + 1]));
         c->ktime_ms += ms;
@@ -162,7 +165,7 @@ extern "C" int sgp_kernel_timing(sgp_ctx c, int32_t enable)
 extern "C" int sgp_kernel_stats(sgp_ctx c, double *total_ms, int64_t *launches)
 {
     if (!c) return SGP_EINVAL;
-    SGP_TRY(ktimer_flush(c));
+    SGP_TRY(ktimer_flush(c, INT32_MAX));
     if (total_ms) *total_ms = c->ktime_ms;
     if (launches) *launches = c->klaunches;
     return SGP_OK;

@@ -399,10 +399,12 @@ __global__ void k_set_scalars(PcgScalars *S, int64_t K, double tol2, int fixed, 
     S[k] = s;
 }
 
+// open[0]: clusters not done; open[1]: iterations of cluster 0
 __global__ void k_any_open(const PcgScalars *S, int64_t K, int32_t *open)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < K && !S[k].done) atomicAdd(open, 1);
+    if (k == 0) open[1] = S[0].iter;
 }
 
 // rowptr at the cluster offsets (block offsets of the clusters)
@@ -458,21 +460,26 @@ static int fin(sgp_ctx ctx, int op, const double *part, int nblk, const int32_t 
 // past convergence change nothing.
 template <class T>
 static int pcg_chunk(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w, PcgScalars *S, double *part,
-                     int count)
+                     int count, int it0 = 0)
 {
     hipStream_t st = ctx->stream;
     const int64_t K = w.K;
     // one cluster: the sweeps stop with it; several: every sweep runs
     PcgScalars *gate = K == 1 ? S : nullptr;
     for (int c = 0; c < count; c++) {
-        SGP_TRY(ktimer_begin(ctx));
+        // kernel timing brackets one product per chunk, the third (by then
+        // the host has queued well ahead of the GPU, so the pair times the
+        // kernel and not the wait for its launch); an event pair per product
+        // would itself cost time
+        const bool timed = c == std::min(2, count - 1);
+        if (timed) SGP_TRY(ktimer_begin(ctx, it0 + c));
         if (K == 1) {
             SGP_TRY(spmv_t<T>(ctx, A, v.p, v.q, S, part, 1));
-            SGP_TRY(ktimer_end(ctx));
+            if (timed) SGP_TRY(ktimer_end(ctx));
             SGP_TRY(fin(ctx, FIN_ALPHA, part, w.mv_nb, w.mv_first, w.mv_nb_dev, S, 1));
         } else {
             SGP_TRY(spmv_t<T>(ctx, A, v.p, v.q, nullptr, nullptr, 0));
-            SGP_TRY(ktimer_end(ctx));
+            if (timed) SGP_TRY(ktimer_end(ctx));
             k_pq<T><<<w.vec_nb, 256, 0, st>>>(v.p, v.q, w.vec, S, part);
             SGP_TRY(fin(ctx, FIN_ALPHA, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
         }
@@ -546,13 +553,15 @@ static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w
             if (!cg.exec) SGP_TRY(capture_chunk<T>(ctx, A, M, v, w, S, part, chunk, cg));
             HIP_TRY(ctx, hipGraphLaunch(cg.exec, st));
         } else {
-            SGP_TRY(pcg_chunk<T>(ctx, A, M, v, w, S, part, chunk));
+            SGP_TRY(pcg_chunk<T>(ctx, A, M, v, w, S, part, chunk, it));
         }
         it += chunk;
-        SGP_TRY(fill_i32(ctx, open, 0, 1));
+        SGP_TRY(fill_i32(ctx, open, 0, 2));
         k_any_open<<<grid_for(K, 256), 256, 0, st>>>(S, K, open);
-        SGP_TRY(readback(ctx, hopen, open, 4));
-        SGP_TRY(ktimer_flush(ctx));
+        SGP_TRY(readback(ctx, hopen, open, 8));
+        // one cluster: its products past the final iteration were no-ops
+        // (batched products always run for every cluster)
+        SGP_TRY(ktimer_flush(ctx, K == 1 && hopen[0] == 0 ? hopen[1] : INT32_MAX));
         if (hopen[0] == 0) break;
     }
     return SGP_OK;

@@ -52,6 +52,7 @@ struct sgp_ctx_ {
     // per-launch timing of the CG's matrix product (events on ctx->stream)
     int ktiming = 0;
     std::vector<hipEvent_t> kev;   // pairs (before, after)
+    std::vector<int32_t> kev_iter; // CG iteration index (from 0) of each pair's launch
     int kev_used = 0;
     double ktime_ms = 0.0;
     int64_t klaunches = 0;
@@ -66,10 +67,13 @@ struct sgp_ctx_ {
     hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)
 };
 
-// event pair around one timed launch (no-op unless timing is on)
-int ktimer_begin(sgp_ctx ctx);
+// event pair around one timed launch of CG iteration `iter` (no-op unless
+// timing is on)
+int ktimer_begin(sgp_ctx ctx, int32_t iter);
 int ktimer_end(sgp_ctx ctx);
-int ktimer_flush(sgp_ctx ctx);   // synchronises: adds finished pairs to the totals
+// synchronises: adds the finished pairs to the totals, except those of
+// iterations >= iters_done (launched after convergence, which return at once)
+int ktimer_flush(sgp_ctx ctx, int32_t iters_done);
 
 // workspace slots (shared scratch of a context; each call may reuse them)
 enum {
