@@ -204,7 +204,7 @@ typedef struct {
     int32_t precision;    /* SGP_PREC_F64, or SGP_PREC_F32_IR: FP32 inner PCG inside FP64 refinement */
     double inner_rtol;    /* IR only: relative tolerance of each inner FP32 solve */
     int32_t max_outer;    /* IR only: cap on refinement steps */
-    int32_t check_every;  /* iterations between convergence reads by the host (0 = default) */
+    int32_t check_every;  /* CG iterations per chunk between possible convergence reads (0 = the knob) */
 } sgp_solve_opts;
 
 typedef struct {
@@ -297,9 +297,12 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
                         double *energy_prev);
 
 /* Launch-shape knobs of this context (chosen by the autotuner):
- *  "check_every"  CG iterations between the host's convergence reads
- *                 (1..1024, default 8); iterations issued past convergence
- *                 are no-ops on the device
+ *  "check_every"  CG iterations per chunk (1..1024, default 2).  The host
+ *                 reads the convergence state after whole chunks only: after
+ *                 every chunk at first, then, from the decay of the slowest
+ *                 cluster's residual so far, after as many chunks as half
+ *                 the iterations it still needs; iterations issued past
+ *                 convergence are no-ops on the device
  *  "tail_max"     the largest number of tree vertices whose last elimination
  *                 steps run as one LDS-resident workgroup in the tree sweeps
  *                 (0..65536, 0 disables, default 2200; used by factors built

@@ -27,7 +27,7 @@ SCHEDULES = ("contract", "level")
 TAIL_MAX = (0, 1024, 2200)
 LIGHT_HEIGHT = (0, 16, 32, 64)
 SPMV_WAVES = (2, 4, 8)
-CHECK_EVERY = (4, 8, 16, 32)
+CHECK_EVERY = (1, 2, 4, 8, 16)
 GRAPH = (0, 1)
 
 

@@ -399,11 +399,19 @@ __global__ void k_set_scalars(PcgScalars *S, int64_t K, double tol2, int fixed, 
     S[k] = s;
 }
 
-// open[0]: clusters not done; open[1]: iterations of cluster 0
+// open[0]: clusters not done; open[1]: iterations of cluster 0; open[2..3]:
+// the largest (||r||^2 / ||F||^2) / tol^2 of the open clusters, as the bits
+// of a double (zeroed before the launch; positive doubles order as their
+// bits, so an integer maximum picks the largest)
 __global__ void k_any_open(const PcgScalars *S, int64_t K, int32_t *open)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < K && !S[k].done) atomicAdd(open, 1);
+    if (k < K && !S[k].done) {
+        atomicAdd(open, 1);
+        const double q = S[k].tol2 > 0.0 ? S[k].relres2 / S[k].tol2 : 0.0;
+        if (q > 0.0 && isfinite(q))
+            atomicMax((unsigned long long *)(open + 2), (unsigned long long)__double_as_longlong(q));
+    }
     if (k == 0) open[1] = S[0].iter;
 }
 
@@ -547,22 +555,47 @@ static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w
     // graph replay of whole chunks (not while per-launch timing records events)
     const bool graph = ctx->use_graph && !ctx->ktiming;
     ChunkGraph cg;
+    // Chunks issued between two polls of the host.  A fixed iteration count
+    // needs no poll before its end.  Otherwise, after two polls, the decay per
+    // iteration of log(||r||^2 / (tol ||F||)^2) of the slowest open cluster
+    // predicts the iterations it still needs, and the next poll comes after
+    // half of them (whole chunks, at least one): polls thin out while the
+    // solve is far from the tolerance, and iterations issued past
+    // convergence stay within a chunk.
+    int per_poll = fixed > 0 ? (limit + check_every - 1) / check_every : 1;
+    int it_prev = -1;
+    double lg_prev = 0.0;
     for (int it = 0; it < limit;) {
-        int chunk = std::min(check_every, limit - it);
-        if (graph && chunk == check_every) {
-            if (!cg.exec) SGP_TRY(capture_chunk<T>(ctx, A, M, v, w, S, part, chunk, cg));
-            HIP_TRY(ctx, hipGraphLaunch(cg.exec, st));
-        } else {
-            SGP_TRY(pcg_chunk<T>(ctx, A, M, v, w, S, part, chunk, it));
+        for (int b = 0; b < per_poll && it < limit; b++) {
+            int chunk = std::min(check_every, limit - it);
+            if (graph && chunk == check_every) {
+                if (!cg.exec) SGP_TRY(capture_chunk<T>(ctx, A, M, v, w, S, part, chunk, cg));
+                HIP_TRY(ctx, hipGraphLaunch(cg.exec, st));
+            } else {
+                SGP_TRY(pcg_chunk<T>(ctx, A, M, v, w, S, part, chunk, it));
+            }
+            it += chunk;
         }
-        it += chunk;
-        SGP_TRY(fill_i32(ctx, open, 0, 2));
+        SGP_TRY(fill_i32(ctx, open, 0, 4));
         k_any_open<<<grid_for(K, 256), 256, 0, st>>>(S, K, open);
-        SGP_TRY(readback(ctx, hopen, open, 8));
+        SGP_TRY(readback(ctx, hopen, open, 16));
         // one cluster: its products past the final iteration were no-ops
         // (batched products always run for every cluster)
         SGP_TRY(ktimer_flush(ctx, K == 1 && hopen[0] == 0 ? hopen[1] : INT32_MAX));
         if (hopen[0] == 0) break;
+        if (fixed > 0) continue;
+        double worst;
+        memcpy(&worst, hopen + 2, 8);
+        per_poll = 1;
+        if (worst > 1.0 && std::isfinite(worst)) {
+            const double lg = log(worst);
+            if (it_prev >= 0 && lg < lg_prev) {
+                const double rem = -lg / ((lg - lg_prev) / (it - it_prev));
+                per_poll = (int)std::min(1e6, std::max(1.0, 0.5 * rem / check_every));
+            }
+            it_prev = it;
+            lg_prev = lg;
+        }
     }
     return SGP_OK;
 }

@@ -57,7 +57,7 @@ struct sgp_ctx_ {
     double ktime_ms = 0.0;
     int64_t klaunches = 0;
     // launch-shape knobs (sgp_tune); none changes a result beyond rounding order
-    int check_every = 8;           // CG iterations between the host's convergence reads
+    int check_every = 2;           // CG iterations per chunk (the host polls after whole chunks)
     int tail_max = 2200;           // vertices at most left for the one-workgroup tail of the tree sweeps
     int use_graph = 0;             // replay a captured chunk of CG iterations as one hipGraph
     int spmv_waves = 4;            // waves per workgroup of the block-CSR product (2, 4 or 8)

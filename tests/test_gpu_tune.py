@@ -37,7 +37,7 @@ def _system(ctx, n=20000, seed=11):
 
 
 def test_defaults_and_rejections(ctx):
-    assert ctx.tune_get("check_every") == 8 and ctx.tune_get("tail_max") == 2200
+    assert ctx.tune_get("check_every") == 2 and ctx.tune_get("tail_max") == 2200
     assert ctx.tune_get("graph") == 0 and ctx.tune_get("spmv_waves") == 4
     assert ctx.tune_get("light_height") == 0 and ctx.tune_get("light_cap") == 512
     assert ctx.tune_get("spmv_form") == 1
@@ -100,7 +100,7 @@ def test_check_every_and_tail_max_are_bitwise_neutral(ctx):
         ctx.tune("check_every", ce)
         v, i = ctx.pcg_solve(A, M, F)
         assert i["iters"] == iref["iters"] and torch.equal(v, ref), ce
-    ctx.tune("check_every", 8)
+    ctx.tune("check_every", 2)
     for tm in (0, 300):
         ctx.tune("tail_max", tm)
         M2 = ctx.factor_tree(g, T)
