@@ -146,7 +146,7 @@ __global__ void k_contract_select(int64_t n, int32_t s, const int32_t *par, cons
 }
 
 __global__ void k_contract_apply(int64_t n, int32_t s, const int32_t *stepv, const int32_t *up0,
-                                 const int32_t *up1, int32_t *par, int32_t *nch, int32_t *xch, int32_t *cnt)
+                                 const int32_t *up1, int32_t *par, int32_t *nch, int32_t *xch)
 {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n || stepv[v] != s) return;
@@ -158,7 +158,63 @@ __global__ void k_contract_apply(int64_t n, int32_t s, const int32_t *stepv, con
         atomicSub(&nch[p], 1);
         atomicXor(&xch[p], (int32_t)v);
     }
-    atomicAdd(cnt, 1);
+}
+
+// Progress of the schedule without a counter that every vertex increments
+// (atomics on one address serialise): per block the vertices still
+// unscheduled and the largest step given so far, then one block combines.
+constexpr int SCHED_STAT_BLOCKS = 1024;
+
+__global__ __launch_bounds__(256) void k_sched_stats(int64_t n, const int32_t *stepv, int32_t *part)
+{
+    __shared__ int32_t sa[4], sm[4];
+    int32_t alive = 0, mx = -1;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+        const int32_t st = stepv[v];
+        alive += st < 0;
+        mx = st > mx ? st : mx;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        alive += __shfl_xor(alive, o, 64);
+        const int32_t m2 = __shfl_xor(mx, o, 64);
+        mx = m2 > mx ? m2 : mx;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sa[threadIdx.x >> 6] = alive;
+        sm[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sa[0] + sa[1] + sa[2] + sa[3];
+        int32_t m = sm[0];
+        for (int k = 1; k < 4; k++) m = sm[k] > m ? sm[k] : m;
+        part[2 * blockIdx.x + 1] = m;
+    }
+}
+
+// out[0]: vertices unscheduled, out[1]: largest step given (-1: none)
+__global__ __launch_bounds__(256) void k_sched_final(int nb, const int32_t *part, int32_t *out)
+{
+    __shared__ int32_t sa[256], sm[256];
+    int32_t alive = 0, mx = -1;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        alive += part[2 * b];
+        mx = part[2 * b + 1] > mx ? part[2 * b + 1] : mx;
+    }
+    sa[threadIdx.x] = alive;
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            sa[threadIdx.x] += sa[threadIdx.x + st];
+            sm[threadIdx.x] = sm[threadIdx.x + st] > sm[threadIdx.x] ? sm[threadIdx.x + st] : sm[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sa[0];
+        out[1] = sm[0];
+    }
 }
 
 // The first round's changes, pulled by every surviving vertex from its
@@ -167,14 +223,10 @@ __global__ void k_contract_apply(int64_t n, int32_t s, const int32_t *stepv, con
 // children of p are exactly its tree neighbours whose parent is p.
 __global__ void k_contract_pull0(int64_t n, const int32_t *parent, const int32_t *tptr, const int32_t *tadj,
                                  const int32_t *stepv, const int32_t *up0, const int32_t *up1, int32_t *par,
-                                 int32_t *nch, int32_t *xch, int32_t *cnt)
+                                 int32_t *nch, int32_t *xch)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    if (stepv[p] == 0) {
-        atomicAdd(cnt, 1);
-        return;
-    }
+    if (p >= n || stepv[p] == 0) return;
     int32_t nc = nch[p], xc = xch[p];
     for (int32_t t = tptr[p]; t < tptr[p + 1]; t++) {
         const int32_t v = tadj[t];
@@ -1130,26 +1182,39 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
         LAUNCH_CHECK(ctx);
         S = T->max_depth + 1;
     } else {
-        int32_t *par, *nch, *xch, *cnt;
+        int32_t *par, *nch, *xch, *stat;
         SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP3], n + 1, &par));
         SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP4], n + 1, &nch));
         SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP5], n + 1, &xch));
-        SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP6], 16, &cnt));   // cnt[0]: raking total; cnt[4..]: round counts
+        SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP6], 2 * SCHED_STAT_BLOCKS + 4, &stat));   // per-block stats, then out[2]
         SGP_TRY(fill_i32(ctx, nch, 0, n));
         SGP_TRY(fill_i32(ctx, xch, 0, n));
-        SGP_TRY(fill_i32(ctx, cnt, 0, 1));
         k_contract_init<<<grid_for(n, 256), 256, 0, st>>>(n, parent, par, nch, xch, stepv);
         LAUNCH_CHECK(ctx);
+        const int stat_nb = (int)std::min<int64_t>(SCHED_STAT_BLOCKS, grid_for(n, 256));
+        int32_t *stat_out = stat + 2 * SCHED_STAT_BLOCKS;
+        // host copy of (unscheduled, largest step) after the rounds so far
+        auto progress = [&](int64_t &alive, int32_t &maxstep) -> int {
+            k_sched_stats<<<stat_nb, 256, 0, st>>>(n, stepv, stat);
+            k_sched_final<<<1, 256, 0, st>>>(stat_nb, stat, stat_out);
+            LAUNCH_CHECK(ctx);
+            SGP_TRY(readback(ctx, hbuf, stat_out, 8));
+            alive = hbuf[0];
+            maxstep = hbuf[1];
+            return SGP_OK;
+        };
         int64_t done = 0;
         // rake-only rounds: the light subtrees
         while (done < n && S < ctx->light_height) {
             k_rake_select<<<grid_for(n, 256), 256, 0, st>>>(n, S, par, nch, stepv, up0, up1);
-            k_contract_apply<<<grid_for(n, 256), 256, 0, st>>>(n, S, stepv, up0, up1, par, nch, xch, cnt);
+            k_contract_apply<<<grid_for(n, 256), 256, 0, st>>>(n, S, stepv, up0, up1, par, nch, xch);
             LAUNCH_CHECK(ctx);
             S++;
-            SGP_TRY(readback(ctx, hbuf, cnt, 4));
-            if (hbuf[0] <= done) return set_err(ctx, SGP_EINVAL, "factor_tree: raking made no progress");
-            done = hbuf[0];
+            int64_t alive;
+            int32_t maxstep;
+            SGP_TRY(progress(alive, maxstep));
+            if (n - alive <= done) return set_err(ctx, SGP_EINVAL, "factor_tree: raking made no progress");
+            done = n - alive;
         }
         // a tree raked away completely runs as ordinary steps
         if (S > 0 && done < n) {
@@ -1180,31 +1245,30 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
             k_light_wg<<<grid_for(n, 256), 256, 0, st>>>(n, ja, wgr, wgv);
             LAUNCH_CHECK(ctx);
         }
-        // rounds in batches of ROUNDS_PER_READ with one readback of their
-        // per-round counts: rounds past the last vertex select nothing
+        // rounds in batches of ROUNDS_PER_READ with one readback of the
+        // progress: rounds past the last vertex select nothing, and every
+        // round before it schedules at least one vertex (a forest always has
+        // a leaf), so the step count is the largest step given plus one
         constexpr int ROUNDS_PER_READ = 8;
-        int32_t *rcnt = cnt + 4;
         while (done < n) {
             if (S > 100000) return set_err(ctx, SGP_EINVAL, "factor_tree: contraction did not finish");
-            SGP_TRY(fill_i32(ctx, rcnt, 0, ROUNDS_PER_READ));
             for (int b = 0; b < ROUNDS_PER_READ; b++) {
                 const int32_t s = S + b;
                 k_contract_select<<<grid_for(n, 256), 256, 0, st>>>(n, s, par, nch, xch, stepv, up0, up1);
                 if (s == 0)
                     k_contract_pull0<<<grid_for(n, 256), 256, 0, st>>>(n, parent, (const int32_t *)T->tptr.p,
                                                                       (const int32_t *)T->tadj.p, stepv, up0, up1,
-                                                                      par, nch, xch, rcnt);
+                                                                      par, nch, xch);
                 else
-                    k_contract_apply<<<grid_for(n, 256), 256, 0, st>>>(n, s, stepv, up0, up1, par, nch, xch,
-                                                                      rcnt + b);
+                    k_contract_apply<<<grid_for(n, 256), 256, 0, st>>>(n, s, stepv, up0, up1, par, nch, xch);
             }
             LAUNCH_CHECK(ctx);
-            SGP_TRY(readback(ctx, hbuf, rcnt, 4 * ROUNDS_PER_READ));
-            for (int b = 0; b < ROUNDS_PER_READ && done < n; b++) {
-                if (hbuf[b] <= 0) return set_err(ctx, SGP_EINVAL, "factor_tree: contraction made no progress");
-                done += hbuf[b];
-                S++;
-            }
+            int64_t alive;
+            int32_t maxstep;
+            SGP_TRY(progress(alive, maxstep));
+            if (n - alive <= done) return set_err(ctx, SGP_EINVAL, "factor_tree: contraction made no progress");
+            done = n - alive;
+            S = maxstep + 1;
         }
     }
     M->steps = S;

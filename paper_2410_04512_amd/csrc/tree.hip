@@ -285,14 +285,21 @@ __global__ void k_depth(int64_t n, const int32_t *parent, const int32_t *dpos, c
                         const int32_t *wval, int32_t *depth, int32_t *maxd)
 {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    int32_t d = 0;
-    if (parent[v] >= 0) {
-        int32_t g = dpos[v];
-        d = excl[g] + wval[g];   // inclusive running sum of the tour up to v's entry
+    int32_t d = 0;   // lanes past n take part in the wave maximum with 0
+    if (v < n) {
+        if (parent[v] >= 0) {
+            int32_t g = dpos[v];
+            d = excl[g] + wval[g];   // inclusive running sum of the tour up to v's entry
+        }
+        depth[v] = d;
     }
-    depth[v] = d;
-    atomicMax(maxd, d);
+    // the wave's largest depth, then one atomic per wave that can raise it
+    // (an atomic per vertex on one address would serialise)
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t d2 = __shfl_xor(d, o, 64);
+        d = d2 > d ? d2 : d;
+    }
+    if ((threadIdx.x & 63) == 0 && d > *(volatile int32_t *)maxd) atomicMax(maxd, d);
 }
 
 __global__ void k_count_roots(int64_t n, const int32_t *parent, int32_t *cnt)
