@@ -96,6 +96,28 @@ __global__ void k_bv_mine(const int32_t *act, int64_t na, const int32_t *ei, con
     if (wb == bestw[b] && e < beste[b]) atomicMin(&beste[b], e);
 }
 
+// The first round's best edges, pulled by every vertex from its own edge list
+// (every vertex is its own component then): the same maximum of (w, then
+// smaller id) as the two atomic passes, without their atomics.
+__global__ void k_bv_first(int64_t n, const int32_t *rowptr, const int32_t *ent_edge, const double4 *wu,
+                           unsigned long long *bestw, int32_t *beste)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    unsigned long long bw = 0ull;
+    int32_t be = INT_MAX;
+    for (int32_t p = rowptr[v]; p < rowptr[v + 1]; p++) {
+        const int32_t e = ent_edge[p];
+        const unsigned long long wb = (unsigned long long)__double_as_longlong(wu[e].x);
+        if (wb > bw || (wb == bw && e < be)) {
+            bw = wb;
+            be = e;
+        }
+    }
+    bestw[v] = bw;
+    beste[v] = be;
+}
+
 __global__ void k_bv_hook(const int32_t *ei, const int32_t *ej, int64_t n, const int32_t *comp,
                           const int32_t *beste, int32_t *nxt, int32_t *is_tree, int32_t *flag)
 {
@@ -350,9 +372,14 @@ extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
     SGP_TRY(fill_i32(ctx, is_tree, 0, m + 1));
     int64_t na = m;
     for (int round = 0; round < 64 && na > 0; round++) {
-        k_bv_clear_best<<<grid_for(n, 256), 256, 0, st>>>(bestw, beste, n);
-        k_bv_maxw<<<grid_for(na, 256), 256, 0, st>>>(act, na, ei, ej, wu, comp, bestw);
-        k_bv_mine<<<grid_for(na, 256), 256, 0, st>>>(act, na, ei, ej, wu, comp, bestw, beste);
+        if (round == 0) {
+            k_bv_first<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->rowptr.p,
+                                                        (const int32_t *)g->ent_edge.p, wu, bestw, beste);
+        } else {
+            k_bv_clear_best<<<grid_for(n, 256), 256, 0, st>>>(bestw, beste, n);
+            k_bv_maxw<<<grid_for(na, 256), 256, 0, st>>>(act, na, ei, ej, wu, comp, bestw);
+            k_bv_mine<<<grid_for(na, 256), 256, 0, st>>>(act, na, ei, ej, wu, comp, bestw, beste);
+        }
         SGP_TRY(fill_i32(ctx, flag, 0, 1));
         k_bv_hook<<<grid_for(n, 256), 256, 0, st>>>(ei, ej, n, comp, beste, nxt, is_tree, flag);
         LAUNCH_CHECK(ctx);
