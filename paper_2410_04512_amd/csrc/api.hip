@@ -74,7 +74,7 @@ extern "C" void sgp_graph_free(sgp_graph g)
     if (!g) return;
     (void)hipDeviceSynchronize();
     release(g->rowptr); release(g->col); release(g->ent_edge); release(g->ei);
-    release(g->ej); release(g->wu); release(g->inst_off); release(g->inst_of);
+    release(g->ej); release(g->wu); release(g->inst_off); release(g->inst_of); release(g->w);
     release(g->perm); release(g->inv);
     delete g;
 }

@@ -191,7 +191,7 @@ __global__ void k_compact_rows(const int32_t *slots, int max_deg, const int32_t 
 
 // Upper edges of row i: ids eoff[i] .. eoff[i+1]-1, geometry as the contact test.
 __global__ void k_edges(const double *pos, const double *R, const int32_t *rowptr, const int32_t *col,
-                        const int32_t *eoff, int64_t n, int32_t *ei, int32_t *ej, double4 *wu)
+                        const int32_t *eoff, int64_t n, int32_t *ei, int32_t *ej, double4 *wu, double *w)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -208,6 +208,7 @@ __global__ void k_edges(const double *pos, const double *R, const int32_t *rowpt
         ei[e] = (int32_t)i;
         ej[e] = (int32_t)j;
         wu[e] = make_double4(s - d, dx / d, dy / d, dz / d);
+        w[e] = s - d;
         e++;
     }
 }
@@ -361,13 +362,15 @@ static int collide_impl(sgp_ctx ctx, int64_t n, const double *pos, const double 
     g->m = m;
     int32_t *col, *ee, *ei, *ej;
     double4 *wu;
+    double *wv;
     SGP_TRY(ensure_t(ctx, g->col, 2 * m + 1, &col));
     SGP_TRY(ensure_t(ctx, g->ent_edge, 2 * m + 1, &ee));
     SGP_TRY(ensure_t(ctx, g->ei, m + 1, &ei));
     SGP_TRY(ensure_t(ctx, g->ej, m + 1, &ej));
     SGP_TRY(ensure_t(ctx, g->wu, m + 1, &wu));
+    SGP_TRY(ensure_t(ctx, g->w, m + 1, &wv));
     k_compact_rows<<<grid_for(n, 256), 256, 0, st>>>(slots, max_deg, rowptr, n, col);
-    k_edges<<<grid_for(n, 128), 128, 0, st>>>(pos, radius, rowptr, col, upc, n, ei, ej, wu);
+    k_edges<<<grid_for(n, 128), 128, 0, st>>>(pos, radius, rowptr, col, upc, n, ei, ej, wu, wv);
     k_entry_edges<<<grid_for(n, 128), 128, 0, st>>>(rowptr, col, upc, n, ee);
     LAUNCH_CHECK(ctx);
     return SGP_OK;

@@ -91,6 +91,7 @@ struct sgp_graph_ {
     int64_t n = 0, m = 0, n_inst = 1;
     uint64_t version = 0;   // changes whenever a collide rewrites the graph
     DevBuf rowptr, col, ent_edge, ei, ej, wu, inst_off, inst_of;
+    DevBuf w;   // the contacts' w alone (dense, for passes that read only w)
     DevBuf perm, inv;
     std::vector<int64_t> h_inst_off;
 };

@@ -65,7 +65,7 @@ SGP_DEV void wave_max_by_key(unsigned long long *slot, int32_t key, unsigned lon
     if (pending && val > slot[key]) atomicMax(&slot[key], val);
 }
 
-__global__ void k_bv_maxw(const int32_t *act, int64_t na, const int32_t *ei, const int32_t *ej, const double4 *wu,
+__global__ void k_bv_maxw(const int32_t *act, int64_t na, const int32_t *ei, const int32_t *ej, const double *w,
                           const int32_t *comp, unsigned long long *bestw)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -77,13 +77,13 @@ __global__ void k_bv_maxw(const int32_t *act, int64_t na, const int32_t *ei, con
         a = comp[ei[e]];
         b = comp[ej[e]];
         ok = a != b;
-        wb = (unsigned long long)__double_as_longlong(wu[e].x);
+        wb = (unsigned long long)__double_as_longlong(w[e]);
     }
     wave_max_by_key(bestw, a, wb, ok);
     wave_max_by_key(bestw, b, wb, ok);
 }
 
-__global__ void k_bv_mine(const int32_t *act, int64_t na, const int32_t *ei, const int32_t *ej, const double4 *wu,
+__global__ void k_bv_mine(const int32_t *act, int64_t na, const int32_t *ei, const int32_t *ej, const double *w,
                           const int32_t *comp, const unsigned long long *bestw, int32_t *beste)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -91,7 +91,7 @@ __global__ void k_bv_mine(const int32_t *act, int64_t na, const int32_t *ei, con
     int32_t e = act[k];
     int32_t a = comp[ei[e]], b = comp[ej[e]];
     if (a == b) return;
-    unsigned long long wb = (unsigned long long)__double_as_longlong(wu[e].x);
+    unsigned long long wb = (unsigned long long)__double_as_longlong(w[e]);
     if (wb == bestw[a] && e < beste[a]) atomicMin(&beste[a], e);
     if (wb == bestw[b] && e < beste[b]) atomicMin(&beste[b], e);
 }
@@ -99,7 +99,7 @@ __global__ void k_bv_mine(const int32_t *act, int64_t na, const int32_t *ei, con
 // The first round's best edges, pulled by every vertex from its own edge list
 // (every vertex is its own component then): the same maximum of (w, then
 // smaller id) as the two atomic passes, without their atomics.
-__global__ void k_bv_first(int64_t n, const int32_t *rowptr, const int32_t *ent_edge, const double4 *wu,
+__global__ void k_bv_first(int64_t n, const int32_t *rowptr, const int32_t *ent_edge, const double *w,
                            unsigned long long *bestw, int32_t *beste)
 {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -108,7 +108,7 @@ __global__ void k_bv_first(int64_t n, const int32_t *rowptr, const int32_t *ent_
     int32_t be = INT_MAX;
     for (int32_t p = rowptr[v]; p < rowptr[v + 1]; p++) {
         const int32_t e = ent_edge[p];
-        const unsigned long long wb = (unsigned long long)__double_as_longlong(wu[e].x);
+        const unsigned long long wb = (unsigned long long)__double_as_longlong(w[e]);
         if (wb > bw || (wb == bw && e < be)) {
             bw = wb;
             be = e;
@@ -350,7 +350,7 @@ extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
         return SGP_OK;
     }
     const int32_t *ei = (const int32_t *)g->ei.p, *ej = (const int32_t *)g->ej.p;
-    const double4 *wu = (const double4 *)g->wu.p;
+    const double *wonly = (const double *)g->w.p;
     // ---- Boruvka
     unsigned long long *bestw;
     int32_t *beste, *nxt, *nxt2, *is_tree, *flag;
@@ -374,11 +374,11 @@ extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
     for (int round = 0; round < 64 && na > 0; round++) {
         if (round == 0) {
             k_bv_first<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->rowptr.p,
-                                                        (const int32_t *)g->ent_edge.p, wu, bestw, beste);
+                                                        (const int32_t *)g->ent_edge.p, wonly, bestw, beste);
         } else {
             k_bv_clear_best<<<grid_for(n, 256), 256, 0, st>>>(bestw, beste, n);
-            k_bv_maxw<<<grid_for(na, 256), 256, 0, st>>>(act, na, ei, ej, wu, comp, bestw);
-            k_bv_mine<<<grid_for(na, 256), 256, 0, st>>>(act, na, ei, ej, wu, comp, bestw, beste);
+            k_bv_maxw<<<grid_for(na, 256), 256, 0, st>>>(act, na, ei, ej, wonly, comp, bestw);
+            k_bv_mine<<<grid_for(na, 256), 256, 0, st>>>(act, na, ei, ej, wonly, comp, bestw, beste);
         }
         SGP_TRY(fill_i32(ctx, flag, 0, 1));
         k_bv_hook<<<grid_for(n, 256), 256, 0, st>>>(ei, ej, n, comp, beste, nxt, is_tree, flag);
