@@ -237,8 +237,10 @@ __global__ void k_tsort(int64_t n, const int32_t *tptr, int32_t *adj, int32_t *a
 }
 
 // twin, Euler successor, cut at the root of each tree
+// sr[k] = (successor, rank so far) of dart k, one 8-byte word: a jump reads
+// both with one gather
 __global__ void k_tour(int64_t nd, const int32_t *tptr, const int32_t *adj, const int32_t *adje,
-                       const int32_t *comp, int32_t *twin, int32_t *succ, int32_t *rank)
+                       const int32_t *comp, int32_t *twin, int2 *sr)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nd) return;
@@ -252,23 +254,26 @@ __global__ void k_tour(int64_t nd, const int32_t *tptr, const int32_t *adj, cons
     int32_t nx = (lo + 1 < tptr[b + 1]) ? lo + 1 : tptr[b];
     bool is_root = comp[b] == b;   // components are labelled by their smallest vertex
     if (is_root && nx == tptr[b]) nx = -1;   // tour of b's tree ends when it returns to b the last time
-    succ[k] = nx;
-    rank[k] = (nx < 0) ? 0 : 1;
+    sr[k] = make_int2(nx, nx < 0 ? 0 : 1);
 }
 
-__global__ void k_rank_jump(int64_t nd, const int32_t *nxt_in, const int32_t *rank_in, int32_t *nxt_out,
-                            int32_t *rank_out)
+__global__ void k_rank_jump(int64_t nd, const int2 *sr_in, int2 *sr_out)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nd) return;
-    int32_t nx = nxt_in[k];
-    if (nx < 0) {
-        nxt_out[k] = -1;
-        rank_out[k] = rank_in[k];
+    const int2 a = sr_in[k];
+    if (a.x < 0) {
+        sr_out[k] = a;
         return;
     }
-    rank_out[k] = rank_in[k] + rank_in[nx];
-    nxt_out[k] = nxt_in[nx];
+    const int2 b = sr_in[a.x];
+    sr_out[k] = make_int2(b.x, a.y + b.y);
+}
+
+__global__ void k_rank_unpack(int64_t nd, const int2 *sr, int32_t *rank)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nd) rank[k] = sr[k].y;
 }
 
 // component tour lengths at the root's index: 2 (size - 1) = rank(first dart) + 1
@@ -427,26 +432,25 @@ extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
     if (nt > 0) k_tdeg<<<grid_for(nt, 256), 256, 0, st>>>(te, nt, ei, ej, tdeg);
     SGP_TRY(scan_exclusive(ctx, tdeg, tptr, n));
     const int64_t nd = 2 * nt;
-    int32_t *adj, *adje, *from, *twin, *succ, *rank, *succ2, *rank2;
+    int32_t *adj, *adje, *from, *twin, *slots, *rank;
     SGP_TRY(ensure_t(ctx, T->tadj, nd + 1, &adj));
     SGP_TRY(ensure_t(ctx, T->tadje, nd + 1, &adje));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_VAL_A], nd + 1, &from));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_VAL_B], nd + 1, &twin));
-    SGP_TRY(ensure_t(ctx, ctx->ws[WS_SLOTS], 4 * (nd + 1), &succ));
-    succ2 = succ + (nd + 1);
-    rank = succ2 + (nd + 1);
-    rank2 = rank + (nd + 1);
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_SLOTS], 6 * (nd + 1), &slots));
+    int2 *sra = (int2 *)slots, *srb = sra + (nd + 1);
+    rank = slots + 4 * (nd + 1);
     int32_t *hmax = (int32_t *)ctx->pinned;
     if (nt > 0) {
         k_tfill<<<grid_for(nt, 256), 256, 0, st>>>(te, nt, ei, ej, tptr, cur, adj, adje);
         k_tsort<<<grid_for(n, 256), 256, 0, st>>>(n, tptr, adj, adje, from);
-        k_tour<<<grid_for(nd, 256), 256, 0, st>>>(nd, tptr, adj, adje, comp, twin, succ, rank);
+        k_tour<<<grid_for(nd, 256), 256, 0, st>>>(nd, tptr, adj, adje, comp, twin, sra);
         LAUNCH_CHECK(ctx);
         for (int64_t span = 1; span < nd; span *= 2) {
-            k_rank_jump<<<grid_for(nd, 256), 256, 0, st>>>(nd, succ, rank, succ2, rank2);
-            std::swap(succ, succ2);
-            std::swap(rank, rank2);
+            k_rank_jump<<<grid_for(nd, 256), 256, 0, st>>>(nd, sra, srb);
+            std::swap(sra, srb);
         }
+        k_rank_unpack<<<grid_for(nd, 256), 256, 0, st>>>(nd, sra, rank);
         LAUNCH_CHECK(ctx);
         // buffer reuse: cur (done) holds the tour lengths, then the entry
         // positions; tdeg (scanned into tptr already) holds the tour bases
