@@ -53,47 +53,80 @@ __global__ void k_int_degree(int64_t n, const int32_t *rowptr, const int32_t *pe
 // forms the diagonal block.
 constexpr int ASM_LANES = 16;
 
-__global__ void k_assemble(int64_t n, const int32_t *rowptr, const int32_t *col, const int32_t *ent_edge,
-                           const double4 *wu, const int32_t *perm, const int32_t *inv, double gpar, double gperp,
-                           double gmed, const int32_t *brow, int32_t *bcol, double *val, int32_t *diagpos,
-                           int32_t *ecol, double *ew, double *dg)
+__global__ __launch_bounds__(256) void k_assemble(int64_t n, const int32_t *rowptr, const int32_t *col,
+                                                  const int32_t *ent_edge, const double4 *wu, const int32_t *perm,
+                                                  const int32_t *inv, double gpar, double gperp, double gmed,
+                                                  const int32_t *brow, int32_t *bcol, double *val,
+                                                  int32_t *diagpos, int32_t *ecol, double *ew, double *dg)
 {
+    // per 16-lane group: the 16 blocks W of one round, for the diagonal sum
+    __shared__ double sW[256 / ASM_LANES][ASM_LANES][9];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = t / ASM_LANES;
     const int c0 = (int)(t % ASM_LANES);
-    if (i >= n) return;
-    const int32_t u = perm[i];
-    const int32_t b = rowptr[u], e = rowptr[u + 1];
-    const int64_t k0 = brow[i];
-    for (int32_t c = c0; c < e - b; c += ASM_LANES) {
-        const double4 q = wu[ent_edge[b + c]];
-        double W[9], B[9];
-        friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
-        for (int x = 0; x < 9; x++) B[x] = -W[x];
-        put_sym(val, k0 + c, B);
-        const int32_t jc = inv[col[b + c]];
-        bcol[k0 + c] = jc;
-        // edge form: entry k0 + c - i
-        const int64_t ke = k0 + c - i;
-        double *g = ew + (ke >> 6) * 256 + (ke & 63);
-        g[0] = q.x;
-        g[64] = q.y;
-        g[128] = q.z;
-        g[192] = q.w;
-        ecol[ke] = jc;
+    const int grp = threadIdx.x / ASM_LANES;
+    const bool row_ok = i < n;
+    int32_t b = 0, e = 0;
+    int64_t k0 = 0;
+    if (row_ok) {
+        const int32_t u = perm[i];
+        b = rowptr[u];
+        e = rowptr[u + 1];
+        k0 = brow[i];
+    }
+    const int deg = e - b;
+    // rounds of 16 blocks; the same count for the whole wave (its largest row)
+    int rounds = (deg + ASM_LANES - 1) / ASM_LANES;
+    for (int o = 32; o > 0; o >>= 1) {
+        const int r2 = __shfl_xor(rounds, o, 64);
+        rounds = r2 > rounds ? r2 : rounds;
+    }
+    // lane x < 9 of the group keeps entry x of the diagonal block and adds the
+    // blocks' entry x in the row's neighbour order, as the definition sums them
+    double d = (c0 < 9 && c0 % 4 == 0) ? gmed : 0.0;
+    for (int r = 0; r < rounds; r++) {
+        const int c = r * ASM_LANES + c0;
+        double W[9];
+        for (int x = 0; x < 9; x++) W[x] = 0.0;
+        if (row_ok && c < deg) {
+            const double4 q = wu[ent_edge[b + c]];
+            double B[9];
+            friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
+            for (int x = 0; x < 9; x++) B[x] = -W[x];
+            put_sym(val, k0 + c, B);
+            const int32_t jc = inv[col[b + c]];
+            bcol[k0 + c] = jc;
+            // edge form: entry k0 + c - i
+            const int64_t ke = k0 + c - i;
+            double *g = ew + (ke >> 6) * 256 + (ke & 63);
+            g[0] = q.x;
+            g[64] = q.y;
+            g[128] = q.z;
+            g[192] = q.w;
+            ecol[ke] = jc;
+        }
+        for (int x = 0; x < 9; x++) sW[grp][c0][x] = W[x];
+        // lanes exchange through LDS within their wave only
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+        if (c0 < 9) {
+            const int kmax = deg - r * ASM_LANES < ASM_LANES ? deg - r * ASM_LANES : ASM_LANES;
+            for (int k = 0; k < kmax; k++) d = d + sW[grp][k][c0];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    }
+    if (!row_ok) return;
+    // the six distinct entries of the symmetric diagonal block, one per lane
+    const int slot = c0 == 0 ? 0 : c0 == 1 ? 1 : c0 == 2 ? 2 : c0 == 4 ? 3 : c0 == 5 ? 4 : c0 == 8 ? 5 : -1;
+    const int64_t k = k0 + deg;
+    if (slot >= 0) {
+        val[(k >> 6) * 384 + 64 * slot + (k & 63)] = d;
+        dg[(i >> 6) * 384 + 64 * slot + (i & 63)] = d;
     }
     if (c0 == 0) {
-        double D[9];
-        for (int x = 0; x < 9; x++) D[x] = (x % 4 == 0) ? gmed : 0.0;
-        for (int32_t p = b; p < e; p++) {
-            const double4 q = wu[ent_edge[p]];
-            double W[9];
-            friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
-            for (int x = 0; x < 9; x++) D[x] = D[x] + W[x];
-        }
-        const int64_t k = k0 + (e - b);
-        put_sym(val, k, D);
-        put_sym(dg, i, D);
         bcol[k] = (int32_t)i;
         diagpos[i] = (int32_t)k;
     }
