@@ -15,7 +15,7 @@
  * is fused into an add behind our back (the contact geometry must round the
  * same way as the definition written here).
  *
- * Readings of the paper taken here (each one is listed in the design doc):
+ * Readings of the paper taken here (where it is silent or ambiguous):
  *  - contact: d_ij = sqrt((dx*dx + dy*dy) + dz*dz), dx = x_j - x_i, contact
  *    iff d_ij < R_i + R_j (strict), overlap w_ij = (R_i + R_j) - d_ij stands
  *    in for the contact area A_ij, u_ij = (r_j - r_i)/d_ij for i < j.

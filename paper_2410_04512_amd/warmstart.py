@@ -5,8 +5,8 @@ the friction solve, an explicit Euler position update) runs through libsgp:
 collide -> forces -> assemble_gamma -> build_tree -> factor_tree -> pcg_solve
 -> euler.  The warm start is not part of the paper's method: a message-passing
 network maps (F, v_prev) on the collision graph to a guess x0 for the solve.
-CG to the same relative residual stays the judge, so the network only changes
-how many iterations the solve needs.  The network is trained on the energy
+CG to the same relative residual still decides the result, so the network
+only changes how many iterations the solve needs.  The network is trained on the energy
 norm of its error, ||v_hat - v||_Gamma, the norm CG's progress is measured in;
 at run time its guess is used when its energy 0.5 x' Gamma x - x' F is below
 that of v_prev, and v_prev is the fallback.
