@@ -79,6 +79,19 @@ __global__ void k_tree_blocks(int64_t n, const int32_t *tptr, const int32_t *tad
 
 // ---------------------------------------------------------------- schedules
 
+// (w, u) of the first step's couplings: plane 0 the edge to the up-link
+// (the tree parent), plane 1 for a compressed vertex the edge from its child
+__global__ void k_step0_wu(int32_t q1, const int32_t *elim, const int32_t *upq, const int32_t *pedge,
+                           const double4 *wu, double4 *out)
+{
+    const int32_t q = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q >= q1) return;
+    const int32_t pe = pedge[elim[q]];
+    out[q] = pe >= 0 ? wu[pe] : make_double4(0.0, 0.0, 0.0, 0.0);
+    const int32_t qb = upq[2 * q + 1];
+    out[q1 + q] = qb >= 0 ? wu[pedge[elim[qb]]] : make_double4(0.0, 0.0, 0.0, 0.0);
+}
+
 __global__ void k_sched_level(int64_t n, const int32_t *depth, const int32_t *parent, int32_t maxd,
                               int32_t *stepv, int32_t *up0, int32_t *up1)
 {
@@ -580,6 +593,96 @@ SGP_DEV void bwd_vertex(int32_t q, const int32_t *elim, const int32_t *upq, cons
     z[3 * v + 2] = n2;
 }
 
+// -W p for the block W = w (g_perp I + (g_par - g_perp) u u^T) of contact
+// e = (w, u): the coupling of a first-step vertex, from 4 values instead of 9
+template <class T>
+SGP_DEV void neg_w_mv(const T *e, T gpar, T gperp, T p0, T p1, T p2, T &o0, T &o1, T &o2)
+{
+    const T w = e[0], u0 = e[1], u1 = e[2], u2 = e[3];
+    const T c = (gpar - gperp) * ((u0 * p0 + u1 * p1) + u2 * p2);
+    o0 = -(w * (gperp * p0 + c * u0));
+    o1 = -(w * (gperp * p1 + c * u1));
+    o2 = -(w * (gperp * p2 + c * u2));
+}
+
+// The first elimination step, couplings from (w, u) (planes of ws values):
+// forward, its vertices have no in-slots, so y = Dinv r and the pushes
+// follow; backward, x = y - Dinv (sum over up-links of W x) and only z is
+// written (no vertex reads a first-step x).
+template <class T>
+__global__ void k_fwd_step0(int32_t q1, const int32_t *elim, const int32_t *tout, const T *wu, int64_t ws,
+                            T gpar, T gperp, const T *Dinv, const T *r, T *y, T *cs, const PcgScalars *s)
+{
+    const int32_t q = (int32_t)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
+    if (q >= q1) return;
+    const int32_t dn = done_flag(s);
+    const int64_t v = elim[q];
+    const int32_t to0 = tout[2 * q], to1 = tout[2 * q + 1];
+    T d[6], e0[4], e1[4];
+    for (int k = 0; k < 6; k++) d[k] = Dinv[6 * (int64_t)q + k];
+    for (int k = 0; k < 4; k++) e0[k] = wu[4 * (int64_t)q + k];
+    const T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
+    if (to1 >= 0)
+        for (int k = 0; k < 4; k++) e1[k] = wu[ws + 4 * (int64_t)q + k];
+    keep_loads_above();
+    if (dn) return;
+    T o0, o1, o2;
+    sym_mv(d, b0, b1, b2, o0, o1, o2);
+    y[3 * (int64_t)q] = o0;
+    y[3 * (int64_t)q + 1] = o1;
+    y[3 * (int64_t)q + 2] = o2;
+    if (to0 >= 0) {
+        T *c = cs + 3 * (int64_t)to0;
+        neg_w_mv(e0, gpar, gperp, o0, o1, o2, c[0], c[1], c[2]);
+    }
+    if (to1 >= 0) {
+        T *c = cs + 3 * (int64_t)to1;
+        neg_w_mv(e1, gpar, gperp, o0, o1, o2, c[0], c[1], c[2]);
+    }
+}
+
+template <class T>
+__global__ void k_bwd_step0(int32_t q1, const int32_t *elim, const int32_t *upq, const T *wu, int64_t ws, T gpar,
+                            T gperp, const T *Dinv, const T *y, T *z, const PcgScalars *s)
+{
+    const int32_t q = (int32_t)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
+    if (q >= q1) return;
+    const int32_t dn = done_flag(s);
+    const int32_t w0 = upq[2 * q], w1 = upq[2 * q + 1];
+    const int64_t v = elim[q];
+    T d[6], e0[4], e1[4];
+    for (int k = 0; k < 6; k++) d[k] = Dinv[6 * (int64_t)q + k];
+    for (int k = 0; k < 4; k++) e0[k] = wu[4 * (int64_t)q + k];
+    const T y0 = y[3 * (int64_t)q], y1 = y[3 * (int64_t)q + 1], y2 = y[3 * (int64_t)q + 2];
+    const int64_t u0 = w0 >= 0 ? w0 : q, u1 = w1 >= 0 ? w1 : q;
+    const T p0 = y[3 * u0], p1 = y[3 * u0 + 1], p2 = y[3 * u0 + 2];
+    const T x0 = y[3 * u1], x1 = y[3 * u1 + 1], x2 = y[3 * u1 + 2];
+    if (w1 >= 0)
+        for (int k = 0; k < 4; k++) e1[k] = wu[ws + 4 * (int64_t)q + k];
+    keep_loads_above();
+    if (dn) return;
+    T a0 = 0, a1 = 0, a2 = 0;
+    if (w0 >= 0) {
+        T c0, c1, c2;
+        neg_w_mv(e0, gpar, gperp, p0, p1, p2, c0, c1, c2);
+        a0 = a0 + c0;
+        a1 = a1 + c1;
+        a2 = a2 + c2;
+    }
+    if (w1 >= 0) {
+        T c0, c1, c2;
+        neg_w_mv(e1, gpar, gperp, x0, x1, x2, c0, c1, c2);
+        a0 = a0 + c0;
+        a1 = a1 + c1;
+        a2 = a2 + c2;
+    }
+    T e0_, e1_, e2_;
+    sym_mv(d, a0, a1, a2, e0_, e1_, e2_);
+    z[3 * v] = y0 - e0_;
+    z[3 * v + 1] = y1 - e1_;
+    z[3 * v + 2] = y2 - e2_;
+}
+
 template <class T>
 __global__ void k_fwd_step(int32_t q0, int32_t q1, const int32_t *elim, const int32_t *in_ptr,
                            const int32_t *tout, const T *F, int64_t fs, const T *Dinv, const T *r, T *y, T *cs,
@@ -1002,7 +1105,7 @@ __global__ void k_copy_vec(int64_t len, const T *a, T *b, const PcgScalars *s)
 
 template <class T>
 static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y, T *cs, const T *r, T *z,
-                       PcgScalars *s)
+                       PcgScalars *s, const T *wu0)
 {
     hipStream_t st = ctx->stream;
     // r and z are in the internal order
@@ -1016,9 +1119,15 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
     if (L > 0)
         k_fwd_light<T><<<M->light_nwg, 256, 0, st>>>(L, M->light_nwg, wptr, elim, in_ptr, tout, F, fs, Dinv, r, y,
                                                     cs, s);
+    // the first step from the contacts' (w, u) when it is one of these launches
+    const bool step0_wu = wu0 && L == 0 && ts > 0 && M->n_wu0 == sp[1];
+    const T gp = (T)M->gpar, gq = (T)M->gperp;
     for (int k = L; k < ts; k++) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
-        if (q1 > q0)
+        if (k == 0 && step0_wu)
+            k_fwd_step0<T><<<grid_for(q1, 256), 256, 0, st>>>(q1, elim, tout, wu0, 4 * (int64_t)q1, gp, gq, Dinv, r,
+                                                              y, cs, s);
+        else if (q1 > q0)
             k_fwd_step<T><<<grid_for(q1 - q0, 256), 256, 0, st>>>(q0, q1, elim, in_ptr, tout, F, fs, Dinv, r, y, cs,
                                                                   s);
     }
@@ -1040,7 +1149,10 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
     }
     for (int k = ts - 1; k >= L; k--) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
-        if (q1 > q0)
+        if (k == 0 && step0_wu)
+            k_bwd_step0<T><<<grid_for(q1, 256), 256, 0, st>>>(q1, elim, upq, wu0, 4 * (int64_t)q1, gp, gq, Dinv, y,
+                                                              z, s);
+        else if (q1 > q0)
             k_bwd_step<T><<<grid_for(q1 - q0, 256), 256, 0, st>>>(q0, q1, elim, upq, F, fs, Dinv, y, z, s, k > 0);
     }
     if (L > 0)
@@ -1063,7 +1175,7 @@ int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScala
         return SGP_OK;
     }
     return tree_sweeps<double>(ctx, M, (const double *)M->F.p, (const double *)M->Dinv.p, (double *)M->y.p,
-                               (double *)M->cs.p, r, z, s);
+                               (double *)M->cs.p, r, z, s, M->n_wu0 > 0 ? (const double *)M->wu0.p : nullptr);
 }
 
 int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s)
@@ -1075,7 +1187,7 @@ int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars
         return SGP_OK;
     }
     return tree_sweeps<float>(ctx, M, (const float *)M->F32.p, (const float *)M->Dinv32.p, (float *)M->y32.p,
-                              (float *)M->cs32.p, r, z, s);
+                              (float *)M->cs32.p, r, z, s, M->n_wu0 > 0 ? (const float *)M->wu032.p : nullptr);
 }
 
 __global__ void k_to_f32(int64_t len, const double *a, float *b)
@@ -1099,6 +1211,11 @@ int prec_make32(sgp_ctx ctx, sgp_prec M)
         SGP_TRY(ensure_t(ctx, M->cs32, 6 * n + 6, &cs32));
         k_to_f32<<<grid_for(18 * n, 256), 256, 0, st>>>(18 * n, (const double *)M->F.p, F32);
         k_to_f32<<<grid_for(6 * n, 256), 256, 0, st>>>(6 * n, (const double *)M->Dinv.p, D32);
+        if (M->n_wu0 > 0) {
+            float *w32;
+            SGP_TRY(ensure_t(ctx, M->wu032, 8 * M->n_wu0 + 8, &w32));
+            k_to_f32<<<grid_for(8 * M->n_wu0, 256), 256, 0, st>>>(8 * M->n_wu0, (const double *)M->wu0.p, w32);
+        }
     } else if (M->kind == PREC_JACOBI) {
         SGP_TRY(ensure_t(ctx, M->Dinv32, 6 * n + 1, &D32));
         k_to_f32<<<grid_for(6 * n, 256), 256, 0, st>>>(6 * n, (const double *)M->jdinv.p, D32);
@@ -1357,6 +1474,20 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
                                                                   9 * n, Dinv, status);
     }
     LAUNCH_CHECK(ctx);
+    // the first step's couplings in their (w, u) form (no light steps: with
+    // them the first step runs inside the light-subtree sweeps)
+    M->n_wu0 = 0;
+    M->gpar = g_par;
+    M->gperp = g_perp;
+    if (S > 0 && M->light_steps == 0 && M->h_step_ptr[1] > 0) {
+        const int32_t q1 = M->h_step_ptr[1];
+        double *w0;
+        SGP_TRY(ensure_t(ctx, M->wu0, 8 * (size_t)q1 + 8, &w0));
+        k_step0_wu<<<grid_for(q1, 256), 256, 0, st>>>(q1, elim, upq, (const int32_t *)T->pedge.p,
+                                                      (const double4 *)g->wu.p, (double4 *)w0);
+        LAUNCH_CHECK(ctx);
+        M->n_wu0 = q1;
+    }
     // push slots of the forward sweep: in-list position of every (q, k)
     int32_t *tout;
     double *cs;

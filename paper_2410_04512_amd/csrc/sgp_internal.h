@@ -144,6 +144,12 @@ struct sgp_prec_ {
     int32_t tail_nt = 0, tail_ni = 0;                   // tail vertices, tail-internal push slots
     DevBuf tail_iptr, tail_tslot;                       // per tail target: first internal slot; per (q,k): its slot
     DevBuf tail_b;                                      // [tail_nt][3] right-hand sides entering the tail
+    // the first step's couplings as the contacts' (w, u) (nothing has been
+    // eliminated before it, so each is -W_e of a tree edge): planes
+    // [2][n_wu0][4], read by the first step of the sweeps instead of F
+    DevBuf wu0, wu032;
+    int64_t n_wu0 = 0;
+    double gpar = 0, gperp = 0;
     DevBuf F32, Dinv32, y32, cs32;                      // FP32 copies for the refinement inner solve
     bool have32 = false;
     DevBuf jdinv;                                       // Jacobi: [n][6]
