@@ -605,13 +605,30 @@ SGP_DEV void neg_w_mv(const T *e, T gpar, T gperp, T p0, T p1, T p2, T &o0, T &o
     o2 = -(w * (gperp * p2 + c * u2));
 }
 
+// The pivot solve of a first-step vertex with at most one tree edge (a leaf,
+// or a lone vertex: w = 0): its pivot is P_qq = g_med I + W_e =
+// c I + d u u^T with c = g_med + w g_perp, d = w (g_par - g_perp), whose
+// inverse is I / c - d / (c (c + d)) u u^T (|u| = 1), so it needs no stored
+// inverse; a compressed vertex (two tree edges) uses its stored one.
+template <class T>
+SGP_DEV void leaf_pivot_solve(const T *e, T gpar, T gperp, T gmed, T b0, T b1, T b2, T &o0, T &o1, T &o2)
+{
+    const T w = e[0], u0 = e[1], u1 = e[2], u2 = e[3];
+    const T c = gmed + w * gperp, cd = gmed + w * gpar;
+    const T beta = (w * (gpar - gperp)) / (c * cd);
+    const T ub = beta * ((u0 * b0 + u1 * b1) + u2 * b2);
+    o0 = b0 / c - ub * u0;
+    o1 = b1 / c - ub * u1;
+    o2 = b2 / c - ub * u2;
+}
+
 // The first elimination step, couplings from (w, u) (planes of ws values):
-// forward, its vertices have no in-slots, so y = Dinv r and the pushes
-// follow; backward, x = y - Dinv (sum over up-links of W x) and only z is
-// written (no vertex reads a first-step x).
+// forward, its vertices have no in-slots, so y = P_qq^{-1} r and the pushes
+// follow; backward, x = y - P_qq^{-1} (sum over up-links of W x) and only z
+// is written (no vertex reads a first-step x).
 template <class T>
 __global__ void k_fwd_step0(int32_t q1, const int32_t *elim, const int32_t *tout, const T *wu, int64_t ws,
-                            T gpar, T gperp, const T *Dinv, const T *r, T *y, T *cs, const PcgScalars *s)
+                            T gpar, T gperp, T gmed, const T *Dinv, const T *r, T *y, T *cs, const PcgScalars *s)
 {
     const int32_t q = (int32_t)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
     if (q >= q1) return;
@@ -619,15 +636,19 @@ __global__ void k_fwd_step0(int32_t q1, const int32_t *elim, const int32_t *tout
     const int64_t v = elim[q];
     const int32_t to0 = tout[2 * q], to1 = tout[2 * q + 1];
     T d[6], e0[4], e1[4];
-    for (int k = 0; k < 6; k++) d[k] = Dinv[6 * (int64_t)q + k];
     for (int k = 0; k < 4; k++) e0[k] = wu[4 * (int64_t)q + k];
     const T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
-    if (to1 >= 0)
+    if (to1 >= 0) {
         for (int k = 0; k < 4; k++) e1[k] = wu[ws + 4 * (int64_t)q + k];
+        for (int k = 0; k < 6; k++) d[k] = Dinv[6 * (int64_t)q + k];
+    }
     keep_loads_above();
     if (dn) return;
     T o0, o1, o2;
-    sym_mv(d, b0, b1, b2, o0, o1, o2);
+    if (to1 >= 0)
+        sym_mv(d, b0, b1, b2, o0, o1, o2);
+    else
+        leaf_pivot_solve(e0, gpar, gperp, gmed, b0, b1, b2, o0, o1, o2);
     y[3 * (int64_t)q] = o0;
     y[3 * (int64_t)q + 1] = o1;
     y[3 * (int64_t)q + 2] = o2;
@@ -643,7 +664,7 @@ __global__ void k_fwd_step0(int32_t q1, const int32_t *elim, const int32_t *tout
 
 template <class T>
 __global__ void k_bwd_step0(int32_t q1, const int32_t *elim, const int32_t *upq, const T *wu, int64_t ws, T gpar,
-                            T gperp, const T *Dinv, const T *y, T *z, const PcgScalars *s)
+                            T gperp, T gmed, const T *Dinv, const T *y, T *z, const PcgScalars *s)
 {
     const int32_t q = (int32_t)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
     if (q >= q1) return;
@@ -651,14 +672,15 @@ __global__ void k_bwd_step0(int32_t q1, const int32_t *elim, const int32_t *upq,
     const int32_t w0 = upq[2 * q], w1 = upq[2 * q + 1];
     const int64_t v = elim[q];
     T d[6], e0[4], e1[4];
-    for (int k = 0; k < 6; k++) d[k] = Dinv[6 * (int64_t)q + k];
     for (int k = 0; k < 4; k++) e0[k] = wu[4 * (int64_t)q + k];
     const T y0 = y[3 * (int64_t)q], y1 = y[3 * (int64_t)q + 1], y2 = y[3 * (int64_t)q + 2];
     const int64_t u0 = w0 >= 0 ? w0 : q, u1 = w1 >= 0 ? w1 : q;
     const T p0 = y[3 * u0], p1 = y[3 * u0 + 1], p2 = y[3 * u0 + 2];
     const T x0 = y[3 * u1], x1 = y[3 * u1 + 1], x2 = y[3 * u1 + 2];
-    if (w1 >= 0)
+    if (w1 >= 0) {
         for (int k = 0; k < 4; k++) e1[k] = wu[ws + 4 * (int64_t)q + k];
+        for (int k = 0; k < 6; k++) d[k] = Dinv[6 * (int64_t)q + k];
+    }
     keep_loads_above();
     if (dn) return;
     T a0 = 0, a1 = 0, a2 = 0;
@@ -677,7 +699,10 @@ __global__ void k_bwd_step0(int32_t q1, const int32_t *elim, const int32_t *upq,
         a2 = a2 + c2;
     }
     T e0_, e1_, e2_;
-    sym_mv(d, a0, a1, a2, e0_, e1_, e2_);
+    if (w1 >= 0)
+        sym_mv(d, a0, a1, a2, e0_, e1_, e2_);
+    else
+        leaf_pivot_solve(e0, gpar, gperp, gmed, a0, a1, a2, e0_, e1_, e2_);
     z[3 * v] = y0 - e0_;
     z[3 * v + 1] = y1 - e1_;
     z[3 * v + 2] = y2 - e2_;
@@ -1121,12 +1146,12 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
                                                     cs, s);
     // the first step from the contacts' (w, u) when it is one of these launches
     const bool step0_wu = wu0 && L == 0 && ts > 0 && M->n_wu0 == sp[1];
-    const T gp = (T)M->gpar, gq = (T)M->gperp;
+    const T gp = (T)M->gpar, gq = (T)M->gperp, gm = (T)M->gmed;
     for (int k = L; k < ts; k++) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
         if (k == 0 && step0_wu)
-            k_fwd_step0<T><<<grid_for(q1, 256), 256, 0, st>>>(q1, elim, tout, wu0, 4 * (int64_t)q1, gp, gq, Dinv, r,
-                                                              y, cs, s);
+            k_fwd_step0<T><<<grid_for(q1, 256), 256, 0, st>>>(q1, elim, tout, wu0, 4 * (int64_t)q1, gp, gq, gm, Dinv,
+                                                              r, y, cs, s);
         else if (q1 > q0)
             k_fwd_step<T><<<grid_for(q1 - q0, 256), 256, 0, st>>>(q0, q1, elim, in_ptr, tout, F, fs, Dinv, r, y, cs,
                                                                   s);
@@ -1150,8 +1175,8 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
     for (int k = ts - 1; k >= L; k--) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
         if (k == 0 && step0_wu)
-            k_bwd_step0<T><<<grid_for(q1, 256), 256, 0, st>>>(q1, elim, upq, wu0, 4 * (int64_t)q1, gp, gq, Dinv, y,
-                                                              z, s);
+            k_bwd_step0<T><<<grid_for(q1, 256), 256, 0, st>>>(q1, elim, upq, wu0, 4 * (int64_t)q1, gp, gq, gm, Dinv,
+                                                              y, z, s);
         else if (q1 > q0)
             k_bwd_step<T><<<grid_for(q1 - q0, 256), 256, 0, st>>>(q0, q1, elim, upq, F, fs, Dinv, y, z, s, k > 0);
     }
@@ -1479,6 +1504,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     M->n_wu0 = 0;
     M->gpar = g_par;
     M->gperp = g_perp;
+    M->gmed = g_med;
     if (S > 0 && M->light_steps == 0 && M->h_step_ptr[1] > 0) {
         const int32_t q1 = M->h_step_ptr[1];
         double *w0;

@@ -149,7 +149,7 @@ struct sgp_prec_ {
     // [2][n_wu0][4], read by the first step of the sweeps instead of F
     DevBuf wu0, wu032;
     int64_t n_wu0 = 0;
-    double gpar = 0, gperp = 0;
+    double gpar = 0, gperp = 0, gmed = 0;
     DevBuf F32, Dinv32, y32, cs32;                      // FP32 copies for the refinement inner solve
     bool have32 = false;
     DevBuf jdinv;                                       // Jacobi: [n][6]
