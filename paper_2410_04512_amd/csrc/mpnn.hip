@@ -387,7 +387,8 @@ __global__ void k_add64(int64_t n, const float *a, int64_t lda, const float *b, 
     dst[i * ldd + c] = a[i * lda + c] + b[i * ldb + c];
 }
 
-// ---------------------------------------------------------------- messages (one wave per row, lane = feature)
+// ---------------------------------------------------------------- messages (forward: 16 lanes per row, four
+// features per lane; backward: one wave per row, lane = feature)
 
 // A row's entries are taken MSG_BATCH at a time: their column ids and edge
 // features first, then all their neighbour gathers, then the arithmetic in
@@ -399,18 +400,21 @@ __global__ __launch_bounds__(256) void k_msg_fwd(int64_t n, const int32_t *rowpt
                                                  const float4 *ef, const float *PQ, const float *bm,
                                                  const float *Wc, float *agg)
 {
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-    const int f = threadIdx.x & 63;
+    // 16 lanes per node, four features per lane (one 16-byte load of a
+    // neighbour's 64 features per 16 lanes), 16 nodes per workgroup
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * 16 + (threadIdx.x >> 4);
+    const int f = 4 * (threadIdx.x & 15);
     if (i >= n) return;
-    const float Pi = PQ[i * 128 + f] + bm[f];
-    const float w0 = Wc[f], w1 = Wc[64 + f], w2 = Wc[128 + f], w3 = Wc[192 + f];
-    float acc = 0.f;
+    const float4 pq = *(const float4 *)(PQ + i * 128 + f), b4 = *(const float4 *)(bm + f);
+    const float P0 = pq.x + b4.x, P1 = pq.y + b4.y, P2 = pq.z + b4.z, P3 = pq.w + b4.w;
+    const float4 w0 = *(const float4 *)(Wc + f), w1 = *(const float4 *)(Wc + 64 + f);
+    const float4 w2 = *(const float4 *)(Wc + 128 + f), w3 = *(const float4 *)(Wc + 192 + f);
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
     const int32_t re = rowptr[i + 1];
     for (int32_t p = rowptr[i]; p < re; p += MSG_BATCH) {
         const int cnt = re - p < MSG_BATCH ? re - p : MSG_BATCH;
         int64_t jj[MSG_BATCH];
-        float4 ee[MSG_BATCH];
-        float qv[MSG_BATCH];
+        float4 ee[MSG_BATCH], qv[MSG_BATCH];
 #pragma unroll
         for (int u = 0; u < MSG_BATCH; u++)
             if (u < cnt) {
@@ -419,16 +423,18 @@ __global__ __launch_bounds__(256) void k_msg_fwd(int64_t n, const int32_t *rowpt
             }
 #pragma unroll
         for (int u = 0; u < MSG_BATCH; u++)
-            if (u < cnt) qv[u] = PQ[jj[u] * 128 + 64 + f];
+            if (u < cnt) qv[u] = *(const float4 *)(PQ + jj[u] * 128 + 64 + f);
 #pragma unroll
         for (int u = 0; u < MSG_BATCH; u++)
             if (u < cnt) {
-                const float4 e = ee[u];
-                const float z = Pi + qv[u] + (e.x * w0 + e.y * w1 + e.z * w2 + e.w * w3);
-                acc += fmaxf(z, 0.f);
+                const float4 e = ee[u], q = qv[u];
+                a0 += fmaxf(P0 + q.x + (e.x * w0.x + e.y * w1.x + e.z * w2.x + e.w * w3.x), 0.f);
+                a1 += fmaxf(P1 + q.y + (e.x * w0.y + e.y * w1.y + e.z * w2.y + e.w * w3.y), 0.f);
+                a2 += fmaxf(P2 + q.z + (e.x * w0.z + e.y * w1.z + e.z * w2.z + e.w * w3.z), 0.f);
+                a3 += fmaxf(P3 + q.w + (e.x * w0.w + e.y * w1.w + e.z * w2.w + e.w * w3.w), 0.f);
             }
     }
-    agg[i * 64 + f] = acc;
+    *(float4 *)(agg + i * 64 + f) = make_float4(a0, a1, a2, a3);
 }
 
 // dP_i = sum over row i of dz_p, dz_p = da_i [z_p > 0]; per-workgroup partials
@@ -791,7 +797,7 @@ int forward(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, Act &A)
     k_relu<<<grid_for(64 * n, 256), 256, 0, st>>>(64 * n, A.pre0, A.h[0]);
     for (int l = 0; l < NL; l++) {
         SGP_TRY(gemm(ctx, A.h[l], 64, W + PK.ab[l], A.PQ, 128, n, 64, 128, nullptr, 0));
-        k_msg_fwd<<<grid_for(n, 4), 256, 0, st>>>(n, rowptr, col, ef, A.PQ, wr + L.b_m[l], wr + L.W_c[l], A.a[l]);
+        k_msg_fwd<<<grid_for(n, 16), 256, 0, st>>>(n, rowptr, col, ef, A.PQ, wr + L.b_m[l], wr + L.W_c[l], A.a[l]);
         SGP_TRY(gemm(ctx, A.h[l], 64, W + PK.u[l], A.U[l], 64, n, 64, 64, wr + L.b_u[l], 0));
         SGP_TRY(gemm(ctx, A.a[l], 64, W + PK.u[l] + 64 * 64, A.U[l], 64, n, 64, 64, nullptr, 1));
         k_residual<<<grid_for(64 * n, 256), 256, 0, st>>>(64 * n, A.h[l], A.U[l], A.h[l + 1]);
