@@ -25,7 +25,10 @@ written in that form so that its gradient is exactly 2 sV (Gamma v_hat - F) /
 (v' F) with respect to `out`: it needs the residual of the guess, not v.
 
 `forward` keeps what the manual `backward` needs; gradients are pinned by
-central finite differences in the tests.
+central finite differences in the tests.  There is no reference optimiser
+here: the trained weights, and so the trained network's guesses, are parity
+unpinned (the CG solve that follows a guess is checked against the solver
+oracle instead).
 """
 from __future__ import annotations
 

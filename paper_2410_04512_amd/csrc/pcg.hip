@@ -96,40 +96,54 @@ SGP_DEV void block_partial(double v, int b, double *part, double *sh)
 
 enum { FIN_ALPHA, FIN_RR_BETA, FIN_RHO, FIN_INIT, FIN_TRUE, FIN_NORM2 };
 
-// fixed-order sum of n partials by the FIN_THREADS threads of k_fin: thread t
-// owns the interleaved sequence t, t+FIN_THREADS, ...; eight running sums
-// (positions mod 8 of that sequence) keep eight loads in flight; each wave
-// then folds its lanes by a butterfly and thread 0 adds the waves in order.
-// Result valid in thread 0.
+// fixed-order sums of n partials by the FIN_THREADS threads of k_fin, for NA
+// arrays (stride ns) at once: thread t owns the interleaved sequence t,
+// t+FIN_THREADS, ...; position j of a pass of U * FIN_THREADS partials goes
+// to running sum j mod U, and all U * NA loads of a pass are issued together
+// (one pass covers the 1M-cell product's 10k partials), so the partials,
+// just written by the producer, cost one round trip instead of one per
+// FIN_THREADS.  Each thread adds its U sums pairwise, each wave folds its
+// lanes by a butterfly and thread 0 adds the waves in order.  Results valid
+// in thread 0.  sh holds NA * FIN_THREADS / 64 doubles.
 constexpr int FIN_THREADS = 1024;
 
-SGP_DEV double sum_partials8(const double *part, int n, double *sh)
+template <int NA>
+SGP_DEV void sum_partials(const double *part, int64_t ns, int n, double *sh, double *res)
 {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0, a6 = 0.0, a7 = 0.0;
-    int k = threadIdx.x;
-    constexpr int B = FIN_THREADS;
-    for (; k + 7 * B < n; k += 8 * B) {
-        const double v0 = part[k], v1 = part[k + B], v2 = part[k + 2 * B], v3 = part[k + 3 * B];
-        const double v4 = part[k + 4 * B], v5 = part[k + 5 * B], v6 = part[k + 6 * B], v7 = part[k + 7 * B];
-        a0 = a0 + v0;
-        a1 = a1 + v1;
-        a2 = a2 + v2;
-        a3 = a3 + v3;
-        a4 = a4 + v4;
-        a5 = a5 + v5;
-        a6 = a6 + v6;
-        a7 = a7 + v7;
+    constexpr int B = FIN_THREADS, U = NA == 1 ? 16 : NA == 2 ? 8 : 4;
+    double acc[NA][U];
+#pragma unroll
+    for (int a = 0; a < NA; a++)
+#pragma unroll
+        for (int j = 0; j < U; j++) acc[a][j] = 0.0;
+    for (int k = threadIdx.x; k < n; k += U * B) {
+        double v[NA][U];
+#pragma unroll
+        for (int a = 0; a < NA; a++)
+#pragma unroll
+            for (int j = 0; j < U; j++) v[a][j] = k + j * B < n ? part[a * ns + k + j * B] : 0.0;
+#pragma unroll
+        for (int a = 0; a < NA; a++)
+#pragma unroll
+            for (int j = 0; j < U; j++) acc[a][j] = acc[a][j] + v[a][j];
     }
-    for (; k < n; k += B) a0 = a0 + part[k];
-    double v = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
-    for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+#pragma unroll
+    for (int a = 0; a < NA; a++) {
+#pragma unroll
+        for (int h = U / 2; h > 0; h >>= 1)
+#pragma unroll
+            for (int j = 0; j < h; j++) acc[a][j] = acc[a][j] + acc[a][j + h];
+        double v = acc[a][0];
+        for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) sh[a * (B / 64) + (threadIdx.x >> 6)] = v;
+    }
     __syncthreads();
-    double r = 0.0;
     if (threadIdx.x == 0)
-        for (int w = 0; w < FIN_THREADS / 64; w++) r = r + sh[w];
-    __syncthreads();
-    return r;
+        for (int a = 0; a < NA; a++) {
+            double r = 0.0;
+            for (int w = 0; w < B / 64; w++) r = r + sh[a * (B / 64) + w];
+            res[a] = r;
+        }
 }
 
 // Second stage: cluster k = blockIdx.x sums its partials (np values per block,
@@ -137,7 +151,7 @@ SGP_DEV double sum_partials8(const double *part, int n, double *sh)
 __global__ __launch_bounds__(FIN_THREADS) void k_fin(int op, const double *part, int nblk, const int32_t *ifirst,
                                                      const int32_t *inb, PcgScalars *S)
 {
-    __shared__ double sh[FIN_THREADS / 64];
+    __shared__ double sh[3 * FIN_THREADS / 64];
     const int k = blockIdx.x;
     PcgScalars *Sc = S + k;
     if (op != FIN_INIT && op != FIN_TRUE && op != FIN_NORM2 && Sc->done) {
@@ -146,11 +160,15 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int op, const double *part,
         return;
     }
     const int f = ifirst[k], nbk = inb[k];
-    double t0 = sum_partials8(part + f, nbk, sh);
-    double t1 = (op == FIN_INIT || op == FIN_NORM2 || op == FIN_RR_BETA) ? sum_partials8(part + nblk + f, nbk, sh)
-                                                                          : 0.0;
-    double t2 = (op == FIN_INIT) ? sum_partials8(part + 2 * nblk + f, nbk, sh) : 0.0;
+    double t[3] = {0.0, 0.0, 0.0};
+    if (op == FIN_INIT)
+        sum_partials<3>(part + f, nblk, nbk, sh, t);
+    else if (op == FIN_NORM2 || op == FIN_RR_BETA)
+        sum_partials<2>(part + f, nblk, nbk, sh, t);
+    else
+        sum_partials<1>(part + f, nblk, nbk, sh, t);
     if (threadIdx.x != 0) return;
+    const double t0 = t[0], t1 = t[1], t2 = t[2];
     switch (op) {
     case FIN_ALPHA:
         Sc->pq = t0;
