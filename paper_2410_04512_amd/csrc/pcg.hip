@@ -40,6 +40,18 @@ struct BlockTab {
     const int32_t *ifirst, *inb;         // per cluster: first block, number of blocks
 };
 
+// Vector kernels run 256 threads per block over VEC_ROWS rows, so a thread
+// owns at most VEC_EPT of the block's 3 * VEC_ROWS elements (t, t+256, ...).
+// Its loads are all issued before its first store (a store might alias a
+// later element's load, so a plain loop would wait for every element in
+// turn), unconditionally: a thread past the block's ne elements reloads
+// element ne-1 (vec_idx) and drops the result.
+constexpr int VEC_ROWS = 256;
+constexpr int VEC_EPT = 3 * VEC_ROWS / 256;
+
+SGP_DEV int vec_idx(int u, int ne) { return min((int)threadIdx.x + 256 * u, ne - 1); }
+SGP_DEV bool vec_own(int u, int ne) { return (int)threadIdx.x + 256 * u < ne; }
+
 // host-side construction: clusters are cut into blocks of rows_per_block rows
 static void build_tab(const std::vector<int64_t> &off, int rows_per_block, std::vector<int32_t> &buf,
                       int32_t &nblocks)
@@ -314,11 +326,20 @@ __global__ __launch_bounds__(256) void k_update_r(T *r, const T *q, BlockTab tab
     if (Sc->done) return;
     const T alpha = (T)Sc->alpha;
     double rr = 0.0;
-    for (int t = threadIdx.x; t < ne; t += 256) {
-        const int64_t i = e0 + t;
-        const T ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        rr = rr + (double)ri * (double)ri;
+    if (ne > 0) {
+        T rv[VEC_EPT], qv[VEC_EPT];
+#pragma unroll
+        for (int u = 0; u < VEC_EPT; u++) {
+            rv[u] = r[e0 + vec_idx(u, ne)];
+            qv[u] = q[e0 + vec_idx(u, ne)];
+        }
+#pragma unroll
+        for (int u = 0; u < VEC_EPT; u++)
+            if (vec_own(u, ne)) {
+                const T ri = rv[u] - alpha * qv[u];
+                r[e0 + vec_idx(u, ne)] = ri;
+                rr = rr + (double)ri * (double)ri;
+            }
     }
     block_partial(rr, blockIdx.x, part, sh);
 }
@@ -333,7 +354,17 @@ __global__ __launch_bounds__(256) void k_pq(const T *p, const T *q, BlockTab tab
     const int ne = block_elems(tab, blockIdx.x, e0, inst);
     if (S[inst].done) return;
     double d = 0.0;
-    for (int t = threadIdx.x; t < ne; t += 256) d = d + (double)p[e0 + t] * (double)q[e0 + t];
+    if (ne > 0) {
+        T pv[VEC_EPT], qv[VEC_EPT];
+#pragma unroll
+        for (int u = 0; u < VEC_EPT; u++) {
+            pv[u] = p[e0 + vec_idx(u, ne)];
+            qv[u] = q[e0 + vec_idx(u, ne)];
+        }
+#pragma unroll
+        for (int u = 0; u < VEC_EPT; u++)
+            if (vec_own(u, ne)) d = d + (double)pv[u] * (double)qv[u];
+    }
     block_partial(d, blockIdx.x, part, sh);
 }
 
@@ -347,7 +378,17 @@ __global__ __launch_bounds__(256) void k_rz(const T *r, const T *z, BlockTab tab
     const int ne = block_elems(tab, blockIdx.x, e0, inst);
     if (S[inst].done) return;
     double rz = 0.0;
-    for (int t = threadIdx.x; t < ne; t += 256) rz = rz + (double)r[e0 + t] * (double)z[e0 + t];
+    if (ne > 0) {
+        T rv[VEC_EPT], zv[VEC_EPT];
+#pragma unroll
+        for (int u = 0; u < VEC_EPT; u++) {
+            rv[u] = r[e0 + vec_idx(u, ne)];
+            zv[u] = z[e0 + vec_idx(u, ne)];
+        }
+#pragma unroll
+        for (int u = 0; u < VEC_EPT; u++)
+            if (vec_own(u, ne)) rz = rz + (double)rv[u] * (double)zv[u];
+    }
     block_partial(rz, blockIdx.x, part, sh);
 }
 
@@ -360,22 +401,30 @@ __global__ __launch_bounds__(256) void k_update_xp(T *x, T *p, const T *z, Block
     const int ne = block_elems(tab, blockIdx.x, e0, inst);
     const PcgScalars *Sc = S + inst;
     const int32_t dn = Sc->done;
-    if (dn != 0 && dn != 3) return;
+    if ((dn != 0 && dn != 3) || ne == 0) return;
     const T alpha = (T)Sc->alpha;
-    if (dn == 3) {
-        for (int t = threadIdx.x; t < ne; t += 256) {
-            const int64_t i = e0 + t;
-            x[i] = x[i] + alpha * p[i];
-        }
+    T xv[VEC_EPT], pv[VEC_EPT];
+#pragma unroll
+    for (int u = 0; u < VEC_EPT; u++) {
+        xv[u] = x[e0 + vec_idx(u, ne)];
+        pv[u] = p[e0 + vec_idx(u, ne)];
+    }
+    if (dn == 3) {   // finishing: the last x update only
+#pragma unroll
+        for (int u = 0; u < VEC_EPT; u++)
+            if (vec_own(u, ne)) x[e0 + vec_idx(u, ne)] = xv[u] + alpha * pv[u];
         return;
     }
     const T beta = (T)Sc->beta;
-    for (int t = threadIdx.x; t < ne; t += 256) {
-        const int64_t i = e0 + t;
-        const T pi = p[i];
-        x[i] = x[i] + alpha * pi;
-        p[i] = z[i] + beta * pi;
-    }
+    T zv[VEC_EPT];
+#pragma unroll
+    for (int u = 0; u < VEC_EPT; u++) zv[u] = z[e0 + vec_idx(u, ne)];
+#pragma unroll
+    for (int u = 0; u < VEC_EPT; u++)
+        if (vec_own(u, ne)) {
+            x[e0 + vec_idx(u, ne)] = xv[u] + alpha * pv[u];
+            p[e0 + vec_idx(u, ne)] = zv[u] + beta * pv[u];
+        }
 }
 
 // partial of ||F - q||^2 (q = Gamma x)
@@ -626,7 +675,7 @@ static int prepare_work(sgp_ctx ctx, sgp_bsr A, const std::vector<int64_t> &off,
 {
     const int64_t K = (int64_t)off.size() - 1;
     w.K = K;
-    build_tab(off, 256, w.vec_buf, w.vec_nb);
+    build_tab(off, VEC_ROWS, w.vec_buf, w.vec_nb);
     w.mv_nb = spmv_blocks(ctx, A);
     w.vec_buf.push_back(0);
     w.vec_buf.push_back(w.mv_nb);
