@@ -197,14 +197,14 @@ SGP_DEV void edge_product(T *a, int s, const T *e, T x0, T x1, T x2, T gpar, T g
     a[3 * s + 2] = w * (gperp * x2 + c * u2);
 }
 
-template <class T, int SPMV_WAVES>
+template <class T, int SPMV_WAVES, bool EDGES>
 __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_edge(const int32_t *__restrict__ rowptr,
                                                                const int32_t *__restrict__ ecol,
                                                                const T *__restrict__ ew, const T *__restrict__ dg,
                                                                T gpar, T gperp, const T *__restrict__ x,
                                                                T *__restrict__ y, const int32_t *__restrict__ wrow,
-                                                               int64_t nwaves, const PcgScalars *S, double *part,
-                                                               int mode)
+                                                               int64_t nwaves, int64_t ne, const PcgScalars *S,
+                                                               double *part, int mode)
 {
     __shared__ T acc[SPMV_WAVES][3 * EDGE_SLOTS];
     __shared__ double sh[SPMV_WAVES];
@@ -212,49 +212,52 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_edge(const int32_t *__
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t w = lb * SPMV_WAVES + wv;
-    int32_t r_lo = 0, r_hi = 0;
-    int64_t kb = 0, ke = 0;
     const int64_t base = w * EDGE_BLOCKS;
-    if (w < nwaves) {
-        r_lo = wrow[w];
-        r_hi = wrow[w + 1];
-        kb = (int64_t)rowptr[r_lo] - r_lo;
-        ke = (int64_t)rowptr[r_hi] - r_hi;
-    }
-    T *a = acc[wv];
-    // a lane's first row: its diagonal block and x, loaded before anything
-    // waits (rows past the first 64 of a wave load theirs in the row loop)
-    const int32_t row0 = r_lo + lane;
-    const bool has_row = row0 < r_hi;
-    T dr[6], pr[3];
-    if (has_row) {
-        const T *dgr = dg + ((int64_t)row0 >> 6) * 384 + (row0 & 63);
-        for (int t = 0; t < 6; t++) dr[t] = dgr[64 * t];
-        for (int t = 0; t < 3; t++) pr[t] = x[3 * (int64_t)row0 + t];
-    }
-    // the wave's 64-entry groups: all (w, u) and columns first, then the
-    // gathers, then the products
-    const T *gb = ew + (base >> 6) * 256 + lane;
-    bool on[EDGE_GROUPS];
+    // Loads in two rounds, with no branch around any of them (a load's wait
+    // counter is in order, and at a branch the compiler waits for everything
+    // issued before it): the wave's row range (a wave past the last reads
+    // the last one's and owns no rows), then (w, u) and column of every
+    // entry in [base, base + EDGE_BLOCKS) (lanes past the last entry reload
+    // it), whatever rows they belong to -- entries below kb belong to the
+    // previous wave's last row and are loaded, not used.  Then the row
+    // bounds, the first row's diagonal block and x, and the gathers.
+    // EDGES = false: a product without entries (ne = 0), diagonal blocks only.
+    const int64_t wc = min(w, nwaves - 1);
+    int32_t r_lo = wrow[wc], r_hi = wrow[wc + 1];
     T e[EDGE_GROUPS][4], xv[EDGE_GROUPS][3];
     int64_t j[EDGE_GROUPS];
+    if (EDGES) {
 #pragma unroll
-    for (int q = 0; q < EDGE_GROUPS; q++) {
-        const int64_t k = base + 64 * q + lane;
-        on[q] = k >= kb && k < ke;
-        j[q] = 0;
-        if (on[q]) {
-            for (int t = 0; t < 4; t++) e[q][t] = gb[256 * q + 64 * t];
+        for (int q = 0; q < EDGE_GROUPS; q++) {
+            const int64_t k = min(base + 64 * q + lane, ne - 1);
+            const T *g = ew + (k >> 6) * 256 + (k & 63);
+            for (int t = 0; t < 4; t++) e[q][t] = g[64 * t];
             j[q] = ecol[k];
         }
     }
+    if (w >= nwaves) r_hi = r_lo;
+    const int64_t kb = (int64_t)rowptr[r_lo] - r_lo, ke = (int64_t)rowptr[r_hi] - r_hi;
+    T *a = acc[wv];
+    // a lane's first row (lanes past the wave's rows reload a valid one)
+    const int32_t row0 = r_lo + lane;
+    T dr[6], pr[3];
+    {
+        const int32_t rc = max(min(row0, r_hi - 1), 0);
+        const T *dgr = dg + ((int64_t)rc >> 6) * 384 + (rc & 63);
+        for (int t = 0; t < 6; t++) dr[t] = dgr[64 * t];
+        for (int t = 0; t < 3; t++) pr[t] = x[3 * (int64_t)rc + t];
+    }
+    if (EDGES) {
 #pragma unroll
-    for (int q = 0; q < EDGE_GROUPS; q++)
-        if (on[q])
+        for (int q = 0; q < EDGE_GROUPS; q++)
             for (int t = 0; t < 3; t++) xv[q][t] = x[3 * j[q] + t];
 #pragma unroll
-    for (int q = 0; q < EDGE_GROUPS; q++)
-        if (on[q]) edge_product(a, 64 * q + lane, e[q], xv[q][0], xv[q][1], xv[q][2], gpar, gperp);
+        for (int q = 0; q < EDGE_GROUPS; q++) {
+            const int64_t k = base + 64 * q + lane;
+            if (k >= kb && k < ke)
+                edge_product(a, 64 * q + lane, e[q], xv[q][0], xv[q][1], xv[q][2], gpar, gperp);
+        }
+    }
     // entries of the last row that run past the groups
     for (int64_t c = base + EDGE_BLOCKS; c < ke; c += 64) {
         const int64_t k = c + lane;
@@ -322,12 +325,19 @@ static int spmv_launch(sgp_ctx ctx, sgp_bsr A, const T *val, const T *ew, const 
     if (ctx->spmv_form) {
         const int32_t *ec = (const int32_t *)A->ecol.p, *ewr = (const int32_t *)A->ewrow.p;
         const T gp = (T)A->gpar, gq = (T)A->gperp;
-        switch (ctx->spmv_waves) {
-        case 2: k_spmv_edge<T, 2><<<nb, 128, 0, st>>>(rp, ec, ew, dg, gp, gq, x, y, ewr, nw, S, part, mode); break;
-        case 4: k_spmv_edge<T, 4><<<nb, 256, 0, st>>>(rp, ec, ew, dg, gp, gq, x, y, ewr, nw, S, part, mode); break;
-        case 8: k_spmv_edge<T, 8><<<nb, 512, 0, st>>>(rp, ec, ew, dg, gp, gq, x, y, ewr, nw, S, part, mode); break;
+        const int64_t ne = A->nnzb - A->n;
+#define SGP_EDGE_LAUNCH(W, E) \
+    k_spmv_edge<T, W, E><<<nb, 64 * W, 0, st>>>(rp, ec, ew, dg, gp, gq, x, y, ewr, nw, ne, S, part, mode)
+        switch (ctx->spmv_waves * 2 + (ne > 0)) {
+        case 4: SGP_EDGE_LAUNCH(2, false); break;
+        case 5: SGP_EDGE_LAUNCH(2, true); break;
+        case 8: SGP_EDGE_LAUNCH(4, false); break;
+        case 9: SGP_EDGE_LAUNCH(4, true); break;
+        case 16: SGP_EDGE_LAUNCH(8, false); break;
+        case 17: SGP_EDGE_LAUNCH(8, true); break;
         default: return set_err(ctx, SGP_EINVAL, "spmv: unsupported waves per workgroup %d", ctx->spmv_waves);
         }
+#undef SGP_EDGE_LAUNCH
     } else {
         switch (ctx->spmv_waves) {
         case 2: k_spmv_sym<T, 2><<<nb, 128, 0, st>>>(rp, bc, val, x, y, wr, nw, S, part, mode); break;
