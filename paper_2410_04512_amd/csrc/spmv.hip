@@ -220,7 +220,8 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_edge(const int32_t *__
     // entry in [base, base + EDGE_BLOCKS) (lanes past the last entry reload
     // it), whatever rows they belong to -- entries below kb belong to the
     // previous wave's last row and are loaded, not used.  Then the row
-    // bounds, the first row's diagonal block and x, and the gathers.
+    // bounds, the first row's diagonal block, x and row pointers, and the
+    // gathers.
     // EDGES = false: a product without entries (ne = 0), diagonal blocks only.
     const int64_t wc = min(w, nwaves - 1);
     int32_t r_lo = wrow[wc], r_hi = wrow[wc + 1];
@@ -241,22 +242,25 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_edge(const int32_t *__
     // a lane's first row (lanes past the wave's rows reload a valid one)
     const int32_t row0 = r_lo + lane;
     T dr[6], pr[3];
+    int32_t rp0, rp1;
     {
         const int32_t rc = max(min(row0, r_hi - 1), 0);
         const T *dgr = dg + ((int64_t)rc >> 6) * 384 + (rc & 63);
         for (int t = 0; t < 6; t++) dr[t] = dgr[64 * t];
         for (int t = 0; t < 3; t++) pr[t] = x[3 * (int64_t)rc + t];
+        rp0 = rowptr[rc];
+        rp1 = rowptr[rc + 1];
     }
     if (EDGES) {
 #pragma unroll
         for (int q = 0; q < EDGE_GROUPS; q++)
             for (int t = 0; t < 3; t++) xv[q][t] = x[3 * j[q] + t];
+        // every lane parks its products; slots of entries outside the wave's
+        // rows (below kb, or past the last entry) are never read back (a
+        // condition here would let the compiler sink the loads into it)
 #pragma unroll
-        for (int q = 0; q < EDGE_GROUPS; q++) {
-            const int64_t k = base + 64 * q + lane;
-            if (k >= kb && k < ke)
-                edge_product(a, 64 * q + lane, e[q], xv[q][0], xv[q][1], xv[q][2], gpar, gperp);
-        }
+        for (int q = 0; q < EDGE_GROUPS; q++)
+            edge_product(a, 64 * q + lane, e[q], xv[q][0], xv[q][1], xv[q][2], gpar, gperp);
     }
     // entries of the last row that run past the groups
     for (int64_t c = base + EDGE_BLOCKS; c < ke; c += 64) {
@@ -275,12 +279,14 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_edge(const int32_t *__
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
     double d = 0.0;
     for (int32_t row = row0; row < r_hi; row += 64) {
-        const int s0 = (int)((int64_t)rowptr[row] - row - base), s1 = (int)((int64_t)rowptr[row + 1] - (row + 1) - base);
         if (row != row0) {
             const T *dgr = dg + ((int64_t)row >> 6) * 384 + (row & 63);
             for (int t = 0; t < 6; t++) dr[t] = dgr[64 * t];
             for (int t = 0; t < 3; t++) pr[t] = x[3 * (int64_t)row + t];
+            rp0 = rowptr[row];
+            rp1 = rowptr[row + 1];
         }
+        const int s0 = (int)((int64_t)rp0 - row - base), s1 = (int)((int64_t)rp1 - (row + 1) - base);
         const T p0 = pr[0], p1 = pr[1], p2 = pr[2];
         T y0 = dr[0] * p0 + dr[1] * p1 + dr[2] * p2;
         T y1 = dr[1] * p0 + dr[3] * p1 + dr[4] * p2;
