@@ -240,6 +240,30 @@ def test_empty_input(ctx):
     assert info["iters"] == 0
 
 
+@pytest.mark.parametrize("waves", [2, 4, 8])
+def test_no_contacts(ctx, waves):
+    """Cells that touch nothing: Gamma = g_med I (a product without
+    off-diagonal entries), every cell is a tree of its own, and the tree
+    preconditioner is Gamma itself, so CG stops after one iteration at
+    v = F / g_med."""
+    n = 300
+    pos = np.stack([np.arange(n) * 5.0, np.zeros(n), np.zeros(n)], axis=1)
+    c = {"pos": pos, "radius": np.ones(n), "force": np.random.default_rng(3).normal(size=(n, 3))}
+    ctx.tune("spmv_waves", waves)
+    try:
+        out = gpu_chain(ctx, c)
+        assert out["g"].size() == (n, 0)
+        x = np.random.default_rng(4).normal(size=(n, 3))
+        y = host(ctx.spmv(out["A"], to_dev(x)))
+        assert np.array_equal(y, x * O.G_MED)
+        oo = O.solve_pipeline(c["pos"], c["radius"], c["force"])
+        assert out["info"]["status"] == 0 and out["info"]["iters"] == oo["info"].iters == 1
+        v = host(out["v"])
+        assert np.abs(v - oo["x"]).max() <= 1e-12 * np.abs(oo["x"]).max()
+    finally:
+        ctx.tune("spmv_waves", 4)
+
+
 def test_tree_graph_one_iteration(ctx):
     pos = np.array([[1.9 * k, 0.1 * np.sin(k), 0.0] for k in range(40)])
     c = {"pos": pos, "radius": np.ones(40), "force": np.random.default_rng(0).normal(size=(40, 3))}
