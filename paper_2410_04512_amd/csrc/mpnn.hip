@@ -168,12 +168,14 @@ __global__ void k_pack(const float *theta, Layout L, Packed P, unsigned short *w
 // B is staged in LDS in fragment order (a lane's four k-values adjacent, one
 // 8-byte read); a wave converts the A fragments of its 16-row tile to BF16
 // once and reuses them for every column tile.  A workgroup (4 waves) covers
-// GEMM_ROWS rows.
-constexpr int GEMM_ROWS = 256;
+// GEMM_ROWS rows (one 16-row tile per wave: more waves in flight than
+// several tiles per wave, whose loads would wait for the previous tile).
+constexpr int GEMM_ROWS = 64;
 
 template <int KT>
 __global__ __launch_bounds__(256) void k_gemm(const float *A, int64_t lda, const unsigned short *B, float *C,
-                                              int64_t ldc, int64_t M, int N, const float *bias, int accumulate)
+                                              int64_t ldc, int64_t M, int N, const float *bias, int accumulate,
+                                              float *R)
 {
     __shared__ bf16x4 sB[KT * 8 * 64];
     const int NT = N >> 4;
@@ -189,28 +191,120 @@ __global__ __launch_bounds__(256) void k_gemm(const float *A, int64_t lda, const
     for (int it = 0; it < GEMM_ROWS / 64; it++) {
         const int64_t r0 = (int64_t)blockIdx.x * GEMM_ROWS + 64 * it + 16 * wv;
         if (r0 >= M) break;
-        const int64_t arow = r0 + lr;
+        // every load of the tile before any store, unconditional (rows past
+        // M read row M-1 and are not stored): a load behind a store, or in a
+        // branch, would wait for it
+        const int64_t arow = min(r0 + lr, M - 1);
+        float4 av[KT];
+#pragma unroll
+        for (int kt = 0; kt < KT; kt++) av[kt] = *(const float4 *)(A + arow * lda + 16 * kt + 4 * lg);
+        float bv[8], cv[8][4];
+#pragma unroll
+        for (int nt = 0; nt < 8; nt++) {
+            bv[nt] = bias && nt < NT ? bias[16 * nt + lr] : 0.f;
+            if (accumulate && nt < NT)
+                for (int t = 0; t < 4; t++) cv[nt][t] = C[min(r0 + 4 * lg + t, M - 1) * ldc + 16 * nt + lr];
+        }
+        keep_loads_above();
         bf16x4 a[KT];
 #pragma unroll
         for (int kt = 0; kt < KT; kt++) {
-            float4 v = arow < M ? *(const float4 *)(A + arow * lda + 16 * kt + 4 * lg) : make_float4(0.f, 0.f, 0.f, 0.f);
-            a[kt][0] = (short)f2bf(v.x);
-            a[kt][1] = (short)f2bf(v.y);
-            a[kt][2] = (short)f2bf(v.z);
-            a[kt][3] = (short)f2bf(v.w);
+            a[kt][0] = (short)f2bf(av[kt].x);
+            a[kt][1] = (short)f2bf(av[kt].y);
+            a[kt][2] = (short)f2bf(av[kt].z);
+            a[kt][3] = (short)f2bf(av[kt].w);
         }
-        for (int nt = 0; nt < NT; nt++) {
+#pragma unroll
+        for (int nt = 0; nt < 8; nt++) {
+            if (nt >= NT) break;
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kt = 0; kt < KT; kt++)
                 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[kt], sB[(kt * NT + nt) * 64 + lane], acc, 0, 0, 0);
-            const float bv = bias ? bias[16 * nt + lr] : 0.f;
             for (int t = 0; t < 4; t++) {
                 const int64_t row = r0 + 4 * lg + t;
                 if (row >= M) continue;
-                float *c = C + row * ldc + 16 * nt + lr;
-                const float v = acc[t] + bv;
-                *c = accumulate ? *c + v : v;
+                const float v = acc[t] + bv[nt];
+                const float o = accumulate ? cv[nt][t] + v : v;
+                C[row * ldc + 16 * nt + lr] = o;
+                if (R) R[row * ldc + 16 * nt + lr] = fmaxf(o, 0.f);
+            }
+        }
+    }
+}
+
+// One layer's node update in one pass: U = [h, a] W_u + b_u as the two
+// K = 64 products of the unfused form (h against rows 0..63 of W_u plus the
+// bias, then a against rows 64..127, added in that order), kept for the
+// backward pass, and h' = h + relu(U).  The operations and their order are
+// those of two k_gemm launches and the residual pass, so the results are
+// the same bit for bit; h and a are read once and U is not read back.
+__global__ __launch_bounds__(256) void k_gemm_update(const float *H, const float *Ag, const unsigned short *B,
+                                                     const float *bias, float *U, float *Hn, int64_t M)
+{
+    constexpr int KT = 4, NT = 4, N = 64;
+    __shared__ bf16x4 sB[2 * KT * NT * 64];
+    for (int e = threadIdx.x; e < 2 * KT * NT * 64; e += 256) {
+        const int half = e / (KT * NT * 64), f = e % (KT * NT * 64);
+        const int ln = f & 63, tile = f >> 6, kt = tile / NT, nt = tile % NT;
+        bf16x4 b;
+        for (int t = 0; t < 4; t++)
+            b[t] = (short)B[(64 * half + 16 * kt + 4 * (ln >> 4) + t) * N + 16 * nt + (ln & 15)];
+        sB[e] = b;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    for (int it = 0; it < GEMM_ROWS / 64; it++) {
+        const int64_t r0 = (int64_t)blockIdx.x * GEMM_ROWS + 64 * it + 16 * wv;
+        if (r0 >= M) break;
+        // Every load of the tile before any store, unconditional (rows past
+        // M read row M-1; their results are not stored): the fragments of h
+        // and a, and h at the lane's output positions for the residual.  A
+        // load behind a store, or in a branch, would wait for it.
+        const int64_t arow = min(r0 + lr, M - 1);
+        float hv[NT][4];
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++)
+#pragma unroll
+            for (int t = 0; t < 4; t++) hv[nt][t] = H[min(r0 + 4 * lg + t, M - 1) * N + 16 * nt + lr];
+        float4 vh[KT], va[KT];
+#pragma unroll
+        for (int kt = 0; kt < KT; kt++) {
+            vh[kt] = *(const float4 *)(H + arow * 64 + 16 * kt + 4 * lg);
+            va[kt] = *(const float4 *)(Ag + arow * 64 + 16 * kt + 4 * lg);
+        }
+        float bv[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) bv[nt] = bias[16 * nt + lr];
+        keep_loads_above();
+        bf16x4 ah[KT], aa[KT];
+#pragma unroll
+        for (int kt = 0; kt < KT; kt++) {
+            ah[kt][0] = (short)f2bf(vh[kt].x);
+            ah[kt][1] = (short)f2bf(vh[kt].y);
+            ah[kt][2] = (short)f2bf(vh[kt].z);
+            ah[kt][3] = (short)f2bf(vh[kt].w);
+            aa[kt][0] = (short)f2bf(va[kt].x);
+            aa[kt][1] = (short)f2bf(va[kt].y);
+            aa[kt][2] = (short)f2bf(va[kt].z);
+            aa[kt][3] = (short)f2bf(va[kt].w);
+        }
+        for (int nt = 0; nt < NT; nt++) {
+            f32x4 acc1 = {0.f, 0.f, 0.f, 0.f}, acc2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kt = 0; kt < KT; kt++) {
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[kt], sB[(kt * NT + nt) * 64 + lane], acc1, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aa[kt], sB[KT * NT * 64 + (kt * NT + nt) * 64 + lane],
+                                                                 acc2, 0, 0, 0);
+            }
+            for (int t = 0; t < 4; t++) {
+                const int64_t row = r0 + 4 * lg + t;
+                if (row >= M) continue;
+                const int64_t o = row * N + 16 * nt + lr;
+                const float u = (acc1[t] + bv[nt]) + (acc2[t] + 0.f);
+                U[o] = u;
+                Hn[o] = hv[nt][t] + fmaxf(u, 0.f);
             }
         }
     }
@@ -357,19 +451,6 @@ __global__ void k_int_entries(int64_t n, const int32_t *perm, const int32_t *inv
     }
 }
 
-__global__ void k_relu(int64_t len, const float *a, float *b)
-{
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < len) b[t] = fmaxf(a[t], 0.f);
-}
-
-// h_next = h + relu(U)
-__global__ void k_residual(int64_t len, const float *h, const float *U, float *hn)
-{
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < len) hn[t] = h[t] + fmaxf(U[t], 0.f);
-}
-
 // dst = src * (mask > 0)
 __global__ void k_mask(int64_t len, const float *src, const float *mask, float *dst)
 {
@@ -412,18 +493,21 @@ __global__ __launch_bounds__(256) void k_msg_fwd(int64_t n, const int32_t *rowpt
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
     const int32_t re = rowptr[i + 1];
     for (int32_t p = rowptr[i]; p < re; p += MSG_BATCH) {
+        // a batch's loads are unconditional (entries past the row's end
+        // reload its last one and are not summed) and precede every use: a
+        // load in a branch makes the compiler wait for it there
         const int cnt = re - p < MSG_BATCH ? re - p : MSG_BATCH;
-        int64_t jj[MSG_BATCH];
+        int32_t jj[MSG_BATCH];
         float4 ee[MSG_BATCH], qv[MSG_BATCH];
 #pragma unroll
-        for (int u = 0; u < MSG_BATCH; u++)
-            if (u < cnt) {
-                jj[u] = col[p + u];
-                ee[u] = ef[p + u];
-            }
+        for (int u = 0; u < MSG_BATCH; u++) {
+            const int32_t pc = min(p + u, re - 1);
+            jj[u] = col[pc];
+            ee[u] = ef[pc];
+        }
 #pragma unroll
-        for (int u = 0; u < MSG_BATCH; u++)
-            if (u < cnt) qv[u] = *(const float4 *)(PQ + jj[u] * 128 + 64 + f);
+        for (int u = 0; u < MSG_BATCH; u++) qv[u] = *(const float4 *)(PQ + (int64_t)jj[u] * 128 + 64 + f);
+        keep_loads_above();
 #pragma unroll
         for (int u = 0; u < MSG_BATCH; u++)
             if (u < cnt) {
@@ -691,15 +775,16 @@ Act carve(float *base, int64_t n)
 }
 
 int gemm(sgp_ctx ctx, const float *A, int64_t lda, const unsigned short *B, float *C, int64_t ldc, int64_t M, int K,
-         int N, const float *bias, int acc)
+         int N, const float *bias, int acc, float *relu_out = nullptr)
 {
     if (M <= 0) return SGP_OK;
     const int64_t nb = grid_for(M, GEMM_ROWS);
     hipStream_t st = ctx->stream;
+    float *R = relu_out;
     switch (K) {
-    case 16: k_gemm<1><<<nb, 256, 0, st>>>(A, lda, B, C, ldc, M, N, bias, acc); break;
-    case 64: k_gemm<4><<<nb, 256, 0, st>>>(A, lda, B, C, ldc, M, N, bias, acc); break;
-    case 128: k_gemm<8><<<nb, 256, 0, st>>>(A, lda, B, C, ldc, M, N, bias, acc); break;
+    case 16: k_gemm<1><<<nb, 256, 0, st>>>(A, lda, B, C, ldc, M, N, bias, acc, R); break;
+    case 64: k_gemm<4><<<nb, 256, 0, st>>>(A, lda, B, C, ldc, M, N, bias, acc, R); break;
+    case 128: k_gemm<8><<<nb, 256, 0, st>>>(A, lda, B, C, ldc, M, N, bias, acc, R); break;
     default: return set_err(ctx, SGP_EINVAL, "mpnn gemm: unsupported K");
     }
     LAUNCH_CHECK(ctx);
@@ -793,14 +878,14 @@ int forward(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, Act &A)
     const Packed &PK = M->PK;
     const int32_t *rowptr = (const int32_t *)M->irow.p, *col = (const int32_t *)M->icol.p;   // internal order
     const float4 *ef = (const float4 *)M->efeat.p;
-    SGP_TRY(gemm(ctx, A.x16, 16, W + PK.in16, A.pre0, 64, n, 16, 64, wr + L.b_in, 0));
-    k_relu<<<grid_for(64 * n, 256), 256, 0, st>>>(64 * n, A.pre0, A.h[0]);
+    // input layer: pre0 kept for the backward pass, h0 = relu(pre0) in the same pass
+    SGP_TRY(gemm(ctx, A.x16, 16, W + PK.in16, A.pre0, 64, n, 16, 64, wr + L.b_in, 0, A.h[0]));
     for (int l = 0; l < NL; l++) {
         SGP_TRY(gemm(ctx, A.h[l], 64, W + PK.ab[l], A.PQ, 128, n, 64, 128, nullptr, 0));
         k_msg_fwd<<<grid_for(n, 16), 256, 0, st>>>(n, rowptr, col, ef, A.PQ, wr + L.b_m[l], wr + L.W_c[l], A.a[l]);
-        SGP_TRY(gemm(ctx, A.h[l], 64, W + PK.u[l], A.U[l], 64, n, 64, 64, wr + L.b_u[l], 0));
-        SGP_TRY(gemm(ctx, A.a[l], 64, W + PK.u[l] + 64 * 64, A.U[l], 64, n, 64, 64, nullptr, 1));
-        k_residual<<<grid_for(64 * n, 256), 256, 0, st>>>(64 * n, A.h[l], A.U[l], A.h[l + 1]);
+        if (n > 0)
+            k_gemm_update<<<grid_for(n, GEMM_ROWS), 256, 0, st>>>(A.h[l], A.a[l], W + PK.u[l], wr + L.b_u[l], A.U[l],
+                                                                  A.h[l + 1], n);
     }
     SGP_TRY(gemm(ctx, A.h[NL], 64, W + PK.out16, A.out16, 16, n, 64, 16, nullptr, 0));
     // b_out (3 entries) added by a tiny pass
