@@ -501,6 +501,60 @@ SGP_DEV void sum_slots(int32_t t, int32_t te, const T *cs, T &b0, T &b1, T &b2)
     }
 }
 
+// The same sum with the first chunk of four slots and the last one to three
+// loaded together, ahead of any wait, and unconditionally (indices clamped
+// into [t, max(te - 1, t)]; the slot array holds a spare slot past its end):
+// a load in a branch makes the compiler wait for every earlier load there.
+// Chunks between them are loaded four at a time.  Faster for the tail's
+// pre-sums (many slots per vertex: 5.1 -> 4.8 us), slower in the step
+// kernels (~6.2 -> ~7.2 us per small step: larger code, fewer vertices with
+// many slots), which keep sum_slots.
+template <class T>
+SGP_DEV void sum_slots_early(int32_t t, int32_t te, const T *cs, T &b0, T &b1, T &b2)
+{
+    const int32_t n = te - t, full = n & ~3, last = te > t ? te - 1 : t;
+    T h[12], r[9];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const T *c = cs + 3 * (int64_t)min(t + k, last);
+        h[3 * k] = c[0];
+        h[3 * k + 1] = c[1];
+        h[3 * k + 2] = c[2];
+    }
+#pragma unroll
+    for (int u = 0; u < 3; u++) {
+        const T *c = cs + 3 * (int64_t)min(t + full + u, last);
+        r[3 * u] = c[0];
+        r[3 * u + 1] = c[1];
+        r[3 * u + 2] = c[2];
+    }
+    keep_loads_above();
+    if (full >= 4) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            b0 = b0 - h[3 * k];
+            b1 = b1 - h[3 * k + 1];
+            b2 = b2 - h[3 * k + 2];
+        }
+    }
+    for (int32_t m = t + 4; m < t + full; m += 4) {
+        const T *c = cs + 3 * (int64_t)m;
+        T c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5];
+        T c6 = c[6], c7 = c[7], c8 = c[8], c9 = c[9], c10 = c[10], c11 = c[11];
+        b0 = b0 - c0; b1 = b1 - c1; b2 = b2 - c2;
+        b0 = b0 - c3; b1 = b1 - c4; b2 = b2 - c5;
+        b0 = b0 - c6; b1 = b1 - c7; b2 = b2 - c8;
+        b0 = b0 - c9; b1 = b1 - c10; b2 = b2 - c11;
+    }
+#pragma unroll
+    for (int u = 0; u < 3; u++) {
+        const bool on = u < n - full;
+        b0 = on ? b0 - r[3 * u] : b0;
+        b1 = on ? b1 - r[3 * u + 1] : b1;
+        b2 = on ? b2 - r[3 * u + 2] : b2;
+    }
+}
+
 // forward substitution of one vertex q (pivot solve folded in), then the
 // push of its contributions to the vertices above it.  The loads come in
 // rounds: what depends on q alone (ids, the pivot, the first coupling
@@ -812,7 +866,7 @@ __global__ __launch_bounds__(64) void k_tail_pre(int32_t Qt, int32_t nt, const i
     const int64_t v = elim[q];
     T b0 = r[3 * v], b1 = r[3 * v + 1], b2 = r[3 * v + 2];
     const int32_t te = in_ptr[q + 1] - (iptr[i + 1] - iptr[i]);
-    sum_slots<T>(in_ptr[q], te, cs, b0, b1, b2);
+    sum_slots_early<T>(in_ptr[q], te, cs, b0, b1, b2);
     keep_loads_above();
     if (dn) return;
     tb[3 * (int64_t)i] = b0;
