@@ -256,7 +256,8 @@ def main():
                     help="build the system once, then run only the named kernel (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only (a single solve is not sharded "
+                                   "across GPUs); use --gpus 1"}))
         sys.exit(2)
 
     import numpy as np
