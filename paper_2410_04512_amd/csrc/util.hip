@@ -271,21 +271,22 @@ int radix_sort_pairs(sgp_ctx ctx, uint32_t *keys, int32_t *vals, uint32_t *ktmp,
 // ---------------------------------------------------------------- permutations
 
 // gather: dst[i] = src[idx[i]]; scatter: dst[idx[i]] = src[i] (3-vectors)
+// one thread per component (3 n of them): the contiguous side is accessed
+// with consecutive addresses across the wave, the permuted side in 24-byte runs
 __global__ void k_permute_rows(const int32_t *idx, const double *src, double *dst, int64_t n, int scatter)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int64_t j = idx[i];
-    int64_t a = scatter ? i : j, b = scatter ? j : i;
-    dst[3 * b] = src[3 * a];
-    dst[3 * b + 1] = src[3 * a + 1];
-    dst[3 * b + 2] = src[3 * a + 2];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 3 * n) return;
+    const int64_t i = e / 3, c = e - 3 * i;
+    const int64_t j = idx[i];
+    const int64_t a = scatter ? i : j, b = scatter ? j : i;
+    dst[3 * b + c] = src[3 * a + c];
 }
 
 int permute_rows(sgp_ctx ctx, const int32_t *idx, const double *src, double *dst, int64_t n, int scatter)
 {
     if (n <= 0) return SGP_OK;
-    k_permute_rows<<<grid_for(n, 256), 256, 0, ctx->stream>>>(idx, src, dst, n, scatter);
+    k_permute_rows<<<grid_for(3 * n, 256), 256, 0, ctx->stream>>>(idx, src, dst, n, scatter);
     LAUNCH_CHECK(ctx);
     return SGP_OK;
 }
