@@ -122,10 +122,20 @@ __global__ void k_inverse(const int32_t *perm, int64_t n, int32_t *inv)
 // --------------------------------------------------------------- 3. contacts
 
 // flags[0]: capacity overflow, flags[1]: coincident centres in contact
-__global__ void k_neighbors(const double4 *sp, const int32_t *sidx, const uint32_t *key, int64_t n, Grid g,
-                            const int32_t *cstart, const int32_t *cend, int max_deg, int32_t *slots,
-                            int32_t *deg, int32_t *upcnt, int32_t *flags)
+constexpr int NB_THREADS = 128;
+
+__global__ __launch_bounds__(NB_THREADS) void k_neighbors(const double4 *sp, const int32_t *sidx,
+                                                          const uint32_t *key, int64_t n, Grid g,
+                                                          const int32_t *cstart, const int32_t *cend, int max_deg,
+                                                          int32_t *slots, int32_t *deg, int32_t *upcnt,
+                                                          int32_t *flags)
 {
+    // the thread's sorted neighbour list lives in LDS (max_deg rounded up to
+    // an odd stride: the threads of a wave touch different banks): in
+    // private memory its insertion stores would be vector-memory stores, and
+    // every candidate load after them would wait for them
+    extern __shared__ int32_t snb[];
+    int32_t *nb = snb + threadIdx.x * (max_deg | 1);
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int32_t i = sidx[s];
@@ -136,7 +146,6 @@ __global__ void k_neighbors(const double4 *sp, const int32_t *sidx, const uint32
     const int cx = (int)(c % g.dim[0]);
     const int cy = (int)((c / g.dim[0]) % g.dim[1]);
     const int cz = (int)(c / ((int64_t)g.dim[0] * g.dim[1]));
-    int32_t nb[MAXD_LIMIT];
     int cnt = 0, up = 0;
     bool overflow = false, coincident = false;
     for (int z = cz - 1; z <= cz + 1; z++) {
@@ -179,37 +188,48 @@ __global__ void k_neighbors(const double4 *sp, const int32_t *sidx, const uint32
 
 // --------------------------------------------------------------- 4-6. CSR and edges
 
+// The per-row passes below run ROW_LANES lanes per row, lane k taking the
+// row's entries k, k + ROW_LANES, ...: a row's entries are independent, and
+// one thread walking its row would wait for each entry's stores before the
+// next entry's loads (a wave's memory counter is waited on in order).
+constexpr int ROW_LANES = 16;
+
 __global__ void k_compact_rows(const int32_t *slots, int max_deg, const int32_t *rowptr, int64_t n,
                                int32_t *col)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / ROW_LANES;
     if (i >= n) return;
-    int32_t b = rowptr[i], e = rowptr[i + 1];
+    const int32_t b = rowptr[i], e = rowptr[i + 1];
     const int32_t *row = slots + i * max_deg;
-    for (int32_t p = b; p < e; p++) col[p] = row[p - b];
+    for (int32_t p = b + (int32_t)(t % ROW_LANES); p < e; p += ROW_LANES) col[p] = row[p - b];
 }
 
-// Upper edges of row i: ids eoff[i] .. eoff[i+1]-1, geometry as the contact test.
+// Upper edges of row i: ids eoff[i] .. eoff[i+1]-1, geometry as the contact
+// test.  The row's columns ascend, so its upper entries are its last
+// eoff[i+1] - eoff[i], and an upper entry's edge id is eoff[i] plus its rank
+// among them.
 __global__ void k_edges(const double *pos, const double *R, const int32_t *rowptr, const int32_t *col,
                         const int32_t *eoff, int64_t n, int32_t *ei, int32_t *ej, double4 *wu, double *w)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / ROW_LANES;
     if (i >= n) return;
-    int32_t e = eoff[i];
+    const int32_t e0 = eoff[i], re = rowptr[i + 1];
+    const int32_t up0 = re - (eoff[i + 1] - e0);   // first upper entry
     const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2], ri = R[i];
-    for (int32_t p = rowptr[i]; p < rowptr[i + 1]; p++) {
-        int64_t j = col[p];
-        if (j < i) continue;
+    for (int32_t p = up0 + (int32_t)(t % ROW_LANES); p < re; p += ROW_LANES) {
+        const int64_t j = col[p];
         double dx = pos[3 * j + 0] - xi;
         double dy = pos[3 * j + 1] - yi;
         double dz = pos[3 * j + 2] - zi;
         double d = sqrt((dx * dx + dy * dy) + dz * dz);
         double s = ri + R[j];
+        const int32_t e = e0 + (p - up0);
         ei[e] = (int32_t)i;
         ej[e] = (int32_t)j;
         wu[e] = make_double4(s - d, dx / d, dy / d, dz / d);
         w[e] = s - d;
-        e++;
     }
 }
 
@@ -219,11 +239,12 @@ __global__ void k_edges(const double *pos, const double *R, const int32_t *rowpt
 __global__ void k_entry_edges(const int32_t *rowptr, const int32_t *col, const int32_t *eoff, int64_t n,
                               int32_t *ent_edge)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / ROW_LANES;
     if (i >= n) return;
     int32_t b = rowptr[i], e = rowptr[i + 1];
     int32_t nlow_i = (e - b) - (eoff[i + 1] - eoff[i]);
-    for (int32_t p = b; p < e; p++) {
+    for (int32_t p = b + (int32_t)(t % ROW_LANES); p < e; p += ROW_LANES) {
         int32_t j = col[p];
         if (j > i) {
             ent_edge[p] = eoff[i] + (p - b - nlow_i);
@@ -346,8 +367,9 @@ static int collide_impl(sgp_ctx ctx, int64_t n, const double *pos, const double 
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP3], n + 1, &upc));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP4], 4, &flags));
     SGP_TRY(fill_i32(ctx, flags, 0, 4));
-    k_neighbors<<<grid_for(n, 128), 128, 0, st>>>(sp, va, ka, n, gr, cstart, cend, max_deg, slots, deg, upc,
-                                                  flags);
+    const size_t nb_lds = sizeof(int32_t) * NB_THREADS * (size_t)(max_deg | 1);
+    k_neighbors<<<grid_for(n, NB_THREADS), NB_THREADS, nb_lds, st>>>(sp, va, ka, n, gr, cstart, cend, max_deg,
+                                                                     slots, deg, upc, flags);
     LAUNCH_CHECK(ctx);
     // 4. rows and edge numbering
     SGP_TRY(scan_exclusive(ctx, deg, rowptr, n));
@@ -369,9 +391,9 @@ static int collide_impl(sgp_ctx ctx, int64_t n, const double *pos, const double 
     SGP_TRY(ensure_t(ctx, g->ej, m + 1, &ej));
     SGP_TRY(ensure_t(ctx, g->wu, m + 1, &wu));
     SGP_TRY(ensure_t(ctx, g->w, m + 1, &wv));
-    k_compact_rows<<<grid_for(n, 256), 256, 0, st>>>(slots, max_deg, rowptr, n, col);
-    k_edges<<<grid_for(n, 128), 128, 0, st>>>(pos, radius, rowptr, col, upc, n, ei, ej, wu, wv);
-    k_entry_edges<<<grid_for(n, 128), 128, 0, st>>>(rowptr, col, upc, n, ee);
+    k_compact_rows<<<grid_for(ROW_LANES * n, 256), 256, 0, st>>>(slots, max_deg, rowptr, n, col);
+    k_edges<<<grid_for(ROW_LANES * n, 256), 256, 0, st>>>(pos, radius, rowptr, col, upc, n, ei, ej, wu, wv);
+    k_entry_edges<<<grid_for(ROW_LANES * n, 256), 256, 0, st>>>(rowptr, col, upc, n, ee);
     LAUNCH_CHECK(ctx);
     return SGP_OK;
 }
