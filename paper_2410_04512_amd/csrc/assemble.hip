@@ -89,12 +89,13 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t n, const int32_t *rowp
         double W[9];
         for (int x = 0; x < 9; x++) W[x] = 0.0;
         if (row_ok && c < deg) {
+            // both gathers before the first store (a load behind a store waits for it)
             const double4 q = wu[ent_edge[b + c]];
+            const int32_t jc = inv[col[b + c]];
             double B[9];
             friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
             for (int x = 0; x < 9; x++) B[x] = -W[x];
             put_sym(val, k0 + c, B);
-            const int32_t jc = inv[col[b + c]];
             bcol[k0 + c] = jc;
             // edge form: entry k0 + c - i
             const int64_t ke = k0 + c - i;

@@ -57,6 +57,10 @@ __global__ void k_tree_blocks(int64_t n, const int32_t *tptr, const int32_t *tad
 {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
+    // the parent edge's (w, u) is loaded before the first store (a load
+    // behind a store waits for it)
+    const int32_t e = pedge[v];
+    const double4 qe = wu[e >= 0 ? e : 0];
     double P[9];
     for (int t = 0; t < 9; t++) P[t] = (t % 4 == 0) ? gmed : 0.0;
     for (int32_t k = tptr[v]; k < tptr[v + 1]; k++) {
@@ -66,9 +70,8 @@ __global__ void k_tree_blocks(int64_t n, const int32_t *tptr, const int32_t *tad
         for (int t = 0; t < 9; t++) P[t] = P[t] + W[t];
     }
     for (int t = 0; t < 9; t++) Pd[9 * v + t] = P[t];
-    int32_t e = pedge[v];
     if (e >= 0) {
-        double4 q = wu[e];
+        const double4 q = qe;
         double W[9];
         friction_block_dev(q.x, q.y, q.z, q.w, gpar, gperp, W);
         for (int t = 0; t < 9; t++) E[9 * v + t] = -W[t];

@@ -308,25 +308,33 @@ __global__ void k_orient(int64_t nd, const int32_t *adj, const int32_t *adje, co
     }
 }
 
-__global__ void k_depth(int64_t n, const int32_t *parent, const int32_t *dpos, const int32_t *excl,
-                        const int32_t *wval, int32_t *depth, int32_t *maxd)
+__global__ __launch_bounds__(256) void k_depth(int64_t n, const int32_t *parent, const int32_t *dpos,
+                                               const int32_t *excl, const int32_t *wval, int32_t *depth,
+                                               int32_t *maxd)
 {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t d = 0;   // lanes past n take part in the wave maximum with 0
-    if (v < n) {
-        if (parent[v] >= 0) {
-            int32_t g = dpos[v];
-            d = excl[g] + wval[g];   // inclusive running sum of the tour up to v's entry
-        }
-        depth[v] = d;
+    __shared__ int32_t sd[4];
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t dv = 0;   // lanes past n take part in the block maximum with 0
+    if (v < n && parent[v] >= 0) {
+        const int32_t g = dpos[v];
+        dv = excl[g] + wval[g];   // inclusive running sum of the tour up to v's entry
     }
-    // the wave's largest depth, then one atomic per wave that can raise it
-    // (an atomic per vertex on one address would serialise)
+    int32_t d = dv;
+    // the block's largest depth, then one atomic per block that can raise it
+    // (an atomic per vertex on one address would serialise); the current
+    // maximum is read before any store, and the depth is stored last
     for (int o = 32; o > 0; o >>= 1) {
         const int32_t d2 = __shfl_xor(d, o, 64);
         d = d2 > d ? d2 : d;
     }
-    if ((threadIdx.x & 63) == 0 && d > *(volatile int32_t *)maxd) atomicMax(maxd, d);
+    if ((threadIdx.x & 63) == 0) sd[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t bm = sd[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) bm = sd[w] > bm ? sd[w] : bm;
+        if (bm > *(volatile int32_t *)maxd) atomicMax(maxd, bm);
+    }
+    if (v < n) depth[v] = dv;
 }
 
 __global__ void k_count_roots(int64_t n, const int32_t *parent, int32_t *cnt)
