@@ -346,7 +346,9 @@ int sgp_kernel_stats(sgp_ctx ctx, double *total_ms, int64_t *launches);
 
 /* Duration of the last call of each phase on this context, measured with HIP
  * events on its stream, in milliseconds:
- * [0] collide, [1] assemble, [2] build_tree, [3] factor, [4] solve. */
+ * [0] collide, [1] assemble, [2] build_tree, [3] factor, [4] solve.
+ * The phases record their events without waiting for them; this call waits
+ * for the last recorded phase ends that were not read yet. */
 int sgp_phase_times(sgp_ctx ctx, double *ms5);
 
 #ifdef __cplusplus

@@ -52,7 +52,16 @@ extern "C" int sgp_set_stream(sgp_ctx c, void *hip_stream)
 extern "C" int sgp_phase_times(sgp_ctx c, double *ms5)
 {
     if (!c || !ms5) return SGP_EINVAL;
-    for (int k = 0; k < 5; k++) ms5[k] = c->phase_ms[k];
+    for (int k = 0; k < 5; k++) {
+        if (c->phase_pending[k]) {
+            float ms = 0.f;
+            if (hipEventSynchronize(c->ev[2 * k + 1]) == hipSuccess &&
+                hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) == hipSuccess)
+                c->phase_ms[k] = ms;
+            c->phase_pending[k] = false;
+        }
+        ms5[k] = c->phase_ms[k];
+    }
     return SGP_OK;
 }
 

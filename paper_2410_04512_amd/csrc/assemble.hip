@@ -214,11 +214,7 @@ extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double
                                                  g_perp, g_med, brow, bcol, val, dpos, ecol, ew, dg);
     LAUNCH_CHECK(ctx);
     SGP_TRY(bsr_prepare(ctx, A));
-    if (ctx->ev[3]) {
-        (void)hipEventRecord(ctx->ev[3], st);
-        (void)hipEventSynchronize(ctx->ev[3]);
-        (void)hipEventElapsedTime(&ctx->phase_ms[1], ctx->ev[2], ctx->ev[3]);
-    }
+    phase_end(ctx, 1);
     return SGP_OK;
 }
 

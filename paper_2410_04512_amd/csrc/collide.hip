@@ -404,11 +404,7 @@ extern "C" int sgp_collide(sgp_ctx ctx, int64_t n, const double *pos, const doub
     int64_t off[2] = {0, n};
     if (ctx && ctx->ev[0]) (void)hipEventRecord(ctx->ev[0], ctx->stream);
     int s = collide_impl(ctx, n, pos, radius, max_deg, g, 1, off);
-    if (s == SGP_OK && ctx->ev[1]) {
-        (void)hipEventRecord(ctx->ev[1], ctx->stream);
-        (void)hipEventSynchronize(ctx->ev[1]);
-        (void)hipEventElapsedTime(&ctx->phase_ms[0], ctx->ev[0], ctx->ev[1]);
-    }
+    if (s == SGP_OK) phase_end(ctx, 0);
     return s;
 }
 
@@ -421,11 +417,7 @@ extern "C" int sgp_collide_batched(sgp_ctx ctx, int64_t n_inst, const int64_t *o
         if (offsets[k + 1] < offsets[k]) return set_err(ctx, SGP_EINVAL, "collide_batched: offsets decrease");
     if (ctx->ev[0]) (void)hipEventRecord(ctx->ev[0], ctx->stream);
     int s = collide_impl(ctx, offsets[n_inst], pos, radius, max_deg, g, n_inst, offsets);
-    if (s == SGP_OK && ctx->ev[1]) {
-        (void)hipEventRecord(ctx->ev[1], ctx->stream);
-        (void)hipEventSynchronize(ctx->ev[1]);
-        (void)hipEventElapsedTime(&ctx->phase_ms[0], ctx->ev[0], ctx->ev[1]);
-    }
+    if (s == SGP_OK) phase_end(ctx, 0);
     return s;
 }
 

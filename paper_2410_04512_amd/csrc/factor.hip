@@ -1586,11 +1586,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     LAUNCH_CHECK(ctx);
     SGP_TRY(tail_tables(ctx, M, n, in_ptr, in_src, tout));
     SGP_TRY(readback(ctx, hbuf, status, 4));
-    if (ctx->ev[7]) {
-        (void)hipEventRecord(ctx->ev[7], st);
-        (void)hipEventSynchronize(ctx->ev[7]);
-        (void)hipEventElapsedTime(&ctx->phase_ms[3], ctx->ev[6], ctx->ev[7]);
-    }
+    phase_end(ctx, 3);
     if (hbuf[0]) return set_err(ctx, SGP_ENOTSPD, "factor_tree: a pivot block is not positive definite");
     return SGP_OK;
 }

@@ -903,11 +903,7 @@ static int solve_common(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<in
     } else {
         s = solve_f64(ctx, A, M, off, F, v, opts, info);
     }
-    if (s == SGP_OK && ctx->ev[9]) {
-        (void)hipEventRecord(ctx->ev[9], st);
-        (void)hipEventSynchronize(ctx->ev[9]);
-        (void)hipEventElapsedTime(&ctx->phase_ms[4], ctx->ev[8], ctx->ev[9]);
-    }
+    if (s == SGP_OK) phase_end(ctx, 4);
     if (s != SGP_OK) return s;
     int worst = SGP_OK;
     for (int64_t k = 0; k < K; k++)

@@ -49,6 +49,7 @@ struct sgp_ctx_ {
     DevBuf ws[24];                 // scratch workspaces (by role index)
     hipEvent_t ev[12] = {};
     float phase_ms[5] = {0, 0, 0, 0, 0};
+    bool phase_pending[5] = {false, false, false, false, false};   // end recorded, time not read yet
     // per-launch timing of the CG's matrix product (events on ctx->stream)
     int ktiming = 0;
     std::vector<hipEvent_t> kev;   // pairs (before, after)
@@ -185,6 +186,16 @@ inline int ensure_t(sgp_ctx ctx, DevBuf &b, size_t count, T **out)
 }
 void release(DevBuf &b);
 int readback(sgp_ctx ctx, void *host, const void *dev, size_t bytes);   // synchronises
+
+// end of phase k (0 collide, 1 assemble, 2 build_tree, 3 factor, 4 solve):
+// its events are ev[2k], ev[2k+1]; the time is read when it is asked for, so
+// the host does not wait for the phase here
+inline void phase_end(sgp_ctx ctx, int k)
+{
+    if (!ctx->ev[2 * k + 1]) return;
+    (void)hipEventRecord(ctx->ev[2 * k + 1], ctx->stream);
+    ctx->phase_pending[k] = true;
+}
 
 inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads) ? (unsigned)((n + threads - 1) / threads) : 1u; }
 

@@ -486,11 +486,7 @@ extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
         T->max_depth = 0;
         T->n_roots = n;
     }
-    if (ctx->ev[5]) {
-        (void)hipEventRecord(ctx->ev[5], st);
-        (void)hipEventSynchronize(ctx->ev[5]);
-        (void)hipEventElapsedTime(&ctx->phase_ms[2], ctx->ev[4], ctx->ev[5]);
-    }
+    phase_end(ctx, 2);
     return SGP_OK;
 }
 
