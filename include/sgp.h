@@ -320,7 +320,11 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
  *                 rake-and-compress, default 0; used by factors built
  *                 afterwards)
  *  "light_cap"    vertices of such subtrees packed into one workgroup
- *                 (1..2^20, default 512)
+ *                 (1..2^20, default 512); also the packing of the mid
+ *                 steps' components (CONTRACT without light steps: the
+ *                 steps between the first two and the tail, from the first
+ *                 with at most 2^17 vertices left, are swept one workgroup
+ *                 per group of components, in one launch per sweep)
  * Unknown keys or values out of range give SGP_EINVAL.  check_every and
  * graph leave every result bitwise unchanged, and so does tail_max as long as
  * the tail does not reach the first elimination step (that step forms its

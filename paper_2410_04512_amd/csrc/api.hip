@@ -115,7 +115,7 @@ extern "C" void sgp_prec_free(sgp_prec M)
     release(M->F); release(M->Dinv); release(M->y); release(M->F32); release(M->Dinv32); release(M->y32);
     release(M->tout); release(M->cs); release(M->cs32); release(M->step_ptr);
     release(M->elim_int); release(M->perm); release(M->inv); release(M->tail_iptr); release(M->tail_tslot);
-    release(M->tail_b); release(M->light_ptr); release(M->wu0); release(M->wu032);
+    release(M->tail_b); release(M->light_ptr); release(M->mid_ptr); release(M->wu0); release(M->wu032);
     release(M->jdinv);
     delete M;
 }

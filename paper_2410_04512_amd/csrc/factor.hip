@@ -346,6 +346,68 @@ __global__ void k_light_ptr(int64_t n, const uint32_t *key, int64_t lim, int32_t
     for (int64_t k = lo + 1; k <= hi; k++) wptr[k] = (int32_t)q;
 }
 
+// ---- mid steps grouped by component (CONTRACT without light steps)
+//
+// The steps between the first, large ones and the tail hold few vertices
+// each, and their vertices, joined by their up-links, fall apart into small
+// components (the pieces of the tree hanging below the tail's vertices: tens
+// of vertices each).  Every push and every read of x between steps stays
+// inside a component or goes to the tail, so each component is handed to one
+// workgroup of the sweeps (packed in the internal order up to light_cap
+// vertices), which walks those steps with a barrier between them, with the
+// kernels of the light subtrees: one launch per sweep instead of one per step.
+
+// jr[v] = v for a vertex of steps m0..m1-1, -1 otherwise
+__global__ void k_mid_init(int64_t n, const int32_t *stepv, int32_t m0, int32_t m1, int32_t *jr)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) jr[v] = stepv[v] >= m0 && stepv[v] < m1 ? (int32_t)v : -1;
+}
+
+// one round of label propagation along the up-links between mid vertices:
+// both ends take the smaller label (labels only decrease and stay members of
+// the component, so they converge to its smallest vertex); flag: a link still
+// joined two labels
+__global__ void k_mid_link(int64_t n, const int32_t *up0, const int32_t *up1, int32_t *jr, int32_t *flag)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t a = jr[v];
+    if (a < 0) return;
+    const int32_t u[2] = {up0[v], up1[v]};
+    for (int k = 0; k < 2; k++) {
+        if (u[k] < 0) continue;
+        const int32_t b = jr[u[k]];
+        if (b < 0 || b == a) continue;
+        if (b < a)
+            atomicMin(&jr[v], b);
+        else
+            atomicMin(&jr[u[k]], a);
+        flag[0] = 1;
+    }
+}
+
+// jr[v] = jr[jr[v]]: a label's own label is no larger
+__global__ void k_mid_jump(int64_t n, int32_t *jr)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t a = jr[v];
+    if (a >= 0) jr[v] = jr[a];
+}
+
+// first q of every (step, workgroup) key in [lo, hi], at wptr[key - lo]; keys sorted
+__global__ void k_mid_ptr(int64_t n, const uint32_t *key, int64_t lo, int64_t hi, int32_t *wptr)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > n) return;
+    int64_t a = q == 0 ? lo - 1 : (int64_t)key[q - 1];
+    int64_t b = q == n ? hi : (int64_t)key[q];
+    if (a < lo - 1) a = lo - 1;
+    if (b > hi) b = hi;
+    for (int64_t k = a + 1; k <= b; k++) wptr[k - lo] = (int32_t)q;
+}
+
 // step boundaries from the keys sorted by step: sptr[s] = first q of step s
 __global__ void k_step_bounds(int64_t n, const uint32_t *skey, uint32_t div, int32_t S, int32_t *sptr)
 {
@@ -854,6 +916,8 @@ static size_t tail_lds_bytes(size_t elem, int64_t nt, int64_t ni, int64_t nsteps
 // tail vertices at most: every vertex pushes to at most two others and a step
 // holds at least one vertex, so 3 * 8 * 3 nt + 4 (nt + 1) bytes always suffice
 constexpr int TAIL_MAX_VERTICES = (TAIL_LDS_BYTES - 4) / 76;
+constexpr int TAIL_DEFAULT_VERTICES = 2200;   // the tail_max knob's default
+constexpr int64_t MID_MAX_VERTICES = 1 << 17;   // vertices left at the first mid step at most
 
 // The tail's right-hand sides before its first step: r minus the pushes from
 // vertices eliminated before the tail (all finished by the launch boundary).
@@ -1209,8 +1273,19 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
     // the first step from the contacts' (w, u) when it is one of these launches
     const bool step0_wu = wu0 && L == 0 && ts > 0 && M->n_wu0 == sp[1];
     const T gp = (T)M->gpar, gq = (T)M->gperp, gm = (T)M->gmed;
+    // the mid steps m0..m1-1 below the tail: one launch per sweep, a
+    // workgroup per packed group of components
+    const int32_t m0 = M->mid_step0, m1 = std::min(M->mid_step0 + M->mid_steps, ts);
+    const bool mid = M->mid_steps > 0 && m0 >= L && m1 - m0 >= 2;
+    const int32_t *mptr = (const int32_t *)M->mid_ptr.p;
     for (int k = L; k < ts; k++) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
+        if (mid && k == m0) {
+            k_fwd_light<T><<<M->mid_nwg, 256, 0, st>>>(m1 - m0, M->mid_nwg, mptr, elim, in_ptr, tout, F, fs, Dinv, r,
+                                                       y, cs, s);
+            k = m1 - 1;
+            continue;
+        }
         if (k == 0 && step0_wu)
             k_fwd_step0<T><<<grid_for(q1, 256), 256, 0, st>>>(q1, elim, tout, wu0, 4 * (int64_t)q1, gp, gq, gm, Dinv,
                                                               r, y, cs, s);
@@ -1236,6 +1311,11 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
     }
     for (int k = ts - 1; k >= L; k--) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
+        if (mid && k == m1 - 1) {
+            k_bwd_light<T><<<M->mid_nwg, 256, 0, st>>>(m1 - m0, M->mid_nwg, mptr, elim, upq, F, fs, Dinv, y, z, s);
+            k = m0;
+            continue;
+        }
         if (k == 0 && step0_wu)
             k_bwd_step0<T><<<grid_for(q1, 256), 256, 0, st>>>(q1, elim, upq, wu0, 4 * (int64_t)q1, gp, gq, gm, Dinv,
                                                               y, z, s);
@@ -1476,6 +1556,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
         }
     }
     M->steps = S;
+    M->mid_step0 = M->mid_steps = M->mid_nwg = 0;
     // elimination order: by (step, id)
     uint32_t *ka, *kb;
     int32_t *elim, *vb, *pos, *scnt, *sptr;
@@ -1486,23 +1567,28 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     SGP_TRY(ensure_t(ctx, M->pos, n + 1, &pos));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP7], (size_t)S + 2, &scnt));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP8], (size_t)S + 2, &sptr));
-    // keys (step, light workgroup); the sort is stable, so the vertices of one
-    // key stay in the internal order
-    if ((int64_t)S * nwg >= ((int64_t)1 << 31)) return set_err(ctx, SGP_EINVAL, "factor_tree: schedule too large");
-    int sbits = 1;
-    while (((int64_t)1 << sbits) < (int64_t)S * nwg) sbits++;
+    (void)scnt;
     SGP_TRY(copy_order(ctx, M->perm, M->inv, g->perm, g->inv, n));
-    k_stepkeys<<<grid_for(n, 256), 256, 0, st>>>(n, stepv, light ? wgv : nullptr, (uint32_t)nwg,
-                                               (const int32_t *)g->perm.p, ka, elim);
-    LAUNCH_CHECK(ctx);
-    SGP_TRY(radix_sort_pairs(ctx, ka, elim, kb, vb, n, sbits));
     int32_t *elim_int;
     SGP_TRY(ensure_t(ctx, M->elim_int, n + 1, &elim_int));
-    k_map_ids<<<grid_for(n, 256), 256, 0, st>>>(n, elim, (const int32_t *)g->inv.p, elim_int);
-    k_invperm<<<grid_for(n, 256), 256, 0, st>>>(n, elim, pos);
-    (void)scnt;
-    k_step_bounds<<<grid_for(n + 1, 256), 256, 0, st>>>(n, ka, (uint32_t)nwg, S, sptr);
-    LAUNCH_CHECK(ctx);
+    // keys (step, workgroup of a light or mid vertex, else 0); the sort is
+    // stable, so the vertices of one key stay in the internal order
+    auto order = [&](const int32_t *wg, int32_t nw) -> int {
+        if ((int64_t)S * nw >= ((int64_t)1 << 31)) return set_err(ctx, SGP_EINVAL, "factor_tree: schedule too large");
+        int sbits = 1;
+        while (((int64_t)1 << sbits) < (int64_t)S * nw) sbits++;
+        k_stepkeys<<<grid_for(n, 256), 256, 0, st>>>(n, stepv, wg, (uint32_t)nw, (const int32_t *)g->perm.p, ka,
+                                                   elim);
+        LAUNCH_CHECK(ctx);
+        SGP_TRY(radix_sort_pairs(ctx, ka, elim, kb, vb, n, sbits));
+        k_map_ids<<<grid_for(n, 256), 256, 0, st>>>(n, elim, (const int32_t *)g->inv.p, elim_int);
+        k_invperm<<<grid_for(n, 256), 256, 0, st>>>(n, elim, pos);
+        k_step_bounds<<<grid_for(n + 1, 256), 256, 0, st>>>(n, ka, (uint32_t)nw, S, sptr);
+        LAUNCH_CHECK(ctx);
+        M->h_step_ptr.resize(S + 1);
+        return readback(ctx, M->h_step_ptr.data(), sptr, (S + 1) * sizeof(int32_t));
+    };
+    SGP_TRY(order(light ? wgv : nullptr, nwg));
     M->light_steps = light;
     M->light_nwg = light ? nwg : 0;
     if (light) {
@@ -1511,9 +1597,66 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
         SGP_TRY(ensure_t(ctx, M->light_ptr, (size_t)lim + 2, &wptr));
         k_light_ptr<<<grid_for(n + 1, 256), 256, 0, st>>>(n, ka, lim, wptr);
         LAUNCH_CHECK(ctx);
+    } else if (schedule == SGP_SCHED_CONTRACT) {
+        // the mid steps: from the first step (after the first two) with at
+        // most MID_MAX_VERTICES vertices left, up to the first step with at
+        // most the default tail size left.  Fixed by the schedule alone (not
+        // by tail_max), so the elimination order does not depend on the tail.
+        const std::vector<int32_t> &hs = M->h_step_ptr;
+        int32_t m0 = 2, m1 = S;
+        while (m0 < S && n - hs[m0] > MID_MAX_VERTICES) m0++;
+        const int tdef = std::min(TAIL_DEFAULT_VERTICES, TAIL_MAX_VERTICES);
+        while (m1 > m0 && n - hs[m1 - 1] <= tdef) m1--;
+        if (m1 - m0 >= 2) {
+            int32_t *ja, *jb, *lcnt, *lstart, *wgr, *mw, *flag;
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP3], n + 1, &ja));
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP4], n + 1, &jb));
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP5], n + 1, &lcnt));
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_KEY_B], 2 * n + 2, &lstart));
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_VAL_A], n + 1, &wgr));
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP9], n + 1, &mw));
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP6], 2 * SCHED_STAT_BLOCKS + 4, &flag));
+            k_mid_init<<<grid_for(n, 256), 256, 0, st>>>(n, stepv, m0, m1, ja);
+            LAUNCH_CHECK(ctx);
+            // label propagation, four rounds per check (components are small)
+            bool converged = false;
+            for (int it = 0; it < 64 && !converged; it++) {
+                SGP_TRY(fill_i32(ctx, flag, 0, 1));
+                for (int r = 0; r < 4; r++) {
+                    k_mid_link<<<grid_for(n, 256), 256, 0, st>>>(n, up0, up1, ja, flag);
+                    k_mid_jump<<<grid_for(n, 256), 256, 0, st>>>(n, ja);
+                }
+                LAUNCH_CHECK(ctx);
+                int32_t hf;
+                SGP_TRY(readback(ctx, &hf, flag, 4));
+                // a round that found no link between two labels: every component is uniform
+                if (!hf) converged = true;
+            }
+            if (converged) {
+                SGP_TRY(fill_i32(ctx, lcnt, 0, n));
+                k_light_count<<<grid_for(n, 256), 256, 0, st>>>(n, ja, lcnt);
+                k_light_vals<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->perm.p, ja, lcnt, jb);
+                LAUNCH_CHECK(ctx);
+                SGP_TRY(scan_exclusive(ctx, jb, lstart, n));
+                int32_t total;
+                SGP_TRY(readback(ctx, &total, lstart + n, 4));
+                const int32_t cap = std::max(ctx->light_cap, 1);
+                const int32_t mnwg = std::max((total + cap - 1) / cap, 1);
+                k_light_rootwg<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->perm.p, ja, lstart, cap, wgr);
+                k_light_wg<<<grid_for(n, 256), 256, 0, st>>>(n, ja, wgr, mw);
+                LAUNCH_CHECK(ctx);
+                SGP_TRY(order(mw, mnwg));
+                int32_t *wptr;
+                const int64_t lo = (int64_t)m0 * mnwg, hi = (int64_t)m1 * mnwg;
+                SGP_TRY(ensure_t(ctx, M->mid_ptr, (size_t)(hi - lo) + 2, &wptr));
+                k_mid_ptr<<<grid_for(n + 1, 256), 256, 0, st>>>(n, ka, lo, hi, wptr);
+                LAUNCH_CHECK(ctx);
+                M->mid_step0 = m0;
+                M->mid_steps = m1 - m0;
+                M->mid_nwg = mnwg;
+            }
+        }
     }
-    M->h_step_ptr.resize(S + 1);
-    SGP_TRY(readback(ctx, M->h_step_ptr.data(), sptr, (S + 1) * sizeof(int32_t)));
     int32_t *dsp;
     SGP_TRY(ensure_t(ctx, M->step_ptr, (size_t)S + 2, &dsp));
     HIP_TRY(ctx, hipMemcpyAsync(dsp, sptr, (S + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, st));

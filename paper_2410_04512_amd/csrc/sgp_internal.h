@@ -141,6 +141,8 @@ struct sgp_prec_ {
     DevBuf step_ptr;                                    // device copy of h_step_ptr
     int32_t light_steps = 0, light_nwg = 0;             // steps < light_steps: subtrees, one workgroup each
     DevBuf light_ptr;                                   // [light_steps * light_nwg + 1] first q of (step, workgroup)
+    int32_t mid_step0 = 0, mid_steps = 0, mid_nwg = 0;  // steps mid_step0.. +mid_steps: components, one workgroup each
+    DevBuf mid_ptr;                                     // [mid_steps * mid_nwg + 1] first q of (step, workgroup)
     int32_t tail_step = 0;                              // steps >= tail_step run in one workgroup
     int32_t tail_nt = 0, tail_ni = 0;                   // tail vertices, tail-internal push slots
     DevBuf tail_iptr, tail_tslot;                       // per tail target: first internal slot; per (q,k): its slot
