@@ -364,10 +364,11 @@ __global__ void k_mid_init(int64_t n, const int32_t *stepv, int32_t m0, int32_t 
     if (v < n) jr[v] = stepv[v] >= m0 && stepv[v] < m1 ? (int32_t)v : -1;
 }
 
-// one round of label propagation along the up-links between mid vertices:
-// both ends take the smaller label (labels only decrease and stay members of
-// the component, so they converge to its smallest vertex); flag: a link still
-// joined two labels
+// one round of hooking along the up-links between mid vertices: where the
+// two ends carry different labels, the larger label (a vertex of the
+// component) takes the smaller one as its label.  Labels only decrease and
+// stay members of the component, so with the jumps below they converge to
+// its smallest vertex; flag: a link still joined two labels
 __global__ void k_mid_link(int64_t n, const int32_t *up0, const int32_t *up1, int32_t *jr, int32_t *flag)
 {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -380,9 +381,9 @@ __global__ void k_mid_link(int64_t n, const int32_t *up0, const int32_t *up1, in
         const int32_t b = jr[u[k]];
         if (b < 0 || b == a) continue;
         if (b < a)
-            atomicMin(&jr[v], b);
+            atomicMin(&jr[a], b);
         else
-            atomicMin(&jr[u[k]], a);
+            atomicMin(&jr[b], a);
         flag[0] = 1;
     }
 }
