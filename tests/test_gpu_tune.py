@@ -162,6 +162,41 @@ def test_light_subtree_sweeps_match_oracle(ctx, lh, cap):
     assert i32["status"] == 0 and i32["relres_true"] <= 1.0001e-8
 
 
+@pytest.mark.parametrize("cap,tail", [(1, 2200), (64, 2200), (512, 2200), (512, 256), (512, 0)])
+def test_mid_step_sweeps_match_oracle(ctx, cap, tail):
+    """The mid elimination steps swept one workgroup per group of components
+    (60k cells: steps from the third on, up to the default tail), with one
+    component per workgroup, small and default packing, and with the tail
+    smaller than the default (steps between the mid range and the tail as
+    launches of their own) or off: the tree solve against the oracle's, FP64
+    and FP32, a converged CG, and results that do not depend on the tail."""
+    c, g, A, T = _system(ctx, 60000, 21)
+    ctx.tune("light_cap", cap)
+    ctx.tune("tail_max", tail)
+    try:
+        M = ctx.factor_tree(g, T)
+        og = O.collide(c["pos"], c["radius"])
+        fo = O.tree_factor(og, O.build_tree(og))
+        b = np.random.default_rng(cap).normal(size=(60000, 3))
+        zo = O.tree_solve(fo, b)
+        z = host(ctx.prec_apply(M, to_dev(b)))
+        assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+        F = to_dev(c["force"])
+        v, info = ctx.pcg_solve(A, M, F)
+        assert info["status"] == 0 and info["relres_true"] <= 1.0001e-8
+        check_velocity(host(v), info["iters"], O.assemble(og), c["force"], fo)
+        w, i32 = ctx.pcg_solve(A, M, F, precision="f32ir", inner_rtol=1e-4)
+        assert i32["status"] == 0 and i32["relres_true"] <= 1.0001e-8
+        if tail != 2200:   # the grouping is fixed by the schedule: the tail changes nothing
+            ctx.tune("tail_max", 2200)
+            M2 = ctx.factor_tree(g, T)
+            v2, info2 = ctx.pcg_solve(A, M2, F)
+            assert info2["iters"] == info["iters"] and torch.equal(v, v2)
+    finally:
+        ctx.tune("light_cap", 512)
+        ctx.tune("tail_max", 2200)
+
+
 def test_light_subtrees_batched(ctx):
     """A batch of separate trees (several of them raked away completely)."""
     sizes = [3000, 20, 9000, 1, 700]
