@@ -357,6 +357,35 @@ __global__ void k_light_ptr(int64_t n, const uint32_t *key, int64_t lim, int32_t
 // vertices), which walks those steps with a barrier between them, with the
 // kernels of the light subtrees: one launch per sweep instead of one per step.
 
+// vertices per step (S <= HIST_MAX_STEPS): per-block LDS counts, part[b * S + s]
+constexpr int HIST_MAX_STEPS = 256;
+
+__global__ __launch_bounds__(256) void k_step_hist(int64_t n, const int32_t *stepv, int32_t S, int32_t *part)
+{
+    __shared__ int32_t h[HIST_MAX_STEPS];
+    for (int s = threadIdx.x; s < S; s += 256) h[s] = 0;
+    __syncthreads();
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+        const int32_t st = stepv[v];
+        if (st >= 0 && st < S) atomicAdd(&h[st], 1);
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < S; s += 256) part[(int64_t)blockIdx.x * S + s] = h[s];
+}
+
+// out[s] = sum over the nb blocks' counts of step s: one workgroup per step
+__global__ __launch_bounds__(256) void k_step_hist_sum(int nb, int32_t S, const int32_t *part, int32_t *out)
+{
+    __shared__ int32_t sw[4];
+    const int32_t s = blockIdx.x;
+    int32_t c = 0;
+    for (int b = threadIdx.x; b < nb; b += 256) c += part[(int64_t)b * S + s];
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) out[s] = sw[0] + sw[1] + sw[2] + sw[3];
+}
+
 // jr[v] = v for a vertex of steps m0..m1-1, -1 otherwise
 __global__ void k_mid_init(int64_t n, const int32_t *stepv, int32_t m0, int32_t m1, int32_t *jr)
 {
@@ -1589,27 +1618,33 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
         M->h_step_ptr.resize(S + 1);
         return readback(ctx, M->h_step_ptr.data(), sptr, (S + 1) * sizeof(int32_t));
     };
-    SGP_TRY(order(light ? wgv : nullptr, nwg));
     M->light_steps = light;
     M->light_nwg = light ? nwg : 0;
-    if (light) {
-        int32_t *wptr;
-        const int64_t lim = (int64_t)light * nwg;
-        SGP_TRY(ensure_t(ctx, M->light_ptr, (size_t)lim + 2, &wptr));
-        k_light_ptr<<<grid_for(n + 1, 256), 256, 0, st>>>(n, ka, lim, wptr);
+    // the mid steps (CONTRACT without light steps): from the first step
+    // (after the first two) with at most MID_MAX_VERTICES vertices left, up to
+    // the first step with at most the default tail size left.  Fixed by the
+    // schedule alone (not by tail_max), so the elimination order does not
+    // depend on the tail.  The step sizes come from a histogram of the steps,
+    // the components' workgroups from the labelling, and one sort orders the
+    // vertices by (step, workgroup).
+    int32_t *mw = nullptr, mnwg = 1, m0 = 2, m1 = S;
+    if (!light && schedule == SGP_SCHED_CONTRACT && S <= HIST_MAX_STEPS && S >= 4) {
+        const int hnb = (int)std::min<int64_t>(SCHED_STAT_BLOCKS, grid_for(n, 256));
+        int32_t *hpart;
+        SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP6], (size_t)hnb * S + S + 8, &hpart));
+        int32_t *hout = hpart + (size_t)hnb * S;
+        k_step_hist<<<hnb, 256, 0, st>>>(n, stepv, S, hpart);
+        k_step_hist_sum<<<S, 256, 0, st>>>(hnb, S, hpart, hout);
         LAUNCH_CHECK(ctx);
-    } else if (schedule == SGP_SCHED_CONTRACT) {
-        // the mid steps: from the first step (after the first two) with at
-        // most MID_MAX_VERTICES vertices left, up to the first step with at
-        // most the default tail size left.  Fixed by the schedule alone (not
-        // by tail_max), so the elimination order does not depend on the tail.
-        const std::vector<int32_t> &hs = M->h_step_ptr;
-        int32_t m0 = 2, m1 = S;
-        while (m0 < S && n - hs[m0] > MID_MAX_VERTICES) m0++;
+        std::vector<int32_t> cnt(S);
+        SGP_TRY(readback(ctx, cnt.data(), hout, S * sizeof(int32_t)));
+        std::vector<int64_t> left(S + 1, 0);   // left[k]: vertices of steps >= k
+        for (int32_t k = S - 1; k >= 0; k--) left[k] = left[k + 1] + cnt[k];
+        while (m0 < S && left[m0] > MID_MAX_VERTICES) m0++;
         const int tdef = std::min(TAIL_DEFAULT_VERTICES, TAIL_MAX_VERTICES);
-        while (m1 > m0 && n - hs[m1 - 1] <= tdef) m1--;
+        while (m1 > m0 && left[m1 - 1] <= tdef) m1--;
         if (m1 - m0 >= 2) {
-            int32_t *ja, *jb, *lcnt, *lstart, *wgr, *mw, *flag;
+            int32_t *ja, *jb, *lcnt, *lstart, *wgr, *flag;
             SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP3], n + 1, &ja));
             SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP4], n + 1, &jb));
             SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP5], n + 1, &lcnt));
@@ -1619,7 +1654,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
             SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP6], 2 * SCHED_STAT_BLOCKS + 4, &flag));
             k_mid_init<<<grid_for(n, 256), 256, 0, st>>>(n, stepv, m0, m1, ja);
             LAUNCH_CHECK(ctx);
-            // label propagation, four rounds per check (components are small)
+            // hooking and jumping, four rounds per check (components are small)
             bool converged = false;
             for (int it = 0; it < 64 && !converged; it++) {
                 SGP_TRY(fill_i32(ctx, flag, 0, 1));
@@ -1630,7 +1665,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
                 LAUNCH_CHECK(ctx);
                 int32_t hf;
                 SGP_TRY(readback(ctx, &hf, flag, 4));
-                // a round that found no link between two labels: every component is uniform
+                // a check whose rounds found no link between two labels: every component is uniform
                 if (!hf) converged = true;
             }
             if (converged) {
@@ -1642,21 +1677,34 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
                 int32_t total;
                 SGP_TRY(readback(ctx, &total, lstart + n, 4));
                 const int32_t cap = std::max(ctx->light_cap, 1);
-                const int32_t mnwg = std::max((total + cap - 1) / cap, 1);
+                mnwg = std::max((total + cap - 1) / cap, 1);
                 k_light_rootwg<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->perm.p, ja, lstart, cap, wgr);
                 k_light_wg<<<grid_for(n, 256), 256, 0, st>>>(n, ja, wgr, mw);
                 LAUNCH_CHECK(ctx);
-                SGP_TRY(order(mw, mnwg));
-                int32_t *wptr;
-                const int64_t lo = (int64_t)m0 * mnwg, hi = (int64_t)m1 * mnwg;
-                SGP_TRY(ensure_t(ctx, M->mid_ptr, (size_t)(hi - lo) + 2, &wptr));
-                k_mid_ptr<<<grid_for(n + 1, 256), 256, 0, st>>>(n, ka, lo, hi, wptr);
-                LAUNCH_CHECK(ctx);
-                M->mid_step0 = m0;
-                M->mid_steps = m1 - m0;
-                M->mid_nwg = mnwg;
+            } else {
+                mw = nullptr;
             }
         }
+    }
+    if (light) {
+        SGP_TRY(order(wgv, nwg));
+        int32_t *wptr;
+        const int64_t lim = (int64_t)light * nwg;
+        SGP_TRY(ensure_t(ctx, M->light_ptr, (size_t)lim + 2, &wptr));
+        k_light_ptr<<<grid_for(n + 1, 256), 256, 0, st>>>(n, ka, lim, wptr);
+        LAUNCH_CHECK(ctx);
+    } else if (mw) {
+        SGP_TRY(order(mw, mnwg));
+        int32_t *wptr;
+        const int64_t lo = (int64_t)m0 * mnwg, hi = (int64_t)m1 * mnwg;
+        SGP_TRY(ensure_t(ctx, M->mid_ptr, (size_t)(hi - lo) + 2, &wptr));
+        k_mid_ptr<<<grid_for(n + 1, 256), 256, 0, st>>>(n, ka, lo, hi, wptr);
+        LAUNCH_CHECK(ctx);
+        M->mid_step0 = m0;
+        M->mid_steps = m1 - m0;
+        M->mid_nwg = mnwg;
+    } else {
+        SGP_TRY(order(nullptr, 1));
     }
     int32_t *dsp;
     SGP_TRY(ensure_t(ctx, M->step_ptr, (size_t)S + 2, &dsp));
