@@ -31,7 +31,7 @@ constexpr int WAVE_GROUPS = 2;                       // 64-block groups per wave
 constexpr int WAVE_BLOCKS = 64 * WAVE_GROUPS;
 constexpr int ROW_MAX = 65;                          // blocks per row at most (max_deg 64 + diagonal)
 constexpr int ACC_SLOTS = WAVE_BLOCKS + ROW_MAX;     // product slots per wave
-constexpr int EDGE_GROUPS = 4;                       // 64-entry groups per wave, edge form
+constexpr int EDGE_GROUPS = 5;                       // 64-entry groups per wave, edge form
 constexpr int EDGE_BLOCKS = 64 * EDGE_GROUPS;
 constexpr int EDGE_SLOTS = EDGE_BLOCKS + ROW_MAX;
 
