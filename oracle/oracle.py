@@ -239,6 +239,37 @@ def tree_solve(f: Factor, b):
     return x.reshape(-1, 3)
 
 
+def tree_solve_f32(f: Factor, b):
+    """P^{-1} b by the FP32 tree solve of the refinement's inner solve
+    (factor rounded to FP32, FP32 arithmetic), widened to FP64."""
+    t = f.tree
+    b = _c(b, np.float64).reshape(-1)
+    x = np.zeros(3 * t.n)
+    child = t.child if t.child.size else np.zeros(1, np.int32)
+    st = lib().orc_tree_solve_f32(C.c_int64(t.n), _i32(t.parent), _i32(t.order), _i32(t.child_ptr), _i32(child),
+                                  _f64(_c(f.D, np.float64)), _f64(_c(f.L, np.float64)), _f64(b), _f64(x))
+    if st != OK:
+        raise OracleError(st, "tree_solve_f32")
+    return x.reshape(-1, 3)
+
+
+def ir_inner(A: BSR, f: Factor, rhs, inner_tol=1e-5, max_iter=10_000, check=True):
+    """One FP32 inner solve of the refinement: CG on Gamma d = rhs to relative
+    inner_tol with FP32 product and sweeps.  Returns (d, iterations, status)."""
+    t = f.tree
+    rhs = _c(rhs, np.float64).reshape(-1)
+    d = np.zeros(3 * A.n)
+    it = np.zeros(1, np.int32)
+    child = t.child if t.child.size else np.zeros(1, np.int32)
+    st = lib().orc_ir_inner(C.c_int64(A.n), _i32(A.rowptr), _i32(A.bcol), _f64(_c(A.val, np.float64)),
+                            _i32(t.parent), _i32(t.order), _i32(t.child_ptr), _i32(child),
+                            _f64(_c(f.D, np.float64)), _f64(_c(f.L, np.float64)), _f64(rhs), _f64(d),
+                            C.c_double(inner_tol), C.c_int(max_iter), _i32(it))
+    if check and st != OK:
+        raise OracleError(st, "ir_inner")
+    return d.reshape(-1, 3), int(it[0]), int(st)
+
+
 @dataclass
 class SolveInfo:
     status: int

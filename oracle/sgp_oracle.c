@@ -818,6 +818,62 @@ static int inv3_spd(const double D[9], double Di[9])
     return ORC_OK;
 }
 
+/* The tree solve of Appendix B.1 in FP32: ForwardSolve, DiagSolve and
+ * BackwardSolve as orc_tree_solve does them, with FP32 storage and FP32
+ * arithmetic; the factor is given as FP32 copies (Dinvf = D^{-1} inverted in
+ * FP64 and rounded, Lf = L_{p(i),i} rounded). */
+static void tree_apply_f32(int64_t n, const int32_t *parent, const int32_t *order, const int32_t *child_ptr,
+                           const int32_t *child, const float *Dinvf, const float *Lf, const float *src, float *dst)
+{
+    /* ForwardSolve: children before parents (decreasing depth) */
+    for (int64_t qq = 0; qq < n; qq++) {
+        int32_t i = order[qq];
+        float s0 = src[3 * (int64_t)i], s1 = src[3 * (int64_t)i + 1], s2 = src[3 * (int64_t)i + 2];
+        for (int32_t c = child_ptr[i]; c < child_ptr[i + 1]; c++) {
+            int32_t j = child[c];
+            const float *Lm = &Lf[9 * (int64_t)j];
+            const float *zj = &dst[3 * (int64_t)j];
+            s0 = s0 - (Lm[0] * zj[0] + Lm[1] * zj[1] + Lm[2] * zj[2]);
+            s1 = s1 - (Lm[3] * zj[0] + Lm[4] * zj[1] + Lm[5] * zj[2]);
+            s2 = s2 - (Lm[6] * zj[0] + Lm[7] * zj[1] + Lm[8] * zj[2]);
+        }
+        dst[3 * (int64_t)i] = s0; dst[3 * (int64_t)i + 1] = s1; dst[3 * (int64_t)i + 2] = s2;
+    }
+    /* DiagSolve: y_i = D_i^{-1} z_i */
+    for (int64_t i = 0; i < n; i++) {
+        const float *Di = &Dinvf[9 * i];
+        float a0 = dst[3 * i], a1 = dst[3 * i + 1], a2 = dst[3 * i + 2];
+        dst[3 * i] = Di[0] * a0 + Di[1] * a1 + Di[2] * a2;
+        dst[3 * i + 1] = Di[3] * a0 + Di[4] * a1 + Di[5] * a2;
+        dst[3 * i + 2] = Di[6] * a0 + Di[7] * a1 + Di[8] * a2;
+    }
+    /* BackwardSolve: parents before children, x_i = y_i - L_{p(i),i}^T x_{p(i)} */
+    for (int64_t qq = n - 1; qq >= 0; qq--) {
+        int32_t i = order[qq], pp = parent[i];
+        if (pp < 0) continue;
+        const float *Lm = &Lf[9 * (int64_t)i];
+        const float *xp = &dst[3 * (int64_t)pp];
+        for (int a = 0; a < 3; a++)
+            dst[3 * (int64_t)i + a] = dst[3 * (int64_t)i + a] - (Lm[a] * xp[0] + Lm[3 + a] * xp[1] + Lm[6 + a] * xp[2]);
+    }
+}
+
+/* y = Gamma x in FP32 storage and arithmetic (block rows as orc_spmv). */
+static void spmv_f32(int64_t n, const int32_t *rowptr, const int32_t *bcol, const float *valf, const float *src,
+                     float *dst)
+{
+    for (int64_t i = 0; i < n; i++) {
+        float s[3] = {0.0f, 0.0f, 0.0f};
+        for (int32_t kk = rowptr[i]; kk < rowptr[i + 1]; kk++) {
+            const float *B = &valf[9 * (int64_t)kk];
+            const float *xj = &src[3 * (int64_t)bcol[kk]];
+            for (int a = 0; a < 3; a++)
+                s[a] = s[a] + (B[3 * a] * xj[0] + B[3 * a + 1] * xj[1] + B[3 * a + 2] * xj[2]);
+        }
+        dst[3 * i] = s[0]; dst[3 * i + 1] = s[1]; dst[3 * i + 2] = s[2];
+    }
+}
+
 /* Inner solve of one refinement step: CG on Gamma d = r with FP32 storage and
  * FP32 arithmetic for the matrix product and the tree sweeps; dot products
  * are accumulated in FP64 and the step lengths alpha, beta are FP64 numbers
@@ -840,56 +896,12 @@ static int ir_inner(int64_t n, const int32_t *rowptr, const int32_t *bcol, const
     for (int64_t t = 0; t < len; t++) { r[t] = (float)rhs[t]; x[t] = 0.0f; nb = nb + (double)r[t] * (double)r[t]; }
     nb = sqrt(nb);
     if (nb == 0.0) goto done;
-#define TREE_APPLY_F32(src, dst)                                                          \
-    do {                                                                                  \
-        for (int64_t qq = 0; qq < n; qq++) {                                              \
-            int32_t i = order[qq];                                                        \
-            float s0 = (src)[3 * (int64_t)i], s1 = (src)[3 * (int64_t)i + 1], s2 = (src)[3 * (int64_t)i + 2]; \
-            for (int32_t c = child_ptr[i]; c < child_ptr[i + 1]; c++) {                   \
-                int32_t j = child[c];                                                     \
-                const float *Lm = &Lf[9 * (int64_t)j];                                    \
-                const float *zj = &(dst)[3 * (int64_t)j];                                 \
-                s0 = s0 - (Lm[0] * zj[0] + Lm[1] * zj[1] + Lm[2] * zj[2]);                \
-                s1 = s1 - (Lm[3] * zj[0] + Lm[4] * zj[1] + Lm[5] * zj[2]);                \
-                s2 = s2 - (Lm[6] * zj[0] + Lm[7] * zj[1] + Lm[8] * zj[2]);                \
-            }                                                                             \
-            (dst)[3 * (int64_t)i] = s0; (dst)[3 * (int64_t)i + 1] = s1; (dst)[3 * (int64_t)i + 2] = s2; \
-        }                                                                                 \
-        for (int64_t i = 0; i < n; i++) {                                                 \
-            const float *Di = &Dinvf[9 * i];                                              \
-            float a0 = (dst)[3 * i], a1 = (dst)[3 * i + 1], a2 = (dst)[3 * i + 2];        \
-            (dst)[3 * i] = Di[0] * a0 + Di[1] * a1 + Di[2] * a2;                          \
-            (dst)[3 * i + 1] = Di[3] * a0 + Di[4] * a1 + Di[5] * a2;                      \
-            (dst)[3 * i + 2] = Di[6] * a0 + Di[7] * a1 + Di[8] * a2;                      \
-        }                                                                                 \
-        for (int64_t qq = n - 1; qq >= 0; qq--) {                                         \
-            int32_t i = order[qq], pp = parent[i];                                        \
-            if (pp < 0) continue;                                                         \
-            const float *Lm = &Lf[9 * (int64_t)i];                                        \
-            const float *xp = &(dst)[3 * (int64_t)pp];                                    \
-            for (int a = 0; a < 3; a++)                                                   \
-                (dst)[3 * (int64_t)i + a] = (dst)[3 * (int64_t)i + a] - (Lm[a] * xp[0] + Lm[3 + a] * xp[1] + Lm[6 + a] * xp[2]); \
-        }                                                                                 \
-    } while (0)
-#define SPMV_F32(src, dst)                                                                \
-    do {                                                                                  \
-        for (int64_t i = 0; i < n; i++) {                                                 \
-            float s[3] = {0.0f, 0.0f, 0.0f};                                              \
-            for (int32_t kk = rowptr[i]; kk < rowptr[i + 1]; kk++) {                      \
-                const float *B = &valf[9 * (int64_t)kk];                                  \
-                const float *xj = &(src)[3 * (int64_t)bcol[kk]];                          \
-                for (int a = 0; a < 3; a++)                                               \
-                    s[a] = s[a] + (B[3 * a] * xj[0] + B[3 * a + 1] * xj[1] + B[3 * a + 2] * xj[2]); \
-            }                                                                             \
-            (dst)[3 * i] = s[0]; (dst)[3 * i + 1] = s[1]; (dst)[3 * i + 2] = s[2];        \
-        }                                                                                 \
-    } while (0)
-    TREE_APPLY_F32(r, z);
+    tree_apply_f32(n, parent, order, child_ptr, child, Dinvf, Lf, r, z);
     for (int64_t t = 0; t < len; t++) p[t] = z[t];
     double rho = 0.0;
     for (int64_t t = 0; t < len; t++) rho = rho + (double)r[t] * (double)z[t];
     while (k < max_iter) {
-        SPMV_F32(p, q);
+        spmv_f32(n, rowptr, bcol, valf, p, q);
         double pq = 0.0;
         for (int64_t t = 0; t < len; t++) pq = pq + (double)p[t] * (double)q[t];
         if (!(pq > 0.0) || !isfinite(pq)) { status = ORC_EBREAKDOWN; break; }
@@ -900,19 +912,73 @@ static int ir_inner(int64_t n, const int32_t *rowptr, const int32_t *bcol, const
         double nr = 0.0;
         for (int64_t t = 0; t < len; t++) nr = nr + (double)r[t] * (double)r[t];
         if (sqrt(nr) / nb <= inner_tol) break;
-        TREE_APPLY_F32(r, z);
+        tree_apply_f32(n, parent, order, child_ptr, child, Dinvf, Lf, r, z);
         double rho_new = 0.0;
         for (int64_t t = 0; t < len; t++) rho_new = rho_new + (double)r[t] * (double)z[t];
         float beta = (float)(rho_new / rho);
         rho = rho_new;
         for (int64_t t = 0; t < len; t++) p[t] = z[t] + beta * p[t];
     }
-#undef TREE_APPLY_F32
-#undef SPMV_F32
 done:
     if (x) for (int64_t t = 0; t < len; t++) d[t] = (double)x[t];
     *iters = k;
     free(r); free(z); free(p); free(q); free(x);
+    return status;
+}
+
+/* The FP32 copies the inner solve uses: Gamma's blocks rounded, the pivots
+ * inverted in FP64 and rounded, the couplings rounded. */
+static int round_factor_f32(int64_t n, const double *Dt, const double *Lt, float *Dinvf, float *Lf)
+{
+    for (int64_t i = 0; i < n; i++) {
+        double Di[9];
+        if (inv3_spd(&Dt[9 * i], Di) != ORC_OK) return ORC_ENOTSPD;
+        for (int t = 0; t < 9; t++) { Dinvf[9 * i + t] = (float)Di[t]; Lf[9 * i + t] = (float)Lt[9 * i + t]; }
+    }
+    return ORC_OK;
+}
+
+/* x = P^{-1} b by the FP32 tree solve above (b rounded to FP32 on entry, x
+ * widened to FP64 on exit).  Exported so the FP32 sweeps can be pinned on
+ * their own. */
+int orc_tree_solve_f32(int64_t n, const int32_t *parent, const int32_t *order, const int32_t *child_ptr,
+                       const int32_t *child, const double *Dt, const double *Lt, const double *b, double *x)
+{
+    float *Dinvf = malloc((size_t)(9 * n + 1) * sizeof(float));
+    float *Lf = malloc((size_t)(9 * n + 1) * sizeof(float));
+    float *bf = calloc((size_t)(3 * n + 1), sizeof(float));
+    float *xf = malloc((size_t)(3 * n + 1) * sizeof(float));
+    int status = ORC_OK;
+    if (!Dinvf || !Lf || !bf || !xf) { status = ORC_ENOMEM; goto done; }
+    if ((status = round_factor_f32(n, Dt, Lt, Dinvf, Lf)) != ORC_OK) goto done;
+    for (int64_t t = 0; t < 3 * n; t++) bf[t] = (float)b[t];
+    tree_apply_f32(n, parent, order, child_ptr, child, Dinvf, Lf, bf, xf);
+    for (int64_t t = 0; t < 3 * n; t++) x[t] = (double)xf[t];
+done:
+    free(Dinvf); free(Lf); free(bf); free(xf);
+    return status;
+}
+
+/* One inner FP32 solve of Gamma d = rhs to relative inner_tol (the inner
+ * step of the refinement below), exported for its own pins. */
+int orc_ir_inner(int64_t n, const int32_t *rowptr, const int32_t *bcol, const double *val,
+                 const int32_t *parent, const int32_t *order, const int32_t *child_ptr, const int32_t *child,
+                 const double *Dt, const double *Lt, const double *rhs, double *d, double inner_tol,
+                 int max_iter, int32_t *iters)
+{
+    int64_t nnzb = rowptr[n];
+    float *valf = malloc((size_t)(9 * nnzb + 1) * sizeof(float));
+    float *Dinvf = malloc((size_t)(9 * n + 1) * sizeof(float));
+    float *Lf = malloc((size_t)(9 * n + 1) * sizeof(float));
+    int status = ORC_OK, it = 0;
+    if (!valf || !Dinvf || !Lf) { status = ORC_ENOMEM; goto done; }
+    for (int64_t t = 0; t < 9 * nnzb; t++) valf[t] = (float)val[t];
+    if ((status = round_factor_f32(n, Dt, Lt, Dinvf, Lf)) != ORC_OK) goto done;
+    status = ir_inner(n, rowptr, bcol, valf, parent, order, child_ptr, child, Dinvf, Lf, rhs, d, inner_tol,
+                      max_iter, &it);
+done:
+    if (iters) *iters = it;
+    free(valf); free(Dinvf); free(Lf);
     return status;
 }
 
@@ -938,11 +1004,7 @@ int orc_ir_solve(int64_t n, const int32_t *rowptr, const int32_t *bcol, const do
     double relres = 0.0;
     if (!valf || !Dinvf || !Lf || !r || !q || !d) { status = ORC_ENOMEM; goto done; }
     for (int64_t t = 0; t < 9 * nnzb; t++) valf[t] = (float)val[t];
-    for (int64_t i = 0; i < n; i++) {
-        double Di[9];
-        if (inv3_spd(&Dt[9 * i], Di) != ORC_OK) { status = ORC_ENOTSPD; goto done; }
-        for (int t = 0; t < 9; t++) { Dinvf[9 * i + t] = (float)Di[t]; Lf[9 * i + t] = (float)Lt[9 * i + t]; }
-    }
+    if (round_factor_f32(n, Dt, Lt, Dinvf, Lf) != ORC_OK) { status = ORC_ENOTSPD; goto done; }
     for (int64_t t = 0; t < len; t++) x[t] = 0.0;
     double nF = sqrt(dot(len, F, F));
     if (nF == 0.0) goto done;

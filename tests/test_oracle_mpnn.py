@@ -143,3 +143,51 @@ def test_energy_gradients_match_central_differences():
         num[k] = (Lp - Lm) / (2 * h)
     err = np.abs(num - grad[idx])
     assert np.all(err <= 1e-6 * np.abs(grad[idx]).max() + 1e-7 * np.abs(num)), err.max()
+
+
+def hand_case():
+    """A three-cell chain 0 - 1 - 2 along x (centres 1.9 apart, unit radii:
+    neighbours overlap by w = 2 - 1.9, cells 0 and 2 do not touch) and
+    parameters that route single features through one message-passing layer,
+    so that the output is known by hand:
+      h_i[0]  = relu(F_i,x / sF)                          (W_in)
+      z_p[1]  = h_j[0],  z_p[3] = n_ij,x,  z_p[5] = w_ij / sW   (W_b, W_c of layer 0)
+      h_i[2], h_i[4], h_i[6] += the sums over i's neighbours of those (W_u)
+      out_i   = (h_i[2], h_i[4], h_i[6]),  v_hat = sV out    (W_out)
+    Layers 1 and 2 are zero and leave h unchanged.  With F_x = (1, 2, 4),
+    n_ij = (r_i - r_j)/d_ij and the chain's geometry:
+      out[:, 0] = sum of the neighbours' F_x      = (2, 1 + 4, 2)
+      out[:, 1] = sum of max(n_ij,x, 0)           = (0, 1, 1)
+      out[:, 2] = sum of w_ij / sW                = (w, 2 w, w) / sW
+    (the cell's own feature in place of its neighbour's would give
+    (1, 4, 4) in column 0; n pointing i -> j would give (1, 1, 0) in column 1)."""
+    pos = np.array([[0.0, 0.0, 0.0], [1.9, 0.0, 0.0], [3.8, 0.0, 0.0]])
+    R = np.ones(3)
+    F = np.array([[1.0, 0.5, -0.25], [2.0, -1.0, 0.75], [4.0, 0.0, 1.5]])
+    vprev = np.array([[0.1, 0.2, 0.3], [-0.4, 0.5, -0.6], [0.7, -0.8, 0.9]])
+    sF, sV, sW = 1.0, 2.0, 0.1
+    p = {name: np.zeros(shape) for name, shape in N.LAYOUT}
+    H = N.HID
+    p["W_in"][0, 0] = 1.0
+    p["W_b0"][0, 1] = 1.0
+    p["W_c0"][1, 3] = 1.0
+    p["W_c0"][0, 5] = 1.0
+    p["W_u0"][H + 1, 2] = 1.0
+    p["W_u0"][H + 3, 4] = 1.0
+    p["W_u0"][H + 5, 6] = 1.0
+    p["W_out"][2, 0] = 1.0
+    p["W_out"][4, 1] = 1.0
+    p["W_out"][6, 2] = 1.0
+    w = 2.0 - 1.9
+    want = sV * np.array([[2.0, 0.0, w / sW], [5.0, 1.0, 2 * w / sW], [2.0, 1.0, w / sW]])
+    return pos, R, F, vprev, (sF, sV, sW), N.pack(p), want
+
+
+def test_hand_computed_three_cell_forward():
+    pos, R, F, vprev, scales, theta, want = hand_case()
+    g = O.collide(pos, R)
+    assert g.m == 2 and list(g.ei) == [0, 1] and list(g.ej) == [1, 2]
+    ee = N.entry_edges(g.rowptr, g.col, g.ei, g.ej)
+    rows, e = N.edge_features(g.rowptr, g.col, g.ei, g.ej, g.w, g.u, ee, scales[2])
+    out, _ = N.forward(theta, F, vprev, g.rowptr, g.col, e, rows, scales)
+    assert np.allclose(scales[1] * out, want, rtol=1e-12, atol=1e-15), scales[1] * out

@@ -235,3 +235,67 @@ def test_mixed_precision_refinement():
     # the FP32 inner solve alone stalls near FP32 accuracy: refinement is needed
     x1, info1 = O.ir_solve(A, c["force"], f, tol=1e-8, inner_tol=1e-12, max_outer=1, check=False)
     assert info1.status == O.ENOCONV
+
+
+# ---------------------------------------------------------------- FP32 inner solve of the refinement
+
+def test_fp32_tree_solve_against_fp64_and_dense():
+    """The FP32 sweeps solve P x = b to FP32 accuracy: against the FP64 tree
+    solve and against a dense solve of P (a transposed or misplaced coupling
+    would leave an O(1) error).  Bound: the forward error of a solve with
+    FP32 data and arithmetic, kappa(P) * n_depth * 2^-24, loosely 1e-3 here."""
+    _, g, _, t, f = _setup(400, 2)
+    b = np.random.default_rng(5).normal(size=(g.n, 3))
+    x32 = O.tree_solve_f32(f, b)
+    x64 = O.tree_solve(f, b)
+    xd = np.linalg.solve(_dense_P(g, t), b.ravel()).reshape(-1, 3)
+    e64 = np.linalg.norm(x32 - x64) / np.linalg.norm(x64)
+    ed = np.linalg.norm(x32 - xd) / np.linalg.norm(xd)
+    assert e64 <= 1e-3 and ed <= 1e-3, (e64, ed)
+    # not FP64: the FP32 path really rounds
+    assert e64 > 1e-12
+    # the residual of the FP32 result in P is small relative to b
+    r = b.ravel() - _dense_P(g, t) @ x32.ravel()
+    assert np.linalg.norm(r) <= 1e-4 * np.linalg.norm(b)
+
+
+def test_fp32_tree_solve_rigid_translation():
+    """P (1 (x) t) = g_med (1 (x) t) (tree Laplacian rows sum to zero), so the
+    FP32 tree solve maps 1 (x) t to (1 (x) t)/g_med to FP32 accuracy."""
+    _, g, _, t, f = _setup(300, 4)
+    tv = np.array([0.3, -1.2, 0.7])
+    b = np.tile(tv, (g.n, 1))
+    x = O.tree_solve_f32(f, b)
+    assert np.allclose(x, b / G0, rtol=1e-3, atol=0.0)
+
+
+@pytest.mark.parametrize("kind", ["chain", "comb"])
+def test_fp32_inner_solve_one_iteration_on_tree_graphs(kind):
+    """A tree-shaped collision graph has P = Gamma, so the inner FP32 CG stops
+    after one iteration with FP32 accuracy; its result is the dense solution
+    to FP32 accuracy (this pins the FP32 sweeps' couplings: a transposed one
+    makes P != Gamma)."""
+    pos, R = _chain_or_comb(kind)
+    g = O.collide(pos, R)
+    A = O.assemble(g)
+    t = O.build_tree(g)
+    f = O.tree_factor(g, t)
+    rhs = np.random.default_rng(1).normal(size=(g.n, 3))
+    d, it, st = O.ir_inner(A, f, rhs, inner_tol=1e-4)
+    assert st == O.OK and it == 1
+    xd = np.linalg.solve(A.dense(), rhs.ravel())
+    assert np.linalg.norm(d.ravel() - xd) <= 1e-4 * np.linalg.norm(xd)
+
+
+def test_fp32_inner_iterations_match_fp64_pcg():
+    """At an inner tolerance FP32 can reach (1e-4), the FP32 inner CG takes the
+    FP64 tree-PCG's iteration count to within rounding (+-2), and its result
+    has the FP64 solve's accuracy at that tolerance."""
+    c, g, A, t, f = _setup(1000, 0)
+    rhs = c["force"]
+    for tol in (1e-3, 1e-4):
+        d, it, st = O.ir_inner(A, f, rhs, inner_tol=tol)
+        x64, info = O.pcg(A, rhs, "tree", f, tol=tol)
+        assert st == O.OK and abs(it - info.iters) <= 2, (tol, it, info.iters)
+        r = rhs.ravel() - O.spmv(A, d).ravel()
+        assert np.linalg.norm(r) <= 1.5 * tol * np.linalg.norm(rhs)
