@@ -287,11 +287,12 @@ int sgp_mpnn_grad(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, const dou
  * sample; loss as above.  Synchronises. */
 int sgp_mpnn_train_step(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, const double *F,
                         const double *vprev, const double *v, double lr, double *loss);
-/* Initial guess for the CG: x0 = the network's v_hat if its energy
- * 0.5 x' Gamma x - x' F is lower than that of v_prev, else v_prev (the lower
- * energy is the smaller Gamma-norm error).  x0 device [n][3], may alias vprev.
- * used_net, energy_net, energy_prev: host outputs (may be NULL).
- * Synchronises. */
+/* Initial guess for the CG: of v_prev, the network's v_hat and zero, the
+ * one of lowest energy 0.5 x' Gamma x - x' F (the lower energy is the
+ * smaller Gamma-norm error; zero has energy 0), preferring them in that
+ * order on ties.  x0 device [n][3], may alias vprev.  used_net (host, may be
+ * NULL): 0 = v_prev, 1 = the network's guess, 2 = zero; energy_net,
+ * energy_prev: host outputs (may be NULL).  Synchronises. */
 int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, const double *F,
                         const double *vprev, double *x0, int32_t *used_net, double *energy_net,
                         double *energy_prev);

@@ -695,13 +695,25 @@ __global__ void k_energy_dout(int64_t n, const int32_t *perm, const double *q, c
         dout16[16 * i + a] = a < 3 ? (float)(scale * (q[3 * u + a] - F[3 * u + a])) : 0.f;
 }
 
-// x0 = the guess with the lower energy 0.5 x' Gamma x - x' F (ties keep v_prev)
+// The start of lowest energy E(x) = 0.5 x' Gamma x - x' F among v_prev, the
+// network's guess and zero (E = 0), in that order of preference on ties
+// (0: v_prev, 1: the network, 2: zero).  Lower energy is the smaller
+// Gamma-norm error, since E(x) - E(v) = 0.5 ||x - v||^2_Gamma.
+SGP_DEV int pick_start(double en, double ep)
+{
+    if (ep <= en && ep <= 0.0) return 0;
+    return en <= 0.0 ? 1 : 2;
+}
+
+// x0 holds v_prev on entry
 __global__ void k_pick(int64_t len, const double *s_net, const double *s_prev, const double *guess, double *x0)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= len) return;
     const double en = 0.5 * s_net[0] - s_net[1], ep = 0.5 * s_prev[0] - s_prev[1];
-    if (en < ep) x0[t] = guess[t];
+    const int k = pick_start(en, ep);
+    if (k == 1) x0[t] = guess[t];
+    if (k == 2) x0[t] = 0.0;
 }
 
 __global__ void k_sum_double(const double *part, int np, double *out)
@@ -1154,7 +1166,8 @@ extern "C" int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr
     double hs[6];
     SGP_TRY(readback(ctx, hs, s, sizeof hs));
     const double en = 0.5 * hs[0] - hs[1], ep = 0.5 * hs[3] - hs[4];
-    if (used_net) *used_net = en < ep ? 1 : 0;
+    // the host's choice repeats the kernel's comparisons on the same values
+    if (used_net) *used_net = (ep <= en && ep <= 0.0) ? 0 : (en <= 0.0 ? 1 : 2);
     if (energy_net) *energy_net = en;
     if (energy_prev) *energy_prev = ep;
     return SGP_OK;

@@ -249,15 +249,17 @@ class Mpnn(_Handle):
         return loss.value
 
     def warm_start(self, g, A, F, vprev, x0=None):
-        """Initial guess: the network's v_hat or v_prev, whichever has the lower
-        energy under Gamma.  Returns (x0, {"used_net", "energy_net", "energy_prev"})."""
+        """Initial guess: v_prev, the network's v_hat or zero, whichever has the
+        lowest energy under Gamma.  Returns (x0, {"used_net", "used_zero",
+        "energy_net", "energy_prev"})."""
         x0 = torch.empty_like(vprev) if x0 is None else x0
         used = C.c_int32()
         en, ep = C.c_double(), C.c_double()
         self.ctx._check(lib().sgp_mpnn_warm_start(self.ctx.h, self.h, g.h, A.h, _ptr(F, torch.float64, "F"),
                                                   _ptr(vprev, torch.float64, "vprev"), _ptr(x0, torch.float64, "x0"),
                                                   C.byref(used), C.byref(en), C.byref(ep)), "sgp_mpnn_warm_start")
-        return x0, {"used_net": bool(used.value), "energy_net": en.value, "energy_prev": ep.value}
+        return x0, {"used_net": used.value == 1, "used_zero": used.value == 2, "energy_net": en.value,
+                    "energy_prev": ep.value}
 
 
 class Context:

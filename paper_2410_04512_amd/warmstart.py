@@ -8,8 +8,8 @@ network maps (F, v_prev) on the collision graph to a guess x0 for the solve.
 CG to the same relative residual still decides the result, so the network
 only changes how many iterations the solve needs.  The network is trained on the energy
 norm of its error, ||v_hat - v||_Gamma, the norm CG's progress is measured in;
-at run time its guess is used when its energy 0.5 x' Gamma x - x' F is below
-that of v_prev, and v_prev is the fallback.
+at run time the start of lowest energy 0.5 x' Gamma x - x' F among v_prev
+(the fallback), the network's guess and zero is used.
 
 Protocol: steps 1..n_train solve from x0 = v_prev and keep (graph, Gamma, F,
 v_prev, v) as training samples; the network is then trained on the GPU (Adam
@@ -62,9 +62,10 @@ def run(ctx: Context, pos, radius, noise_fn, n_steps=200, n_train=100, dt=0.01, 
         epochs=20, lr=1e-3, rtol=1e-8, seed=0, schedule="contract", log=None, on_test_step=None):
     """Run the protocol.  `pos` (device [n][3] FP64) is advanced in place;
     `noise_fn(step, n)` returns the active force of a step (host or device).
-    `on_test_step(t, pos, F, x0, v)`, if given, sees every test step's
-    positions (before the update), forces, learned initial guess and solved
-    velocity.  Returns per-step records and the training history."""
+    `on_test_step(t, pos, F, x0, v, iters)`, if given, sees every test
+    step's positions (before the update), forces, learned initial guess,
+    solved velocity and the solve's iteration count.  Returns per-step
+    records and the training history."""
     n = pos.shape[0]
     dev = pos.device
     v_prev = torch.zeros((n, 3), dtype=torch.float64, device=dev)
@@ -112,12 +113,13 @@ def run(ctx: Context, pos, radius, noise_fn, n_steps=200, n_train=100, dt=0.01, 
         v_b, ib = ctx.pcg_solve(A, M, F, v=x0, use_x0=True, rtol=rtol)
         ms_b = (_now(ctx) - t0) * 1e3
         if on_test_step:
-            on_test_step(t, pos, F, x0_kept, v_b)
+            on_test_step(t, pos, F, x0_kept, v_b, ib["iters"])
         # report only: the energy of the solution, E* = -0.5 v' F, scales the
         # energies of the guesses to relative Gamma-norm errors (zero start = 1)
         e_star = -0.5 * float(torch.dot(v_b.reshape(-1), F.reshape(-1)))
         test_rec.append({"step": t, "iters_zero": iz["iters"], "iters_prev": ia["iters"], "iters_learned": ib["iters"],
                          "ms_zero": ms_z, "ms_prev": ms_a, "ms_learned": ms_b, "used_net": ws["used_net"],
+                         "used_zero": ws["used_zero"],
                          "err_net": (ws["energy_net"] - e_star) / -e_star,
                          "err_prev": (ws["energy_prev"] - e_star) / -e_star,
                          "relres_true": max(iz["relres_true"], ia["relres_true"], ib["relres_true"]),
@@ -149,6 +151,7 @@ def summary(res):
     out["iter_ratio_vs_zero"] = out["mean_iters_learned"] / out["mean_iters_zero"]
     out["wall_ratio_vs_zero"] = out["mean_ms_learned"] / out["mean_ms_zero"]
     out["net_used"] = int(sum(r["used_net"] for r in te))
+    out["zero_used"] = int(sum(r["used_zero"] for r in te))
     out["max_relres_true"] = float(max(r["relres_true"] for r in te))
     out["all_converged"] = all(r["status"] == 0 for r in te)
     out["train_seconds"] = res["train_seconds"]

@@ -178,35 +178,70 @@ def test_full_1M_bench_configuration(ctx):
     r = c["force"] - O.spmv(oa, host(out["v"]))
     relres = np.linalg.norm(r) / np.linalg.norm(c["force"])
     assert relres <= 1.0001e-8, relres
-    # sampled rows of the preconditioner apply: oracle forward/backward on the full tree
+    # the whole preconditioner apply: oracle forward/backward on the full tree
+    fo = O.tree_factor(og, ot)
     b = np.random.default_rng(0).normal(size=(n, 3))
     z = host(ctx.prec_apply(out["M"], to_dev(b)))
-    zo = O.tree_solve(O.tree_factor(og, ot), b)
+    zo = O.tree_solve(fo, b)
     assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+    # the velocity against the oracle's own tree-PCG from the same start
+    print("1M: oracle tree-PCG", flush=True)
+    err = check_velocity(host(out["v"]), out["info"]["iters"], oa, c["force"], fo)
+    print(f"1M: velocity error vs the oracle {err:.2e}", flush=True)
 
 
+@pytest.mark.timeout(900)
 def test_full_4M_refinement_configuration(ctx):
-    """The mixed-precision workload (4M cells): graph bit-exact, FP64 residual of
-    the refined velocity recomputed by the oracle meets 1e-8."""
+    """The mixed-precision workload (4M cells): graph (ei, ej, w, u) and tree
+    (edges, parent, depth) bit-exact against the oracle; the plain FP64
+    tree-PCG velocity against the oracle's own FP64 tree-PCG (same start,
+    same stopping rule) to 1e-8; the FP32-inside-FP64 refinement's velocity:
+    its FP64 residual, recomputed by the oracle, meets 1e-8, and its error
+    against the oracle's FP64 solution is stated (bounded by
+    kappa(Gamma) * 1e-8 with kappa <= 2e3)."""
     n = 4_000_000
     c = sphere_cluster(n, 0)
     print("4M: GPU chain", flush=True)
     pos, R, F = to_dev(c["pos"]), to_dev(c["radius"]), to_dev(c["force"])
     g = ctx.collide(pos, R)
     A = ctx.assemble_gamma(g)
-    M = ctx.factor_tree(g, ctx.build_tree(g))
-    v, info = ctx.pcg_solve(A, M, F, precision="f32ir", inner_rtol=1e-4)
-    assert info["status"] == 0
+    T = ctx.build_tree(g)
+    M = ctx.factor_tree(g, T)
+    v64, i64 = ctx.pcg_solve(A, M, F)
+    v32, i32 = ctx.pcg_solve(A, M, F, precision="f32ir", inner_rtol=1e-4)
+    assert i64["status"] == 0 and i32["status"] == 0
+    v64, v32 = host(v64), host(v32)
     print("4M: oracle collide", flush=True)
     og = O.collide(c["pos"], c["radius"])
     e = ctx.graph_export(g)
-    for f in ("ei", "ej", "w"):
+    for f in ("ei", "ej", "w", "u"):
         assert np.array_equal(host(e[f]), getattr(og, f)), f
     del e
+    print("4M: oracle Prim", flush=True)
+    ot = O.build_tree(og)
+    t = ctx.tree_export(T, n)
+    assert np.array_equal(host(t["tree_edge"]), ot.tree_edge)
+    assert np.array_equal(host(t["parent"]), ot.parent)
+    assert np.array_equal(host(t["depth"]), ot.depth)
+    del t
     oa = O.assemble(og)
-    r = c["force"] - O.spmv(oa, host(v))
+    r = c["force"] - O.spmv(oa, v32)
     relres = np.linalg.norm(r) / np.linalg.norm(c["force"])
     assert relres <= 1.0001e-8, relres
+    print("4M: oracle tree-PCG", flush=True)
+    fo = O.tree_factor(og, ot)
+    xo, io = O.pcg(oa, c["force"], "tree", fo)
+    assert abs(io.iters - i64["iters"]) <= 1, (io.iters, i64["iters"])
+    if io.iters == i64["iters"]:
+        e64 = np.linalg.norm(v64 - xo) / np.linalg.norm(xo)
+    else:
+        e64 = check_velocity(v64, i64["iters"], oa, c["force"], fo)
+    assert e64 <= 1e-8, e64
+    e32 = np.linalg.norm(v32 - xo) / np.linalg.norm(xo)
+    print(f"4M: FP64 iterations {i64['iters']} (oracle {io.iters}), error vs the oracle {e64:.2e}; "
+          f"FP32-IR {i32['iters']} inner / {i32['outer_iters']} outer, relres {relres:.2e}, "
+          f"error vs the oracle's FP64 solution {e32:.2e}", flush=True)
+    assert e32 <= 2e3 * 1e-8, e32
 
 
 def test_full_batched_256_configuration(ctx):
@@ -234,7 +269,10 @@ def test_full_batched_256_configuration(ctx):
         ctx.tune(k, val)
     assert all(i["status"] == 0 and i["relres_true"] <= 1.0001e-8 for i in infos)
     order = np.argsort(sizes)
+    # the three smallest, two mid-sized and the two largest (which run the
+    # large-step and mid-step sweep kernels at full width)
     sample = list(order[:3]) + [int(np.argsort(np.abs(sizes - 20000))[0]), int(np.argsort(np.abs(sizes - 8000))[0])]
+    sample += [int(k) for k in order[-2:]]
     e = {k: host(t) for k, t in ctx.graph_export(g).items()}
     te = host(ctx.tree_export(T, int(off[-1]))["tree_edge"])
     # edge ranges of the instances: edges are numbered instance by instance
@@ -258,7 +296,8 @@ def test_full_learned_warm_start_configuration(ctx):
     """The benchmark's learned warm-start run (200k cells, 200 steps, training
     on steps 1-100): every solve converges; at sampled test steps the oracle,
     from the GPU's positions, reproduces the forces bit for bit, its FP64
-    residual of the GPU's velocity meets 1e-8, and the learned initial guess
+    residual of the GPU's velocity meets 1e-8, its own tree-PCG from the same
+    learned initial guess gives the GPU's velocity to 1e-8, and that guess
     has an energy no higher than the zero start's."""
     from paper_2410_04512_amd import warmstart as W
     from workloads import dynamics_noise
@@ -266,23 +305,27 @@ def test_full_learned_warm_start_configuration(ctx):
     c = sphere_cluster(n, 0)
     kept = {}
 
-    def hook(t, pos, F, x0, v):
+    def hook(t, pos, F, x0, v, iters):
         if t in (101, 160):
-            kept[t] = (host(pos), host(F), host(x0), host(v))
+            kept[t] = (host(pos), host(F), host(x0), host(v), iters)
 
     res = W.run(ctx, to_dev(c["pos"]), to_dev(c["radius"]), dynamics_noise, n_steps=200, n_train=100, epochs=30,
                 lr=3e-3, log=lambda s: print(s, flush=True), on_test_step=hook)
     s = W.summary(res)
     assert s["all_converged"] and s["max_relres_true"] <= 1.0001e-8
     assert s["mean_iters_learned"] < s["mean_iters_prev"]
-    for t, (pos, F, x0, v) in kept.items():
+    for t, (pos, F, x0, v, iters) in kept.items():
         print(f"learned: oracle check of step {t}", flush=True)
         og = O.collide(pos, c["radius"])
         Fo = O.forces(og, dynamics_noise(t, n), 5.0)
         assert np.array_equal(F, Fo)
-        r = Fo - O.spmv(O.assemble(og), v)
+        oa = O.assemble(og)
+        r = Fo - O.spmv(oa, v)
         relres = np.linalg.norm(r) / np.linalg.norm(Fo)
         assert relres <= 1.0001e-8, (t, relres)
+        # the velocity against the oracle's tree-PCG from the same learned x0
+        err = check_velocity(v, iters, oa, Fo, O.tree_factor(og, O.build_tree(og)), x0=x0)
+        print(f"learned: step {t}: {iters} iterations, velocity error vs the oracle {err:.2e}", flush=True)
         # the learned guess was a better start than zero in the energy norm
         e0 = 0.5 * x0.ravel() @ O.spmv(O.assemble(og), x0).ravel() - x0.ravel() @ Fo.ravel()
         assert e0 <= 0.0, (t, e0)

@@ -120,9 +120,10 @@ def _oracle_energy(theta, c, og, oa, vprev, v, scales):
     return N.loss_grad(theta, c["force"], vprev, v, og.rowptr, og.col, e, rows, scales, lambda x: O.spmv(oa, x))
 
 
-def test_warm_start_picks_the_lower_energy(ctx):
-    """x0 is the network's guess exactly when its energy 0.5 x'Gx - x'F (checked
-    against the oracle's product) is below v_prev's; both branches exercised."""
+def test_warm_start_picks_the_lowest_energy(ctx):
+    """x0 is, of v_prev, the network's guess and zero, the first one of lowest
+    energy 0.5 x'Gx - x'F (energies checked against the oracle's product);
+    all three branches exercised."""
     c, og, vprev, v = _sample(2000, 7)
     oa = O.assemble(og)
     F = c["force"]
@@ -135,9 +136,10 @@ def test_warm_start_picks_the_lower_energy(ctx):
     A = ctx.assemble_gamma(g)
     garbage = 50.0 * np.random.default_rng(9).normal(size=v.shape)
     # a zero network guesses 0 (energy 0): it beats a garbage v_prev and loses
-    # to the solution itself (the lowest energy)
-    cases = [(N.init_params(1), vprev, None), (np.zeros(N.param_count()), garbage, True),
-             (N.init_params(1), v, False)]
+    # to the solution itself (the lowest energy); a network with inflated
+    # weights guesses far off, and with a garbage v_prev the zero start wins
+    cases = [(N.init_params(1), vprev, None), (np.zeros(N.param_count()), garbage, 1),
+             (N.init_params(1), v, 0), (50.0 * N.init_params(3), garbage, 2)]
     for theta, vp, expect in cases:
         M = P.Mpnn(ctx)
         M.set_params(theta, float(F.std()), float(v.std()), 0.1)
@@ -147,7 +149,24 @@ def test_warm_start_picks_the_lower_energy(ctx):
         ep, sp = energy(vp)
         assert abs(info["energy_net"] - en) <= 1e-10 * sn
         assert abs(info["energy_prev"] - ep) <= 1e-10 * sp
-        assert info["used_net"] == (en < ep)
+        pick = 0 if (info["energy_prev"] <= info["energy_net"] and info["energy_prev"] <= 0.0) else \
+            (1 if info["energy_net"] <= 0.0 else 2)
+        assert info["used_net"] == (pick == 1) and info["used_zero"] == (pick == 2)
         if expect is not None:
-            assert info["used_net"] == expect
-        assert np.array_equal(host(x0), vh if info["used_net"] else vp)
+            assert pick == expect, (pick, expect, en, ep)
+        want = (vp, vh, np.zeros_like(vp))[pick]
+        assert np.array_equal(host(x0), want)
+
+
+def test_hand_computed_three_cell_forward(ctx):
+    """The hand-worked three-cell case of the oracle's pins (neighbour term
+    h_j, edge direction n_ij = (r_i - r_j)/d_ij, overlap feature), through the
+    GPU network: every input and weight is exact in BF16, so only the overlap
+    feature (w/sW = 1 + 2^-49 rounds to 1) differs from the exact answer."""
+    from tests.test_oracle_mpnn import hand_case
+    pos, R, F, vprev, scales, theta, want = hand_case()
+    M = P.Mpnn(ctx)
+    M.set_params(theta, *scales)
+    g = ctx.collide(to_dev(pos), to_dev(R))
+    vh = host(M.forward(g, to_dev(F), to_dev(vprev)))
+    assert np.allclose(vh, want, rtol=1e-6, atol=1e-6), vh
