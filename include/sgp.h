@@ -192,6 +192,19 @@ int sgp_prec_info(sgp_prec M, int32_t *steps, int32_t *tail_step, int32_t *light
  * this is ForwardSolve, DiagSolve and BackwardSolve of Appendix B.1. */
 int sgp_prec_apply(sgp_ctx ctx, sgp_prec M, const double *r, double *z);
 
+/* The same apply as sgp_prec_apply, same kernels and bitwise the same z, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): it calls no
+ * hipMalloc, hipFree or other allocating routine.  Its scratch (r and z in
+ * the library's internal order) is a static device array of 48 MiB per GPU,
+ * reserved when the library's code object is loaded and held until the
+ * process ends; its address is taken at sgp_create.  Systems of more than
+ * 1,048,576 cells (2^20) give SGP_EINVAL, with nothing launched.  Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, contexts or host threads) race and must be ordered by the caller.
+ * r and z: device [n][3] FP64, caller numbering, must not overlap. */
+int sgp_prec_apply_noalloc(sgp_ctx ctx, sgp_prec M, const double *r, double *z);
+
 /* -------------------------------------------- Section 1.1: the solve */
 
 enum { SGP_PREC_F64 = 0, SGP_PREC_F32_IR = 1 };

@@ -21,6 +21,11 @@ extern "C" int sgp_create(sgp_ctx *out, void *hip_stream)
         sgp_destroy(c);
         return SGP_EHIP;
     }
+    const int s = noalloc_scratch_init(c);
+    if (s != SGP_OK) {
+        sgp_destroy(c);
+        return s;
+    }
     c->n_tickets = 64;
     *out = c;
     return SGP_OK;

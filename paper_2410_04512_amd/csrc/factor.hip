@@ -34,6 +34,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <mutex>
 
 // ---------------------------------------------------------------- W and P_ii
 
@@ -1839,6 +1840,56 @@ extern "C" int sgp_prec_steps(sgp_prec M, int32_t *steps)
     if (!M || !steps) return SGP_EINVAL;
     *steps = M->steps;
     return SGP_OK;
+}
+
+// ---- the apply without allocation
+//
+// sgp_prec_apply_noalloc keeps r and z in the internal order in this
+// file-scope device array instead of the context's grow-only workspaces.  In
+// host code `scratch` names a host-side stand-in, not device memory: its
+// device address is taken once per device with hipGetSymbolAddress (at
+// context creation) and only that address is ever passed to kernels.
+static __device__ __align__(256) double scratch[2 * 3 * NOALLOC_MAX_CELLS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static double *g_scratch_addr[NOALLOC_MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+int noalloc_scratch_init(sgp_ctx ctx)
+{
+    const int dev = ctx->device;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return set_err(ctx, SGP_EINVAL, "device %d beyond the %d devices the static scratch serves", dev,
+                       NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_addr[dev]) return SGP_OK;
+    void *p = nullptr;
+    HIP_TRY(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return set_err(ctx, SGP_EHIP, "hipGetSymbolAddress returned no address for the static scratch");
+    g_scratch_addr[dev] = (double *)p;
+    return SGP_OK;
+}
+
+extern "C" int sgp_prec_apply_noalloc(sgp_ctx ctx, sgp_prec M, const double *r, double *z)
+{
+    if (!ctx || !M) return set_err(ctx, SGP_EINVAL, "prec_apply_noalloc: null handle");
+    const int64_t n = M->n;
+    if (n == 0) return SGP_OK;
+    if (!r || !z) return set_err(ctx, SGP_EINVAL, "prec_apply_noalloc: null vector");
+    if (n > NOALLOC_MAX_CELLS)
+        return set_err(ctx, SGP_EINVAL, "prec_apply_noalloc: %lld cells exceed the static scratch (at most %lld)",
+                       (long long)n, (long long)NOALLOC_MAX_CELLS);
+    double *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (ctx->device >= 0 && ctx->device < NOALLOC_MAX_DEVICES) base = g_scratch_addr[ctx->device];
+    }
+    if (!base) return set_err(ctx, SGP_EHIP, "prec_apply_noalloc: static scratch not set up on device %d", ctx->device);
+    double *ri = base, *zi = base + 3 * NOALLOC_MAX_CELLS;
+    const int32_t *perm = (const int32_t *)M->perm.p;
+    SGP_TRY(permute_rows(ctx, perm, r, ri, n, 0));
+    SGP_TRY(prec_apply_f64(ctx, M, ri, zi, nullptr));
+    return permute_rows(ctx, perm, zi, z, n, 1);
 }
 
 extern "C" int sgp_prec_apply(sgp_ctx ctx, sgp_prec M, const double *r, double *z)

@@ -218,6 +218,11 @@ int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScala
 int permute_rows(sgp_ctx ctx, const int32_t *idx, const double *src, double *dst, int64_t n, int scatter);
 int copy_order(sgp_ctx ctx, DevBuf &dperm, DevBuf &dinv, const DevBuf &sperm, const DevBuf &sinv, int64_t n);
 int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s);
+// cells at most for sgp_prec_apply_noalloc (its static scratch holds two
+// [n][3] FP64 vectors: 48 MiB per device)
+constexpr int64_t NOALLOC_MAX_CELLS = (int64_t)1 << 20;
+// device address of that scratch on the context's device, taken once per device
+int noalloc_scratch_init(sgp_ctx ctx);
 int prec_make32(sgp_ctx ctx, sgp_prec M);
 int tail_setup_attr(sgp_ctx ctx);
 int bsr_make32(sgp_ctx ctx, sgp_bsr A);

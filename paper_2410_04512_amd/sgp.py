@@ -73,6 +73,7 @@ _SIGS = {
     "sgp_make_jacobi": (C.c_int, [_vp, _vp, _vp]),
     "sgp_prec_steps": (C.c_int, [_vp, C.POINTER(_i32)]),
     "sgp_prec_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sgp_prec_apply_noalloc": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sgp_pcg_solve": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
     "sgp_pcg_solve_batched": (C.c_int, [_vp, _vp, _vp, _i64, C.POINTER(_i64), _vp, _vp,
                                         C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
@@ -386,6 +387,13 @@ class Context:
         z = torch.empty_like(r) if z is None else z
         self._check(lib().sgp_prec_apply(self.h, M.h, _ptr(r, torch.float64, "r"), _ptr(z, torch.float64, "z")),
                     "sgp_prec_apply")
+        return z
+
+    def prec_apply_noalloc(self, M: Prec, r, z):
+        """z = M^{-1} r through the entry point that allocates nothing (static
+        device scratch; at most 2^20 cells); z must be given."""
+        self._check(lib().sgp_prec_apply_noalloc(self.h, M.h, _ptr(r, torch.float64, "r"),
+                                                 _ptr(z, torch.float64, "z")), "sgp_prec_apply_noalloc")
         return z
 
     # ---------------------------------------------------------------- Section 1.1
