@@ -97,6 +97,21 @@ int sgp_collide(sgp_ctx ctx, int64_t n, const double *pos, const double *radius,
 int sgp_collide_batched(sgp_ctx ctx, int64_t n_inst, const int64_t *offsets,
                         const double *pos, const double *radius, int32_t max_deg, sgp_graph g);
 
+/* What collide stores as a contact's w (the contact area A_ij of eq.
+ * cell_cell_friction), for the collides that follow on this context:
+ *  SGP_CONTACT_OVERLAP  w = R_i + R_j - d_ij, the overlap (default);
+ *  SGP_CONTACT_HERTZ    the contact area of the Hertz model that the paper's
+ *                       benchmark cells use (Section 5.1; the paper names the
+ *                       model, not its formula): two spheres pressed together
+ *                       by the overlap delta touch in a disc of radius
+ *                       sqrt(R* delta), R* = R_i R_j / (R_i + R_j), so
+ *                       w = pi R* delta, evaluated as
+ *                       (pi * ((R_i * R_j) / (R_i + R_j))) * delta.
+ * The contact test, u and the edge numbering do not change.  Unknown models
+ * give SGP_EINVAL. */
+enum { SGP_CONTACT_OVERLAP = 0, SGP_CONTACT_HERTZ = 1 };
+int sgp_set_contact_model(sgp_ctx ctx, int32_t model);
+
 /* Sizes: n cells, m contacts.  Host outputs; either may be NULL. */
 int sgp_graph_size(sgp_graph g, int64_t *n, int64_t *m);
 

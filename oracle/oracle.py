@@ -86,8 +86,10 @@ class Graph:
         return int(self.ei.shape[0])
 
 
-def collide(pos, radius, method: str = "auto") -> Graph:
-    """Collision graph (Section 2, Steps 1-2), canonical order."""
+def collide(pos, radius, method: str = "auto", area: str = "overlap") -> Graph:
+    """Collision graph (Section 2, Steps 1-2), canonical order.  w is the
+    overlap (area="overlap") or the Hertz contact area pi R* overlap
+    (area="hertz", the paper's benchmark cells, Section 5.1)."""
     pos = _c(pos, np.float64).reshape(-1, 3)
     radius = _c(radius, np.float64).reshape(-1)
     n = pos.shape[0]
@@ -110,6 +112,11 @@ def collide(pos, radius, method: str = "auto") -> Graph:
                 arr(g.ei, m, np.int32), arr(g.ej, m, np.int32), arr(g.w, m, np.float64),
                 arr(g.u, 3 * m, np.float64).reshape(m, 3))
     lib().orc_graph_free(gp)
+    if area == "hertz":
+        if m > 0:
+            lib().orc_hertz_area(C.c_int64(m), _i32(out.ei), _i32(out.ej), _f64(radius), _f64(out.w))
+    elif area != "overlap":
+        raise ValueError(f"unknown contact area model {area!r}")
     return out
 
 

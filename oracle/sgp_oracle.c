@@ -237,6 +237,22 @@ fail:
     return NULL;
 }
 
+/* The contact area of the Hertz model for the paper's benchmark cells
+ * (Section 5.1 names the model without its formula): two spheres of radii
+ * R_i, R_j pressed together by the overlap delta touch in a disc of radius
+ * a = sqrt(R* delta), R* = R_i R_j / (R_i + R_j), so the area is
+ * A = pi R* delta.  w holds delta on entry and A on return:
+ * A = (pi * ((R_i * R_j) / (R_i + R_j))) * delta, in that order. */
+void orc_hertz_area(int64_t m, const int32_t *ei, const int32_t *ej, const double *R, double *w)
+{
+    const double pi = 3.14159265358979323846;
+    for (int64_t e = 0; e < m; e++) {
+        double ri = R[ei[e]], rj = R[ej[e]];
+        double rs = (ri * rj) / (ri + rj);
+        w[e] = (pi * rs) * w[e];
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Step 3 (eq. cell_cell_friction) and the block Laplacian (Definition).     */
 /* ------------------------------------------------------------------------ */

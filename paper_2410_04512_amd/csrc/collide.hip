@@ -209,8 +209,11 @@ __global__ void k_compact_rows(const int32_t *slots, int max_deg, const int32_t 
 // test.  The row's columns ascend, so its upper entries are its last
 // eoff[i+1] - eoff[i], and an upper entry's edge id is eoff[i] plus its rank
 // among them.
+// w of a contact: the overlap s - d, or with `hertz` the contact area of the
+// Hertz model, pi R* (s - d) with R* = R_i R_j / (R_i + R_j), evaluated as
+// (pi * ((R_i * R_j) / (R_i + R_j))) * (s - d)
 __global__ void k_edges(const double *pos, const double *R, const int32_t *rowptr, const int32_t *col,
-                        const int32_t *eoff, int64_t n, int32_t *ei, int32_t *ej, double4 *wu, double *w)
+                        const int32_t *eoff, int64_t n, int hertz, int32_t *ei, int32_t *ej, double4 *wu, double *w)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = t / ROW_LANES;
@@ -224,12 +227,15 @@ __global__ void k_edges(const double *pos, const double *R, const int32_t *rowpt
         double dy = pos[3 * j + 1] - yi;
         double dz = pos[3 * j + 2] - zi;
         double d = sqrt((dx * dx + dy * dy) + dz * dz);
-        double s = ri + R[j];
+        const double rj = R[j];
+        double s = ri + rj;
+        double a = s - d;
+        if (hertz) a = (3.14159265358979323846 * ((ri * rj) / (ri + rj))) * a;
         const int32_t e = e0 + (p - up0);
         ei[e] = (int32_t)i;
         ej[e] = (int32_t)j;
-        wu[e] = make_double4(s - d, dx / d, dy / d, dz / d);
-        w[e] = s - d;
+        wu[e] = make_double4(a, dx / d, dy / d, dz / d);
+        w[e] = a;
     }
 }
 
@@ -392,7 +398,8 @@ static int collide_impl(sgp_ctx ctx, int64_t n, const double *pos, const double 
     SGP_TRY(ensure_t(ctx, g->wu, m + 1, &wu));
     SGP_TRY(ensure_t(ctx, g->w, m + 1, &wv));
     k_compact_rows<<<grid_for(ROW_LANES * n, 256), 256, 0, st>>>(slots, max_deg, rowptr, n, col);
-    k_edges<<<grid_for(ROW_LANES * n, 256), 256, 0, st>>>(pos, radius, rowptr, col, upc, n, ei, ej, wu, wv);
+    k_edges<<<grid_for(ROW_LANES * n, 256), 256, 0, st>>>(pos, radius, rowptr, col, upc, n,
+                                                          ctx->contact_model == SGP_CONTACT_HERTZ, ei, ej, wu, wv);
     k_entry_edges<<<grid_for(ROW_LANES * n, 256), 256, 0, st>>>(rowptr, col, upc, n, ee);
     LAUNCH_CHECK(ctx);
     return SGP_OK;
@@ -419,6 +426,15 @@ extern "C" int sgp_collide_batched(sgp_ctx ctx, int64_t n_inst, const int64_t *o
     int s = collide_impl(ctx, offsets[n_inst], pos, radius, max_deg, g, n_inst, offsets);
     if (s == SGP_OK) phase_end(ctx, 0);
     return s;
+}
+
+extern "C" int sgp_set_contact_model(sgp_ctx ctx, int32_t model)
+{
+    if (!ctx) return SGP_EINVAL;
+    if (model != SGP_CONTACT_OVERLAP && model != SGP_CONTACT_HERTZ)
+        return set_err(ctx, SGP_EINVAL, "set_contact_model: unknown model %d", model);
+    ctx->contact_model = model;
+    return SGP_OK;
 }
 
 extern "C" int sgp_graph_size(sgp_graph g, int64_t *n, int64_t *m)

@@ -628,7 +628,9 @@ static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w
     // predicts the iterations it still needs, and the next poll comes after
     // half of them (whole chunks, at least one): polls thin out while the
     // solve is far from the tolerance, and iterations issued past
-    // convergence stay within a chunk.
+    // convergence stay within a chunk.  CG's residual is not monotone: where
+    // it stalls, the prediction runs away, so a poll never waits for more
+    // than a quarter of the iterations done so far (at least 8).
     int per_poll = fixed > 0 ? (limit + check_every - 1) / check_every : 1;
     int it_prev = -1;
     double lg_prev = 0.0;
@@ -658,7 +660,8 @@ static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w
             const double lg = log(worst);
             if (it_prev >= 0 && lg < lg_prev) {
                 const double rem = -lg / ((lg - lg_prev) / (it - it_prev));
-                per_poll = (int)std::min(1e6, std::max(1.0, 0.5 * rem / check_every));
+                const double cap = std::max(8.0, 0.25 * it) / check_every;
+                per_poll = (int)std::max(1.0, std::min(cap, 0.5 * rem / check_every));
             }
             it_prev = it;
             lg_prev = lg;

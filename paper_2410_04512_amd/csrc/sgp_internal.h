@@ -66,6 +66,7 @@ struct sgp_ctx_ {
     int light_height = 0;          // rake rounds whose subtrees the sweeps handle one workgroup each (0: off)
     int light_cap = 512;           // vertices of such subtrees packed into one workgroup
     hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)
+    int contact_model = SGP_CONTACT_OVERLAP;   // what collide stores as a contact's w
 };
 
 // event pair around one timed launch of CG iteration `iter` (no-op unless

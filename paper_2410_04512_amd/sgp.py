@@ -74,6 +74,7 @@ _SIGS = {
     "sgp_prec_steps": (C.c_int, [_vp, C.POINTER(_i32)]),
     "sgp_prec_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sgp_prec_apply_noalloc": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sgp_set_contact_model": (C.c_int, [_vp, _i32]),
     "sgp_pcg_solve": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
     "sgp_pcg_solve_batched": (C.c_int, [_vp, _vp, _vp, _i64, C.POINTER(_i64), _vp, _vp,
                                         C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
@@ -295,6 +296,11 @@ class Context:
         return torch.device("cuda", torch.cuda.current_device())
 
     # ---------------------------------------------------------------- Steps 1-2
+    def set_contact_model(self, model: str):
+        """What later collides store as w: "overlap" (default) or "hertz"."""
+        code = {"overlap": 0, "hertz": 1}[model]
+        self._check(lib().sgp_set_contact_model(self.h, code), "sgp_set_contact_model")
+
     def collide(self, pos, radius, max_deg=32, g: Graph | None = None) -> Graph:
         n = pos.shape[0]
         if pos.shape != (n, 3) or radius.shape != (n,):

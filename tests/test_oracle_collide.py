@@ -95,3 +95,24 @@ def test_coincident_centres_rejected():
     assert e.value.status == O.EINVAL
     with pytest.raises(O.OracleError):
         O.collide(np.zeros((2, 3)), np.ones(2), "cells")
+
+
+def test_hertz_contact_area_closed_form():
+    """Two spheres pressed together by an overlap delta touch in a disc of
+    radius sqrt(R* delta), R* = R1 R2 / (R1 + R2) (Hertz), so the area is
+    pi R* delta; equal spheres of radius r give pi r delta / 2."""
+    r1, r2, d = 0.5, 0.75, 1.1
+    pos = np.array([[0.0, 0.0, 0.0], [d, 0.0, 0.0]])
+    R = np.array([r1, r2])
+    g0 = O.collide(pos, R)
+    g1 = O.collide(pos, R, area="hertz")
+    delta = (r1 + r2) - d
+    assert g0.w[0] == delta
+    want = np.pi * (r1 * r2 / (r1 + r2)) * delta
+    assert abs(g1.w[0] - want) <= 1e-15 * want
+    # the area grows linearly with the overlap and with the reduced radius
+    pos2 = np.array([[0.0, 0.0, 0.0], [0.9, 0.0, 0.0]])
+    g2 = O.collide(pos2, np.array([0.5, 0.5]), area="hertz")
+    assert abs(g2.w[0] - np.pi * 0.25 * 0.1) <= 1e-15
+    # same contacts, same u, same numbering as the overlap model
+    assert np.array_equal(g0.ei, g1.ei) and np.array_equal(g0.u, g1.u)
