@@ -180,7 +180,8 @@ def extra_mixed(P, dev, n=4_000_000):
 def extra_batched(P, dev, n_inst=256, steps=3, log=None):
     """256 spheroids, sizes log-uniform in [1e3, 2e5], seeds 1..256: one batched
     pipeline (collide -> assemble -> tree -> factor -> PCG over all instances at
-    once), knobs chosen by the autotuner on this batch."""
+    once), knobs chosen by the autotuner on this batch; eager steps, and the
+    same step recorded once and replayed as one hipGraph (sgp_step_*)."""
     import numpy as np
     import torch
     from paper_2410_04512_amd import autotune
@@ -217,10 +218,25 @@ def extra_batched(P, dev, n_inst=256, steps=3, log=None):
     rel = np.array([i["relres_true"] for i in infos])
     st = np.array([i["status"] for i in infos])
     ms = 1e3 * float(np.median(times))
+    # the same step recorded once and replayed as one hipGraph (the tuned
+    # knobs stay set on ctx and are copied into the step)
+    S = P.Step(ctx)
+    vs = torch.zeros_like(F)
+    t_rec, _ = _sync_time(lambda: S.record_batched(off, pos, R, F, vs, schedule=sched))
+    rtimes = []
+    for _ in range(steps):
+        t, (code, rinfos) = _sync_time(lambda: S.replay())
+        rtimes.append(t)
+    replay_ms = 1e3 * float(np.median(rtimes))
+    rvalues, rbytes = S.size()
+    del S
     return {"workload": f"{n_inst} spheroids, sizes log-uniform [1e3, 2e5] (sum {int(off[-1])} cells), seeds 1..{n_inst}",
             "solves_per_s": n_inst / (ms * 1e-3), "ms_per_step": ms, "solve_ms": 1e3 * float(np.median(solve_t)),
             "iters_min": int(it.min()), "iters_mean": float(it.mean()), "iters_max": int(it.max()),
             "max_relres_true": float(rel.max()), "all_converged": bool((st == 0).all()),
+            "graph_step": {"replay_ms_per_step": replay_ms, "replay_solves_per_s": n_inst / (replay_ms * 1e-3),
+                           "record_ms": 1e3 * t_rec, "recorded_values": rvalues, "recorded_bytes": rbytes,
+                           "iters_equal_eager": [i["iters"] for i in rinfos] == [i["iters"] for i in infos]},
             "tuned": {k: v for k, v in tuned.items() if k not in ("prec", "table", "defaults")},
             "tune_table_ms": {k: 1e3 * v for k, v in tuned["table"].items()}}
 

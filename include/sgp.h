@@ -51,7 +51,8 @@ typedef enum {
     SGP_ENOTSPD = -5,     /* a 3x3 pivot block is not symmetric positive definite */
     SGP_ENOCONV = -6,     /* max_iter reached before the tolerance */
     SGP_EBREAKDOWN = -7,  /* CG breakdown: p.Gamma p <= 0 or not finite */
-    SGP_ENONFINITE = -8   /* NaN or Inf in an input or an iterate */
+    SGP_ENONFINITE = -8,  /* NaN or Inf in an input or an iterate */
+    SGP_ESTALE = -9       /* a recorded step cannot replay these inputs: record it again */
 } sgp_status;
 
 typedef struct sgp_ctx_ *sgp_ctx;
@@ -60,6 +61,7 @@ typedef struct sgp_bsr_ *sgp_bsr;
 typedef struct sgp_tree_ *sgp_tree;
 typedef struct sgp_prec_ *sgp_prec;
 typedef struct sgp_mpnn_ *sgp_mpnn;
+typedef struct sgp_step_ *sgp_step;
 
 /* ---------------------------------------------------------------- context */
 
@@ -265,6 +267,53 @@ int sgp_pcg_solve_batched(sgp_ctx ctx, sgp_bsr A, sgp_prec M, int64_t n_inst,
 /* ||F - Gamma x|| / ||F|| in FP64 (host output; F, x device [n][3]).
  * Synchronises.  Used to pick the better of two initial guesses. */
 int sgp_residual_norm(sgp_ctx ctx, sgp_bsr A, const double *F, const double *x, double *relres);
+
+/* ------------------------------- a whole batched step as one hipGraph */
+
+/* The batched step collide -> assemble_gamma -> (build_tree -> factor_tree
+ * | make_jacobi) -> pcg_solve_batched, recorded once and then replayed as a
+ * single hipGraph launch: no host round trip inside the step.
+ *
+ * A step owns a context and graph, matrix, tree and preconditioner handles
+ * of its own (created by sgp_step_create on the caller's device), so the
+ * buffers its graph points to are never grown or freed by other calls; the
+ * caller's context lends its stream and its launch-shape knobs and contact
+ * model (copied at recording).
+ *
+ * sgp_step_record_batched runs the step eagerly with these arguments (the
+ * same meaning as in the single calls; prec: SGP_STEP_NONE, SGP_STEP_JACOBI
+ * or SGP_STEP_TREE; schedule as for sgp_factor_tree) and keeps every value
+ * the host reads back on the way (bounding box, edge count, the rounds of the
+ * spanning tree and of the elimination schedule, the schedule's step sizes,
+ * the CG's convergence polls) and every host table it uploads.  It then runs
+ * the same host code again under stream capture, with each of those values
+ * taken from the recording and checked on the device against the live value,
+ * and instantiates the graph.  v receives the velocities, info (host,
+ * [n_inst]) the solve results.  Synchronises.
+ *
+ * The step keeps the device pointers pos, radius, F and v: they must stay
+ * allocated until the step is freed or recorded again.
+ *
+ * sgp_step_replay launches the graph on the context's stream.  A replay is
+ * valid only for the recorded inputs: before launching, a 64-bit device-side
+ * hash of pos, radius, F (and v when opts->use_x0) is compared with the
+ * recorded one, and changed inputs give SGP_ESTALE without launching
+ * anything (the launch sizes, buffer sizes and iteration count of the graph
+ * are the recorded data's; other data could index past buffers sized for the
+ * recorded contacts).  After the graph, a flag set by the device-side
+ * comparisons is read back (SGP_ESTALE if any differed).  v receives the
+ * velocities, info the solve results (bitwise those of the recorded run).
+ * Synchronises once for the hash and once for the flag. */
+enum { SGP_STEP_NONE = 0, SGP_STEP_JACOBI = 1, SGP_STEP_TREE = 2 };
+int sgp_step_create(sgp_ctx ctx, sgp_step *out);
+void sgp_step_free(sgp_step S);
+int sgp_step_record_batched(sgp_ctx ctx, sgp_step S, int64_t n_inst, const int64_t *offsets,
+                            const double *pos, const double *radius, int32_t max_deg, double g_par,
+                            double g_perp, double g_med, int32_t prec, int32_t schedule, const double *F,
+                            double *v, const sgp_solve_opts *opts, sgp_solve_info *info);
+int sgp_step_replay(sgp_ctx ctx, sgp_step S, sgp_solve_info *info);
+/* Recorded host-visible values and their total bytes (host outputs, NULL = skip). */
+int sgp_step_size(sgp_step S, int64_t *values, int64_t *bytes);
 
 /* ------------------------------------- Section 2, Steps 2 and 5 (dynamics) */
 

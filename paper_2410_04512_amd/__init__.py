@@ -5,7 +5,7 @@ package only marshals arguments to it (see sgp.py).  There is no fallback:
 without the built library every call raises.
 """
 from .sgp import (  # noqa: F401
-    SgpError, Context, Graph, Bsr, Tree, Prec, Mpnn, lib, LIB_PATH,
+    SgpError, Context, Graph, Bsr, Tree, Prec, Mpnn, Step, lib, LIB_PATH,
     SCHED_LEVEL, SCHED_CONTRACT, OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENOTSPD, ENOCONV,
-    EBREAKDOWN, ENONFINITE,
+    EBREAKDOWN, ENONFINITE, ESTALE,
 )

@@ -177,7 +177,7 @@ extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double
     if (!(g_par > 0) || !(g_perp > 0) || !(g_med >= 0))
         return set_err(ctx, SGP_EINVAL, "assemble_gamma: need g_par > 0, g_perp > 0, g_med >= 0");
     hipStream_t st = ctx->stream;
-    if (ctx->ev[2]) (void)hipEventRecord(ctx->ev[2], st);
+    phase_begin(ctx, 1);
     const int64_t n = g->n, nnzb = n + 2 * g->m;
     A->n = n;
     A->nnzb = nnzb;

@@ -266,6 +266,8 @@ __global__ void k_entry_edges(const int32_t *rowptr, const int32_t *col, const i
     }
 }
 
+__global__ void k_copy_count(const int32_t *src, int32_t *dst) { *dst = *src; }
+
 __global__ void k_inst_of(const int64_t *off, int64_t n_inst, int32_t *inst_of)
 {
     int64_t k = blockIdx.x;
@@ -290,7 +292,7 @@ static int collide_impl(sgp_ctx ctx, int64_t n, const double *pos, const double 
     SGP_TRY(ensure_t(ctx, g->rowptr, n + 1, &rowptr));
     int64_t *d_off;
     SGP_TRY(ensure_t(ctx, g->inst_off, n_inst + 1, &d_off));
-    HIP_TRY(ctx, hipMemcpyAsync(d_off, h_off, (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    SGP_TRY(upload(ctx, d_off, h_off, (n_inst + 1) * sizeof(int64_t)));
     int32_t *inst_of = nullptr;
     if (n_inst > 1) {
         SGP_TRY(ensure_t(ctx, g->inst_of, n + 1, &inst_of));
@@ -381,9 +383,9 @@ static int collide_impl(sgp_ctx ctx, int64_t n, const double *pos, const double 
     SGP_TRY(scan_exclusive(ctx, deg, rowptr, n));
     SGP_TRY(scan_exclusive(ctx, upc, upc, n));   // upc becomes eoff [n+1]
     int32_t hs[4];
-    HIP_TRY(ctx, hipMemcpyAsync(hs, flags, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipMemcpyAsync(hs + 2, upc + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipStreamSynchronize(st));
+    k_copy_count<<<1, 1, 0, st>>>(upc + n, flags + 2);   // the edge count beside the two flags: one readback
+    LAUNCH_CHECK(ctx);
+    SGP_TRY(readback(ctx, hs, flags, 3 * sizeof(int32_t)));
     if (hs[0]) return set_err(ctx, SGP_ECAPACITY, "collide: a cell has more than max_deg=%d contacts", max_deg);
     if (hs[1]) return set_err(ctx, SGP_EINVAL, "collide: coincident centres in contact");
     int64_t m = hs[2];
@@ -409,7 +411,7 @@ extern "C" int sgp_collide(sgp_ctx ctx, int64_t n, const double *pos, const doub
                            sgp_graph g)
 {
     int64_t off[2] = {0, n};
-    if (ctx && ctx->ev[0]) (void)hipEventRecord(ctx->ev[0], ctx->stream);
+    phase_begin(ctx, 0);
     int s = collide_impl(ctx, n, pos, radius, max_deg, g, 1, off);
     if (s == SGP_OK) phase_end(ctx, 0);
     return s;
@@ -422,7 +424,7 @@ extern "C" int sgp_collide_batched(sgp_ctx ctx, int64_t n_inst, const int64_t *o
     if (offsets[0] != 0) return set_err(ctx, SGP_EINVAL, "collide_batched: offsets[0] must be 0");
     for (int64_t k = 0; k < n_inst; k++)
         if (offsets[k + 1] < offsets[k]) return set_err(ctx, SGP_EINVAL, "collide_batched: offsets decrease");
-    if (ctx->ev[0]) (void)hipEventRecord(ctx->ev[0], ctx->stream);
+    phase_begin(ctx, 0);
     int s = collide_impl(ctx, offsets[n_inst], pos, radius, max_deg, g, n_inst, offsets);
     if (s == SGP_OK) phase_end(ctx, 0);
     return s;

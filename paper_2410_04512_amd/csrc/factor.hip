@@ -1423,6 +1423,12 @@ int prec_make32(sgp_ctx ctx, sgp_prec M)
     return SGP_OK;
 }
 
+__global__ void k_pair(const int32_t *a, const int32_t *b, int32_t *out)
+{
+    out[0] = *a;
+    out[1] = *b;
+}
+
 static int tail_tables(sgp_ctx ctx, sgp_prec M, int64_t n, const int32_t *in_ptr, const int32_t *in_src,
                        const int32_t *tout)
 {
@@ -1433,10 +1439,11 @@ static int tail_tables(sgp_ctx ctx, sgp_prec M, int64_t n, const int32_t *in_ptr
     SGP_TRY(tail_setup_attr(ctx));
     const int32_t Qt = M->h_step_ptr[M->tail_step];
     const int32_t nt = (int32_t)(n - Qt);
-    int32_t hin[2];
-    HIP_TRY(ctx, hipMemcpyAsync(&hin[0], in_ptr + Qt, 4, hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipMemcpyAsync(&hin[1], in_ptr + n, 4, hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipStreamSynchronize(st));
+    int32_t hin[2], *pair;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_PAIR], 2, &pair));
+    k_pair<<<1, 1, 0, st>>>(in_ptr + Qt, in_ptr + n, pair);
+    LAUNCH_CHECK(ctx);
+    SGP_TRY(readback(ctx, hin, pair, sizeof hin));
     const int32_t t0 = hin[0], t1 = hin[1];
     int32_t *flag, *rank, *iptr, *tslot;
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP8], (size_t)(t1 - t0) + 2, &flag));
@@ -1470,7 +1477,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
         return set_err(ctx, SGP_EINVAL, "factor_tree: unknown schedule %d", schedule);
     if (T->n != g->n) return set_err(ctx, SGP_EINVAL, "factor_tree: tree and graph differ in size");
     hipStream_t st = ctx->stream;
-    if (ctx->ev[6]) (void)hipEventRecord(ctx->ev[6], st);
+    phase_begin(ctx, 3);
     const int64_t n = g->n;
     M->kind = PREC_TREE;
     M->n = n;

@@ -620,7 +620,7 @@ static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w
     const int64_t K = w.K;
     const int limit = fixed > 0 ? fixed : max_iter;
     // graph replay of whole chunks (not while per-launch timing records events)
-    const bool graph = ctx->use_graph && !ctx->ktiming;
+    const bool graph = ctx->use_graph && !ctx->ktiming && ctx->plan_mode == PLAN_OFF;
     ChunkGraph cg;
     // Chunks issued between two polls of the host.  A fixed iteration count
     // needs no poll before its end.  Otherwise, after two polls, the decay per
@@ -685,7 +685,7 @@ static int prepare_work(sgp_ctx ctx, sgp_bsr A, const std::vector<int64_t> &off,
     int32_t *d;
     size_t nv = w.vec_buf.size();
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP6], nv + 2, &d));
-    HIP_TRY(ctx, hipMemcpyAsync(d, w.vec_buf.data(), nv * 4, hipMemcpyHostToDevice, ctx->stream));
+    SGP_TRY(upload(ctx, d, w.vec_buf.data(), nv * 4));
     w.vec = tab_ptrs(d, w.vec_nb, K);
     w.mv_first = d + nv - 2;
     w.mv_nb_dev = d + nv - 1;
@@ -898,7 +898,7 @@ static int solve_common(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<in
         return SGP_OK;
     }
     hipStream_t st = ctx->stream;
-    if (ctx->ev[8]) (void)hipEventRecord(ctx->ev[8], st);
+    phase_begin(ctx, 4);
     int s;
     if (opts->precision == SGP_PREC_F32_IR) {
         if (K != 1) return set_err(ctx, SGP_EINVAL, "pcg_solve: FP32 refinement is single-cluster only");

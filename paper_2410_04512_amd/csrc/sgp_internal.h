@@ -39,6 +39,24 @@ __device__ inline int32_t done_flag(const PcgScalars *s)
 // one of its arms and make them wait for the branch condition.
 __device__ inline void keep_loads_above() { __asm__ __volatile__("" ::: "memory"); }
 
+// A recorded pipeline step (sgp_step_*): every value the host read back
+// during an eager run, and every block of host data it uploaded, in order.
+// While a step is captured into a hipGraph the same host code runs again;
+// each readback then returns the recorded value at once and enqueues a
+// device-side comparison of the live value with it instead (a mismatch sets
+// `flag`: the data no longer has the recorded structure), and each upload
+// copies the recorded block from `arena` (device) so the graph holds no
+// pointer to host memory.
+enum { PLAN_OFF = 0, PLAN_RECORD = 1, PLAN_CAPTURE = 2 };
+struct StepPlan {
+    std::vector<uint8_t> bytes;   // recorded values back to back
+    std::vector<size_t> off, len;
+    std::vector<uint8_t> kind;    // 0: read back by the host, 1: uploaded by the host
+    size_t pos = 0;               // next entry while capturing
+    DevBuf arena;                 // device copy of `bytes`
+    DevBuf flag;                  // int32: 1 once a live value differed from the recorded one
+};
+
 struct sgp_ctx_ {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -67,6 +85,8 @@ struct sgp_ctx_ {
     int light_cap = 512;           // vertices of such subtrees packed into one workgroup
     hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)
     int contact_model = SGP_CONTACT_OVERLAP;   // what collide stores as a contact's w
+    int plan_mode = PLAN_OFF;      // recording or capturing a step (sgp_step_*)
+    StepPlan *plan = nullptr;
 };
 
 // event pair around one timed launch of CG iteration `iter` (no-op unless
@@ -81,6 +101,7 @@ int ktimer_flush(sgp_ctx ctx, int32_t iters_done);
 enum {
     WS_KEY_A, WS_KEY_B, WS_VAL_A, WS_VAL_B, WS_HIST, WS_TILES, WS_SLOTS, WS_DEG, WS_TMP0, WS_TMP1,
     WS_TMP2, WS_TMP3, WS_TMP4, WS_TMP5, WS_TMP6, WS_TMP7, WS_PART, WS_SCAL, WS_TMP8, WS_TMP9,
+    WS_PAIR,   // a few words gathered for one readback
     WS_COUNT
 };
 
@@ -189,13 +210,19 @@ inline int ensure_t(sgp_ctx ctx, DevBuf &b, size_t count, T **out)
 }
 void release(DevBuf &b);
 int readback(sgp_ctx ctx, void *host, const void *dev, size_t bytes);   // synchronises
+// host -> device copy of a small block of host data (ordered on the stream)
+int upload(sgp_ctx ctx, void *dev, const void *host, size_t bytes);
 
 // end of phase k (0 collide, 1 assemble, 2 build_tree, 3 factor, 4 solve):
 // its events are ev[2k], ev[2k+1]; the time is read when it is asked for, so
 // the host does not wait for the phase here
+inline void phase_begin(sgp_ctx ctx, int k)
+{
+    if (ctx && ctx->ev[2 * k] && ctx->plan_mode != PLAN_CAPTURE) (void)hipEventRecord(ctx->ev[2 * k], ctx->stream);
+}
 inline void phase_end(sgp_ctx ctx, int k)
 {
-    if (!ctx->ev[2 * k + 1]) return;
+    if (!ctx->ev[2 * k + 1] || ctx->plan_mode == PLAN_CAPTURE) return;
     (void)hipEventRecord(ctx->ev[2 * k + 1], ctx->stream);
     ctx->phase_pending[k] = true;
 }

@@ -347,7 +347,7 @@ extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
 {
     if (!ctx || !g || !T) return set_err(ctx, SGP_EINVAL, "build_tree: null handle");
     hipStream_t st = ctx->stream;
-    if (ctx->ev[4]) (void)hipEventRecord(ctx->ev[4], st);
+    phase_begin(ctx, 2);
     const int64_t n = g->n, m = g->m;
     T->n = n;
     int32_t *comp, *parent, *pedge, *depth, *te;

@@ -29,6 +29,8 @@ int set_err(sgp_ctx ctx, int code, const char *fmt, ...)
 int ensure(sgp_ctx ctx, DevBuf &b, size_t bytes)
 {
     if (bytes <= b.bytes && b.p) return SGP_OK;
+    if (ctx && ctx->plan_mode == PLAN_CAPTURE)   // the recorded run sized every buffer of the step
+        return set_err(ctx, SGP_EINVAL, "step capture: a buffer would grow (%zu bytes)", bytes);
     if (b.p) {
         hipError_t e = hipFree(b.p);
         b.p = nullptr;
@@ -53,10 +55,64 @@ void release(DevBuf &b)
     b.bytes = 0;
 }
 
+// flag = 1 if the live bytes differ from the recorded ones
+__global__ void k_plan_check(const uint8_t *live, const uint8_t *rec, int64_t bytes, int32_t *flag)
+{
+    int differ = 0;
+    for (int64_t t = threadIdx.x; t < bytes; t += blockDim.x) differ |= live[t] != rec[t];
+    if (__syncthreads_or(differ) && threadIdx.x == 0) *flag = 1;
+}
+
+static int plan_entry(sgp_ctx ctx, size_t bytes, uint8_t kind, size_t &off)
+{
+    StepPlan &P = *ctx->plan;
+    if (P.pos >= P.len.size() || P.len[P.pos] != bytes || P.kind[P.pos] != kind)
+        return set_err(ctx, SGP_EINVAL, "step capture: the host read %zu bytes where the recorded run read %zu",
+                       bytes, P.pos < P.len.size() ? P.len[P.pos] : (size_t)0);
+    off = P.off[P.pos++];
+    return SGP_OK;
+}
+
+static void plan_append(sgp_ctx ctx, const void *host, size_t bytes, uint8_t kind)
+{
+    StepPlan &P = *ctx->plan;
+    P.off.push_back(P.bytes.size());
+    P.len.push_back(bytes);
+    P.kind.push_back(kind);
+    P.bytes.insert(P.bytes.end(), (const uint8_t *)host, (const uint8_t *)host + bytes);
+}
+
 int readback(sgp_ctx ctx, void *host, const void *dev, size_t bytes)
 {
+    if (ctx->plan_mode == PLAN_CAPTURE) {
+        size_t off;
+        SGP_TRY(plan_entry(ctx, bytes, 0, off));
+        memcpy(host, ctx->plan->bytes.data() + off, bytes);
+        k_plan_check<<<1, 256, 0, ctx->stream>>>((const uint8_t *)dev, (const uint8_t *)ctx->plan->arena.p + off,
+                                                 (int64_t)bytes, (int32_t *)ctx->plan->flag.p);
+        LAUNCH_CHECK(ctx);
+        return SGP_OK;
+    }
     HIP_TRY(ctx, hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->plan_mode == PLAN_RECORD) plan_append(ctx, host, bytes, 0);
+    return SGP_OK;
+}
+
+int upload(sgp_ctx ctx, void *dev, const void *host, size_t bytes)
+{
+    if (bytes == 0) return SGP_OK;
+    if (ctx->plan_mode == PLAN_CAPTURE) {
+        size_t off;
+        SGP_TRY(plan_entry(ctx, bytes, 1, off));
+        if (memcmp(host, ctx->plan->bytes.data() + off, bytes) != 0)
+            return set_err(ctx, SGP_EINVAL, "step capture: host data differs from the recorded run");
+        HIP_TRY(ctx, hipMemcpyAsync(dev, (const uint8_t *)ctx->plan->arena.p + off, bytes, hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+        return SGP_OK;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, ctx->stream));
+    if (ctx->plan_mode == PLAN_RECORD) plan_append(ctx, host, bytes, 1);
     return SGP_OK;
 }
 

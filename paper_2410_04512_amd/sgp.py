@@ -15,10 +15,10 @@ import torch
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsgp.so")
 
-OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENOTSPD, ENOCONV, EBREAKDOWN, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENOTSPD, ENOCONV, EBREAKDOWN, ENONFINITE, ESTALE = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 SCHED_LEVEL, SCHED_CONTRACT = 0, 1
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ECAPACITY", -5: "ENOTSPD",
-           -6: "ENOCONV", -7: "EBREAKDOWN", -8: "ENONFINITE"}
+           -6: "ENOCONV", -7: "EBREAKDOWN", -8: "ENONFINITE", -9: "ESTALE"}
 
 _lib = None
 
@@ -75,6 +75,12 @@ _SIGS = {
     "sgp_prec_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sgp_prec_apply_noalloc": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sgp_set_contact_model": (C.c_int, [_vp, _i32]),
+    "sgp_step_create": (C.c_int, [_vp, C.POINTER(_vp)]),
+    "sgp_step_free": (None, [_vp]),
+    "sgp_step_record_batched": (C.c_int, [_vp, _vp, _i64, C.POINTER(_i64), _vp, _vp, _i32, _dbl, _dbl, _dbl, _i32,
+                                          _i32, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
+    "sgp_step_replay": (C.c_int, [_vp, _vp, C.POINTER(SolveInfo)]),
+    "sgp_step_size": (C.c_int, [_vp, C.POINTER(_i64), C.POINTER(_i64)]),
     "sgp_pcg_solve": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
     "sgp_pcg_solve_batched": (C.c_int, [_vp, _vp, _vp, _i64, C.POINTER(_i64), _vp, _vp,
                                         C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
@@ -200,6 +206,44 @@ class Prec(_Handle):
         lib().sgp_prec_info(self.h, C.byref(s), C.byref(t), C.byref(lt), sizes)
         return {"steps": s.value, "tail_step": t.value, "light_steps": lt.value,
                 "step_sizes": [sizes[k] for k in range(s.value)]}
+
+
+class Step(_Handle):
+    """A batched step recorded once and replayed as one hipGraph (sgp_step_*).
+    Keeps the tensors it was recorded with alive."""
+    _free = "sgp_step_free"
+
+    def __init__(self, ctx):
+        super().__init__(ctx, "sgp_step_create")
+        self.keep = None
+
+    def size(self):
+        v, b = C.c_int64(), C.c_int64()
+        lib().sgp_step_size(self.h, C.byref(v), C.byref(b))
+        return v.value, b.value
+
+    def record_batched(self, offsets, pos, radius, F, v, prec="tree", g_par=1.0, g_perp=0.1, g_med=1e-3,
+                       schedule="contract", max_deg=32, rtol=1e-8, max_iter=10000, use_x0=False, check_every=0):
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        k = off.shape[0] - 1
+        o = self.ctx._opts(rtol, max_iter, 0, use_x0, "f64", 1e-5, 50, check_every)
+        infos = (SolveInfo * k)()
+        code = {"none": 0, "jacobi": 1, "tree": 2}[prec]
+        sch = {"level": SCHED_LEVEL, "contract": SCHED_CONTRACT}[schedule]
+        self.keep = (pos, radius, F, v)
+        self.ctx._check(lib().sgp_step_record_batched(
+            self.ctx.h, self.h, k, off.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(pos, torch.float64, "pos"),
+            _ptr(radius, torch.float64, "radius"), max_deg, g_par, g_perp, g_med, code, sch,
+            _ptr(F, torch.float64, "F"), _ptr(v, torch.float64, "v"), C.byref(o), infos), "sgp_step_record_batched")
+        self.n_inst = k
+        return [infos[i].as_dict() for i in range(k)]
+
+    def replay(self, check=True):
+        infos = (SolveInfo * self.n_inst)()
+        st = lib().sgp_step_replay(self.ctx.h, self.h, infos)
+        if check:
+            self.ctx._check(st, "sgp_step_replay")
+        return st, [infos[i].as_dict() for i in range(self.n_inst)]
 
 
 class Mpnn(_Handle):
