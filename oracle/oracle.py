@@ -211,6 +211,43 @@ def build_tree(g: Graph, method: str = "prim") -> Tree:
     return Tree(n, te, parent, pedge, depth, order, cptr, child[:int(cptr[n])].copy())
 
 
+def forest_clusters(pos, radius, K, offsets=None):
+    """Clusters of the local-MST forest (Section 6, Discussion): Z-order runs of
+    K cells per instance."""
+    pos = _c(pos, np.float64).reshape(-1, 3)
+    radius = _c(radius, np.float64).reshape(-1)
+    n = pos.shape[0]
+    off = np.array([0, n], np.int64) if offsets is None else _c(offsets, np.int64)
+    cl = np.zeros(max(n, 1), np.int32)
+    st = lib().orc_forest_clusters(C.c_int64(n), _f64(pos), _f64(radius), C.c_int64(off.shape[0] - 1),
+                                   _p(off, C.c_int64), C.c_int32(int(K)), _i32(cl))
+    if st != OK:
+        raise OracleError(st, "forest_clusters")
+    return cl[:n].copy()
+
+
+def build_forest(g: Graph, pos, radius, K, offsets=None):
+    """The local-MST forest: Prim's maximum spanning forest of the graph
+    without its edges between clusters, rooted as build_tree roots.  Returns
+    (Tree, cluster of every cell)."""
+    cl = forest_clusters(pos, radius, K, offsets)
+    keep = np.nonzero(cl[g.ei] == cl[g.ej])[0].astype(np.int32) if g.m else np.zeros(0, np.int32)
+    sub = Graph(g.n, g.rowptr, g.col, g.ei[keep], g.ej[keep], g.w[keep], g.u[keep])
+    te_sub = prim(sub)[0]
+    te = np.sort(keep[te_sub]).astype(np.int32)
+    n = g.n
+    parent = np.zeros(n, np.int32); pedge = np.zeros(n, np.int32); depth = np.zeros(n, np.int32)
+    st = lib().orc_root_forest(C.c_int64(n), C.c_int64(te.shape[0]), _i32(te), _i32(g.ei), _i32(g.ej),
+                               _i32(parent), _i32(pedge), _i32(depth))
+    if st != OK:
+        raise OracleError(st, "root_forest")
+    order = np.zeros(n, np.int32); cptr = np.zeros(n + 1, np.int32); child = np.zeros(max(n, 1), np.int32)
+    st = lib().orc_tree_order(C.c_int64(n), _i32(parent), _i32(depth), _i32(order), _i32(cptr), _i32(child))
+    if st != OK:
+        raise OracleError(st, "tree_order")
+    return Tree(n, te, parent, pedge, depth, order, cptr, child[:int(cptr[n])].copy()), cl
+
+
 @dataclass
 class Factor:
     tree: Tree

@@ -254,6 +254,69 @@ void orc_hertz_area(int64_t m, const int32_t *ei, const int32_t *ej, const doubl
 }
 
 /* ------------------------------------------------------------------------ */
+/* Section 6 (Discussion): clusters of a spatial subdivision, each with its  */
+/* own spanning tree.                                                        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t inst;
+    uint64_t z;
+    int32_t id;
+} zcell;
+
+static int cmp_zcell(const void *pa, const void *pb)
+{
+    const zcell *a = pa, *b = pb;
+    if (a->inst != b->inst) return a->inst < b->inst ? -1 : 1;
+    if (a->z != b->z) return a->z < b->z ? -1 : 1;
+    return (a->id > b->id) - (a->id < b->id);
+}
+
+/* The cells of every instance (instance k: cells off[k] .. off[k+1]-1) in the
+ * Z-order of a uniform grid, cut into runs of K; cluster ids run instance by
+ * instance.  Grid: cubes of side h = 2 max R (1 if every radius is 0) with a
+ * corner at the bounding box's minimum over all cells; the coordinates of a
+ * cell are floor((x - lo) / h) per axis, and its Z-order position is the
+ * Morton code: bit b of the x, y and z coordinates becomes bit 3b, 3b + 1 and
+ * 3b + 2.  Equal codes keep the cell ids in order. */
+int orc_forest_clusters(int64_t n, const double *pos, const double *R, int64_t n_inst, const int64_t *off,
+                        int32_t K, int32_t *cluster)
+{
+    if (n == 0) return ORC_OK;
+    if (K < 1) return ORC_EINVAL;
+    double lo[3] = {pos[0], pos[1], pos[2]}, rmax = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        for (int a = 0; a < 3; a++)
+            if (pos[3 * i + a] < lo[a]) lo[a] = pos[3 * i + a];
+        if (R[i] > rmax) rmax = R[i];
+    }
+    double h = rmax > 0.0 ? 2.0 * rmax : 1.0;
+    zcell *c = malloc((size_t)n * sizeof(zcell));
+    if (!c) return ORC_ENOMEM;
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; i++) {
+        while (i >= off[k + 1]) k++;
+        uint64_t z = 0;
+        for (int a = 0; a < 3; a++) {
+            double f = floor((pos[3 * i + a] - lo[a]) / h);
+            uint64_t ca = f > 0.0 ? (uint64_t)f : 0;
+            for (int b = 0; b < 21; b++) z |= ((ca >> b) & 1u) << (3 * b + a);
+        }
+        c[i].inst = k;
+        c[i].z = z;
+        c[i].id = (int32_t)i;
+    }
+    qsort(c, (size_t)n, sizeof(zcell), cmp_zcell);
+    int32_t first = 0;   /* first cluster id of the current instance */
+    for (int64_t q = 0; q < n_inst; q++) {
+        for (int64_t p = off[q]; p < off[q + 1]; p++) cluster[c[p].id] = first + (int32_t)((p - off[q]) / K);
+        first += (int32_t)((off[q + 1] - off[q] + K - 1) / K);
+    }
+    free(c);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Step 3 (eq. cell_cell_friction) and the block Laplacian (Definition).     */
 /* ------------------------------------------------------------------------ */
 
