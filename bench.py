@@ -17,7 +17,8 @@ Prints ONE JSON line.  Besides the headline value it carries:
                 sample of the same workload (setup + a fixed number of CG
                 iterations, extrapolated to the GPU's iteration count);
   extra         the other workloads, each bounded to seconds of GPU time:
-                block-Jacobi PCG on the same 1M system; the 1k-cell solve's
+                block-Jacobi PCG and the local-MST forest (Z-order clusters
+                of 512 to 2048 cells) on the same 1M system; the 1k-cell solve's
                 latency with and without hipGraph replay; FP32-inner refinement
                 against plain FP64 at 4M cells; 256 independent spheroids in
                 one batched pipeline with autotuned knobs; the learned warm
@@ -108,6 +109,24 @@ def extra_jacobi(ctx, A, M, F):
     tt, (_, it) = _sync_time(lambda: ctx.pcg_solve(A, M, F, torch.zeros_like(F), rtol=1e-8))
     return {"jacobi_pcg": {"iters": ij["iters"], "solve_ms": 1e3 * tj},
             "tree_pcg": {"iters": it["iters"], "solve_ms": 1e3 * tt}}
+
+
+def extra_forest(ctx, g, A, F, pos, R, sizes=(512, 1024, 2048)):
+    """The local-MST forest (Section 6, Discussion) on the same 1M system:
+    Z-order clusters of K cells, each with its own maximum spanning forest,
+    every sweep one launch.  Setup (forest + factor) and solve ms,
+    iterations."""
+    import torch
+    out = {}
+    for K in sizes:
+        t_setup, (T, M) = _sync_time(lambda: (lambda T: (T, ctx.factor_tree(g, T)))(ctx.build_forest(g, pos, R, K)))
+        ctx.pcg_solve(A, M, F, torch.zeros_like(F), rtol=1e-8)
+        ts, (_, info) = _sync_time(lambda: ctx.pcg_solve(A, M, F, torch.zeros_like(F), rtol=1e-8))
+        nt, n_roots, depth = T.size()
+        out[f"K{K}"] = {"iters": info["iters"], "solve_ms": 1e3 * ts, "setup_ms": 1e3 * t_setup,
+                        "clusters": ctx.tree_clusters(T, g.size()[0])[1], "trees": n_roots, "max_depth": depth,
+                        "elim_steps": M.steps(), "us_per_iter": 1e3 * 1e3 * ts / max(info["iters"], 1)}
+    return out
 
 
 def extra_small(P, dev, reps=30):
@@ -344,7 +363,7 @@ def main():
     ap.add_argument("--schedule", default="contract", choices=["contract", "level"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--extras", default="jacobi,small,mixed,batched,learned,paper",
+    ap.add_argument("--extras", default="jacobi,forest,small,mixed,batched,learned,paper",
                     help="comma list of extra workloads to run after the headline")
     ap.add_argument("--spmv-form", type=int, choices=[0, 1], default=None,
                     help="product form: 0 stored 3x3 blocks, 1 contacts' (w, u) (the library default)")
@@ -469,6 +488,8 @@ def main():
             t_x = time.perf_counter()
             if name == "jacobi":
                 ex.update(extra_jacobi(ctx, A, M, F))
+            elif name == "forest":
+                ex["forest_1M"] = extra_forest(ctx, g, A, F, pos, R)
             elif name == "small":
                 ex["small_1k"] = extra_small(P, dev)
             elif name == "mixed":

@@ -160,6 +160,33 @@ void sgp_tree_free(sgp_tree T);
  * Synchronises the stream. */
 int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T);
 
+/* The local-MST forest of Section 6 (Discussion): the cells are cut into
+ * clusters by a spatial subdivision and every cluster keeps a maximum
+ * spanning forest of its own contacts; contacts between clusters are left
+ * out of the preconditioner (still a subgraph of the collision graph, so the
+ * support bound lambda_min(P^{-1} Gamma) >= 1 of Section 4 holds) and no
+ * tree path leaves a cluster.  Clusters: the cells of every instance of g in
+ * the Z-order of a uniform grid, cut into runs of cluster_size (the last run
+ * of an instance may be shorter); grid cubes of side 2 max R (1 if every
+ * radius is 0) anchored at the bounding box's minimum corner, cell coordinates
+ * floor((x - lo) / h) in FP64, Z-order = the Morton code interleaving the
+ * bits of (c_x, c_y, c_z) from the lowest (x lowest), ties by cell id; cluster
+ * ids numbered instance by instance in that order.  pos, radius: the device
+ * arrays g was built from.  The forest is the maximum spanning forest of the
+ * graph without its edges between clusters (same order and ties as
+ * sgp_build_tree), each tree rooted at its smallest cell id.  sgp_factor_tree
+ * on such a forest (CONTRACT schedule) groups every elimination step by
+ * component, so each sweep of the apply is one launch.  More than 1024 grid
+ * cells along an axis, or Z-order keys with the instance over 32 bits, give
+ * SGP_EINVAL.  Synchronises the stream. */
+int sgp_build_forest(sgp_ctx ctx, sgp_graph g, const double *pos, const double *radius,
+                     int32_t cluster_size, sgp_tree T);
+
+/* The cluster of every cell (device int32 [n], caller numbering; NULL =
+ * skip) and the number of clusters (host, NULL = skip) of a forest from
+ * sgp_build_forest (0 clusters and nothing copied for sgp_build_tree). */
+int sgp_tree_clusters(sgp_ctx ctx, sgp_tree T, int32_t *cluster, int64_t *n_clusters);
+
 /* n_tree_edges = n - (number of trees); n_roots; max_depth (host outputs,
  * NULL = skip). */
 int sgp_tree_size(sgp_tree T, int64_t *n_tree_edges, int64_t *n_roots, int32_t *max_depth);

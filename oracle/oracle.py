@@ -234,7 +234,12 @@ def build_forest(g: Graph, pos, radius, K, offsets=None):
     keep = np.nonzero(cl[g.ei] == cl[g.ej])[0].astype(np.int32) if g.m else np.zeros(0, np.int32)
     sub = Graph(g.n, g.rowptr, g.col, g.ei[keep], g.ej[keep], g.w[keep], g.u[keep])
     te_sub = prim(sub)[0]
-    te = np.sort(keep[te_sub]).astype(np.int32)
+    return tree_from_edges(g, keep[te_sub]), cl
+
+
+def tree_from_edges(g: Graph, tree_edge) -> "Tree":
+    """Root a forest given by its edge ids (each tree at its smallest vertex)."""
+    te = np.sort(np.asarray(tree_edge)).astype(np.int32)
     n = g.n
     parent = np.zeros(n, np.int32); pedge = np.zeros(n, np.int32); depth = np.zeros(n, np.int32)
     st = lib().orc_root_forest(C.c_int64(n), C.c_int64(te.shape[0]), _i32(te), _i32(g.ei), _i32(g.ej),
@@ -245,7 +250,7 @@ def build_forest(g: Graph, pos, radius, K, offsets=None):
     st = lib().orc_tree_order(C.c_int64(n), _i32(parent), _i32(depth), _i32(order), _i32(cptr), _i32(child))
     if st != OK:
         raise OracleError(st, "tree_order")
-    return Tree(n, te, parent, pedge, depth, order, cptr, child[:int(cptr[n])].copy()), cl
+    return Tree(n, te, parent, pedge, depth, order, cptr, child[:int(cptr[n])].copy())
 
 
 @dataclass

@@ -430,6 +430,102 @@ extern "C" int sgp_collide_batched(sgp_ctx ctx, int64_t n_inst, const int64_t *o
     return s;
 }
 
+// --------------------------------------------------------------- clusters of the local forest
+//
+// Clusters for the local-MST forest (Section 6, Discussion: a spatial
+// subdivision into clusters of a few hundred cells, each with a spanning tree
+// of its own): the cells of every instance in the Z-order of a uniform grid,
+// cut into runs of K.  Grid: cubes of side h = 2 max R (1 if all radii are
+// 0), anchored at the bounding box's minimum corner (over all instances);
+// cell coordinates c_a = floor((x_a - lo_a) / h); Z-order = the Morton code
+// interleaving the bits of (c_x, c_y, c_z) from the lowest (x lowest), ties
+// by cell id.  Cluster ids run instance by instance; an instance's last run
+// may be shorter than K.
+
+SGP_DEV uint32_t spread3(uint32_t v)
+{
+    uint32_t r = 0;
+    for (int b = 0; b < 10; b++) r |= ((v >> b) & 1u) << (3 * b);
+    return r;
+}
+
+__global__ void k_zkeys(const double *pos, int64_t n, double lox, double loy, double loz, double h, int bits,
+                        const int32_t *inst_of, uint32_t *key, int32_t *val)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double lo[3] = {lox, loy, loz};
+    uint32_t m = 0;
+    for (int a = 0; a < 3; a++) {
+        const double c = floor((pos[3 * i + a] - lo[a]) / h);
+        const uint32_t ci = c > 0.0 ? (uint32_t)c : 0u;
+        m |= spread3(ci) << a;
+    }
+    const uint32_t inst = inst_of ? (uint32_t)inst_of[i] : 0u;
+    key[i] = (inst << (3 * bits)) | m;
+    val[i] = (int32_t)i;
+}
+
+// sorted position p -> cluster of its cell
+__global__ void k_zclusters(int64_t n, const int32_t *sorted, const int32_t *inst_of, const int64_t *off,
+                            const int32_t *cbase, int32_t K, int32_t *cluster)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t i = sorted[p];
+    const int32_t k = inst_of ? inst_of[i] : 0;
+    cluster[i] = cbase[k] + (int32_t)((p - off[k]) / K);
+}
+
+int forest_partition(sgp_ctx ctx, sgp_graph g, const double *pos, const double *radius, int32_t K,
+                     int32_t *cluster, int64_t *n_clusters)
+{
+    hipStream_t st = ctx->stream;
+    const int64_t n = g->n, n_inst = g->n_inst;
+    *n_clusters = 0;
+    if (n == 0) return SGP_OK;
+    double *part, *box;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_PART], 8 * 256 + 16, &part));
+    box = part + 8 * 256;
+    k_bbox<<<256, 256, 0, st>>>(pos, radius, n, part, box, ctx->tickets);
+    LAUNCH_CHECK(ctx);
+    double hb[8];
+    SGP_TRY(readback(ctx, hb, box, sizeof hb));
+    if (hb[7] == 1.0) return set_err(ctx, SGP_ENONFINITE, "build_forest: non-finite position");
+    if (hb[7] == 2.0) return set_err(ctx, SGP_EINVAL, "build_forest: negative or non-finite radius");
+    const double h = hb[6] > 0.0 ? 2.0 * hb[6] : 1.0;
+    int bits = 1;
+    for (int a = 0; a < 3; a++)
+        while (bits < 10 && floor((hb[3 + a] - hb[a]) / h) >= (double)(1 << bits)) bits++;
+    for (int a = 0; a < 3; a++)
+        if (floor((hb[3 + a] - hb[a]) / h) >= (double)(1 << bits))
+            return set_err(ctx, SGP_EINVAL, "build_forest: more than 1024 grid cells along an axis");
+    int ibits = 0;
+    while (((int64_t)1 << ibits) < n_inst) ibits++;
+    if (3 * bits + ibits > 32) return set_err(ctx, SGP_EINVAL, "build_forest: Z-order keys exceed 32 bits");
+    // first cluster of every instance
+    std::vector<int32_t> cb(n_inst + 1, 0);
+    for (int64_t k = 0; k < n_inst; k++)
+        cb[k + 1] = cb[k] + (int32_t)((g->h_inst_off[k + 1] - g->h_inst_off[k] + K - 1) / K);
+    int32_t *cbase;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_PAIR], n_inst + 2, &cbase));
+    SGP_TRY(upload(ctx, cbase, cb.data(), (n_inst + 1) * sizeof(int32_t)));
+    uint32_t *ka, *kb;
+    int32_t *va, *vb;
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_KEY_A], n, &ka));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_KEY_B], n, &kb));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_VAL_A], n, &va));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_VAL_B], n, &vb));
+    const int32_t *inst_of = n_inst > 1 ? (const int32_t *)g->inst_of.p : nullptr;
+    k_zkeys<<<grid_for(n, 256), 256, 0, st>>>(pos, n, hb[0], hb[1], hb[2], h, bits, inst_of, ka, va);
+    LAUNCH_CHECK(ctx);
+    SGP_TRY(radix_sort_pairs(ctx, ka, va, kb, vb, n, std::max(3 * bits + ibits, 1)));
+    k_zclusters<<<grid_for(n, 256), 256, 0, st>>>(n, va, inst_of, (const int64_t *)g->inst_off.p, cbase, K, cluster);
+    LAUNCH_CHECK(ctx);
+    *n_clusters = cb[n_inst];
+    return SGP_OK;
+}
+
 extern "C" int sgp_set_contact_model(sgp_ctx ctx, int32_t model)
 {
     if (!ctx) return SGP_EINVAL;

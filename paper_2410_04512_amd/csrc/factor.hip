@@ -1636,21 +1636,28 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     // the components' workgroups from the labelling, and one sort orders the
     // vertices by (step, workgroup).
     int32_t *mw = nullptr, mnwg = 1, m0 = 2, m1 = S;
-    if (!light && schedule == SGP_SCHED_CONTRACT && S <= HIST_MAX_STEPS && S >= 4) {
-        const int hnb = (int)std::min<int64_t>(SCHED_STAT_BLOCKS, grid_for(n, 256));
-        int32_t *hpart;
-        SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP6], (size_t)hnb * S + S + 8, &hpart));
-        int32_t *hout = hpart + (size_t)hnb * S;
-        k_step_hist<<<hnb, 256, 0, st>>>(n, stepv, S, hpart);
-        k_step_hist_sum<<<S, 256, 0, st>>>(hnb, S, hpart, hout);
-        LAUNCH_CHECK(ctx);
-        std::vector<int32_t> cnt(S);
-        SGP_TRY(readback(ctx, cnt.data(), hout, S * sizeof(int32_t)));
-        std::vector<int64_t> left(S + 1, 0);   // left[k]: vertices of steps >= k
-        for (int32_t k = S - 1; k >= 0; k--) left[k] = left[k + 1] + cnt[k];
-        while (m0 < S && left[m0] > MID_MAX_VERTICES) m0++;
-        const int tdef = std::min(TAIL_DEFAULT_VERTICES, TAIL_MAX_VERTICES);
-        while (m1 > m0 && left[m1 - 1] <= tdef) m1--;
+    // A local forest (sgp_build_forest): every push stays inside a cluster's
+    // tree, so all steps are grouped by component (one launch per sweep, no
+    // single-workgroup tail)
+    const bool forest = T->cluster_size > 0 && !light && schedule == SGP_SCHED_CONTRACT && S >= 2;
+    if (forest) m0 = 0;
+    if (!light && schedule == SGP_SCHED_CONTRACT && ((S <= HIST_MAX_STEPS && S >= 4) || forest)) {
+        if (!forest) {
+            const int hnb = (int)std::min<int64_t>(SCHED_STAT_BLOCKS, grid_for(n, 256));
+            int32_t *hpart;
+            SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP6], (size_t)hnb * S + S + 8, &hpart));
+            int32_t *hout = hpart + (size_t)hnb * S;
+            k_step_hist<<<hnb, 256, 0, st>>>(n, stepv, S, hpart);
+            k_step_hist_sum<<<S, 256, 0, st>>>(hnb, S, hpart, hout);
+            LAUNCH_CHECK(ctx);
+            std::vector<int32_t> cnt(S);
+            SGP_TRY(readback(ctx, cnt.data(), hout, S * sizeof(int32_t)));
+            std::vector<int64_t> left(S + 1, 0);   // left[k]: vertices of steps >= k
+            for (int32_t k = S - 1; k >= 0; k--) left[k] = left[k + 1] + cnt[k];
+            while (m0 < S && left[m0] > MID_MAX_VERTICES) m0++;
+            const int tdef = std::min(TAIL_DEFAULT_VERTICES, TAIL_MAX_VERTICES);
+            while (m1 > m0 && left[m1 - 1] <= tdef) m1--;
+        }
         if (m1 - m0 >= 2) {
             int32_t *ja, *jb, *lcnt, *lstart, *wgr, *flag;
             SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP3], n + 1, &ja));
@@ -1684,7 +1691,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
                 SGP_TRY(scan_exclusive(ctx, jb, lstart, n));
                 int32_t total;
                 SGP_TRY(readback(ctx, &total, lstart + n, 4));
-                const int32_t cap = std::max(ctx->light_cap, 1);
+                const int32_t cap = std::max(forest ? std::max(ctx->light_cap, T->cluster_size) : ctx->light_cap, 1);
                 mnwg = std::max((total + cap - 1) / cap, 1);
                 k_light_rootwg<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->perm.p, ja, lstart, cap, wgr);
                 k_light_wg<<<grid_for(n, 256), 256, 0, st>>>(n, ja, wgr, mw);
@@ -1721,7 +1728,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     // never more than fit in LDS, TAIL_MAX_VERTICES)
     M->tail_step = S;
     int tmax = std::min(ctx->tail_max, TAIL_MAX_VERTICES);
-    while (M->tail_step > light && n - M->h_step_ptr[M->tail_step - 1] <= tmax) M->tail_step--;
+    while (!(forest && mw) && M->tail_step > light && n - M->h_step_ptr[M->tail_step - 1] <= tmax) M->tail_step--;
     // up links and in-lists
     int32_t *upq, *icnt, *in_ptr, *in_src;
     SGP_TRY(ensure_t(ctx, M->up, 2 * n + 2, &upq));

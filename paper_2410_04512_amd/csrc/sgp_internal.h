@@ -146,7 +146,16 @@ struct sgp_tree_ {
     int32_t max_depth = 0;
     DevBuf tree_edge, parent, pedge, depth, comp;
     DevBuf tptr, tadj, tadje;   // forest incidence: rows of tree neighbours, ascending edge id
+    // local forest (sgp_build_forest): cells per cluster (0: a spanning
+    // forest of the whole graph), the cluster of every cell (caller numbering)
+    int32_t cluster_size = 0;
+    int64_t n_clusters = 0;
+    DevBuf cluster;
 };
+
+// clusters of the local forest: Z-order runs of K cells per instance (collide.hip)
+int forest_partition(sgp_ctx ctx, sgp_graph g, const double *pos, const double *radius, int32_t K,
+                     int32_t *cluster, int64_t *n_clusters);
 
 enum { PREC_NONE = 0, PREC_JACOBI = 1, PREC_TREE = 2 };
 

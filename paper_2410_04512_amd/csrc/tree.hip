@@ -99,14 +99,17 @@ __global__ void k_bv_mine(const int32_t *act, int64_t na, const int32_t *ei, con
 // The first round's best edges, pulled by every vertex from its own edge list
 // (every vertex is its own component then): the same maximum of (w, then
 // smaller id) as the two atomic passes, without their atomics.
-__global__ void k_bv_first(int64_t n, const int32_t *rowptr, const int32_t *ent_edge, const double *w,
-                           unsigned long long *bestw, int32_t *beste)
+// With a partition (cl != null), entries to another cluster are not edges.
+__global__ void k_bv_first(int64_t n, const int32_t *rowptr, const int32_t *ent_edge, const int32_t *col,
+                           const int32_t *cl, const double *w, unsigned long long *bestw, int32_t *beste)
 {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     unsigned long long bw = 0ull;
     int32_t be = INT_MAX;
+    const int32_t cv = cl ? cl[v] : 0;
     for (int32_t p = rowptr[v]; p < rowptr[v + 1]; p++) {
+        if (cl && cl[col[p]] != cv) continue;
         const int32_t e = ent_edge[p];
         const unsigned long long wb = (unsigned long long)__double_as_longlong(w[e]);
         if (wb > bw || (wb == bw && e < be)) {
@@ -180,6 +183,13 @@ __global__ void k_bv_pack(const int32_t *act, int64_t na, const int32_t *flag, c
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < na && flag[k]) out[off[k]] = act[k];
+}
+
+// edges inside one cluster
+__global__ void k_intra(const int32_t *ei, const int32_t *ej, int64_t m, const int32_t *cl, int32_t *flag)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) flag[e] = cl[ei[e]] == cl[ej[e]] ? 1 : 0;
 }
 
 __global__ void k_compact_flags(const int32_t *flag, const int32_t *off, int64_t m, int32_t *out)
@@ -343,11 +353,11 @@ __global__ void k_count_roots(int64_t n, const int32_t *parent, int32_t *cnt)
     if (v < n && parent[v] < 0) atomicAdd(cnt, 1);
 }
 
-extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
+// The maximum spanning forest of the graph, or with a partition (cl: the
+// cluster of every cell) of the graph without its edges between clusters.
+static int build_forest_impl(sgp_ctx ctx, sgp_graph g, sgp_tree T, const int32_t *cl)
 {
-    if (!ctx || !g || !T) return set_err(ctx, SGP_EINVAL, "build_tree: null handle");
     hipStream_t st = ctx->stream;
-    phase_begin(ctx, 2);
     const int64_t n = g->n, m = g->m;
     T->n = n;
     int32_t *comp, *parent, *pedge, *depth, *te;
@@ -381,13 +391,28 @@ extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_VAL_B], m + 2, &loff));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_DEG], n + 2, &mr));
     k_bv_reset<<<grid_for(n, 256), 256, 0, st>>>(comp, n);
-    SGP_TRY(iota_i32(ctx, act, m));
     SGP_TRY(fill_i32(ctx, is_tree, 0, m + 1));
     int64_t na = m;
+    if (cl) {
+        // the active edges: those inside a cluster
+        if (m > 0) {
+            k_intra<<<grid_for(m, 256), 256, 0, st>>>(ei, ej, m, cl, lflag);
+            LAUNCH_CHECK(ctx);
+        }
+        SGP_TRY(scan_exclusive(ctx, lflag, loff, m));
+        if (m > 0) k_compact_flags<<<grid_for(m, 256), 256, 0, st>>>(lflag, loff, m, act);
+        LAUNCH_CHECK(ctx);
+        int32_t hn;
+        SGP_TRY(readback(ctx, &hn, loff + m, 4));
+        na = hn;
+    } else {
+        SGP_TRY(iota_i32(ctx, act, m));
+    }
     for (int round = 0; round < 64 && na > 0; round++) {
         if (round == 0) {
             k_bv_first<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->rowptr.p,
-                                                        (const int32_t *)g->ent_edge.p, wonly, bestw, beste);
+                                                        (const int32_t *)g->ent_edge.p, (const int32_t *)g->col.p, cl,
+                                                        wonly, bestw, beste);
         } else {
             k_bv_clear_best<<<grid_for(n, 256), 256, 0, st>>>(bestw, beste, n);
             k_bv_maxw<<<grid_for(na, 256), 256, 0, st>>>(act, na, ei, ej, wonly, comp, bestw);
@@ -486,7 +511,44 @@ extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
         T->max_depth = 0;
         T->n_roots = n;
     }
+    return SGP_OK;
+}
+
+extern "C" int sgp_build_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T)
+{
+    if (!ctx || !g || !T) return set_err(ctx, SGP_EINVAL, "build_tree: null handle");
+    phase_begin(ctx, 2);
+    T->cluster_size = 0;
+    T->n_clusters = 0;
+    SGP_TRY(build_forest_impl(ctx, g, T, nullptr));
     phase_end(ctx, 2);
+    return SGP_OK;
+}
+
+extern "C" int sgp_build_forest(sgp_ctx ctx, sgp_graph g, const double *pos, const double *radius,
+                                int32_t cluster_size, sgp_tree T)
+{
+    if (!ctx || !g || !T) return set_err(ctx, SGP_EINVAL, "build_forest: null handle");
+    if (cluster_size < 1) return set_err(ctx, SGP_EINVAL, "build_forest: cluster_size must be positive");
+    if (g->n > 0 && (!pos || !radius)) return set_err(ctx, SGP_EINVAL, "build_forest: null positions");
+    phase_begin(ctx, 2);
+    int32_t *cl;
+    SGP_TRY(ensure_t(ctx, T->cluster, g->n + 1, &cl));
+    int64_t nc = 0;
+    SGP_TRY(forest_partition(ctx, g, pos, radius, cluster_size, cl, &nc));
+    T->cluster_size = cluster_size;
+    T->n_clusters = nc;
+    SGP_TRY(build_forest_impl(ctx, g, T, cl));
+    phase_end(ctx, 2);
+    return SGP_OK;
+}
+
+extern "C" int sgp_tree_clusters(sgp_ctx ctx, sgp_tree T, int32_t *cluster, int64_t *n_clusters)
+{
+    if (!ctx || !T) return set_err(ctx, SGP_EINVAL, "tree_clusters: null handle");
+    if (n_clusters) *n_clusters = T->n_clusters;
+    if (cluster && T->cluster_size > 0 && T->n > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(cluster, T->cluster.p, T->n * 4, hipMemcpyDeviceToDevice, ctx->stream));
     return SGP_OK;
 }
 

@@ -75,6 +75,8 @@ _SIGS = {
     "sgp_prec_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sgp_prec_apply_noalloc": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sgp_set_contact_model": (C.c_int, [_vp, _i32]),
+    "sgp_build_forest": (C.c_int, [_vp, _vp, _vp, _vp, _i32, _vp]),
+    "sgp_tree_clusters": (C.c_int, [_vp, _vp, _vp, C.POINTER(_i64)]),
     "sgp_step_create": (C.c_int, [_vp, C.POINTER(_vp)]),
     "sgp_step_free": (None, [_vp]),
     "sgp_step_record_batched": (C.c_int, [_vp, _vp, _i64, C.POINTER(_i64), _vp, _vp, _i32, _dbl, _dbl, _dbl, _i32,
@@ -409,6 +411,22 @@ class Context:
         T = T or Tree(self)
         self._check(lib().sgp_build_tree(self.h, g.h, T.h), "sgp_build_tree")
         return T
+
+    def build_forest(self, g: Graph, pos, radius, cluster_size=512, T: Tree | None = None) -> Tree:
+        """Local maximum spanning forest: one per Z-order cluster of cluster_size cells."""
+        T = T or Tree(self)
+        self._check(lib().sgp_build_forest(self.h, g.h, _ptr(pos, torch.float64, "pos"),
+                                           _ptr(radius, torch.float64, "radius"), cluster_size, T.h),
+                    "sgp_build_forest")
+        return T
+
+    def tree_clusters(self, T: Tree, n: int):
+        """(cluster of every cell as a device int32 tensor, number of clusters)."""
+        nc = C.c_int64()
+        out = torch.empty(n, dtype=torch.int32, device=self.dev())
+        self._check(lib().sgp_tree_clusters(self.h, T.h, _ptr(out, torch.int32, "cluster"), C.byref(nc)),
+                    "sgp_tree_clusters")
+        return out, nc.value
 
     def tree_export(self, T: Tree, n: int):
         nt, _, _ = T.size()

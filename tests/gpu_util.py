@@ -83,16 +83,20 @@ def second_cpu_pcg(A, F, prec, factor, k, x0=None):
     return x.reshape(-1, 3)
 
 
-def check_velocity_spread(v_gpu, iters_gpu, A, F, factor, prec="tree", x0=None):
+def check_velocity_spread(v_gpu, iters_gpu, A, F, factor, prec="tree", x0=None, rtol=1e-8):
     """Velocity parity for systems where CG amplifies rounding: within 1e-8 of
     the oracle, or within 10x the spread between the oracle and a second CPU
     implementation at the same iteration count (both correct FP64 runs of the
-    same recurrence in different summation orders).  Returns (error, spread)."""
+    same recurrence in different summation orders).  Iteration counts may
+    differ by more than one where the residual creeps along the tolerance:
+    then the oracle's own recurrence residual at the GPU's count must be
+    within 2x the tolerance (both stopped at the tolerance up to rounding),
+    and the comparison is at that count.  Returns (error, spread)."""
     from oracle import oracle as O
     xo, io = O.pcg(A, F, prec, factor, x0=x0)
     if io.iters != iters_gpu:
-        assert abs(io.iters - iters_gpu) <= 1, (io.iters, iters_gpu)
         xo, io = O.pcg(A, F, prec, factor, x0=x0, fixed_iters=iters_gpu)
+        assert io.relres_rec <= 2 * rtol, (iters_gpu, io.relres_rec)
     den = max(np.linalg.norm(xo), 1e-300)
     err = np.linalg.norm(v_gpu - xo) / den
     if err <= 1e-8:
