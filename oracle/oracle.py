@@ -372,6 +372,70 @@ def ir_solve(A: BSR, F, factor: Factor, tol=1e-8, inner_tol=1e-5, max_outer=50, 
     return x.reshape(-1, 3), info
 
 
+def augment(g: Graph, t: Tree, t_parts=None):
+    """Vaidya's augmented MST (Section 3.1): the MST cut into pieces of about
+    n / t_parts cells (t_parts = ceil(n^(1/4)) by default; orc_aug_pieces),
+    plus, for every pair of pieces joined by a contact, the heaviest such
+    contact (ties: the smaller edge id).  Returns (edge ids of the augmented
+    tree ascending, head of every cell's piece, added edge ids ascending)."""
+    n = g.n
+    if t_parts is None:
+        t_parts = max(1, int(np.ceil(n ** 0.25)))
+    s = max(1, -(-n // t_parts))
+    piece = np.zeros(max(n, 1), np.int32)
+    child = t.child if t.child.size else np.zeros(1, np.int32)
+    st = lib().orc_aug_pieces(C.c_int64(n), _i32(t.parent), _i32(t.order), _i32(t.child_ptr), _i32(child),
+                              C.c_int32(s), _i32(piece))
+    if st != OK:
+        raise OracleError(st, "aug_pieces")
+    piece = piece[:n].copy()
+    added = np.zeros(max(g.m, 1), np.int32)
+    if g.m:
+        st = lib().orc_aug_edges(C.c_int64(g.m), _i32(g.ei), _i32(g.ej), _f64(g.w), _i32(piece), _i32(added))
+        if st != OK:
+            raise OracleError(st, "aug_edges")
+    add = np.nonzero(added[:g.m])[0].astype(np.int32)
+    aug = np.union1d(t.tree_edge, add).astype(np.int32)
+    return aug, piece, np.setdiff1d(add, t.tree_edge).astype(np.int32)
+
+
+def assemble_edges(g: Graph, edges, g_par=G_PAR, g_perp=G_PERP, g_med=G_MED) -> BSR:
+    """The block Laplacian (plus g_med I) of the subgraph with the given edge
+    ids: assembly of the collision graph restricted to those contacts."""
+    edges = np.asarray(edges, dtype=np.int32)
+    ei, ej = g.ei[edges], g.ej[edges]
+    n = g.n
+    deg = np.bincount(np.concatenate([ei, ej]), minlength=n) if edges.size else np.zeros(n, np.int64)
+    rowptr = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
+    rows = np.concatenate([ei, ej]); cols = np.concatenate([ej, ei])
+    order = np.lexsort((cols, rows))
+    sub = Graph(n, rowptr, cols[order].astype(np.int32), ei, ej, g.w[edges], g.u[edges])
+    return assemble(sub, g_par, g_perp, g_med)
+
+
+def fcg(A: BSR, Paug: BSR, f: Factor, F, tol=1e-8, inner_tol=0.1, max_iter=10_000, max_inner=10_000, x0=None,
+        check=True):
+    """Flexible CG on Gamma x = F whose preconditioner is tree-PCG on the
+    augmented MST's Laplacian to relative residual inner_tol.  Returns
+    (x, SolveInfo with iters = outer iterations, outer = inner iterations in all)."""
+    n = A.n
+    t = f.tree
+    F = _c(F, np.float64).reshape(-1)
+    x = np.zeros(3 * n) if x0 is None else _c(x0, np.float64).reshape(-1).copy()
+    ii = np.zeros(2, np.int32); dd = np.zeros(2)
+    child = t.child if t.child.size else np.zeros(1, np.int32)
+    st = lib().orc_fcg(C.c_int64(n), _i32(A.rowptr), _i32(A.bcol), _f64(_c(A.val, np.float64)),
+                       _i32(Paug.rowptr), _i32(Paug.bcol), _f64(_c(Paug.val, np.float64)),
+                       _i32(t.parent), _i32(t.order), _i32(t.child_ptr), _i32(child),
+                       _f64(_c(f.D, np.float64)), _f64(_c(f.L, np.float64)), _f64(F), _f64(x),
+                       C.c_int(0 if x0 is None else 1), C.c_double(tol), C.c_double(inner_tol),
+                       C.c_int(max_iter), C.c_int(max_inner), _i32(ii), _f64(dd))
+    info = SolveInfo(int(st), int(ii[0]), float(dd[0]), float(dd[1]), int(ii[1]))
+    if check and st != OK:
+        raise OracleError(st, "fcg")
+    return x.reshape(-1, 3), info
+
+
 def forces(g: Graph, noise, k_rep=5.0):
     n = g.n
     noise = _c(noise, np.float64).reshape(-1)

@@ -879,6 +879,152 @@ done:
 }
 
 /* ------------------------------------------------------------------------ */
+/* Section 3.1, Vaidya's second preconditioner: the MST plus edges back      */
+/* between its pieces, solved by flexible CG around an inner tree-PCG        */
+/* (the nested CG with the MST as preconditioner of Sections 3 and 5).       */
+/* ------------------------------------------------------------------------ */
+
+/* Cutting the MST into pieces (a tree partition in the manner of Vaidya's
+ * construction): walking the forest children first, every vertex weighs 1
+ * plus the weights of its children that were not cut off; a vertex of
+ * weight >= s is cut off from its parent and heads a piece.  So a piece has
+ * at least s vertices unless it holds a root, and there are at most n / s
+ * pieces besides those of the roots.  order: the vertices children first
+ * (decreasing depth, as orc_tree_order gives them); piece[v] = the head of
+ * v's piece (a cut vertex or a root). */
+int orc_aug_pieces(int64_t n, const int32_t *parent, const int32_t *order, const int32_t *child_ptr,
+                   const int32_t *child, int32_t s, int32_t *piece)
+{
+    int32_t *w = malloc((size_t)(n + 1) * sizeof(int32_t));
+    if (!w) return ORC_ENOMEM;
+    for (int64_t q = 0; q < n; q++) {
+        int32_t v = order[q], wv = 1;
+        for (int32_t c = child_ptr[v]; c < child_ptr[v + 1]; c++)
+            if (w[child[c]] < s) wv += w[child[c]];
+        w[v] = wv;
+    }
+    for (int64_t q = n - 1; q >= 0; q--) {   /* parents first */
+        int32_t v = order[q], p = parent[v];
+        piece[v] = (p >= 0 && w[v] < s) ? piece[p] : v;
+    }
+    free(w);
+    return ORC_OK;
+}
+
+typedef struct {
+    int32_t a, b, e;
+    double w;
+} pair_edge;
+
+static int cmp_pair_edge(const void *pa, const void *pb)
+{
+    const pair_edge *x = pa, *y = pb;
+    if (x->a != y->a) return x->a < y->a ? -1 : 1;
+    if (x->b != y->b) return x->b < y->b ? -1 : 1;
+    if (x->w != y->w) return x->w > y->w ? -1 : 1;   /* heavier first */
+    return (x->e > y->e) - (x->e < y->e);             /* then the smaller id */
+}
+
+/* For every pair of pieces joined by a contact, the heaviest such contact
+ * (ties: the smaller edge id): added[e] = 1 for the chosen edges. */
+int orc_aug_edges(int64_t m, const int32_t *ei, const int32_t *ej, const double *w, const int32_t *piece,
+                  int32_t *added)
+{
+    pair_edge *c = malloc((size_t)(m + 1) * sizeof(pair_edge));
+    if (!c) return ORC_ENOMEM;
+    int64_t k = 0;
+    for (int64_t e = 0; e < m; e++) {
+        added[e] = 0;
+        int32_t a = piece[ei[e]], b = piece[ej[e]];
+        if (a == b) continue;
+        c[k].a = a < b ? a : b;
+        c[k].b = a < b ? b : a;
+        c[k].e = (int32_t)e;
+        c[k].w = w[e];
+        k++;
+    }
+    qsort(c, (size_t)k, sizeof(pair_edge), cmp_pair_edge);
+    for (int64_t t = 0; t < k; t++)
+        if (t == 0 || c[t].a != c[t - 1].a || c[t].b != c[t - 1].b) added[c[t].e] = 1;
+    free(c);
+    return ORC_OK;
+}
+
+/* Flexible CG (Notay 2000, one direction kept) on Gamma x = F with a
+ * preconditioner that is itself an iteration: z = an approximate solution of
+ * P' z = r by tree-PCG on P' (the block Laplacian of the augmented MST, given
+ * as its BSR matrix) from zero to relative residual inner_tol.  Steps:
+ *   r = F - Gamma x, z = inner(r), p = z;
+ *   repeat: q = Gamma p, alpha = (p.r)/(p.q), x += alpha p, r -= alpha q,
+ *           stop if ||r||/||F|| <= tol, z = inner(r), beta = -(z.q)/(p.q),
+ *           p = z + beta p.
+ * info_i[0] = outer iterations, info_i[1] = inner iterations in all;
+ * info_d[0] = recurrence relres, info_d[1] = true relres. */
+int orc_fcg(int64_t n, const int32_t *rowptr, const int32_t *bcol, const double *val, const int32_t *prow,
+            const int32_t *pcol, const double *pval, const int32_t *parent, const int32_t *order,
+            const int32_t *child_ptr, const int32_t *child, const double *Dt, const double *Lt, const double *F,
+            double *x, int use_x0, double tol, double inner_tol, int max_iter, int max_inner, int32_t *info_i,
+            double *info_d)
+{
+    int64_t len = 3 * n;
+    double *r = malloc((size_t)(len + 1) * sizeof(double));
+    double *z = malloc((size_t)(len + 1) * sizeof(double));
+    double *p = malloc((size_t)(len + 1) * sizeof(double));
+    double *q = malloc((size_t)(len + 1) * sizeof(double));
+    int status = ORC_OK, k = 0, inner_total = 0;
+    double relres = 0.0;
+    if (!r || !z || !p || !q) { status = ORC_ENOMEM; goto done; }
+    if (!use_x0) for (int64_t t = 0; t < len; t++) x[t] = 0.0;
+    orc_spmv(n, rowptr, bcol, val, x, q);
+    for (int64_t t = 0; t < len; t++) r[t] = F[t] - q[t];
+    double nF = sqrt(dot(len, F, F));
+    if (nF == 0.0) { for (int64_t t = 0; t < len; t++) x[t] = 0.0; goto done; }
+    relres = sqrt(dot(len, r, r)) / nF;
+    if (relres <= tol) goto done;
+    int32_t ii[1];
+    double dd[2];
+#define INNER()                                                                                          \
+    do {                                                                                                 \
+        int s_ = orc_pcg(n, prow, pcol, pval, ORC_PREC_TREE, parent, order, child_ptr, child, Dt, Lt, r, z, \
+                         0, inner_tol, max_inner, 0, ii, dd);                                            \
+        inner_total += ii[0];                                                                            \
+        if (s_ != ORC_OK && s_ != ORC_ENOCONV) { status = s_; goto done; }                               \
+    } while (0)
+    INNER();
+    for (int64_t t = 0; t < len; t++) p[t] = z[t];
+    while (k < max_iter) {
+        orc_spmv(n, rowptr, bcol, val, p, q);
+        double pq = dot(len, p, q);
+        if (!(pq > 0.0) || !isfinite(pq)) { status = ORC_EBREAKDOWN; break; }
+        double alpha = dot(len, p, r) / pq;
+        for (int64_t t = 0; t < len; t++) x[t] = x[t] + alpha * p[t];
+        for (int64_t t = 0; t < len; t++) r[t] = r[t] - alpha * q[t];
+        k++;
+        relres = sqrt(dot(len, r, r)) / nF;
+        if (relres <= tol) break;
+        INNER();
+        double beta = -dot(len, z, q) / pq;
+        for (int64_t t = 0; t < len; t++) p[t] = z[t] + beta * p[t];
+    }
+#undef INNER
+    if (status == ORC_OK && k >= max_iter && relres > tol) status = ORC_ENOCONV;
+done:
+    if (info_i) { info_i[0] = k; info_i[1] = inner_total; }
+    if (info_d) {
+        info_d[0] = relres;
+        info_d[1] = 0.0;
+        if (r && q && status != ORC_ENOMEM) {
+            double nF2 = sqrt(dot(len, F, F));
+            orc_spmv(n, rowptr, bcol, val, x, q);
+            for (int64_t t = 0; t < len; t++) r[t] = F[t] - q[t];
+            info_d[1] = nF2 > 0.0 ? sqrt(dot(len, r, r)) / nF2 : 0.0;
+        }
+    }
+    free(r); free(z); free(p); free(q);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Mixed precision: FP32 inner tree-PCG inside FP64 iterative refinement.     */
 /* ------------------------------------------------------------------------ */
 
