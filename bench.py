@@ -17,8 +17,9 @@ Prints ONE JSON line.  Besides the headline value it carries:
                 sample of the same workload (setup + a fixed number of CG
                 iterations, extrapolated to the GPU's iteration count);
   extra         the other workloads, each bounded to seconds of GPU time:
-                block-Jacobi PCG and the local-MST forest (Z-order clusters
-                of 512 to 2048 cells) on the same 1M system; the 1k-cell solve's
+                block-Jacobi PCG, the local-MST forest (Z-order clusters
+                of 512 to 2048 cells) and the augmented tree with its nested
+                flexible CG on the same 1M system; the 1k-cell solve's
                 latency with and without hipGraph replay; FP32-inner refinement
                 against plain FP64 at 4M cells; 256 independent spheroids in
                 one batched pipeline with autotuned knobs; the learned warm
@@ -126,6 +127,22 @@ def extra_forest(ctx, g, A, F, pos, R, sizes=(512, 1024, 2048)):
         out[f"K{K}"] = {"iters": info["iters"], "solve_ms": 1e3 * ts, "setup_ms": 1e3 * t_setup,
                         "clusters": ctx.tree_clusters(T, g.size()[0])[1], "trees": n_roots, "max_depth": depth,
                         "elim_steps": M.steps(), "us_per_iter": 1e3 * 1e3 * ts / max(info["iters"], 1)}
+    return out
+
+
+def extra_augmented(ctx, g, T, A, F):
+    """Vaidya's augmented tree (Section 3.1) on the same 1M system with the
+    paper's nested solve: flexible CG around tree-PCG on P' to relative
+    residual 0.1 (Sections 3 and 5); t = ceil(n^(1/4)) pieces, and 64."""
+    import torch
+    out = {}
+    for parts in (0, 64):
+        t_setup, M = _sync_time(lambda: ctx.factor_augmented(g, T, parts=parts, inner_rtol=0.1))
+        npc, nad, _, _ = ctx.prec_augmented(M, g.size()[0])
+        ts, (_, info) = _sync_time(lambda: ctx.pcg_solve(A, M, F, torch.zeros_like(F), rtol=1e-8))
+        out[f"parts{parts if parts else 'auto'}"] = {
+            "pieces": npc, "added": nad, "outer_iters": info["iters"], "inner_iters": info["inner_iters"],
+            "solve_ms": 1e3 * ts, "setup_ms": 1e3 * t_setup, "relres_true": info["relres_true"]}
     return out
 
 
@@ -363,7 +380,7 @@ def main():
     ap.add_argument("--schedule", default="contract", choices=["contract", "level"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--extras", default="jacobi,forest,small,mixed,batched,learned,paper",
+    ap.add_argument("--extras", default="jacobi,forest,augmented,small,mixed,batched,learned,paper",
                     help="comma list of extra workloads to run after the headline")
     ap.add_argument("--spmv-form", type=int, choices=[0, 1], default=None,
                     help="product form: 0 stored 3x3 blocks, 1 contacts' (w, u) (the library default)")
@@ -490,6 +507,8 @@ def main():
                 ex.update(extra_jacobi(ctx, A, M, F))
             elif name == "forest":
                 ex["forest_1M"] = extra_forest(ctx, g, A, F, pos, R)
+            elif name == "augmented":
+                ex["augmented_1M"] = extra_augmented(ctx, g, T, A, F)
             elif name == "small":
                 ex["small_1k"] = extra_small(P, dev)
             elif name == "mixed":

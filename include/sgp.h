@@ -220,6 +220,33 @@ enum { SGP_SCHED_LEVEL = 0, SGP_SCHED_CONTRACT = 1 };
 int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_par, double g_perp,
                     double g_med, int32_t schedule, sgp_prec M);
 
+/* Vaidya's augmented maximum spanning tree (Section 3.1) with the nested
+ * solve of Sections 3 and 5.  The tree (a spanning tree from sgp_build_tree,
+ * not a local forest) is factored as by sgp_factor_tree; then it is cut into
+ * pieces: walking the forest children first, a vertex weighs 1 plus the
+ * weights of its children that were not cut off, and a vertex of weight
+ * >= ceil(n / parts) is cut off from its parent and heads a piece (parts <= 0:
+ * ceil(n^(1/4)), the paper's choice of t).  For every pair of pieces joined
+ * by a contact, the heaviest such contact (ties: the smaller edge id) is
+ * added back; P' is the block Laplacian of the tree and the added contacts
+ * plus g_med I.  sgp_pcg_solve with M then runs flexible CG (Notay; one
+ * direction kept: alpha = p.r / p.q, beta = -z.q / p.q) whose
+ * preconditioner is CG on P' z = r from zero, preconditioned by the tree, to
+ * ||r_inner|| <= inner_rtol ||r|| (0 < inner_rtol < 1; the paper: 0.1).  One
+ * FP64 system to rtol only (SGP_EINVAL for batches, FP32 refinement or fixed
+ * iteration counts); info.iters counts the outer iterations,
+ * info.inner_iters the inner ones in all.  sgp_prec_apply on such an M
+ * applies its tree.  Synchronises. */
+int sgp_factor_augmented(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_par, double g_perp,
+                         double g_med, int32_t schedule, int32_t parts, double inner_rtol, sgp_prec M);
+
+/* The pieces and added contacts of an augmented tree: their counts (host,
+ * NULL = skip), the head of every cell's piece (device int32 [n], caller
+ * numbering, NULL = skip) and the added edge ids ascending (device int32
+ * [added], NULL = skip). */
+int sgp_prec_augmented(sgp_ctx ctx, sgp_prec M, int64_t *pieces, int64_t *added, int32_t *piece,
+                       int32_t *added_edges);
+
 /* Block-Jacobi preconditioner M = blockdiag(Gamma_ii) (comparison method of
  * Section 5). */
 int sgp_make_jacobi(sgp_ctx ctx, sgp_bsr A, sgp_prec M);
@@ -268,7 +295,7 @@ typedef struct {
     int32_t status;       /* sgp_status of the solve */
     int32_t iters;        /* CG iterations (all inner iterations for IR) */
     int32_t outer_iters;  /* IR refinement steps (0 for plain PCG) */
-    int32_t pad;
+    int32_t inner_iters;  /* augmented tree: inner CG iterations in all (0 otherwise) */
     double relres_rec;    /* ||r_k|| / ||F|| of the recurrence (FP64 residual for IR) */
     double relres_true;   /* ||F - Gamma v|| / ||F|| recomputed at the end */
 } sgp_solve_info;

@@ -122,6 +122,8 @@ extern "C" void sgp_prec_free(sgp_prec M)
     release(M->elim_int); release(M->perm); release(M->inv); release(M->tail_iptr); release(M->tail_tslot);
     release(M->tail_b); release(M->light_ptr); release(M->mid_ptr); release(M->wu0); release(M->wu032);
     release(M->jdinv);
+    release(M->aug_piece); release(M->aug_list); release(M->aug_tptr); release(M->aug_tadj); release(M->aug_twu);
+    release(M->aug_ptr); release(M->aug_adj); release(M->aug_wu);
     delete M;
 }
 

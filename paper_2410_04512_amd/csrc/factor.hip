@@ -1483,6 +1483,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     M->n = n;
     M->schedule = schedule;
     M->have32 = false;
+    M->aug = 0;
     M->light_steps = 0;
     M->light_nwg = 0;
     if (n == 0) {
@@ -1815,6 +1816,7 @@ __global__ void k_jacobi_make(int64_t n, const int32_t *diagpos, const double *v
 
 extern "C" int sgp_make_jacobi(sgp_ctx ctx, sgp_bsr A, sgp_prec M)
 {
+    if (M) M->aug = 0;
     if (!ctx || !A || !M) return set_err(ctx, SGP_EINVAL, "make_jacobi: null handle");
     hipStream_t st = ctx->stream;
     M->kind = PREC_JACOBI;

@@ -900,7 +900,20 @@ static int solve_common(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<in
     hipStream_t st = ctx->stream;
     phase_begin(ctx, 4);
     int s;
-    if (opts->precision == SGP_PREC_F32_IR) {
+    if (M && M->aug) {
+        // the augmented tree (Section 3.1): flexible CG around an inner tree-PCG
+        if (K != 1 || opts->precision != SGP_PREC_F64 || opts->fixed_iters > 0)
+            return set_err(ctx, SGP_EINVAL, "pcg_solve: the augmented tree solves one FP64 system to rtol");
+        const int64_t n = A->n;
+        double *Fi, *xi;
+        SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP8], 6 * n + 6, &Fi));
+        xi = Fi + 3 * n + 3;
+        const int32_t *perm = (const int32_t *)A->perm.p;
+        SGP_TRY(permute_rows(ctx, perm, F, Fi, n, 0));
+        if (opts->use_x0) SGP_TRY(permute_rows(ctx, perm, v, xi, n, 0));
+        s = solve_augmented(ctx, A, M, Fi, xi, opts, info);
+        if (s == SGP_OK || info->status != SGP_OK) SGP_TRY(permute_rows(ctx, perm, xi, v, n, 1));
+    } else if (opts->precision == SGP_PREC_F32_IR) {
         if (K != 1) return set_err(ctx, SGP_EINVAL, "pcg_solve: FP32 refinement is single-cluster only");
         s = solve_ir(ctx, A, M, F, v, opts, info);
     } else {

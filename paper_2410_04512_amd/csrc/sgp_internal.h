@@ -187,7 +187,20 @@ struct sgp_prec_ {
     DevBuf F32, Dinv32, y32, cs32;                      // FP32 copies for the refinement inner solve
     bool have32 = false;
     DevBuf jdinv;                                       // Jacobi: [n][6]
+    // augmented tree (sgp_factor_augmented): the tree factor above is the
+    // inner preconditioner; P' = its tree's Laplacian plus the added contacts
+    int aug = 0;
+    double inner_rtol = 0.1;
+    int32_t aug_parts = 0;
+    int64_t aug_pieces = 0, aug_added = 0;
+    DevBuf aug_piece, aug_list;                         // head of every cell's piece; added edge ids ascending
+    DevBuf aug_tptr, aug_tadj, aug_twu;                 // tree rows (caller numbering): neighbour (internal), (w, u)
+    DevBuf aug_ptr, aug_adj, aug_wu;                    // added-contact rows, the same
 };
+
+// the augmented tree's flexible CG (augment.hip); F and x in the internal order
+int solve_augmented(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const double *F, double *x, const sgp_solve_opts *o,
+                    sgp_solve_info *info);
 
 // ---------------------------------------------------------------- errors
 

@@ -37,11 +37,11 @@ class SolveOpts(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("outer_iters", C.c_int32),
-                ("pad", C.c_int32), ("relres_rec", C.c_double), ("relres_true", C.c_double)]
+                ("inner_iters", C.c_int32), ("relres_rec", C.c_double), ("relres_true", C.c_double)]
 
     def as_dict(self):
         return {"status": self.status, "iters": self.iters, "outer_iters": self.outer_iters,
-                "relres_rec": self.relres_rec, "relres_true": self.relres_true}
+                "inner_iters": self.inner_iters, "relres_rec": self.relres_rec, "relres_true": self.relres_true}
 
 
 _vp, _i64, _i32, _dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
@@ -76,6 +76,8 @@ _SIGS = {
     "sgp_prec_apply_noalloc": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sgp_set_contact_model": (C.c_int, [_vp, _i32]),
     "sgp_build_forest": (C.c_int, [_vp, _vp, _vp, _vp, _i32, _vp]),
+    "sgp_factor_augmented": (C.c_int, [_vp, _vp, _vp, _dbl, _dbl, _dbl, _i32, _i32, _dbl, _vp]),
+    "sgp_prec_augmented": (C.c_int, [_vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp, _vp]),
     "sgp_tree_clusters": (C.c_int, [_vp, _vp, _vp, C.POINTER(_i64)]),
     "sgp_step_create": (C.c_int, [_vp, C.POINTER(_vp)]),
     "sgp_step_free": (None, [_vp]),
@@ -445,6 +447,26 @@ class Context:
         sch = {"level": SCHED_LEVEL, "contract": SCHED_CONTRACT}[schedule] if isinstance(schedule, str) else schedule
         self._check(lib().sgp_factor_tree(self.h, g.h, T.h, g_par, g_perp, g_med, sch, M.h), "sgp_factor_tree")
         return M
+
+    def factor_augmented(self, g: Graph, T: Tree, g_par=1.0, g_perp=0.1, g_med=1e-3, schedule="contract",
+                         parts=0, inner_rtol=0.1, M: Prec | None = None) -> Prec:
+        """Vaidya's augmented tree with the nested (flexible CG) solve."""
+        M = M or Prec(self)
+        sch = {"level": SCHED_LEVEL, "contract": SCHED_CONTRACT}[schedule]
+        self._check(lib().sgp_factor_augmented(self.h, g.h, T.h, g_par, g_perp, g_med, sch, parts, inner_rtol, M.h),
+                    "sgp_factor_augmented")
+        return M
+
+    def prec_augmented(self, M: Prec, n: int):
+        """(pieces, added, head of every cell's piece, added edge ids) of an augmented tree."""
+        npc, nad = C.c_int64(), C.c_int64()
+        self._check(lib().sgp_prec_augmented(self.h, M.h, C.byref(npc), C.byref(nad), None, None),
+                    "sgp_prec_augmented")
+        piece = torch.empty(n, dtype=torch.int32, device=self.dev())
+        added = torch.empty(max(nad.value, 1), dtype=torch.int32, device=self.dev())
+        self._check(lib().sgp_prec_augmented(self.h, M.h, None, None, _ptr(piece, torch.int32, "piece"),
+                                             _ptr(added, torch.int32, "added")), "sgp_prec_augmented")
+        return npc.value, nad.value, piece, added[:nad.value]
 
     def make_jacobi(self, A: Bsr, M: Prec | None = None) -> Prec:
         M = M or Prec(self)
