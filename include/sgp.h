@@ -457,8 +457,14 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
  *                 steps between the first two and the tail, from the first
  *                 with at most 2^17 vertices left, are swept one workgroup
  *                 per group of components, in one launch per sweep)
- * Unknown keys or values out of range give SGP_EINVAL.  check_every and
- * graph leave every result bitwise unchanged, and so does tail_max as long as
+ *  "fuse_step0"   1: in sgp_pcg_solve* with a tree preconditioner whose
+ *                 first elimination step runs as launches of its own, that
+ *                 step's forward substitution runs inside the CG's
+ *                 r -= alpha q pass and its backward substitution inside the
+ *                 r.z pass, on the rows each block of those passes holds
+ *                 (default 1; 0: separate launches)
+ * Unknown keys or values out of range give SGP_EINVAL.  check_every,
+ * graph and fuse_step0 leave every result bitwise unchanged, and so does tail_max as long as
  * the tail does not reach the first elimination step (that step forms its
  * couplings from the contacts' (w, u) when it runs as its own launch, from
  * the stored blocks inside the tail: the same values up to rounding);

@@ -467,6 +467,12 @@ __global__ void k_map_ids(int64_t n, const int32_t *ids, const int32_t *inv, int
     if (q < n) out[q] = inv[ids[q]];
 }
 
+__global__ void k_step0_sorted(int32_t q1, const int32_t *elim, int32_t *flag)
+{
+    const int32_t q = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q > 0 && q < q1 && elim[q] <= elim[q - 1]) flag[0] = 1;
+}
+
 __global__ void k_invperm(int64_t n, const int32_t *elim, int32_t *pos)
 {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -745,35 +751,6 @@ SGP_DEV void bwd_vertex(int32_t q, const int32_t *elim, const int32_t *upq, cons
     z[3 * v] = n0;
     z[3 * v + 1] = n1;
     z[3 * v + 2] = n2;
-}
-
-// -W p for the block W = w (g_perp I + (g_par - g_perp) u u^T) of contact
-// e = (w, u): the coupling of a first-step vertex, from 4 values instead of 9
-template <class T>
-SGP_DEV void neg_w_mv(const T *e, T gpar, T gperp, T p0, T p1, T p2, T &o0, T &o1, T &o2)
-{
-    const T w = e[0], u0 = e[1], u1 = e[2], u2 = e[3];
-    const T c = (gpar - gperp) * ((u0 * p0 + u1 * p1) + u2 * p2);
-    o0 = -(w * (gperp * p0 + c * u0));
-    o1 = -(w * (gperp * p1 + c * u1));
-    o2 = -(w * (gperp * p2 + c * u2));
-}
-
-// The pivot solve of a first-step vertex with at most one tree edge (a leaf,
-// or a lone vertex: w = 0): its pivot is P_qq = g_med I + W_e =
-// c I + d u u^T with c = g_med + w g_perp, d = w (g_par - g_perp), whose
-// inverse is I / c - d / (c (c + d)) u u^T (|u| = 1), so it needs no stored
-// inverse; a compressed vertex (two tree edges) uses its stored one.
-template <class T>
-SGP_DEV void leaf_pivot_solve(const T *e, T gpar, T gperp, T gmed, T b0, T b1, T b2, T &o0, T &o1, T &o2)
-{
-    const T w = e[0], u0 = e[1], u1 = e[2], u2 = e[3];
-    const T c = gmed + w * gperp, cd = gmed + w * gpar;
-    const T beta = (w * (gpar - gperp)) / (c * cd);
-    const T ub = beta * ((u0 * b0 + u1 * b1) + u2 * b2);
-    o0 = b0 / c - ub * u0;
-    o1 = b1 / c - ub * u1;
-    o2 = b2 / c - ub * u2;
 }
 
 // The first elimination step, couplings from (w, u) (planes of ws values):
@@ -1285,9 +1262,26 @@ __global__ void k_copy_vec(int64_t len, const T *a, T *b, const PcgScalars *s)
     if (i < len) b[i] = a[i];
 }
 
+// The first elimination step runs as launches of its own (k_fwd_step0,
+// k_bwd_step0): its vertices (elimination positions 0..q1-1) are then in the
+// internal order, since the schedule's sort is stable and gives them all the
+// same key.  Returns q1, or 0 where that step is swept otherwise (light
+// subtrees, grouped components, the tail) or the factor has no (w, u) table.
+int32_t prec_step0_launch(sgp_prec M)
+{
+    if (!M || M->kind != PREC_TREE || M->n_wu0 <= 0 || !M->step0_sorted || M->light_steps > 0 || M->tail_step <= 0)
+        return 0;
+    if ((int64_t)M->h_step_ptr.size() < 2 || M->n_wu0 != M->h_step_ptr[1]) return 0;
+    const int32_t m1 = std::min(M->mid_step0 + M->mid_steps, M->tail_step);
+    if (M->mid_steps > 0 && M->mid_step0 == 0 && m1 >= 2) return 0;
+    return M->h_step_ptr[1];
+}
+
+// skip0: leave out the first elimination step (both sweeps); the caller runs
+// it (the fused vector passes of the CG), only where prec_step0_launch > 0
 template <class T>
 static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y, T *cs, const T *r, T *z,
-                       PcgScalars *s, const T *wu0)
+                       PcgScalars *s, const T *wu0, bool skip0)
 {
     hipStream_t st = ctx->stream;
     // r and z are in the internal order
@@ -1317,6 +1311,7 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
             k = m1 - 1;
             continue;
         }
+        if (k == 0 && step0_wu && skip0) continue;
         if (k == 0 && step0_wu)
             k_fwd_step0<T><<<grid_for(q1, 256), 256, 0, st>>>(q1, elim, tout, wu0, 4 * (int64_t)q1, gp, gq, gm, Dinv,
                                                               r, y, cs, s);
@@ -1347,6 +1342,7 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
             k = m0;
             continue;
         }
+        if (k == 0 && step0_wu && skip0) continue;
         if (k == 0 && step0_wu)
             k_bwd_step0<T><<<grid_for(q1, 256), 256, 0, st>>>(q1, elim, upq, wu0, 4 * (int64_t)q1, gp, gq, gm, Dinv,
                                                               y, z, s);
@@ -1359,7 +1355,7 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
     return SGP_OK;
 }
 
-int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScalars *s)
+int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScalars *s, bool skip0)
 {
     hipStream_t st = ctx->stream;
     if (!M || M->kind == PREC_NONE) {
@@ -1373,10 +1369,11 @@ int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScala
         return SGP_OK;
     }
     return tree_sweeps<double>(ctx, M, (const double *)M->F.p, (const double *)M->Dinv.p, (double *)M->y.p,
-                               (double *)M->cs.p, r, z, s, M->n_wu0 > 0 ? (const double *)M->wu0.p : nullptr);
+                               (double *)M->cs.p, r, z, s, M->n_wu0 > 0 ? (const double *)M->wu0.p : nullptr,
+                               skip0 && prec_step0_launch(M) > 0);
 }
 
-int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s)
+int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s, bool skip0)
 {
     hipStream_t st = ctx->stream;
     if (M->kind == PREC_JACOBI) {
@@ -1385,7 +1382,8 @@ int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars
         return SGP_OK;
     }
     return tree_sweeps<float>(ctx, M, (const float *)M->F32.p, (const float *)M->Dinv32.p, (float *)M->y32.p,
-                              (float *)M->cs32.p, r, z, s, M->n_wu0 > 0 ? (const float *)M->wu032.p : nullptr);
+                              (float *)M->cs32.p, r, z, s, M->n_wu0 > 0 ? (const float *)M->wu032.p : nullptr,
+                              skip0 && prec_step0_launch(M) > 0);
 }
 
 __global__ void k_to_f32(int64_t len, const double *a, float *b)
@@ -1755,7 +1753,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     double *y;
     SGP_TRY(ensure_t(ctx, M->y, 3 * n + 3, &y));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP9], 4, &status));
-    SGP_TRY(fill_i32(ctx, status, 0, 1));
+    SGP_TRY(fill_i32(ctx, status, 0, 2));
     SGP_TRY(fill_f64(ctx, F, 0.0, 18 * n));
     k_tree_blocks<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)T->tptr.p, (const int32_t *)T->tadje.p,
                                                   (const int32_t *)T->pedge.p, (const double4 *)g->wu.p, g_par,
@@ -1772,6 +1770,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     // the first step's couplings in their (w, u) form (no light steps: with
     // them the first step runs inside the light-subtree sweeps)
     M->n_wu0 = 0;
+    M->step0_sorted = false;
     M->gpar = g_par;
     M->gperp = g_perp;
     M->gmed = g_med;
@@ -1781,6 +1780,9 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
         SGP_TRY(ensure_t(ctx, M->wu0, 8 * (size_t)q1 + 8, &w0));
         k_step0_wu<<<grid_for(q1, 256), 256, 0, st>>>(q1, elim, upq, (const int32_t *)T->pedge.p,
                                                       (const double4 *)g->wu.p, (double4 *)w0);
+        // the first step's positions ascend in the internal order (status[1]
+        // otherwise), which lets the CG's vector passes sweep that step
+        k_step0_sorted<<<grid_for(q1, 256), 256, 0, st>>>(q1, elim_int, status + 1);
         LAUNCH_CHECK(ctx);
         M->n_wu0 = q1;
     }
@@ -1793,9 +1795,10 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     k_slot_of<<<grid_for(2 * n, 256), 256, 0, st>>>(in_ptr + n, in_src, tout);
     LAUNCH_CHECK(ctx);
     SGP_TRY(tail_tables(ctx, M, n, in_ptr, in_src, tout));
-    SGP_TRY(readback(ctx, hbuf, status, 4));
+    SGP_TRY(readback(ctx, hbuf, status, 8));
     phase_end(ctx, 3);
     if (hbuf[0]) return set_err(ctx, SGP_ENOTSPD, "factor_tree: a pivot block is not positive definite");
+    M->step0_sorted = M->n_wu0 > 0 && hbuf[1] == 0;
     return SGP_OK;
 }
 

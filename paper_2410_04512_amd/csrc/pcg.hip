@@ -392,6 +392,201 @@ __global__ __launch_bounds__(256) void k_rz(const T *r, const T *z, BlockTab tab
     block_partial(rz, blockIdx.x, part, sh);
 }
 
+// The first elimination step of a tree preconditioner inside the two vector
+// passes around the sweeps.  Its vertices are the elimination positions
+// 0..q1-1, ascending in the internal order, so the block of rows of a vector
+// kernel holds the positions qr[2b]..qr[2b+1]-1 (at most one per thread).
+// r -= alpha q is followed by that step's forward substitution (the work of
+// k_fwd_step0), and r.z is preceded by its backward substitution (that of
+// k_bwd_step0), with r and z of the block's rows taken from LDS instead of
+// gathered: the same operations on the same values as the separate launches,
+// so results are bitwise unchanged.
+template <class T>
+struct Step0Tab {
+    const int32_t *qr, *elim, *tout, *upq;
+    const T *wu, *Dinv;
+    T *y, *cs;
+    int64_t ws;   // offset of the second (w, u) plane
+    T gpar, gperp, gmed;
+};
+
+// the positions of block b: qr[2b] = first position whose vertex is >= row0,
+// qr[2b + 1] the same for row1 (binary search over the ascending vertices)
+__global__ void k_step0_ranges(int32_t nb, BlockTab tab, const int32_t *elim, int32_t q1, int32_t *qr)
+{
+    const int32_t b = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b >= nb) return;
+    for (int k = 0; k < 2; k++) {
+        const int32_t row = k == 0 ? tab.row0[b] : tab.row1[b];
+        int32_t lo = 0, hi = q1;
+        while (lo < hi) {
+            const int32_t mid = lo + (hi - lo) / 2;
+            if (elim[mid] < row)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        qr[2 * b + k] = lo;
+    }
+}
+
+// r -= alpha q with the partial of ||r||^2, then the forward substitution of
+// the block's first-step vertices: y = P_qq^{-1} r and the pushes
+template <class T>
+__global__ __launch_bounds__(256) void k_update_r_s0(T *r, const T *q, BlockTab tab, const PcgScalars *S,
+                                                     double *part, Step0Tab<T> t)
+{
+    __shared__ double sh[256];
+    __shared__ T rl[3 * VEC_ROWS];
+    int inst;
+    int64_t e0;
+    const int ne = block_elems(tab, blockIdx.x, e0, inst);
+    const PcgScalars *Sc = S + inst;
+    if (Sc->done) return;
+    const int32_t qa = t.qr[2 * blockIdx.x], qb = t.qr[2 * blockIdx.x + 1];
+    T rv[VEC_EPT], qx[VEC_EPT];
+    if (ne > 0) {
+#pragma unroll
+        for (int u = 0; u < VEC_EPT; u++) {
+            rv[u] = r[e0 + vec_idx(u, ne)];
+            qx[u] = q[e0 + vec_idx(u, ne)];
+        }
+    }
+    // this thread's first-step vertex (a thread without one reads position 0
+    // and computes nothing)
+    const int32_t qs = qa + (int32_t)threadIdx.x;
+    const bool mine = qs < qb;
+    const int32_t qc = mine ? qs : 0;
+    const int64_t v = t.elim[qc];
+    const int32_t to0 = t.tout[2 * qc], to1 = t.tout[2 * qc + 1];
+    T w0[4], w1[4], d[6];
+    for (int k = 0; k < 4; k++) w0[k] = t.wu[4 * (int64_t)qc + k];
+    if (to1 >= 0) {   // a compressed vertex: second contact and stored pivot
+        for (int k = 0; k < 4; k++) w1[k] = t.wu[t.ws + 4 * (int64_t)qc + k];
+        for (int k = 0; k < 6; k++) d[k] = t.Dinv[6 * (int64_t)qc + k];
+    }
+    const T alpha = (T)Sc->alpha;
+    double rr = 0.0;
+    if (ne > 0) {
+#pragma unroll
+        for (int u = 0; u < VEC_EPT; u++)
+            if (vec_own(u, ne)) {
+                const T ri = rv[u] - alpha * qx[u];
+                r[e0 + vec_idx(u, ne)] = ri;
+                rl[threadIdx.x + 256 * u] = ri;
+                rr = rr + (double)ri * (double)ri;
+            }
+    }
+    __syncthreads();
+    if (mine) {
+        const int64_t i = 3 * (v - e0 / 3);
+        const T b0 = rl[i], b1 = rl[i + 1], b2 = rl[i + 2];
+        T o0, o1, o2;
+        if (to1 >= 0)
+            sym_mv(d, b0, b1, b2, o0, o1, o2);
+        else
+            leaf_pivot_solve(w0, t.gpar, t.gperp, t.gmed, b0, b1, b2, o0, o1, o2);
+        t.y[3 * (int64_t)qc] = o0;
+        t.y[3 * (int64_t)qc + 1] = o1;
+        t.y[3 * (int64_t)qc + 2] = o2;
+        if (to0 >= 0) {
+            T *c = t.cs + 3 * (int64_t)to0;
+            neg_w_mv(w0, t.gpar, t.gperp, o0, o1, o2, c[0], c[1], c[2]);
+        }
+        if (to1 >= 0) {
+            T *c = t.cs + 3 * (int64_t)to1;
+            neg_w_mv(w1, t.gpar, t.gperp, o0, o1, o2, c[0], c[1], c[2]);
+        }
+    }
+    block_partial(rr, blockIdx.x, part, sh);
+}
+
+// the backward substitution of the block's first-step vertices, x =
+// y - P_qq^{-1} (sum over up-links of W x), written to z; then the partial of
+// r.z over the block's rows
+template <class T>
+__global__ __launch_bounds__(256) void k_rz_s0(const T *r, T *z, BlockTab tab, const PcgScalars *S, double *part,
+                                               Step0Tab<T> t)
+{
+    __shared__ double sh[256];
+    __shared__ T zl[3 * VEC_ROWS];
+    int inst;
+    int64_t e0;
+    const int ne = block_elems(tab, blockIdx.x, e0, inst);
+    if (S[inst].done) return;
+    const int32_t qa = t.qr[2 * blockIdx.x], qb = t.qr[2 * blockIdx.x + 1];
+    T rv[VEC_EPT], zv[VEC_EPT];
+    if (ne > 0) {
+#pragma unroll
+        for (int u = 0; u < VEC_EPT; u++) {
+            rv[u] = r[e0 + vec_idx(u, ne)];
+            zv[u] = z[e0 + vec_idx(u, ne)];
+        }
+    }
+    const int32_t qs = qa + (int32_t)threadIdx.x;
+    const bool mine = qs < qb;
+    const int32_t qc = mine ? qs : 0;
+    const int32_t a0 = t.upq[2 * qc], a1 = t.upq[2 * qc + 1];
+    const int64_t v = t.elim[qc];
+    T w0[4], w1[4], d[6];
+    for (int k = 0; k < 4; k++) w0[k] = t.wu[4 * (int64_t)qc + k];
+    const T y0 = t.y[3 * (int64_t)qc], y1 = t.y[3 * (int64_t)qc + 1], y2 = t.y[3 * (int64_t)qc + 2];
+    const int64_t u0 = a0 >= 0 ? a0 : qc, u1 = a1 >= 0 ? a1 : qc;
+    const T p0 = t.y[3 * u0], p1 = t.y[3 * u0 + 1], p2 = t.y[3 * u0 + 2];
+    const T x0 = t.y[3 * u1], x1 = t.y[3 * u1 + 1], x2 = t.y[3 * u1 + 2];
+    if (a1 >= 0) {
+        for (int k = 0; k < 4; k++) w1[k] = t.wu[t.ws + 4 * (int64_t)qc + k];
+        for (int k = 0; k < 6; k++) d[k] = t.Dinv[6 * (int64_t)qc + k];
+    }
+    keep_loads_above();
+    // z of the block's rows as the sweeps left them (the first-step rows are
+    // overwritten below)
+    if (ne > 0) {
+#pragma unroll
+        for (int u = 0; u < VEC_EPT; u++)
+            if (vec_own(u, ne)) zl[threadIdx.x + 256 * u] = zv[u];
+    }
+    __syncthreads();
+    if (mine) {
+        T c0 = 0, c1 = 0, c2 = 0;
+        if (a0 >= 0) {
+            T e0_, e1_, e2_;
+            neg_w_mv(w0, t.gpar, t.gperp, p0, p1, p2, e0_, e1_, e2_);
+            c0 = c0 + e0_;
+            c1 = c1 + e1_;
+            c2 = c2 + e2_;
+        }
+        if (a1 >= 0) {
+            T e0_, e1_, e2_;
+            neg_w_mv(w1, t.gpar, t.gperp, x0, x1, x2, e0_, e1_, e2_);
+            c0 = c0 + e0_;
+            c1 = c1 + e1_;
+            c2 = c2 + e2_;
+        }
+        T s0, s1, s2;
+        if (a1 >= 0)
+            sym_mv(d, c0, c1, c2, s0, s1, s2);
+        else
+            leaf_pivot_solve(w0, t.gpar, t.gperp, t.gmed, c0, c1, c2, s0, s1, s2);
+        const T n0 = y0 - s0, n1 = y1 - s1, n2 = y2 - s2;
+        z[3 * v] = n0;
+        z[3 * v + 1] = n1;
+        z[3 * v + 2] = n2;
+        const int64_t i = 3 * (v - e0 / 3);
+        zl[i] = n0;
+        zl[i + 1] = n1;
+        zl[i + 2] = n2;
+    }
+    __syncthreads();
+    double rz = 0.0;
+    if (ne > 0) {
+#pragma unroll
+        for (int u = 0; u < VEC_EPT; u++)
+            if (vec_own(u, ne)) rz = rz + (double)rv[u] * (double)zl[threadIdx.x + 256 * u];
+    }
+    block_partial(rz, blockIdx.x, part, sh);
+}
+
 // x += alpha p, then p = z + beta p (p only while the solve goes on)
 template <class T>
 __global__ __launch_bounds__(256) void k_update_xp(T *x, T *p, const T *z, BlockTab tab, const PcgScalars *S)
@@ -499,6 +694,8 @@ struct PcgWork {
     const int32_t *mv_first = nullptr;   // {0}
     const int32_t *mv_nb_dev = nullptr;  // {mv_nb}
     int64_t K = 1;
+    int32_t s0_q1 = 0;               // > 0: the first elimination step runs in the vector passes
+    const int32_t *s0_qr = nullptr;  // its positions per vector block
 };
 
 template <class T>
@@ -519,6 +716,27 @@ template <class T>
 struct Vecs {
     T *x, *r, *z, *p, *q;
 };
+
+// the first step's tables of M in precision T
+template <class T>
+static Step0Tab<T> step0_tab(sgp_prec M, const PcgWork &w)
+{
+    const bool f64 = sizeof(T) == 8;
+    Step0Tab<T> t;
+    t.qr = w.s0_qr;
+    t.elim = (const int32_t *)M->elim_int.p;
+    t.tout = (const int32_t *)M->tout.p;
+    t.upq = (const int32_t *)M->up.p;
+    t.wu = (const T *)(f64 ? M->wu0.p : M->wu032.p);
+    t.Dinv = (const T *)(f64 ? M->Dinv.p : M->Dinv32.p);
+    t.y = (T *)(f64 ? M->y.p : M->y32.p);
+    t.cs = (T *)(f64 ? M->cs.p : M->cs32.p);
+    t.ws = 4 * (int64_t)w.s0_q1;
+    t.gpar = (T)M->gpar;
+    t.gperp = (T)M->gperp;
+    t.gmed = (T)M->gmed;
+    return t;
+}
 
 static int fin(sgp_ctx ctx, int op, const double *part, int nblk, const int32_t *ifirst, const int32_t *inb,
                PcgScalars *S, int64_t K)
@@ -559,14 +777,21 @@ static int pcg_chunk(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w, 
             SGP_TRY(fin(ctx, FIN_ALPHA, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
         }
         // partials: ||r||^2 in the first nb entries, r.z in the next nb
-        k_update_r<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.q, w.vec, S, part);
+        const bool s0 = M && w.s0_q1 > 0;
+        if (s0)
+            k_update_r_s0<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.q, w.vec, S, part, step0_tab<T>(M, w));
+        else
+            k_update_r<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.q, w.vec, S, part);
         if (M) {
             if (sizeof(T) == 8)
-                SGP_TRY(prec_apply_f64(ctx, M, (const double *)v.r, (double *)v.z, gate));
+                SGP_TRY(prec_apply_f64(ctx, M, (const double *)v.r, (double *)v.z, gate, s0));
             else
-                SGP_TRY(prec_apply_f32(ctx, M, (const float *)v.r, (float *)v.z, gate));
+                SGP_TRY(prec_apply_f32(ctx, M, (const float *)v.r, (float *)v.z, gate, s0));
         }
-        k_rz<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.z, w.vec, S, part + w.vec_nb);
+        if (s0)
+            k_rz_s0<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.z, w.vec, S, part + w.vec_nb, step0_tab<T>(M, w));
+        else
+            k_rz<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.z, w.vec, S, part + w.vec_nb);
         SGP_TRY(fin(ctx, FIN_RR_BETA, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
         k_update_xp<T><<<w.vec_nb, 256, 0, st>>>(v.x, v.p, v.z, w.vec, S);
         LAUNCH_CHECK(ctx);
@@ -674,7 +899,8 @@ static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w
 // the sweeps (their z is simply not used any more), only in the vector and
 // matrix kernels, which carry the per-cluster test.
 
-static int prepare_work(sgp_ctx ctx, sgp_bsr A, const std::vector<int64_t> &off, PcgWork &w)
+static int prepare_work(sgp_ctx ctx, sgp_bsr A, const std::vector<int64_t> &off, PcgWork &w,
+                        sgp_prec M = nullptr)
 {
     const int64_t K = (int64_t)off.size() - 1;
     w.K = K;
@@ -684,11 +910,20 @@ static int prepare_work(sgp_ctx ctx, sgp_bsr A, const std::vector<int64_t> &off,
     w.vec_buf.push_back(w.mv_nb);
     int32_t *d;
     size_t nv = w.vec_buf.size();
-    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP6], nv + 2, &d));
+    SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP6], nv + 2 + 2 * (size_t)w.vec_nb + 2, &d));
     SGP_TRY(upload(ctx, d, w.vec_buf.data(), nv * 4));
     w.vec = tab_ptrs(d, w.vec_nb, K);
     w.mv_first = d + nv - 2;
     w.mv_nb_dev = d + nv - 1;
+    const int32_t q1 = ctx->fuse_step0 ? prec_step0_launch(M) : 0;
+    if (q1 > 0 && M->n == A->n) {
+        int32_t *qr = d + nv + 2;
+        k_step0_ranges<<<grid_for(w.vec_nb, 256), 256, 0, ctx->stream>>>(w.vec_nb, w.vec,
+                                                                         (const int32_t *)M->elim_int.p, q1, qr);
+        LAUNCH_CHECK(ctx);
+        w.s0_q1 = q1;
+        w.s0_qr = qr;
+    }
     return SGP_OK;
 }
 
@@ -698,7 +933,7 @@ static int solve_f64(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<int64
     hipStream_t st = ctx->stream;
     const int64_t n = A->n, K = (int64_t)off.size() - 1;
     PcgWork w;
-    SGP_TRY(prepare_work(ctx, A, off, w));
+    SGP_TRY(prepare_work(ctx, A, off, w, M));
     double *r, *z, *p, *q, *part, *Fi, *xi;
     PcgScalars *S;
     int32_t *open;
@@ -797,7 +1032,7 @@ static int solve_ir(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const double *F, double 
     SGP_TRY(prec_make32(ctx, M));
     std::vector<int64_t> off = {0, n};
     PcgWork w;
-    SGP_TRY(prepare_work(ctx, A, off, w));
+    SGP_TRY(prepare_work(ctx, A, off, w, M));
     double *r64, *q64, *part, *Fi, *xi;
     float *r, *z, *p, *q, *d;
     PcgScalars *S;
@@ -1019,6 +1254,11 @@ extern "C" int sgp_tune(sgp_ctx ctx, const char *key, int32_t value)
         ctx->light_cap = value;
         return SGP_OK;
     }
+    if (!strcmp(key, "fuse_step0")) {
+        if (value < 0 || value > 1) return set_err(ctx, SGP_EINVAL, "tune: fuse_step0 must be 0 or 1");
+        ctx->fuse_step0 = value;
+        return SGP_OK;
+    }
     return set_err(ctx, SGP_EINVAL, "tune: unknown key '%s'", key);
 }
 
@@ -1032,6 +1272,7 @@ extern "C" int sgp_tune_get(sgp_ctx ctx, const char *key, int32_t *value)
     else if (!strcmp(key, "light_height")) *value = ctx->light_height;
     else if (!strcmp(key, "spmv_form")) *value = ctx->spmv_form;
     else if (!strcmp(key, "light_cap")) *value = ctx->light_cap;
+    else if (!strcmp(key, "fuse_step0")) *value = ctx->fuse_step0;
     else return set_err(ctx, SGP_EINVAL, "tune_get: unknown key '%s'", key);
     return SGP_OK;
 }

@@ -81,6 +81,7 @@ struct sgp_ctx_ {
     int use_graph = 0;             // replay a captured chunk of CG iterations as one hipGraph
     int spmv_waves = 4;            // waves per workgroup of the block-CSR product (2, 4 or 8)
     int spmv_form = 1;             // product from the 3x3 blocks (0) or from the contacts' (w, u) (1)
+    int fuse_step0 = 1;            // CG: first elimination step inside the vector passes around the sweeps
     int light_height = 0;          // rake rounds whose subtrees the sweeps handle one workgroup each (0: off)
     int light_cap = 512;           // vertices of such subtrees packed into one workgroup
     hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)
@@ -183,6 +184,7 @@ struct sgp_prec_ {
     // [2][n_wu0][4], read by the first step of the sweeps instead of F
     DevBuf wu0, wu032;
     int64_t n_wu0 = 0;
+    bool step0_sorted = false;   // positions 0..n_wu0-1 ascend in the internal order
     double gpar = 0, gperp = 0, gmed = 0;
     DevBuf F32, Dinv32, y32, cs32;                      // FP32 copies for the refinement inner solve
     bool have32 = false;
@@ -264,10 +266,11 @@ int iota_i32(sgp_ctx ctx, int32_t *p, int64_t n);
 
 // shared by several translation units
 // r, z in the internal order (used by the CG)
-int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScalars *s);
+int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScalars *s, bool skip0 = false);
 int permute_rows(sgp_ctx ctx, const int32_t *idx, const double *src, double *dst, int64_t n, int scatter);
 int copy_order(sgp_ctx ctx, DevBuf &dperm, DevBuf &dinv, const DevBuf &sperm, const DevBuf &sinv, int64_t n);
-int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s);
+int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s, bool skip0 = false);
+int32_t prec_step0_launch(sgp_prec M);
 // cells at most for sgp_prec_apply_noalloc (its static scratch holds two
 // [n][3] FP64 vectors: 48 MiB per device)
 constexpr int64_t NOALLOC_MAX_CELLS = (int64_t)1 << 20;
@@ -401,6 +404,35 @@ SGP_DEV void sym_mv(const T *s, T x0, T x1, T x2, T &y0, T &y1, T &y2)
     y0 = s[0] * x0 + s[1] * x1 + s[2] * x2;
     y1 = s[1] * x0 + s[3] * x1 + s[4] * x2;
     y2 = s[2] * x0 + s[4] * x1 + s[5] * x2;
+}
+
+// -W p for the block W = w (g_perp I + (g_par - g_perp) u u^T) of contact
+// e = (w, u): the coupling of a first-step vertex, from 4 values instead of 9
+template <class T>
+SGP_DEV void neg_w_mv(const T *e, T gpar, T gperp, T p0, T p1, T p2, T &o0, T &o1, T &o2)
+{
+    const T w = e[0], u0 = e[1], u1 = e[2], u2 = e[3];
+    const T c = (gpar - gperp) * ((u0 * p0 + u1 * p1) + u2 * p2);
+    o0 = -(w * (gperp * p0 + c * u0));
+    o1 = -(w * (gperp * p1 + c * u1));
+    o2 = -(w * (gperp * p2 + c * u2));
+}
+
+// The pivot solve of a first-step vertex with at most one tree edge (a leaf,
+// or a lone vertex: w = 0): its pivot is P_qq = g_med I + W_e =
+// c I + d u u^T with c = g_med + w g_perp, d = w (g_par - g_perp), whose
+// inverse is I / c - d / (c (c + d)) u u^T (|u| = 1), so it needs no stored
+// inverse; a compressed vertex (two tree edges) uses its stored one.
+template <class T>
+SGP_DEV void leaf_pivot_solve(const T *e, T gpar, T gperp, T gmed, T b0, T b1, T b2, T &o0, T &o1, T &o2)
+{
+    const T w = e[0], u0 = e[1], u1 = e[2], u2 = e[3];
+    const T c = gmed + w * gperp, cd = gmed + w * gpar;
+    const T beta = (w * (gpar - gperp)) / (c * cd);
+    const T ub = beta * ((u0 * b0 + u1 * b1) + u2 * b2);
+    o0 = b0 / c - ub * u0;
+    o1 = b1 / c - ub * u1;
+    o2 = b2 / c - ub * u2;
 }
 
 // c = a * b (full 3x3)

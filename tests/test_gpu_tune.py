@@ -264,3 +264,49 @@ def test_edge_form_with_isolated_cells(ctx):
         if s == 1:
             i = off[k]
             assert np.allclose(q1[i], 1e-3 * x[i], rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("n,seed", [(20000, 21), (60000, 22)])
+def test_fused_first_step_is_bitwise_neutral(ctx, n, seed):
+    """The first elimination step inside the CG's vector passes (knob
+    fuse_step0, on by default) gives the same bits as its own launches: FP64
+    from zero and from a warm start, and the FP32-inner refinement."""
+    c, g, A, T = _system(ctx, n, seed)
+    F = to_dev(c["force"])
+    M = ctx.factor_tree(g, T)
+    info = M.info()
+    # the first step runs as launches of its own here (below the tail, no light steps)
+    assert info["tail_step"] > 0 and info["light_steps"] == 0
+    assert ctx.tune_get("fuse_step0") == 1
+    x0 = torch.randn_like(F) * 1e-3
+    runs = {}
+    for fuse in (1, 0):
+        ctx.tune("fuse_step0", fuse)
+        runs[fuse] = (ctx.pcg_solve(A, M, F), ctx.pcg_solve(A, M, F, x0.clone(), use_x0=True),
+                      ctx.pcg_solve(A, M, F, precision="f32ir"))
+    for (va, ia), (vb, ib) in zip(runs[1], runs[0]):
+        assert ia["iters"] == ib["iters"] and ia.get("outer_iters") == ib.get("outer_iters")
+        assert torch.equal(va, vb)
+    ctx.tune("fuse_step0", 1)
+    with pytest.raises(P.SgpError):
+        ctx.tune("fuse_step0", 2)
+
+
+def test_fused_first_step_batched(ctx):
+    sizes = [3000, 500, 12000, 40, 25000, 1]
+    parts = [batched_instance(k + 1, n_override=s) for k, s in enumerate(sizes)]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = to_dev(np.concatenate([p["pos"] for p in parts]))
+    R = to_dev(np.concatenate([p["radius"] for p in parts]))
+    F = to_dev(np.concatenate([p["force"] for p in parts]))
+    g = ctx.collide_batched(off, pos, R)
+    A = ctx.assemble_gamma(g)
+    M = ctx.factor_tree(g, ctx.build_tree(g))
+    assert M.info()["tail_step"] > 0
+    v1, i1 = ctx.pcg_solve_batched(A, M, off, F)
+    ctx.tune("fuse_step0", 0)
+    v0, i0 = ctx.pcg_solve_batched(A, M, off, F)
+    ctx.tune("fuse_step0", 1)
+    assert [a["iters"] for a in i1] == [b["iters"] for b in i0]
+    assert all(a["status"] == 0 for a in i1)
+    assert torch.equal(v0, v1)
