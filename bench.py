@@ -148,26 +148,29 @@ def extra_augmented(ctx, g, T, A, F):
 
 def extra_small(P, dev, reps=30):
     """1000-cell workload (seed 0): latency of one solve and of the whole
-    pipeline, eager launches against hipGraph replay of the CG chunks."""
+    pipeline; the one-workgroup PCG (knob small_solve, the default) against
+    the launch-per-kernel path, eager and with hipGraph replay of the CG
+    chunks."""
     import numpy as np
     from workloads import sphere_cluster
     c = sphere_cluster(1000, 0)
     pos, R, F = dev(c["pos"]), dev(c["radius"]), dev(c["force"])
     ctx = P.Context()
     out = {"workload": "jittered FCC ball, 1000 spheres, seed 0"}
-    for graph in (0, 1):
+    for name, small, graph, ce in (("one_workgroup", 1, 0, 2), ("launches_graph0_check8", 0, 0, 8),
+                                   ("launches_graph1_check8", 0, 1, 8)):
+        ctx.tune("small_solve", small)
         ctx.tune("graph", graph)
-        for ce in (8, 32):
-            ctx.tune("check_every", ce)
-            ts, tp, iters = [], [], 0
-            for r in range(reps + 2):
-                t_all, (A, M, ts_) = _sync_time(lambda: _pipeline(ctx, pos, R, F))
-                if r >= 2:
-                    tp.append(t_all)
-                    ts.append(ts_[0])
-                    iters = ts_[1]
-            out[f"graph{graph}_check{ce}"] = {"solve_us": 1e6 * float(np.median(ts)),
-                                             "pipeline_us": 1e6 * float(np.median(tp)), "iters": iters}
+        ctx.tune("check_every", ce)
+        ts, tp, iters = [], [], 0
+        for r in range(reps + 2):
+            t_all, (A, M, ts_) = _sync_time(lambda: _pipeline(ctx, pos, R, F))
+            if r >= 2:
+                tp.append(t_all)
+                ts.append(ts_[0])
+                iters = ts_[1]
+        out[name] = {"solve_us": 1e6 * float(np.median(ts)), "pipeline_us": 1e6 * float(np.median(tp)),
+                     "iters": iters}
     ctx.close()
     return out
 

@@ -463,6 +463,13 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
  *                 r -= alpha q pass and its backward substitution inside the
  *                 r.z pass, on the rows each block of those passes holds
  *                 (default 1; 0: separate launches)
+ *  "small_solve"  1: sgp_pcg_solve of one FP64 system of at most 1024 cells
+ *                 with a tree preconditioner whose elimination lies wholly in
+ *                 the one-workgroup tail (tail_max >= n) runs every PCG
+ *                 iteration inside one workgroup, in one launch (at most
+ *                 20,000 iterations; default 1; 0: a launch per kernel).  Same
+ *                 product and sweeps; the dot products are summed in another
+ *                 order, so results agree to CG's rounding
  * Unknown keys or values out of range give SGP_EINVAL.  check_every,
  * graph and fuse_step0 leave every result bitwise unchanged, and so does tail_max as long as
  * the tail does not reach the first elimination step (that step forms its

@@ -22,7 +22,7 @@ OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["util.hip", "collide.hip", "assemble.hip", "spmv.hip", "tree.hip", "factor.hip", "pcg.hip",
-           "dynamics.hip", "mpnn.hip", "step.hip", "augment.hip", "api.hip"]
+           "dynamics.hip", "mpnn.hip", "step.hip", "augment.hip", "small.hip", "api.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -179,6 +179,7 @@ extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double
     hipStream_t st = ctx->stream;
     phase_begin(ctx, 1);
     const int64_t n = g->n, nnzb = n + 2 * g->m;
+    A->gen = next_gen();
     A->n = n;
     A->nnzb = nnzb;
     A->have32 = false;

@@ -1478,6 +1478,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     phase_begin(ctx, 3);
     const int64_t n = g->n;
     M->kind = PREC_TREE;
+    M->gen = next_gen();
     M->n = n;
     M->schedule = schedule;
     M->have32 = false;
@@ -1823,6 +1824,7 @@ extern "C" int sgp_make_jacobi(sgp_ctx ctx, sgp_bsr A, sgp_prec M)
     if (!ctx || !A || !M) return set_err(ctx, SGP_EINVAL, "make_jacobi: null handle");
     hipStream_t st = ctx->stream;
     M->kind = PREC_JACOBI;
+    M->gen = next_gen();
     M->n = A->n;
     M->steps = 0;
     M->have32 = false;

@@ -958,18 +958,24 @@ static int solve_f64(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<int64
     int max_iter = o->max_iter > 0 ? o->max_iter : 10000;
     k_set_scalars<<<grid_for(K, 256), 256, 0, st>>>(S, K, o->rtol * o->rtol, fixed, max_iter);
     LAUNCH_CHECK(ctx);
-    if (o->use_x0) SGP_TRY(spmv_f64(ctx, A, x, q, nullptr, nullptr, 0));
-    k_init_res<double><<<w.vec_nb, 256, 0, st>>>(F, q, x, r, o->use_x0, w.vec, part);
-    LAUNCH_CHECK(ctx);
-    SGP_TRY(fin(ctx, FIN_INIT, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
-    k_zero_rows<double><<<w.vec_nb, 256, 0, st>>>(x, w.vec, S, 2);
-    if (M) SGP_TRY(prec_apply_f64(ctx, M, r, z, nullptr));
-    k_init_p<double><<<w.vec_nb, 256, 0, st>>>(r, z, p, w.vec, S, part);
-    LAUNCH_CHECK(ctx);
-    SGP_TRY(fin(ctx, FIN_RHO, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
-    Vecs<double> v = {x, r, z, p, q};
-    int ce = o->check_every > 0 ? o->check_every : ctx->check_every;
-    SGP_TRY(pcg_iterate<double>(ctx, A, M, v, w, S, part, open, ce, max_iter, fixed));
+    // a small single system: every iteration inside one workgroup, one
+    // launch (bounded: at most 20,000 iterations in one launch)
+    if (K == 1 && small_solve_fits(ctx, A, M) && std::max(fixed, max_iter) <= 20000) {
+        SGP_TRY(solve_small(ctx, A, M, F, x, o, S));
+    } else {
+        if (o->use_x0) SGP_TRY(spmv_f64(ctx, A, x, q, nullptr, nullptr, 0));
+        k_init_res<double><<<w.vec_nb, 256, 0, st>>>(F, q, x, r, o->use_x0, w.vec, part);
+        LAUNCH_CHECK(ctx);
+        SGP_TRY(fin(ctx, FIN_INIT, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
+        k_zero_rows<double><<<w.vec_nb, 256, 0, st>>>(x, w.vec, S, 2);
+        if (M) SGP_TRY(prec_apply_f64(ctx, M, r, z, nullptr));
+        k_init_p<double><<<w.vec_nb, 256, 0, st>>>(r, z, p, w.vec, S, part);
+        LAUNCH_CHECK(ctx);
+        SGP_TRY(fin(ctx, FIN_RHO, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
+        Vecs<double> v = {x, r, z, p, q};
+        int ce = o->check_every > 0 ? o->check_every : ctx->check_every;
+        SGP_TRY(pcg_iterate<double>(ctx, A, M, v, w, S, part, open, ce, max_iter, fixed));
+    }
     // true residual
     SGP_TRY(spmv_f64(ctx, A, x, q, nullptr, nullptr, 0));
     k_true_res<<<w.vec_nb, 256, 0, st>>>(F, q, w.vec, part);
@@ -1254,6 +1260,11 @@ extern "C" int sgp_tune(sgp_ctx ctx, const char *key, int32_t value)
         ctx->light_cap = value;
         return SGP_OK;
     }
+    if (!strcmp(key, "small_solve")) {
+        if (value < 0 || value > 1) return set_err(ctx, SGP_EINVAL, "tune: small_solve must be 0 or 1");
+        ctx->small_solve = value;
+        return SGP_OK;
+    }
     if (!strcmp(key, "fuse_step0")) {
         if (value < 0 || value > 1) return set_err(ctx, SGP_EINVAL, "tune: fuse_step0 must be 0 or 1");
         ctx->fuse_step0 = value;
@@ -1273,6 +1284,7 @@ extern "C" int sgp_tune_get(sgp_ctx ctx, const char *key, int32_t *value)
     else if (!strcmp(key, "spmv_form")) *value = ctx->spmv_form;
     else if (!strcmp(key, "light_cap")) *value = ctx->light_cap;
     else if (!strcmp(key, "fuse_step0")) *value = ctx->fuse_step0;
+    else if (!strcmp(key, "small_solve")) *value = ctx->small_solve;
     else return set_err(ctx, SGP_EINVAL, "tune_get: unknown key '%s'", key);
     return SGP_OK;
 }

@@ -82,6 +82,7 @@ struct sgp_ctx_ {
     int spmv_waves = 4;            // waves per workgroup of the block-CSR product (2, 4 or 8)
     int spmv_form = 1;             // product from the 3x3 blocks (0) or from the contacts' (w, u) (1)
     int fuse_step0 = 1;            // CG: first elimination step inside the vector passes around the sweeps
+    int small_solve = 1;           // one-workgroup PCG for small single systems (small.hip)
     int light_height = 0;          // rake rounds whose subtrees the sweeps handle one workgroup each (0: off)
     int light_cap = 512;           // vertices of such subtrees packed into one workgroup
     hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)
@@ -124,6 +125,7 @@ struct sgp_graph_ {
 // distinct entries in 64-block groups (see spmv.hip for the layout).
 struct sgp_bsr_ {
     int64_t n = 0, nnzb = 0;
+    uint64_t gen = 0;   // new at every assembly (next_gen)
     DevBuf rowptr, bcol, val, val32, diagpos;   // internal order
     DevBuf perm, inv;                           // copy of the graph's order
     sgp_graph src = nullptr;                    // graph it was assembled from (canonical export)
@@ -162,6 +164,12 @@ enum { PREC_NONE = 0, PREC_JACOBI = 1, PREC_TREE = 2 };
 
 struct sgp_prec_ {
     int kind = PREC_NONE;
+    uint64_t gen = 0;   // new at every factorisation (next_gen)
+    // the one-workgroup solve's copy of a matrix's entries (small.hip), for
+    // the matrix of generation small_a_gen and this factor's generation
+    DevBuf small_ell;
+    uint64_t small_a_gen = 0, small_m_gen = 0;
+    int32_t small_deg = 0;
     int64_t n = 0;
     int schedule = 0;
     int32_t steps = 0;
@@ -271,6 +279,12 @@ int permute_rows(sgp_ctx ctx, const int32_t *idx, const double *src, double *dst
 int copy_order(sgp_ctx ctx, DevBuf &dperm, DevBuf &dinv, const DevBuf &sperm, const DevBuf &sinv, int64_t n);
 int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s, bool skip0 = false);
 int32_t prec_step0_launch(sgp_prec M);
+// a number no earlier call returned (generations of matrices and factors)
+uint64_t next_gen();
+// the whole PCG of one small system in one workgroup (small.hip)
+bool small_solve_fits(sgp_ctx ctx, sgp_bsr A, sgp_prec M);
+int solve_small(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const double *F, double *x, const sgp_solve_opts *o,
+                PcgScalars *S);
 // cells at most for sgp_prec_apply_noalloc (its static scratch holds two
 // [n][3] FP64 vectors: 48 MiB per device)
 constexpr int64_t NOALLOC_MAX_CELLS = (int64_t)1 << 20;

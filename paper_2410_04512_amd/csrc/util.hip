@@ -358,3 +358,9 @@ int copy_order(sgp_ctx ctx, DevBuf &dperm, DevBuf &dinv, const DevBuf &sperm, co
     }
     return SGP_OK;
 }
+
+uint64_t next_gen()
+{
+    static std::atomic<uint64_t> counter{0};
+    return ++counter;
+}
