@@ -46,19 +46,20 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a 512 MiB copy
 # read and write 512 MiB (summary and commands under profiles/).  Must be
 # re-measured, or set to None, whenever that kernel changes.
-SPMV_TRAFFIC_1M = {0: None, 1: 509.9e6}
+SPMV_TRAFFIC_1M = {0: None, 1: 418.0e6}
 
 
 def spmv_bytes(n: int, nnzb: int, form: int = 1, val_bytes: int = 48) -> int:
     """Algorithmic bytes of one product y = Gamma x as the library forms it.
     Blocks (form 0): every block's 6 distinct entries (the blocks are
     symmetric, 48 B in FP64) and its column index once.  Edge form (form 1):
-    every off-diagonal entry's (w, u) (32 B) and column once, every diagonal
-    block's 6 entries once.  Both: the row pointers once, x once, y once."""
+    every off-diagonal entry's v = sqrt(w) u (24 B) and column once, every
+    diagonal block's 6 entries once.  Both: the row pointers once, x once, y
+    once."""
     if form == 0:
         return nnzb * (val_bytes + 4) + 4 * (n + 1) + 24 * n + 24 * n
     ne = nnzb - n
-    return ne * (32 + 4) + n * 48 + 4 * (n + 1) + 24 * n + 24 * n
+    return ne * (24 + 4) + n * 48 + 4 * (n + 1) + 24 * n + 24 * n
 
 
 def cpu_baseline(c, gpu_iters: int, sample_iters: int = 10):

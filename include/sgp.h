@@ -444,8 +444,9 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
  *  "spmv_waves"   waves per workgroup of the product: 2, 4 or 8 (default 4)
  *  "spmv_form"    how the CG forms Gamma p: 0 from the stored 3x3 blocks,
  *                 1 from the contacts, D_i p_i - sum_j W_ij p_j with
- *                 W_ij p = w (g_perp p + (g_par - g_perp)(u.p) u) (default 1;
- *                 fewer bytes per product; sgp_spmv uses it too)
+ *                 W_ij p = g_perp (v.v) p + (g_par - g_perp)(v.p) v for the
+ *                 contact's v = sqrt(w) u (w u u^T = v v^T; default 1; fewer
+ *                 bytes per product; sgp_spmv uses it too)
  *  "light_height" CONTRACT schedule: the first light_height rounds remove
  *                 leaves only; the subtrees they remove are swept by one
  *                 workgroup each, in one launch per sweep (0..1024, 0 = plain

@@ -97,13 +97,13 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t n, const int32_t *rowp
             for (int x = 0; x < 9; x++) B[x] = -W[x];
             put_sym(val, k0 + c, B);
             bcol[k0 + c] = jc;
-            // edge form: entry k0 + c - i
+            // edge form: entry k0 + c - i keeps v = sqrt(w) u
             const int64_t ke = k0 + c - i;
-            double *g = ew + (ke >> 6) * 256 + (ke & 63);
-            g[0] = q.x;
-            g[64] = q.y;
-            g[128] = q.z;
-            g[192] = q.w;
+            double *g = ew + (ke >> 6) * (64 * EDGE_PLANES) + (ke & 63);
+            const double sw = sqrt(q.x);
+            g[0] = sw * q.y;
+            g[64] = sw * q.z;
+            g[128] = sw * q.w;
             ecol[ke] = jc;
         }
         for (int x = 0; x < 9; x++) sW[grp][c0][x] = W[x];
@@ -205,7 +205,7 @@ extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double
     // zero the padding of the last groups (read by no row, kept finite)
     SGP_TRY(fill_f64(ctx, val + (sym_group_size(nnzb) - 384), 0.0, 384));
     SGP_TRY(fill_f64(ctx, dg + (sym_group_size(n) - 384), 0.0, 384));
-    if (ne > 0) SGP_TRY(fill_f64(ctx, ew + (edge_group_size(ne) - 256), 0.0, 256));
+    if (ne > 0) SGP_TRY(fill_f64(ctx, ew + (edge_group_size(ne) - 64 * EDGE_PLANES), 0.0, 64 * EDGE_PLANES));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_DEG], n + 1, &deg));
     k_int_degree<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)g->rowptr.p, (const int32_t *)g->perm.p, deg);
     SGP_TRY(scan_exclusive(ctx, deg, brow, n));

@@ -133,8 +133,9 @@ struct sgp_bsr_ {
     DevBuf wrow;          // first row of every product wave
     // edge form of the same matrix (internal order): the off-diagonal entries
     // of row i are rowptr[i] - i + c (c < degree; the diagonal block is the
-    // last of every block row); per entry its column and (w, u) in 64-entry
-    // groups of 4 planes; the diagonal blocks as 64-row groups of 6 planes
+    // last of every block row); per entry its column and v = sqrt(w) u in
+    // 64-entry groups of EDGE_PLANES planes; the diagonal blocks as 64-row
+    // groups of 6 planes
     DevBuf ecol, ew, dg, ew32, dg32, ewrow;
     int64_t enwaves = 0;
     int64_t nwaves = 0;
@@ -142,7 +143,10 @@ struct sgp_bsr_ {
 };
 
 inline int64_t sym_group_size(int64_t nnzb) { return ((nnzb + 63) / 64) * 384; }   // values incl. padding
-inline int64_t edge_group_size(int64_t ne) { return ((ne + 63) / 64) * 256; }     // (w, u) incl. padding
+// the edge form keeps per entry v = sqrt(w) u of its contact (w = v.v), in
+// 64-entry groups of EDGE_PLANES planes
+constexpr int EDGE_PLANES = 3;
+inline int64_t edge_group_size(int64_t ne) { return ((ne + 63) / 64) * 64 * EDGE_PLANES; }   // v incl. padding
 
 struct sgp_tree_ {
     int64_t n = 0, nt = 0, n_roots = 0;
@@ -447,6 +451,19 @@ SGP_DEV void leaf_pivot_solve(const T *e, T gpar, T gperp, T gmed, T b0, T b1, T
     o0 = b0 / c - ub * u0;
     o1 = b1 / c - ub * u1;
     o2 = b2 / c - ub * u2;
+}
+
+// W_e p of the block W_e = w (g_perp I + (g_par - g_perp) u u^T) of a
+// contact stored as v = sqrt(w) u: W_e p = g_perp (v.v) p + (g_par - g_perp)
+// (v.p) v (eq. cell_cell_friction with w = v.v and w u u^T = v v^T)
+template <class T>
+SGP_DEV void edge_wp(T v0, T v1, T v2, T x0, T x1, T x2, T gpar, T gperp, T &o0, T &o1, T &o2)
+{
+    const T ww = gperp * ((v0 * v0 + v1 * v1) + v2 * v2);
+    const T c = (gpar - gperp) * ((v0 * x0 + v1 * x1) + v2 * x2);
+    o0 = ww * x0 + c * v0;
+    o1 = ww * x1 + c * v1;
+    o2 = ww * x2 + c * v2;
 }
 
 // c = a * b (full 3x3)

@@ -54,7 +54,7 @@ struct SmallArgs {
     int32_t n, S, ni;
     const int32_t *ecnt;    // entries of the row of each position
     const int32_t *ecol;    // [deg][SMALL_MAX] columns
-    const double *ew;       // [deg][4][SMALL_MAX] (w, u) planes
+    const double *ew;       // [deg][EDGE_PLANES][SMALL_MAX] v = sqrt(w) u planes
     const double *dg;
     double gpar, gperp;
     const int32_t *sp, *elim, *iptr, *tslot, *upq;
@@ -180,12 +180,12 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_pcg(SmallArgs A)
             // Loading both rows' chunks in one round measured slower.
             const int64_t z = c.q;
             for (int32_t base = 0; base < c.cnt; base += SMALL_CHUNK) {
-                double e[SMALL_CHUNK][4];
+                double e[SMALL_CHUNK][EDGE_PLANES];
                 int32_t j[SMALL_CHUNK];
 #pragma unroll
                 for (int s = 0; s < SMALL_CHUNK; s++) {
                     const int64_t sk = min(base + s, c.cnt - 1);
-                    for (int t = 0; t < 4; t++) e[s][t] = A.ew[(4 * sk + t) * SMALL_MAX + z];
+                    for (int t = 0; t < EDGE_PLANES; t++) e[s][t] = A.ew[(EDGE_PLANES * sk + t) * SMALL_MAX + z];
                     j[s] = A.ecol[sk * SMALL_MAX + z];
                 }
 #pragma unroll
@@ -193,11 +193,11 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_pcg(SmallArgs A)
                     if (base + s >= c.cnt) break;
                     const int64_t jj = j[s];
                     const double x0 = pv[3 * jj], x1 = pv[3 * jj + 1], x2 = pv[3 * jj + 2];
-                    const double w = e[s][0], u0 = e[s][1], u1 = e[s][2], u2 = e[s][3];
-                    const double cc = (A.gpar - A.gperp) * ((u0 * x0 + u1 * x1) + u2 * x2);
-                    q[u][0] -= w * (A.gperp * x0 + cc * u0);
-                    q[u][1] -= w * (A.gperp * x1 + cc * u1);
-                    q[u][2] -= w * (A.gperp * x2 + cc * u2);
+                    double o0, o1, o2;
+                    edge_wp(e[s][0], e[s][1], e[s][2], x0, x1, x2, A.gpar, A.gperp, o0, o1, o2);
+                    q[u][0] -= o0;
+                    q[u][1] -= o1;
+                    q[u][2] -= o2;
                 }
             }
         }
@@ -488,8 +488,8 @@ __global__ void k_small_ell(int32_t n, int32_t deg, const int32_t *elim, const i
     const int32_t v = elim[z];
     const int64_t k = (int64_t)rowptr[v] - v + s;
     ecol_out[(int64_t)s * SMALL_MAX + z] = ecol[k];
-    const double *g = ew + (k >> 6) * 256 + (k & 63);
-    for (int t = 0; t < 4; t++) ew_out[(int64_t)(4 * s + t) * SMALL_MAX + z] = g[64 * t];
+    const double *g = ew + (k >> 6) * (64 * EDGE_PLANES) + (k & 63);
+    for (int t = 0; t < EDGE_PLANES; t++) ew_out[(int64_t)(EDGE_PLANES * s + t) * SMALL_MAX + z] = g[64 * t];
 }
 
 // the factor's copy of the matrix entries, built when the matrix or the
@@ -506,9 +506,9 @@ static int small_ell(sgp_ctx ctx, sgp_bsr A, sgp_prec M)
     LAUNCH_CHECK(ctx);
     int32_t deg = 0;
     SGP_TRY(readback(ctx, &deg, tmp + SMALL_MAX, 4));
-    // [cnt: SMALL_MAX][ecol: deg x SMALL_MAX] int32, then [deg][4][SMALL_MAX] doubles
+    // [cnt: SMALL_MAX][ecol: deg x SMALL_MAX] int32, then [deg][EDGE_PLANES][SMALL_MAX] doubles
     const size_t ints = (size_t)(1 + deg) * SMALL_MAX;
-    const size_t bytes = 4 * ints + 8 * 4 * (size_t)deg * SMALL_MAX + 8;
+    const size_t bytes = 4 * ints + 8 * EDGE_PLANES * (size_t)deg * SMALL_MAX + 8;
     int32_t *e;
     SGP_TRY(ensure_t(ctx, M->small_ell, bytes / 4 + 2, &e));
     HIP_TRY(ctx, hipMemcpyAsync(e, tmp, 4 * SMALL_MAX, hipMemcpyDeviceToDevice, st));

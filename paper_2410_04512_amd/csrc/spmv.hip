@@ -190,11 +190,7 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_sym(const int32_t *__r
 template <class T>
 SGP_DEV void edge_product(T *a, int s, const T *e, T x0, T x1, T x2, T gpar, T gperp)
 {
-    const T w = e[0], u0 = e[1], u1 = e[2], u2 = e[3];
-    const T c = (gpar - gperp) * ((u0 * x0 + u1 * x1) + u2 * x2);
-    a[3 * s] = w * (gperp * x0 + c * u0);
-    a[3 * s + 1] = w * (gperp * x1 + c * u1);
-    a[3 * s + 2] = w * (gperp * x2 + c * u2);
+    edge_wp(e[0], e[1], e[2], x0, x1, x2, gpar, gperp, a[3 * s], a[3 * s + 1], a[3 * s + 2]);
 }
 
 template <class T, int SPMV_WAVES, bool EDGES>
@@ -225,14 +221,14 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_edge(const int32_t *__
     // EDGES = false: a product without entries (ne = 0), diagonal blocks only.
     const int64_t wc = min(w, nwaves - 1);
     int32_t r_lo = wrow[wc], r_hi = wrow[wc + 1];
-    T e[EDGE_GROUPS][4], xv[EDGE_GROUPS][3];
+    T e[EDGE_GROUPS][EDGE_PLANES], xv[EDGE_GROUPS][3];
     int64_t j[EDGE_GROUPS];
     if (EDGES) {
 #pragma unroll
         for (int q = 0; q < EDGE_GROUPS; q++) {
             const int64_t k = min(base + 64 * q + lane, ne - 1);
-            const T *g = ew + (k >> 6) * 256 + (k & 63);
-            for (int t = 0; t < 4; t++) e[q][t] = g[64 * t];
+            const T *g = ew + (k >> 6) * (64 * EDGE_PLANES) + (k & 63);
+            for (int t = 0; t < EDGE_PLANES; t++) e[q][t] = g[64 * t];
             j[q] = ecol[k];
         }
     }
@@ -266,9 +262,9 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_edge(const int32_t *__
     for (int64_t c = base + EDGE_BLOCKS; c < ke; c += 64) {
         const int64_t k = c + lane;
         if (k < ke) {
-            const T *g = ew + (c >> 6) * 256 + lane;
-            T ee[4];
-            for (int t = 0; t < 4; t++) ee[t] = g[64 * t];
+            const T *g = ew + (c >> 6) * (64 * EDGE_PLANES) + lane;
+            T ee[EDGE_PLANES];
+            for (int t = 0; t < EDGE_PLANES; t++) ee[t] = g[64 * t];
             const int64_t jj = ecol[k];
             edge_product(a, (int)(k - base), ee, x[3 * jj], x[3 * jj + 1], x[3 * jj + 2], gpar, gperp);
         }

@@ -27,13 +27,13 @@ def test_bench_refuses_more_than_one_gpu():
 def test_product_bytes_at_one_million_cells():
     # 1M-cell workload: n = 1,000,000 rows, m = 5,226,135 contacts, so
     # 10,452,270 off-diagonal entries and nnzb = n + 2m blocks.  Edge form:
-    # per entry (w, u) 32 B + column 4 B; per row a 6-entry diagonal block
+    # per entry v = sqrt(w) u 24 B + column 4 B; per row a 6-entry diagonal block
     # (48 B), a row pointer, x and y (24 B each), plus the final row pointer.
     sys.path.insert(0, ROOT)
     import bench
     n, m = 1_000_000, 5_226_135
     nnzb = n + 2 * m
-    assert bench.spmv_bytes(n, nnzb, form=1) == 476_281_724
+    assert bench.spmv_bytes(n, nnzb, form=1) == 392_663_564
     # block form: every block's 6 distinct FP64 entries and its column
     assert bench.spmv_bytes(n, nnzb, form=0) == 647_518_044
     # FP32 values halve the block bytes only
