@@ -464,6 +464,11 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
  *                 r -= alpha q pass and its backward substitution inside the
  *                 r.z pass, on the rows each block of those passes holds
  *                 (default 1; 0: separate launches)
+ *  "mid_lds"      1: the mid elimination steps (swept one workgroup per group
+ *                 of components) keep the group's push slots and x in LDS
+ *                 and load every constant once per launch (default 1; 0:
+ *                 through global memory, step by step); bitwise the same
+ *                 results
  *  "small_solve"  1: sgp_pcg_solve of one FP64 system of at most 1024 cells
  *                 with a tree preconditioner whose elimination lies wholly in
  *                 the one-workgroup tail (tail_max >= n) runs every PCG
@@ -472,7 +477,7 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
  *                 product and sweeps; the dot products are summed in another
  *                 order, so results agree to CG's rounding
  * Unknown keys or values out of range give SGP_EINVAL.  check_every,
- * graph and fuse_step0 leave every result bitwise unchanged, and so does tail_max as long as
+ * graph, fuse_step0 and mid_lds leave every result bitwise unchanged, and so does tail_max as long as
  * the tail does not reach the first elimination step (that step forms its
  * couplings from the contacts' (w, u) when it runs as its own launch, from
  * the stored blocks inside the tail: the same values up to rounding);

@@ -123,7 +123,7 @@ extern "C" void sgp_prec_free(sgp_prec M)
     release(M->tail_b); release(M->light_ptr); release(M->mid_ptr); release(M->wu0); release(M->wu032);
     release(M->jdinv);
     release(M->aug_piece); release(M->aug_list); release(M->aug_tptr); release(M->aug_tadj); release(M->aug_twu);
-    release(M->aug_ptr); release(M->aug_adj); release(M->aug_wu); release(M->small_ell);
+    release(M->aug_ptr); release(M->aug_adj); release(M->aug_wu); release(M->small_ell); release(M->mid_tab);
     delete M;
 }
 

@@ -1208,6 +1208,320 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
     }
 }
 
+// ---------------------------------------------------------------- mid steps in LDS
+
+// The mid steps (between the large first steps and the tail) split into
+// groups of components, one workgroup each
+// (mid_ptr); every push between mid vertices, and every read of x between
+// them, stays inside a group.  The sweeps below keep a group's push slots and
+// x values in LDS: a thread takes the group's local vertices tid and tid +
+// MID_THREADS (local order: by step, then position), loads all their
+// constants, their r and their slots filled by earlier launches at the start,
+// and then only LDS and barriers separate the steps.  Pushes to vertices
+// outside the group (later steps, the tail) and x of up-links outside it go
+// through global memory as before.  Same operations in the same order as
+// fwd_vertex / bwd_vertex, so results are bitwise unchanged.
+constexpr int MID_THREADS = 512;
+// vertices of one group at most (components are packed by their first
+// vertex's offset / light_cap, so a group can exceed light_cap by up to one
+// component less a vertex)
+constexpr int MID_LDS_MAX = 2 * MID_THREADS;
+
+// per mid vertex (index q - Q0): local index, first LDS slot and number of
+// in-entries from mid vertices; per push (2 (q - Q0) + k): its LDS slot or -1;
+// per up-link: the local index of a mid up-link or -1
+struct MidTab {
+    const int32_t *lid, *lin0, *nint, *lsl, *lup;
+};
+
+constexpr int MID_MAX_STEPS = 64;   // mid steps at most for the LDS sweeps
+
+// the group's position range of each of its L steps, rg[2k] .. rg[2k + 1],
+// loaded into LDS in one round (a walk over global memory would take a
+// dependent round trip per step); ends with a barrier
+SGP_DEV void mid_ranges(int32_t L, int32_t nwg, const int32_t *wptr, int32_t w, int32_t *rg)
+{
+    const int32_t t = threadIdx.x;
+    if (t < 2 * L) rg[t] = wptr[(int64_t)(t >> 1) * nwg + w + (t & 1)];
+    __syncthreads();
+}
+
+// position of local vertex l (ranges in LDS), and its step (-1: none)
+SGP_DEV int32_t mid_local(int32_t L, const int32_t *rg, int32_t l, int32_t &step)
+{
+    int32_t cum = 0;
+    step = -1;
+    int32_t q = 0;
+    for (int32_t k = 0; k < L; k++) {
+        const int32_t a = rg[2 * k], b = rg[2 * k + 1];
+        if (step < 0 && l < cum + (b - a)) {
+            step = k;
+            q = a + (l - cum);
+        }
+        cum += b - a;
+    }
+    return q;
+}
+
+__global__ void k_mid_nint(int32_t Q0, int32_t Q1, const int32_t *in_ptr, const int32_t *in_src, int32_t *nint)
+{
+    const int64_t q = Q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= Q1) return;
+    int32_t c = 0;
+    for (int32_t t = in_ptr[q]; t < in_ptr[q + 1]; t++) c += (in_src[t] >> 1) >= Q0 ? 1 : 0;
+    nint[q - Q0] = c;
+}
+
+// one workgroup per group: local indices and the first LDS slot of every
+// vertex's mid in-entries (exclusive sum in local order); flag: a group with
+// more than MID_LDS_MAX vertices or 2 MID_LDS_MAX slots
+__global__ __launch_bounds__(MID_THREADS) void k_mid_local(int32_t L, int32_t nwg, const int32_t *wptr, int32_t Q0,
+                                                           const int32_t *nint, int32_t *lid, int32_t *lin0,
+                                                           int32_t *flag)
+{
+    __shared__ int32_t cnt[MID_LDS_MAX], tot_sh[1], rg[2 * MID_MAX_STEPS];
+    const int32_t w = blockIdx.x, tid = threadIdx.x;
+    if (L > MID_MAX_STEPS) {
+        if (tid == 0) flag[0] = 1;
+        return;
+    }
+    mid_ranges(L, nwg, wptr, w, rg);
+    int32_t tot = 0;
+    for (int32_t k = 0; k < L; k++) tot += rg[2 * k + 1] - rg[2 * k];
+    if (tot > MID_LDS_MAX) {
+        if (tid == 0) flag[0] = 1;
+        return;
+    }
+    int32_t q[2], st[2];
+    for (int u = 0; u < 2; u++) {
+        const int32_t l = tid + MID_THREADS * u;
+        q[u] = mid_local(L, rg, l, st[u]);
+        cnt[l] = l < tot ? nint[q[u] - Q0] : 0;
+    }
+    __syncthreads();
+    if (tid == 0) {   // exclusive sum, in local order
+        int32_t s = 0;
+        for (int32_t l = 0; l < tot; l++) {
+            const int32_t c = cnt[l];
+            cnt[l] = s;
+            s += c;
+        }
+        tot_sh[0] = s;
+        if (s > 2 * MID_LDS_MAX) flag[0] = 1;
+    }
+    __syncthreads();
+    for (int u = 0; u < 2; u++) {
+        const int32_t l = tid + MID_THREADS * u;
+        if (l >= tot) continue;
+        lid[q[u] - Q0] = l;
+        lin0[q[u] - Q0] = cnt[l];
+    }
+}
+
+// LDS slot of every push between mid vertices (the target's mid in-entries
+// are the last of its in-list: sources ascend in elimination order)
+__global__ void k_mid_lsl(int32_t Q0, int32_t Q1, const int32_t *in_ptr, const int32_t *in_src, const int32_t *nint,
+                          const int32_t *lin0, int32_t *lsl)
+{
+    const int64_t q = Q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= Q1) return;
+    const int32_t ni = nint[q - Q0], f = in_ptr[q + 1] - ni, l0 = lin0[q - Q0];
+    for (int32_t j = 0; j < ni; j++) {
+        const int32_t src = in_src[f + j];
+        lsl[2 * (int64_t)((src >> 1) - Q0) + (src & 1)] = l0 + j;
+    }
+}
+
+__global__ void k_mid_lup(int32_t Q0, int32_t Q1, const int32_t *upq, const int32_t *lid, int32_t *lup)
+{
+    const int64_t q = Q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= Q1) return;
+    for (int k = 0; k < 2; k++) {
+        const int32_t a = upq[2 * q + k];
+        lup[2 * (q - Q0) + k] = a >= Q0 && a < Q1 ? lid[a - Q0] : -1;
+    }
+}
+
+// the forward sweep of the mid steps: y_q = Dinv_q (r_v - its slots), the
+// pushes to LDS (inside the group) or to cs (outside)
+template <class T>
+__global__ __launch_bounds__(MID_THREADS) void k_fwd_mid(int32_t L, int32_t nwg, const int32_t *wptr, int32_t Q0,
+                                                         const int32_t *elim, const int32_t *in_ptr,
+                                                         const int32_t *tout, const T *F, int64_t fs, const T *Dinv,
+                                                         const T *r, T *y, T *cs, MidTab tab, const PcgScalars *s)
+{
+    __shared__ T sl[3 * 2 * MID_LDS_MAX];
+    __shared__ int32_t rg[2 * MID_MAX_STEPS];
+    if (s && s->done) return;
+    const int32_t w = (int32_t)xcd_block(blockIdx.x, gridDim.x), tid = threadIdx.x;
+    mid_ranges(L, nwg, wptr, w, rg);
+    int32_t q[2], st[2], ni[2], l0[2], ls[2][2], to[2][2], t0[2], t1[2];
+    int64_t v[2];
+    T d[2][6], f0[2][9], f1[2][9], b[2][3], h[2][12];
+    // two rounds of loads for both vertices: what the position gives, then
+    // what those values address (r, the second coupling, the first four slots
+    // filled by earlier launches, clamped); one wait between them
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+        q[u] = mid_local(L, rg, tid + MID_THREADS * u, st[u]);
+        const int32_t qc = st[u] >= 0 ? q[u] : Q0;   // a thread without a vertex loads a valid one
+        v[u] = elim[qc];
+        t0[u] = in_ptr[qc];
+        t1[u] = in_ptr[qc + 1];
+        ni[u] = tab.nint[qc - Q0];
+        l0[u] = tab.lin0[qc - Q0];
+        for (int k = 0; k < 2; k++) {
+            to[u][k] = tout[2 * qc + k];
+            ls[u][k] = tab.lsl[2 * (int64_t)(qc - Q0) + k];
+        }
+        for (int t = 0; t < 6; t++) d[u][t] = Dinv[6 * (int64_t)qc + t];
+        for (int t = 0; t < 9; t++) f0[u][t] = F[9 * (int64_t)qc + t];
+    }
+    keep_loads_above();
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+        const int32_t qc = st[u] >= 0 ? q[u] : Q0;
+        b[u][0] = r[3 * v[u]];
+        b[u][1] = r[3 * v[u] + 1];
+        b[u][2] = r[3 * v[u] + 2];
+        // (the second plane is zero without a second link)
+        for (int t = 0; t < 9; t++) f1[u][t] = F[fs + 9 * (int64_t)qc + t];
+        const int32_t te = t1[u] - ni[u], last = te > t0[u] ? te - 1 : t0[u];
+        for (int m = 0; m < 4; m++) {
+            const T *c = cs + 3 * (int64_t)min(t0[u] + m, last);
+            h[u][3 * m] = c[0];
+            h[u][3 * m + 1] = c[1];
+            h[u][3 * m + 2] = c[2];
+        }
+    }
+    keep_loads_above();
+    // r minus the slots filled by earlier launches (the first in-entries), in
+    // slot order: the first four from h, any further ones loaded here
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+        const int32_t te = t1[u] - ni[u];
+        for (int m = 0; m < 4; m++)
+            if (t0[u] + m < te) {
+                b[u][0] = b[u][0] - h[u][3 * m];
+                b[u][1] = b[u][1] - h[u][3 * m + 1];
+                b[u][2] = b[u][2] - h[u][3 * m + 2];
+            }
+        if (t0[u] + 4 < te) sum_slots<T>(t0[u] + 4, te, cs, b[u][0], b[u][1], b[u][2]);
+    }
+    for (int32_t k = 0; k < L; k++) {
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            if (st[u] != k) continue;
+            T c0 = b[u][0], c1 = b[u][1], c2 = b[u][2];
+            for (int32_t j = 0; j < ni[u]; j++) {
+                const T *c = sl + 3 * (l0[u] + j);
+                c0 = c0 - c[0];
+                c1 = c1 - c[1];
+                c2 = c2 - c[2];
+            }
+            T o0, o1, o2;
+            sym_mv(d[u], c0, c1, c2, o0, o1, o2);
+            const int64_t qq = q[u];
+            y[3 * qq] = o0;
+            y[3 * qq + 1] = o1;
+            y[3 * qq + 2] = o2;
+            for (int m = 0; m < 2; m++) {
+                if (to[u][m] < 0) continue;
+                const T *g = m == 0 ? f0[u] : f1[u];
+                T *c = ls[u][m] >= 0 ? sl + 3 * ls[u][m] : cs + 3 * (int64_t)to[u][m];
+                c[0] = g[0] * o0 + g[1] * o1 + g[2] * o2;
+                c[1] = g[3] * o0 + g[4] * o1 + g[5] * o2;
+                c[2] = g[6] * o0 + g[7] * o1 + g[8] * o2;
+            }
+        }
+        // LDS only: the global stores (y, z, pushes out of the group) are
+        // read by no thread of this launch
+        lds_barrier();
+    }
+}
+
+// the backward sweep of the mid steps: x_q = y_q - Dinv_q (sum over up-links
+// of F^T x), x of a mid up-link from LDS, of others from y; x written to y
+// (for the steps below) and to z
+template <class T>
+__global__ __launch_bounds__(MID_THREADS) void k_bwd_mid(int32_t L, int32_t nwg, const int32_t *wptr, int32_t Q0,
+                                                         const int32_t *elim, const int32_t *upq, const T *F,
+                                                         int64_t fs, const T *Dinv, T *y, T *z, MidTab tab,
+                                                         const PcgScalars *s)
+{
+    __shared__ T xl[3 * MID_LDS_MAX];
+    __shared__ int32_t rg[2 * MID_MAX_STEPS];
+    if (s && s->done) return;
+    const int32_t w = (int32_t)xcd_block(blockIdx.x, gridDim.x), tid = threadIdx.x;
+    mid_ranges(L, nwg, wptr, w, rg);
+    int32_t q[2], st[2], lu[2][2], ua[2][2];
+    int64_t v[2];
+    T d[2][6], f0[2][9], f1[2][9], yo[2][3], xo[2][2][3];
+    // two rounds of loads for both vertices, one wait between them
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+        q[u] = mid_local(L, rg, tid + MID_THREADS * u, st[u]);
+        const int32_t qc = st[u] >= 0 ? q[u] : Q0;
+        v[u] = elim[qc];
+        for (int k = 0; k < 2; k++) {
+            ua[u][k] = upq[2 * qc + k];
+            lu[u][k] = tab.lup[2 * (int64_t)(qc - Q0) + k];
+        }
+        for (int t = 0; t < 6; t++) d[u][t] = Dinv[6 * (int64_t)qc + t];
+        for (int t = 0; t < 9; t++) f0[u][t] = F[9 * (int64_t)qc + t];
+        for (int t = 0; t < 9; t++) f1[u][t] = F[fs + 9 * (int64_t)qc + t];
+        for (int t = 0; t < 3; t++) yo[u][t] = y[3 * (int64_t)qc + t];
+    }
+    keep_loads_above();
+    // x of up-links outside the group (final: swept by earlier launches)
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+        const int32_t qc = st[u] >= 0 ? q[u] : Q0;
+        for (int k = 0; k < 2; k++) {
+            const int64_t a = ua[u][k] >= 0 && lu[u][k] < 0 ? ua[u][k] : qc;
+            for (int t = 0; t < 3; t++) xo[u][k][t] = y[3 * a + t];
+        }
+    }
+    for (int32_t k = L - 1; k >= 0; k--) {
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            if (st[u] != k) continue;
+            T a0 = 0, a1 = 0, a2 = 0;
+            for (int m = 0; m < 2; m++) {
+                if (ua[u][m] < 0) continue;
+                const T *g = m == 0 ? f0[u] : f1[u];
+                T x0 = xo[u][m][0], x1 = xo[u][m][1], x2 = xo[u][m][2];
+                if (lu[u][m] >= 0) {
+                    const T *xs = xl + 3 * lu[u][m];
+                    x0 = xs[0];
+                    x1 = xs[1];
+                    x2 = xs[2];
+                }
+                a0 = a0 + (g[0] * x0 + g[3] * x1 + g[6] * x2);
+                a1 = a1 + (g[1] * x0 + g[4] * x1 + g[7] * x2);
+                a2 = a2 + (g[2] * x0 + g[5] * x1 + g[8] * x2);
+            }
+            T e0, e1, e2;
+            sym_mv(d[u], a0, a1, a2, e0, e1, e2);
+            const T n0 = yo[u][0] - e0, n1 = yo[u][1] - e1, n2 = yo[u][2] - e2;
+            const int32_t l = tid + MID_THREADS * u;
+            xl[3 * l] = n0;
+            xl[3 * l + 1] = n1;
+            xl[3 * l + 2] = n2;
+            const int64_t qq = q[u];
+            y[3 * qq] = n0;
+            y[3 * qq + 1] = n1;
+            y[3 * qq + 2] = n2;
+            z[3 * v[u]] = n0;
+            z[3 * v[u] + 1] = n1;
+            z[3 * v[u] + 2] = n2;
+        }
+        // LDS only: the global stores (y, z, pushes out of the group) are
+        // read by no thread of this launch
+        lds_barrier();
+    }
+}
+
 int tail_setup_attr(sgp_ctx ctx)
 {
     static bool done = false;
@@ -1303,8 +1617,22 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
     const int32_t m0 = M->mid_step0, m1 = std::min(M->mid_step0 + M->mid_steps, ts);
     const bool mid = M->mid_steps > 0 && m0 >= L && m1 - m0 >= 2;
     const int32_t *mptr = (const int32_t *)M->mid_ptr.p;
+    // the mid steps in LDS when their tables were built (knob mid_lds)
+    const bool mid_lds = mid && M->mid_lds && ctx->mid_lds && m0 >= 1;
+    MidTab mtab = {};
+    if (mid_lds) {
+        const int32_t Nm = sp[m1] - sp[m0];
+        const int32_t *tb = (const int32_t *)M->mid_tab.p;
+        mtab = {tb, tb + Nm, tb + 2 * (size_t)Nm, tb + 3 * (size_t)Nm, tb + 5 * (size_t)Nm};
+    }
     for (int k = L; k < ts; k++) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
+        if (mid && k == m0 && mid_lds) {
+            k_fwd_mid<T><<<M->mid_nwg, MID_THREADS, 0, st>>>(m1 - m0, M->mid_nwg, mptr, sp[m0], elim, in_ptr, tout, F,
+                                                            fs, Dinv, r, y, cs, mtab, s);
+            k = m1 - 1;
+            continue;
+        }
         if (mid && k == m0) {
             k_fwd_light<T><<<M->mid_nwg, 256, 0, st>>>(m1 - m0, M->mid_nwg, mptr, elim, in_ptr, tout, F, fs, Dinv, r,
                                                        y, cs, s);
@@ -1337,6 +1665,12 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
     }
     for (int k = ts - 1; k >= L; k--) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
+        if (mid && k == m1 - 1 && mid_lds) {
+            k_bwd_mid<T><<<M->mid_nwg, MID_THREADS, 0, st>>>(m1 - m0, M->mid_nwg, mptr, sp[m0], elim, upq, F, fs, Dinv,
+                                                            y, z, mtab, s);
+            k = m0;
+            continue;
+        }
         if (mid && k == m1 - 1) {
             k_bwd_light<T><<<M->mid_nwg, 256, 0, st>>>(m1 - m0, M->mid_nwg, mptr, elim, upq, F, fs, Dinv, y, z, s);
             k = m0;
@@ -1460,6 +1794,34 @@ static int tail_tables(sgp_ctx ctx, sgp_prec M, int64_t n, const int32_t *in_ptr
     M->tail_ni = ni;
     if (tail_lds_bytes(8, nt, ni, M->steps - M->tail_step) > (size_t)TAIL_LDS_BYTES)
         return set_err(ctx, SGP_EINVAL, "factor_tree: tail does not fit in LDS (%d + %d)", nt, ni);
+    return SGP_OK;
+}
+
+// the tables of the LDS mid sweeps (MidTab); flag[0] set when a group is too
+// large for them (the caller then keeps the generic workgroup sweeps)
+static int mid_tables(sgp_ctx ctx, sgp_prec M, const int32_t *in_ptr, const int32_t *in_src, const int32_t *upq,
+                      int32_t *flag)
+{
+    hipStream_t st = ctx->stream;
+    M->mid_lds_built = false;
+    if (M->mid_steps <= 0 || M->light_steps > 0) return SGP_OK;
+    const int32_t m0 = M->mid_step0, m1 = std::min(M->mid_step0 + M->mid_steps, M->tail_step);
+    // (grouped from step 0: the local forest keeps its sweeps)
+    if (m1 - m0 < 2 || m1 - m0 > MID_MAX_STEPS || m0 < 1) return SGP_OK;
+    const int32_t Q0 = M->h_step_ptr[m0], Q1 = M->h_step_ptr[m1], Nm = Q1 - Q0;
+    if (Nm <= 0) return SGP_OK;
+    int32_t *tb;
+    SGP_TRY(ensure_t(ctx, M->mid_tab, 7 * (size_t)Nm + 8, &tb));
+    int32_t *lid = tb, *lin0 = tb + Nm, *nint = tb + 2 * (size_t)Nm, *lsl = tb + 3 * (size_t)Nm,
+            *lup = tb + 5 * (size_t)Nm;
+    SGP_TRY(fill_i32(ctx, lsl, -1, 2 * (int64_t)Nm));
+    k_mid_nint<<<grid_for(Nm, 256), 256, 0, st>>>(Q0, Q1, in_ptr, in_src, nint);
+    k_mid_local<<<M->mid_nwg, MID_THREADS, 0, st>>>(m1 - m0, M->mid_nwg, (const int32_t *)M->mid_ptr.p, Q0, nint, lid,
+                                                    lin0, flag);
+    k_mid_lsl<<<grid_for(Nm, 256), 256, 0, st>>>(Q0, Q1, in_ptr, in_src, nint, lin0, lsl);
+    k_mid_lup<<<grid_for(Nm, 256), 256, 0, st>>>(Q0, Q1, upq, lid, lup);
+    LAUNCH_CHECK(ctx);
+    M->mid_lds_built = true;
     return SGP_OK;
 }
 
@@ -1754,7 +2116,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     double *y;
     SGP_TRY(ensure_t(ctx, M->y, 3 * n + 3, &y));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP9], 4, &status));
-    SGP_TRY(fill_i32(ctx, status, 0, 2));
+    SGP_TRY(fill_i32(ctx, status, 0, 3));
     SGP_TRY(fill_f64(ctx, F, 0.0, 18 * n));
     k_tree_blocks<<<grid_for(n, 256), 256, 0, st>>>(n, (const int32_t *)T->tptr.p, (const int32_t *)T->tadje.p,
                                                   (const int32_t *)T->pedge.p, (const double4 *)g->wu.p, g_par,
@@ -1772,6 +2134,7 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     // them the first step runs inside the light-subtree sweeps)
     M->n_wu0 = 0;
     M->step0_sorted = false;
+    M->mid_lds = M->mid_lds_built = false;
     M->gpar = g_par;
     M->gperp = g_perp;
     M->gmed = g_med;
@@ -1796,10 +2159,12 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     k_slot_of<<<grid_for(2 * n, 256), 256, 0, st>>>(in_ptr + n, in_src, tout);
     LAUNCH_CHECK(ctx);
     SGP_TRY(tail_tables(ctx, M, n, in_ptr, in_src, tout));
-    SGP_TRY(readback(ctx, hbuf, status, 8));
+    SGP_TRY(mid_tables(ctx, M, in_ptr, in_src, upq, status + 2));
+    SGP_TRY(readback(ctx, hbuf, status, 12));
     phase_end(ctx, 3);
     if (hbuf[0]) return set_err(ctx, SGP_ENOTSPD, "factor_tree: a pivot block is not positive definite");
     M->step0_sorted = M->n_wu0 > 0 && hbuf[1] == 0;
+    M->mid_lds = M->mid_lds_built && hbuf[2] == 0;
     return SGP_OK;
 }
 

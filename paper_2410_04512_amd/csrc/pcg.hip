@@ -1260,6 +1260,11 @@ extern "C" int sgp_tune(sgp_ctx ctx, const char *key, int32_t value)
         ctx->light_cap = value;
         return SGP_OK;
     }
+    if (!strcmp(key, "mid_lds")) {
+        if (value < 0 || value > 1) return set_err(ctx, SGP_EINVAL, "tune: mid_lds must be 0 or 1");
+        ctx->mid_lds = value;
+        return SGP_OK;
+    }
     if (!strcmp(key, "small_solve")) {
         if (value < 0 || value > 1) return set_err(ctx, SGP_EINVAL, "tune: small_solve must be 0 or 1");
         ctx->small_solve = value;
@@ -1285,6 +1290,7 @@ extern "C" int sgp_tune_get(sgp_ctx ctx, const char *key, int32_t *value)
     else if (!strcmp(key, "light_cap")) *value = ctx->light_cap;
     else if (!strcmp(key, "fuse_step0")) *value = ctx->fuse_step0;
     else if (!strcmp(key, "small_solve")) *value = ctx->small_solve;
+    else if (!strcmp(key, "mid_lds")) *value = ctx->mid_lds;
     else return set_err(ctx, SGP_EINVAL, "tune_get: unknown key '%s'", key);
     return SGP_OK;
 }

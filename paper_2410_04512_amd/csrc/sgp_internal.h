@@ -83,6 +83,7 @@ struct sgp_ctx_ {
     int spmv_form = 1;             // product from the 3x3 blocks (0) or from the contacts' (w, u) (1)
     int fuse_step0 = 1;            // CG: first elimination step inside the vector passes around the sweeps
     int small_solve = 1;           // one-workgroup PCG for small single systems (small.hip)
+    int mid_lds = 1;               // tree sweeps: the mid steps' slots and x in LDS (factor.hip)
     int light_height = 0;          // rake rounds whose subtrees the sweeps handle one workgroup each (0: off)
     int light_cap = 512;           // vertices of such subtrees packed into one workgroup
     hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)
@@ -187,6 +188,8 @@ struct sgp_prec_ {
     DevBuf light_ptr;                                   // [light_steps * light_nwg + 1] first q of (step, workgroup)
     int32_t mid_step0 = 0, mid_steps = 0, mid_nwg = 0;  // steps mid_step0.. +mid_steps: components, one workgroup each
     DevBuf mid_ptr;                                     // [mid_steps * mid_nwg + 1] first q of (step, workgroup)
+    DevBuf mid_tab;                                     // tables of the LDS mid sweeps (factor.hip, MidTab)
+    bool mid_lds_built = false, mid_lds = false;        // built, and every group fits the LDS sweeps
     int32_t tail_step = 0;                              // steps >= tail_step run in one workgroup
     int32_t tail_nt = 0, tail_ni = 0;                   // tail vertices, tail-internal push slots
     DevBuf tail_iptr, tail_tslot;                       // per tail target: first internal slot; per (q,k): its slot

@@ -310,3 +310,47 @@ def test_fused_first_step_batched(ctx):
     assert [a["iters"] for a in i1] == [b["iters"] for b in i0]
     assert all(a["status"] == 0 for a in i1)
     assert torch.equal(v0, v1)
+
+
+@pytest.mark.parametrize("n,seed", [(60000, 41), (200000, 42)])
+def test_mid_steps_in_lds_are_bitwise_neutral(ctx, n, seed):
+    """The mid steps swept with their slots and x in LDS (knob mid_lds, on by
+    default) give the same bits as the generic workgroup sweeps: the apply,
+    the FP64 solve and the FP32 refinement."""
+    c, g, A, T = _system(ctx, n, seed)
+    F = to_dev(c["force"])
+    M = ctx.factor_tree(g, T)
+    info = M.info()
+    assert info["tail_step"] >= 6 and info["light_steps"] == 0   # mid steps exist below the tail
+    b = torch.randn_like(F)
+    runs = {}
+    for on in (1, 0):
+        ctx.tune("mid_lds", on)
+        runs[on] = (ctx.prec_apply(M, b), ctx.pcg_solve(A, M, F), ctx.pcg_solve(A, M, F, precision="f32ir"))
+    ctx.tune("mid_lds", 1)
+    assert torch.equal(runs[1][0], runs[0][0])
+    for (va, ia), (vb, ib) in zip(runs[1][1:], runs[0][1:]):
+        assert ia["iters"] == ib["iters"] and torch.equal(va, vb)
+    if n <= 60000:   # and the apply against the oracle's tree solve
+        og = O.collide(c["pos"], c["radius"])
+        z = O.tree_solve(O.tree_factor(og, O.build_tree(og)), host(b))
+        assert np.linalg.norm(host(runs[1][0]) - z) <= 1e-10 * np.linalg.norm(z)
+
+
+def test_mid_steps_in_lds_batched(ctx):
+    sizes = [40000, 3000, 70000, 500]
+    parts = [batched_instance(k + 11, n_override=s) for k, s in enumerate(sizes)]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = to_dev(np.concatenate([p["pos"] for p in parts]))
+    R = to_dev(np.concatenate([p["radius"] for p in parts]))
+    F = to_dev(np.concatenate([p["force"] for p in parts]))
+    g = ctx.collide_batched(off, pos, R)
+    A = ctx.assemble_gamma(g)
+    M = ctx.factor_tree(g, ctx.build_tree(g))
+    v1, i1 = ctx.pcg_solve_batched(A, M, off, F)
+    ctx.tune("mid_lds", 0)
+    v0, i0 = ctx.pcg_solve_batched(A, M, off, F)
+    ctx.tune("mid_lds", 1)
+    assert [a["iters"] for a in i1] == [b["iters"] for b in i0]
+    assert all(a["status"] == 0 for a in i1)
+    assert torch.equal(v0, v1)
