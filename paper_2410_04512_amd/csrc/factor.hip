@@ -925,6 +925,9 @@ static size_t tail_lds_bytes(size_t elem, int64_t nt, int64_t ni, int64_t nsteps
 // holds at least one vertex, so 3 * 8 * 3 nt + 4 (nt + 1) bytes always suffice
 constexpr int TAIL_MAX_VERTICES = (TAIL_LDS_BYTES - 4) / 76;
 constexpr int TAIL_DEFAULT_VERTICES = 2200;   // the tail_max knob's default
+// right-hand-side values a tail thread loads: 3 per vertex, up to the most
+// vertices the tail holds
+constexpr int TAIL_RHS_PER_THREAD = (3 * TAIL_MAX_VERTICES + TAIL_THREADS - 1) / TAIL_THREADS;
 constexpr int64_t MID_MAX_VERTICES = 1 << 17;   // vertices left at the first mid step at most
 
 // The tail's right-hand sides before its first step: r minus the pushes from
@@ -1061,12 +1064,21 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
         const int32_t q = Qt + tid < q1a - 1 ? Qt + tid : q1a - 1;
         tail_load_fwd(pa, q, q - Qt, tslot, iptr, F, fs, Dinv);
     }
+    // the step bounds and the right-hand sides with the pre-tail
+    // contributions (k_tail_pre), loaded with the constants above (clamped,
+    // surplus unused) so that one wait covers them all
+    int32_t spv = sp_g[min(s0 + tid, S)];
+    T tbv[TAIL_RHS_PER_THREAD];
+#pragma unroll
+    for (int m = 0; m < TAIL_RHS_PER_THREAD; m++) tbv[m] = tb[min(tid + TAIL_THREADS * m, 3 * nt - 1)];
     keep_loads_above();
     if (dn) return;   // uniform: the whole workgroup leaves
-    for (int32_t k = s0 + tid; k <= S; k += TAIL_THREADS) ssp[k] = sp_g[k];
+    if (s0 + tid <= S) ssp[s0 + tid] = spv;
+    for (int32_t k = s0 + tid + TAIL_THREADS; k <= S; k += TAIL_THREADS) ssp[k] = sp_g[k];
     const int32_t *sp = ssp;
-    // right-hand sides with the pre-tail contributions (k_tail_pre)
-    for (int32_t i = tid; i < 3 * nt; i += TAIL_THREADS) sv[i] = tb[i];
+#pragma unroll
+    for (int m = 0; m < TAIL_RHS_PER_THREAD; m++)
+        if (tid + TAIL_THREADS * m < 3 * nt) sv[tid + TAIL_THREADS * m] = tbv[m];
     lds_barrier();
     // forward: y_q = Dinv_q (b_q - its in-slots), pushes F_q y_q to its
     // up-links' slots
