@@ -440,10 +440,12 @@ __global__ __launch_bounds__(256) void k_update_r_s0(T *r, const T *q, BlockTab 
     __shared__ T rl[3 * VEC_ROWS];
     int inst;
     int64_t e0;
-    const int ne = block_elems(tab, blockIdx.x, e0, inst);
+    // XCD-contiguous rows: the pushes of an XCD's blocks land in one region
+    const int b = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int ne = block_elems(tab, b, e0, inst);
     const PcgScalars *Sc = S + inst;
     if (Sc->done) return;
-    const int32_t qa = t.qr[2 * blockIdx.x], qb = t.qr[2 * blockIdx.x + 1];
+    const int32_t qa = t.qr[2 * b], qb = t.qr[2 * b + 1];
     T rv[VEC_EPT], qx[VEC_EPT];
     if (ne > 0) {
 #pragma unroll
@@ -498,7 +500,7 @@ __global__ __launch_bounds__(256) void k_update_r_s0(T *r, const T *q, BlockTab 
             neg_w_mv(w1, t.gpar, t.gperp, o0, o1, o2, c[0], c[1], c[2]);
         }
     }
-    block_partial(rr, blockIdx.x, part, sh);
+    block_partial(rr, b, part, sh);
 }
 
 // the backward substitution of the block's first-step vertices, x =
@@ -512,9 +514,11 @@ __global__ __launch_bounds__(256) void k_rz_s0(const T *r, T *z, BlockTab tab, c
     __shared__ T zl[3 * VEC_ROWS];
     int inst;
     int64_t e0;
-    const int ne = block_elems(tab, blockIdx.x, e0, inst);
+    // XCD-contiguous rows: the up-links an XCD's blocks read stay in its L2
+    const int b = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int ne = block_elems(tab, b, e0, inst);
     if (S[inst].done) return;
-    const int32_t qa = t.qr[2 * blockIdx.x], qb = t.qr[2 * blockIdx.x + 1];
+    const int32_t qa = t.qr[2 * b], qb = t.qr[2 * b + 1];
     T rv[VEC_EPT], zv[VEC_EPT];
     if (ne > 0) {
 #pragma unroll
@@ -584,7 +588,7 @@ __global__ __launch_bounds__(256) void k_rz_s0(const T *r, T *z, BlockTab tab, c
         for (int u = 0; u < VEC_EPT; u++)
             if (vec_own(u, ne)) rz = rz + (double)rv[u] * (double)zl[threadIdx.x + 256 * u];
     }
-    block_partial(rz, blockIdx.x, part, sh);
+    block_partial(rz, b, part, sh);
 }
 
 // x += alpha p, then p = z + beta p (p only while the solve goes on)
