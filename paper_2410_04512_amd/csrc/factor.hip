@@ -911,6 +911,7 @@ __global__ __launch_bounds__(256) void k_bwd_light(int32_t L, int32_t nwg, const
 // are separated by LDS-only barriers: the next step's prefetched loads stay
 // in flight across them.
 constexpr int TAIL_THREADS = 512;
+constexpr int TAIL_WINDOW = 2 * TAIL_THREADS;   // tail vertices whose constants stay in registers
 constexpr int TAIL_SLOTS = 4;   // LDS reads of in-slots issued together
 constexpr int TAIL_LDS_BYTES = 160 * 1024;
 
@@ -1021,12 +1022,14 @@ SGP_DEV void tail_load_reg(TailReg<T> &p, int32_t q, int32_t i, const int32_t *t
 }
 
 // The tail's steps fall in two parts.  Steps whose vertices all lie in the
-// last TAIL_THREADS tail vertices (the window, from step kw on: usually most
-// of the steps, few vertices each) give vertex base + t to thread t, whose
-// constants are loaded once per launch for both sweeps, so these steps touch
-// no global memory but the backward sweep's stores.  The steps before kw
-// (fewer, larger) give their vertices to threads in order, and a thread's
-// first vertex of the next step is loaded while a step runs.
+// last TAIL_WINDOW tail vertices (the window, from step kw on: usually most
+// of the steps, few vertices each) give vertices base + t and base +
+// TAIL_THREADS + t to thread t, whose constants are loaded once per launch
+// for both sweeps, so these steps touch no global memory but the backward
+// sweep's stores.  The steps before kw (one or two, large) give their
+// vertices to threads in order; a thread's first vertex of the first such
+// step of each sweep is loaded ahead (while the prologue or the window's
+// steps run), the others when their step comes.
 template <class T>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, int32_t kw, int32_t Qt, int32_t q1a,
                                                        int32_t nt, int32_t ni, const int32_t *sp_g, const int32_t *elim,
@@ -1042,14 +1045,15 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
     int32_t *ssp = (int32_t *)(slot + 3 * ni) - s0;
     const int32_t dn = done_flag(s);
     const int tid = threadIdx.x;
-    // the window's vertex of this thread (clamped: a thread past the end
+    // the window's vertices of this thread (clamped: a thread past the end
     // loads the last vertex and never uses it)
-    const int32_t base = nt > TAIL_THREADS ? nt - TAIL_THREADS : 0;
-    const int32_t ir = base + tid;
-    TailReg<T> R;
+    const int32_t base = nt > TAIL_WINDOW ? nt - TAIL_WINDOW : 0;
+    const int32_t ir0 = base + tid, ir1 = base + TAIL_THREADS + tid;
+    TailReg<T> R0, R1;
     {
-        const int32_t i = ir < nt ? ir : nt - 1;
-        tail_load_reg(R, Qt + i, i, tslot, iptr, upq, elim, F, fs, Dinv);
+        const int32_t i0 = ir0 < nt ? ir0 : nt - 1, i1 = ir1 < nt ? ir1 : nt - 1;
+        tail_load_reg(R0, Qt + i0, i0, tslot, iptr, upq, elim, F, fs, Dinv);
+        tail_load_reg(R1, Qt + i1, i1, tslot, iptr, upq, elim, F, fs, Dinv);
     }
     // a thread's first vertex of step k, clamped into the step
     auto vtx = [&](const int32_t *b, int32_t k) {
@@ -1059,7 +1063,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
     };
     // the first step's first vertices (q1a: the end of step s0 when it lies
     // before the window, else Qt + 1), addressed from the arguments alone
-    TailPre<T> pa, pb;
+    TailPre<T> pa;
     {
         const int32_t q = Qt + tid < q1a - 1 ? Qt + tid : q1a - 1;
         tail_load_fwd(pa, q, q - Qt, tslot, iptr, F, fs, Dinv);
@@ -1124,20 +1128,17 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
     auto fwd_pre = [&](int32_t q, const TailPre<T> &c) {
         fwd_one(q - Qt, c.d, c.f0, c.f1, c.a0, c.a1, c.b0, c.b1);
     };
-    // A step before the window: the thread's first vertex from `cur`
-    // (prefetched), further ones loaded here; the next step's first vertex is
-    // prefetched into `nxt` on every path (a thread without a vertex there
-    // loads the step's last one, the last such step reloads its own), so
-    // every path leaves the same loads in flight and the compiler's wait
-    // counts stay partial.
-    auto fstep = [&](int32_t k, TailPre<T> &cur, TailPre<T> &nxt) {
-        {
-            const int32_t q = vtx(sp, k + 1 < kw ? k + 1 : k);
-            tail_load_fwd(nxt, q, q - Qt, tslot, iptr, F, fs, Dinv);
+    // A step before the window: the thread's first vertex from pa (loaded
+    // ahead for the first such step, here for later ones), further ones
+    // loaded here.
+    auto fstep = [&](int32_t k) {
+        if (k > s0) {
+            const int32_t q = vtx(sp, k);
+            tail_load_fwd(pa, q, q - Qt, tslot, iptr, F, fs, Dinv);
         }
         const int32_t q1 = sp[k + 1];
         int32_t q = sp[k] + tid;
-        if (q < q1) fwd_pre(q, cur);
+        if (q < q1) fwd_pre(q, pa);
         for (q += TAIL_THREADS; q < q1; q += TAIL_THREADS) {
             TailPre<T> extra;
             tail_load_fwd(extra, q, q - Qt, tslot, iptr, F, fs, Dinv);
@@ -1145,13 +1146,11 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
         }
         lds_barrier();
     };
-    for (int32_t k = s0; k < kw; k += 2) {
-        fstep(k, pa, pb);
-        if (k + 1 < kw) fstep(k + 1, pb, pa);
-    }
+    for (int32_t k = s0; k < kw; k++) fstep(k);
     for (int32_t k = kw; k < S; k++) {
-        if (ir >= sp[k] - Qt && ir < sp[k + 1] - Qt)
-            fwd_one(ir, R.d, R.f0, R.f1, R.slot0, R.slot1, R.in0, R.in1);
+        const int32_t lo = sp[k] - Qt, hi = sp[k + 1] - Qt;
+        if (ir0 >= lo && ir0 < hi) fwd_one(ir0, R0.d, R0.f0, R0.f1, R0.slot0, R0.slot1, R0.in0, R0.in1);
+        if (ir1 >= lo && ir1 < hi) fwd_one(ir1, R1.d, R1.f0, R1.f1, R1.slot0, R1.slot1, R1.in0, R1.in1);
         lds_barrier();
     }
     // backward: x_q = y_q - Dinv_q (sum over up-links of F^T x), also written
@@ -1196,17 +1195,19 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
         tail_load_bwd(pa, q, upq, elim, F, fs, Dinv);
     }
     for (int32_t k = S - 1; k >= kw; k--) {
-        if (ir >= sp[k] - Qt && ir < sp[k + 1] - Qt) bwd_one(ir, R.d, R.f0, R.f1, R.up0, R.up1, R.id);
+        const int32_t lo = sp[k] - Qt, hi = sp[k + 1] - Qt;
+        if (ir0 >= lo && ir0 < hi) bwd_one(ir0, R0.d, R0.f0, R0.f1, R0.up0, R0.up1, R0.id);
+        if (ir1 >= lo && ir1 < hi) bwd_one(ir1, R1.d, R1.f0, R1.f1, R1.up0, R1.up1, R1.id);
         lds_barrier();
     }
-    auto bstep = [&](int32_t k, TailPre<T> &cur, TailPre<T> &nxt) {
-        {
-            const int32_t q = vtx(sp, k - 1 >= s0 ? k - 1 : k);
-            tail_load_bwd(nxt, q, upq, elim, F, fs, Dinv);
+    auto bstep = [&](int32_t k) {
+        if (k < kw - 1) {
+            const int32_t q = vtx(sp, k);
+            tail_load_bwd(pa, q, upq, elim, F, fs, Dinv);
         }
         const int32_t q1 = sp[k + 1];
         int32_t q = sp[k] + tid;
-        if (q < q1) bwd_pre(q, cur);
+        if (q < q1) bwd_pre(q, pa);
         for (q += TAIL_THREADS; q < q1; q += TAIL_THREADS) {
             TailPre<T> extra;
             tail_load_bwd(extra, q, upq, elim, F, fs, Dinv);
@@ -1214,10 +1215,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
         }
         lds_barrier();
     };
-    for (int32_t k = kw - 1; k >= s0; k -= 2) {
-        bstep(k, pa, pb);
-        if (k - 1 >= s0) bstep(k - 1, pb, pa);
-    }
+    for (int32_t k = kw - 1; k >= s0; k--) bstep(k);
 }
 
 // ---------------------------------------------------------------- mid steps in LDS
@@ -1666,8 +1664,8 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
         T *tb = (T *)M->tail_b.p;
         k_tail_pre<T><<<(nt + 63) / 64, 64, 0, st>>>(sp[ts], nt, elim, in_ptr, (const int32_t *)M->tail_iptr.p, r, cs,
                                                     tb, s);
-        // the first step whose vertices all lie in the last TAIL_THREADS tail vertices
-        const int32_t base = nt > TAIL_THREADS ? nt - TAIL_THREADS : 0;
+        // the first step whose vertices all lie in the last TAIL_WINDOW tail vertices
+        const int32_t base = nt > TAIL_WINDOW ? nt - TAIL_WINDOW : 0;
         int32_t kw = ts;
         while (kw < S && sp[kw] - sp[ts] < base) kw++;
         const int32_t q1a = kw > ts ? sp[ts + 1] : sp[ts] + 1;
