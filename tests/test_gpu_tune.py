@@ -162,14 +162,16 @@ def test_light_subtree_sweeps_match_oracle(ctx, lh, cap):
     assert i32["status"] == 0 and i32["relres_true"] <= 1.0001e-8
 
 
-@pytest.mark.parametrize("cap,tail", [(1, 2200), (64, 2200), (512, 2200), (512, 256), (512, 0)])
+@pytest.mark.parametrize("cap,tail", [(1, 2200), (64, 2200), (512, 2200), (512, 256), (512, 0), (4096, 2200)])
 def test_mid_step_sweeps_match_oracle(ctx, cap, tail):
     """The mid elimination steps swept one workgroup per group of components
     (60k cells: steps from the third on, up to the default tail), with one
-    component per workgroup, small and default packing, and with the tail
-    smaller than the default (steps between the mid range and the tail as
-    launches of their own) or off: the tree solve against the oracle's, FP64
-    and FP32, a converged CG, and results that do not depend on the tail."""
+    component per workgroup, small and default packing, groups too large for
+    the LDS sweeps (4,096-vertex packing: the generic workgroup sweeps run),
+    and with the tail smaller than the default (steps between the mid range
+    and the tail as launches of their own) or off: the tree solve against the
+    oracle's, FP64 and FP32, a converged CG, and results that do not depend on
+    the tail."""
     c, g, A, T = _system(ctx, 60000, 21)
     ctx.tune("light_cap", cap)
     ctx.tune("tail_max", tail)
