@@ -477,13 +477,14 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
  *                 product and sweeps; the dot products are summed in another
  *                 order, so results agree to CG's rounding
  * Unknown keys or values out of range give SGP_EINVAL.  check_every,
- * graph, fuse_step0 and mid_lds leave every result bitwise unchanged, and so does tail_max as long as
- * the tail does not reach the first elimination step (that step forms its
- * couplings from the contacts' (w, u) when it runs as its own launch, from
- * the stored blocks inside the tail: the same values up to rounding);
- * spmv_waves changes only the summation order of the p.q dot product;
- * spmv_form, light_height and light_cap change the order of roundings, so
- * results agree to rounding. */
+ * graph, fuse_step0 and mid_lds leave every result bitwise unchanged, and so
+ * does tail_max as long as the tail does not reach the first elimination
+ * step (that step forms its couplings from the contacts' (w, u) when it runs
+ * as its own launch, from the stored blocks inside the tail: the same values
+ * up to rounding); spmv_waves changes only the summation order of the p.q
+ * dot product; small_solve only that of the dot products; spmv_form,
+ * light_height and light_cap change the order of roundings, so results
+ * agree to rounding. */
 int sgp_tune(sgp_ctx ctx, const char *key, int32_t value);
 /* Current value of a knob (host output). */
 int sgp_tune_get(sgp_ctx ctx, const char *key, int32_t *value);

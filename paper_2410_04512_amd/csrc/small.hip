@@ -139,7 +139,8 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_pcg(SmallArgs A)
         c.a1 = A.upq[2 * qc + 1];
         c.cnt = c.on ? A.ecnt[qc] : 0;
     }
-    double f[2][3], x[2][3], r[2][3], p[2][3], q[2][3], z[2][3];
+    // (a position past n keeps zeros: its values are computed and never used)
+    double f[2][3], x[2][3], r[2][3] = {}, p[2][3] = {}, q[2][3] = {}, z[2][3] = {};
     double acc[3] = {0.0, 0.0, 0.0};   // ||f||^2, ||r||^2, non-finite count
 #pragma unroll
     for (int u = 0; u < 2; u++)
