@@ -352,6 +352,35 @@ def pcg(A: BSR, F, prec: str = "tree", factor: Factor | None = None, x0=None, to
     return x.reshape(-1, 3), info
 
 
+def pcg_gr(A: BSR, F, prec: str = "tree", factor: Factor | None = None, tol=1e-5, mu=1.0, max_iter=10_000,
+           check=True):
+    """PCG from zero stopped on an upper bound of the relative energy-norm
+    error (Gauss-Radau with node mu <= lambda_min(P^-1 Gamma); orc_pcg_gr).
+    Returns (x, info, hist) with info.relres the final error bound and
+    hist[k] = (S_k, phi_k rho_k) for k = 0..iters."""
+    n = A.n
+    F = _c(F, np.float64).reshape(-1)
+    x = np.zeros(3 * n)
+    ii = np.zeros(1, np.int32); dd = np.zeros(2)
+    hist = np.zeros(2 * (max_iter + 1))
+    z32 = np.zeros(1, np.int32); z64 = np.zeros(9)
+    if prec == "tree":
+        t = factor.tree
+        child = t.child if t.child.size else z32
+        tp = (_i32(t.parent), _i32(t.order), _i32(t.child_ptr), _i32(child),
+              _f64(_c(factor.D, np.float64)), _f64(_c(factor.L, np.float64)))
+    else:
+        tp = (_i32(z32), _i32(z32), _i32(z32), _i32(z32), _f64(z64), _f64(z64))
+    st = lib().orc_pcg_gr(C.c_int64(n), _i32(A.rowptr), _i32(A.bcol), _f64(_c(A.val, np.float64)),
+                          C.c_int(PREC[prec]), *tp, _f64(F), _f64(x), C.c_double(tol), C.c_double(mu),
+                          C.c_int(max_iter), _i32(ii), _f64(dd), _f64(hist))
+    info = SolveInfo(int(st), int(ii[0]), float(dd[0]), float(dd[1]))
+    if check and st != OK:
+        raise OracleError(st, "pcg_gr")
+    k = int(ii[0])
+    return x.reshape(-1, 3), info, hist[:2 * (k + 1)].reshape(-1, 2)
+
+
 def ir_solve(A: BSR, F, factor: Factor, tol=1e-8, inner_tol=1e-5, max_outer=50, max_inner=10_000,
              check=True):
     """FP64 iterative refinement around an FP32 inner tree-PCG."""

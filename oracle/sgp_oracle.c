@@ -879,6 +879,90 @@ done:
 }
 
 /* ------------------------------------------------------------------------ */
+/* Stopping on the energy-norm error (Section 5 monitors CG with Gauss-Radau */
+/* error estimates; Section 4's lower eigenvalue bound supplies their mu).   */
+/* ------------------------------------------------------------------------ */
+
+/* PCG from x0 = 0 as orc_pcg, stopped when an upper bound of the relative
+ * energy-norm error ||x - x_k||_G / ||x||_G falls to tol.
+ *   rho_k = r_k' z_k, alpha_k = rho_k / p_k' G p_k, beta_{k+1} = rho_{k+1} / rho_k.
+ *   eps_k = ||x - x_k||_G^2 drops by alpha_k rho_k in step k, so with x0 = 0
+ *   ||x||_G^2 = S_k + eps_k, S_k = sum_{j<k} alpha_j rho_j.
+ *   Gauss-Radau quadrature with a prescribed node mu, 0 < mu <= lambda_min of
+ *   P^{-1} G, bounds eps_k <= phi_k rho_k, phi_0 = 1 / mu,
+ *   phi_{k+1} = (phi_k - alpha_k) / (mu (phi_k - alpha_k) + beta_{k+1}).
+ *   As e / (S + e) grows with e, the relative error squared is at most
+ *   phi_k rho_k / (S_k + phi_k rho_k); the solve stops at the first k where
+ *   that is <= tol^2 (k = 0 included: F = 0 gives x = 0).
+ * hist (may be NULL): 2 (max_iter + 1) doubles, S_k and phi_k rho_k for
+ * k = 0..iters.  info_i[0] = iterations; info_d[0] = the final bound of the
+ * relative error, info_d[1] = the true relative residual. */
+int orc_pcg_gr(int64_t n, const int32_t *rowptr, const int32_t *bcol, const double *val, int prec_kind,
+               const int32_t *parent, const int32_t *order, const int32_t *child_ptr, const int32_t *child,
+               const double *Dt, const double *Lt, const double *F, double *x, double tol, double mu,
+               int max_iter, int32_t *info_i, double *info_d, double *hist)
+{
+    int64_t len = 3 * n;
+    orc_prec M = {prec_kind, n, rowptr, bcol, val, parent, order, child_ptr, child, Dt, Lt};
+    double *r = calloc((size_t)(len + 1), sizeof(double));
+    double *z = malloc((size_t)(len + 1) * sizeof(double));
+    double *p = malloc((size_t)(len + 1) * sizeof(double));
+    double *q = malloc((size_t)(len + 1) * sizeof(double));
+    int status = ORC_OK, k = 0;
+    double rel = 0.0;
+    if (!r || !z || !p || !q) { status = ORC_ENOMEM; goto done; }
+    if (!(mu > 0.0)) { status = ORC_EINVAL; goto done; }
+    if (len == 0) goto done;
+    for (int64_t t = 0; t < len; t++) {
+        if (!isfinite(F[t])) { status = ORC_ENONFINITE; goto done; }
+        x[t] = 0.0;
+        r[t] = F[t];
+    }
+    if ((status = prec_apply(&M, r, z)) != ORC_OK) goto done;
+    for (int64_t t = 0; t < len; t++) p[t] = z[t];
+    double rho = dot(len, r, z), S = 0.0, phi = 1.0 / mu;
+    for (;;) {
+        const double bound = phi * rho;
+        rel = S + bound > 0.0 ? sqrt(bound / (S + bound)) : 0.0;
+        if (hist) {
+            hist[2 * k] = S;
+            hist[2 * k + 1] = bound;
+        }
+        if (rel <= tol) break;
+        if (k >= max_iter) { status = ORC_ENOCONV; break; }
+        orc_spmv(n, rowptr, bcol, val, p, q);
+        double pq = dot(len, p, q);
+        if (!(pq > 0.0) || !isfinite(pq)) { status = ORC_EBREAKDOWN; break; }
+        double alpha = rho / pq;
+        for (int64_t t = 0; t < len; t++) x[t] = x[t] + alpha * p[t];
+        for (int64_t t = 0; t < len; t++) r[t] = r[t] - alpha * q[t];
+        k++;
+        if ((status = prec_apply(&M, r, z)) != ORC_OK) break;
+        double rho_new = dot(len, r, z);
+        if (!isfinite(rho_new)) { status = ORC_ENONFINITE; break; }
+        double beta = rho_new / rho;
+        S = S + alpha * rho;
+        phi = (phi - alpha) / (mu * (phi - alpha) + beta);
+        rho = rho_new;
+        for (int64_t t = 0; t < len; t++) p[t] = z[t] + beta * p[t];
+    }
+done:
+    if (info_i) info_i[0] = k;
+    if (info_d) {
+        info_d[0] = rel;
+        info_d[1] = 0.0;
+        if (r && q && status != ORC_ENOMEM) {
+            double nF = sqrt(dot(len, F, F));
+            orc_spmv(n, rowptr, bcol, val, x, q);
+            for (int64_t t = 0; t < len; t++) r[t] = F[t] - q[t];
+            info_d[1] = nF > 0.0 ? sqrt(dot(len, r, r)) / nF : 0.0;
+        }
+    }
+    free(r); free(z); free(p); free(q);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Section 3.1, Vaidya's second preconditioner: the MST plus edges back      */
 /* between its pieces, solved by flexible CG around an inner tree-PCG        */
 /* (the nested CG with the MST as preconditioner of Sections 3 and 5).       */
