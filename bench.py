@@ -9,15 +9,16 @@ workload: jittered FCC ball of 1,000,000 spheres (nearest-neighbour spacing
 
 Prints ONE JSON line.  Besides the headline value it carries:
   roofline      the CG's product Gamma p (the dominant kernel; by default the
-                edge form k_spmv_edge, from the contacts' (w, u) and the
-                diagonal blocks): algorithmic bytes per launch / its average
+                edge form k_spmv_edge, from the contacts' v = sqrt(w) u and
+                the diagonal blocks): algorithmic bytes per launch / its average
                 launch time, measured with HIP events on the library's stream
                 inside the timed region;
   cpu_baseline  the FP64 CPU oracle timed on this host's cores on a bounded
                 sample of the same workload (setup + a fixed number of CG
                 iterations, extrapolated to the GPU's iteration count);
   extra         the other workloads, each bounded to seconds of GPU time:
-                block-Jacobi PCG, the local-MST forest (Z-order clusters
+                block-Jacobi PCG, the solve stopped on the Gauss-Radau
+                bound of the energy error, the local-MST forest (Z-order clusters
                 of 512 to 2048 cells) and the augmented tree with its nested
                 flexible CG on the same 1M system; the 1k-cell solve's
                 latency with and without hipGraph replay; FP32-inner refinement
@@ -26,7 +27,7 @@ Prints ONE JSON line.  Besides the headline value it carries:
                 start over 200 time steps of a 200k-cell spheroid; the
                 paper's own geometries (Hertz cells, Section 5.1) at 5e4
                 cells without a preconditioner, with block Jacobi and with
-                the tree.
+                the tree (residual rule 1e-8, and the error bound at 1e-5).
 """
 from __future__ import annotations
 
@@ -111,6 +112,24 @@ def extra_jacobi(ctx, A, M, F):
     tt, (_, it) = _sync_time(lambda: ctx.pcg_solve(A, M, F, torch.zeros_like(F), rtol=1e-8))
     return {"jacobi_pcg": {"iters": ij["iters"], "solve_ms": 1e3 * tj},
             "tree_pcg": {"iters": it["iters"], "solve_ms": 1e3 * tt}}
+
+
+def extra_errstop(ctx, A, M, F):
+    """Tree-PCG on the same 1M system stopped on the Gauss-Radau bound of the
+    relative energy error (node mu = 1, Section 4's lambda_min(P^-1 Gamma) >= 1)
+    at 1e-5 (the paper's tolerance) and 1e-8, beside the residual rule at the
+    same tolerances (solve only)."""
+    import torch
+    out = {}
+    for tol in (1e-5, 1e-8):
+        for stop in ("residual", "error"):
+            ctx.pcg_solve(A, M, F, torch.zeros_like(F), rtol=tol, stop=stop)
+            t, (_, info) = _sync_time(lambda: ctx.pcg_solve(A, M, F, torch.zeros_like(F), rtol=tol, stop=stop))
+            r = {"iters": info["iters"], "solve_ms": 1e3 * t, "relres_true": info["relres_true"]}
+            if stop == "error":
+                r["err_bound"] = info["err_bound"]
+            out[f"{stop}_{tol:.0e}"] = r
+    return out
 
 
 def extra_forest(ctx, g, A, F, pos, R, sizes=(512, 1024, 2048)):
@@ -370,6 +389,23 @@ def extra_paper(P, dev, n=50_000, reps=3):
         res["iter_ratio_jacobi_over_tree"] = res["jacobi"]["iters"] / res["tree"]["iters"]
         res["wall_ratio_jacobi_over_tree"] = ((res["jacobi"]["solve_ms"] + res["jacobi"]["setup_ms"]) /
                                               (res["tree"]["solve_ms"] + res["tree"]["setup_ms"]))
+        # CG stopped on the Gauss-Radau bound of the relative energy error at
+        # the paper's tolerance 1e-5 (node mu = 1 with the tree, g_med without
+        # a preconditioner), checked against the known solution
+        xg = float(torch.dot(xt.reshape(-1), F.reshape(-1)))
+        for name, MM in (("none", None), ("tree", M)):
+            ctx.pcg_solve(A, MM, F, rtol=1e-5, stop="error")
+            ts = []
+            for _ in range(reps):
+                t, (v, info) = _sync_time(lambda: ctx.pcg_solve(A, MM, F, rtol=1e-5, stop="error"))
+                ts.append(t)
+            e = v - xt
+            eg = float(torch.dot(e.reshape(-1), ctx.spmv(A, e).reshape(-1)))
+            res[f"error_rule_{name}"] = {"iters": info["iters"], "solve_ms": 1e3 * min(ts),
+                                         "err_bound": info["err_bound"], "true_energy_err": (eg / xg) ** 0.5,
+                                         "true_err": float(torch.linalg.vector_norm(e) / nx)}
+        res["error_rule_iter_ratio_none_over_tree"] = (res["error_rule_none"]["iters"] /
+                                                       res["error_rule_tree"]["iters"])
         out[kind] = res
     ctx.close()
     return out
@@ -384,7 +420,7 @@ def main():
     ap.add_argument("--schedule", default="contract", choices=["contract", "level"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--extras", default="jacobi,forest,augmented,small,mixed,batched,learned,paper",
+    ap.add_argument("--extras", default="jacobi,errstop,forest,augmented,small,mixed,batched,learned,paper",
                     help="comma list of extra workloads to run after the headline")
     ap.add_argument("--spmv-form", type=int, choices=[0, 1], default=None,
                     help="product form: 0 stored 3x3 blocks, 1 contacts' (w, u) (the library default)")
@@ -509,6 +545,8 @@ def main():
             t_x = time.perf_counter()
             if name == "jacobi":
                 ex.update(extra_jacobi(ctx, A, M, F))
+            elif name == "errstop":
+                ex["error_rule_1M"] = extra_errstop(ctx, A, M, F)
             elif name == "forest":
                 ex["forest_1M"] = extra_forest(ctx, g, A, F, pos, R)
             elif name == "augmented":

@@ -279,9 +279,18 @@ int sgp_prec_apply_noalloc(sgp_ctx ctx, sgp_prec M, const double *r, double *z);
 /* -------------------------------------------- Section 1.1: the solve */
 
 enum { SGP_PREC_F64 = 0, SGP_PREC_F32_IR = 1 };
+/* Stopping rule: the recurrence residual, or an upper bound of the relative
+ * energy-norm error ||v - v_k||_Gamma / ||v||_Gamma (Gauss-Radau quadrature
+ * over CG's own coefficients with a node mu <= lambda_min(P^-1 Gamma): the
+ * error estimates Section 5 monitors CG with, the lower eigenvalue bound of
+ * Section 4 supplying mu).  With x0 = 0, ||v||^2 = S_k + eps_k for S_k =
+ * sum_{j<k} alpha_j rho_j (rho_j = r_j'z_j), and eps_k <= phi_k rho_k with
+ * phi_0 = 1/mu, phi_{k+1} = (phi_k - alpha_k) / (mu (phi_k - alpha_k) +
+ * beta_{k+1}); the solve stops when phi_k rho_k / (S_k + phi_k rho_k) <= rtol^2. */
+enum { SGP_STOP_RESIDUAL = 0, SGP_STOP_ERROR = 1 };
 
 typedef struct {
-    double rtol;          /* stop when ||r_k|| / ||F|| <= rtol (recurrence residual) */
+    double rtol;          /* stop when ||r_k|| / ||F|| <= rtol (recurrence residual), or see stop */
     int32_t max_iter;     /* iteration cap (inner iterations in total for IR) */
     int32_t fixed_iters;  /* > 0: run exactly this many iterations, ignore rtol */
     int32_t use_x0;       /* 1: v holds the initial guess on entry; 0: start from 0 */
@@ -289,6 +298,12 @@ typedef struct {
     double inner_rtol;    /* IR only: relative tolerance of each inner FP32 solve */
     int32_t max_outer;    /* IR only: cap on refinement steps */
     int32_t check_every;  /* CG iterations per chunk between possible convergence reads (0 = the knob) */
+    int32_t stop;         /* SGP_STOP_RESIDUAL, or SGP_STOP_ERROR: rtol bounds the relative energy-norm
+                             error (FP64 from x0 = 0 only; not with the augmented tree) */
+    int32_t reserved;     /* 0 */
+    double mu;            /* SGP_STOP_ERROR: the Gauss-Radau node, a lower bound of lambda_min(P^-1
+                             Gamma); <= 0: 1 for a tree or forest preconditioner (Section 4),
+                             g_med without one, required (> 0) with block Jacobi */
 } sgp_solve_opts;
 
 typedef struct {
@@ -298,6 +313,7 @@ typedef struct {
     int32_t inner_iters;  /* augmented tree: inner CG iterations in all (0 otherwise) */
     double relres_rec;    /* ||r_k|| / ||F|| of the recurrence (FP64 residual for IR) */
     double relres_true;   /* ||F - Gamma v|| / ||F|| recomputed at the end */
+    double err_bound;     /* SGP_STOP_ERROR: the final bound of the relative energy-norm error (else 0) */
 } sgp_solve_info;
 
 /* Solve Gamma v = F by preconditioned CG (left form of Section 1.1's split

@@ -200,10 +200,21 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int op, const double *part,
             Sc->done = 1;
             break;
         }
+        bool conv;
+        if (Sc->stop == SGP_STOP_ERROR) {
+            // the Gauss-Radau bound of the energy error after this step
+            const double a = Sc->alpha, beta = t1 / Sc->rho;
+            Sc->gs = Sc->gs + a * Sc->rho;
+            Sc->phi = (Sc->phi - a) / (Sc->mu * (Sc->phi - a) + beta);
+            Sc->gbound = Sc->phi * t1;
+            conv = Sc->gbound <= Sc->tol2 * (Sc->gs + Sc->gbound);
+        } else {
+            conv = Sc->relres2 <= Sc->tol2;
+        }
         bool stop = false;
         if (Sc->fixed) {
             stop = Sc->iter >= Sc->fixed;
-        } else if (Sc->relres2 <= Sc->tol2) {
+        } else if (conv) {
             stop = true;
         } else if (Sc->iter >= Sc->max_iter) {
             Sc->status = SGP_ENOCONV;
@@ -216,6 +227,11 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int op, const double *part,
     }
     case FIN_RHO:
         Sc->rho = t0;
+        if (Sc->stop == SGP_STOP_ERROR) {
+            Sc->phi = 1.0 / Sc->mu;
+            Sc->gs = 0.0;
+            Sc->gbound = Sc->phi * t0;
+        }
         break;
     case FIN_INIT:   // t0 = ||F||^2, t1 = ||r||^2, t2 = bad-input count
         Sc->nF2 = t0;
@@ -227,8 +243,8 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int op, const double *part,
             Sc->done = 1;
         } else if (t0 == 0.0) {
             Sc->done = 2;   // zero force: v = 0
-        } else if (!Sc->fixed && Sc->relres2 <= Sc->tol2) {
-            Sc->done = 1;
+        } else if (!Sc->fixed && (Sc->stop == SGP_STOP_ERROR ? Sc->tol2 >= 1.0 : Sc->relres2 <= Sc->tol2)) {
+            Sc->done = 1;   // (from x0 = 0 the relative energy error is 1)
         }
         break;
     case FIN_TRUE:
@@ -654,7 +670,8 @@ __global__ void k_zero_rows(T *x, BlockTab tab, const PcgScalars *S, int want_do
     x[3 * row + 2] = 0;
 }
 
-__global__ void k_set_scalars(PcgScalars *S, int64_t K, double tol2, int fixed, int max_iter)
+__global__ void k_set_scalars(PcgScalars *S, int64_t K, double tol2, int fixed, int max_iter, int stop = 0,
+                              double mu = 1.0)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
@@ -662,6 +679,8 @@ __global__ void k_set_scalars(PcgScalars *S, int64_t K, double tol2, int fixed, 
     s.tol2 = tol2;
     s.fixed = fixed;
     s.max_iter = max_iter;
+    s.stop = stop;
+    s.mu = mu;
     S[k] = s;
 }
 
@@ -960,11 +979,14 @@ static int solve_f64(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<int64
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP4], 8, &open));
     int fixed = std::max(0, o->fixed_iters);
     int max_iter = o->max_iter > 0 ? o->max_iter : 10000;
-    k_set_scalars<<<grid_for(K, 256), 256, 0, st>>>(S, K, o->rtol * o->rtol, fixed, max_iter);
+    const bool err_stop = o->stop == SGP_STOP_ERROR;
+    double mu = o->mu;
+    if (err_stop && !(mu > 0.0)) mu = M ? 1.0 : A->gmed;   // Section 4: lambda_min(P^-1 Gamma) >= 1; Gamma >= g_med I
+    k_set_scalars<<<grid_for(K, 256), 256, 0, st>>>(S, K, o->rtol * o->rtol, fixed, max_iter, o->stop, mu);
     LAUNCH_CHECK(ctx);
     // a small single system: every iteration inside one workgroup, one
     // launch (bounded: at most 20,000 iterations in one launch)
-    if (K == 1 && small_solve_fits(ctx, A, M) && std::max(fixed, max_iter) <= 20000) {
+    if (K == 1 && !err_stop && small_solve_fits(ctx, A, M) && std::max(fixed, max_iter) <= 20000) {
         SGP_TRY(solve_small(ctx, A, M, F, x, o, S));
     } else {
         if (o->use_x0) SGP_TRY(spmv_f64(ctx, A, x, q, nullptr, nullptr, 0));
@@ -997,6 +1019,7 @@ static int solve_f64(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<int64
         I.iters = s.iter;
         I.relres_rec = s.nF2 > 0 ? sqrt(s.relres2) : 0.0;
         I.relres_true = s.nF2 > 0 ? sqrt(s.rz / s.nF2) : 0.0;
+        if (err_stop && s.nF2 > 0) I.err_bound = s.gs + s.gbound > 0 ? sqrt(s.gbound / (s.gs + s.gbound)) : 1.0;
     }
     return SGP_OK;
 }
@@ -1137,6 +1160,14 @@ static int solve_common(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<in
     if (M && M->kind != PREC_NONE && M->n != A->n) return set_err(ctx, SGP_EINVAL, "pcg_solve: M and A differ in size");
     if (!(opts->rtol >= 0.0)) return set_err(ctx, SGP_EINVAL, "pcg_solve: rtol must be >= 0");
     if (M && M->kind == PREC_NONE) M = nullptr;
+    if (opts->stop != SGP_STOP_RESIDUAL && opts->stop != SGP_STOP_ERROR)
+        return set_err(ctx, SGP_EINVAL, "pcg_solve: unknown stopping rule %d", opts->stop);
+    if (opts->stop == SGP_STOP_ERROR) {
+        if (opts->use_x0 || opts->precision != SGP_PREC_F64 || (M && M->aug))
+            return set_err(ctx, SGP_EINVAL, "pcg_solve: the error bound needs an FP64 solve from x0 = 0 (no augmented tree)");
+        if (M && M->kind == PREC_JACOBI && !(opts->mu > 0.0))
+            return set_err(ctx, SGP_EINVAL, "pcg_solve: the error bound with block Jacobi needs mu > 0");
+    }
     const int64_t K = (int64_t)off.size() - 1;
     if (A->n == 0) {
         for (int64_t k = 0; k < K; k++) memset(&info[k], 0, sizeof info[k]);

@@ -22,7 +22,9 @@ struct DevBuf {
 // Per-context scalar block for the PCG drivers and reductions (device).
 struct PcgScalars {
     double rho, alpha, beta, pq, rr, rz, nF2, tol2, relres2;
-    int32_t iter, done, status, fixed, max_iter, pad0;
+    int32_t iter, done, status, fixed, max_iter, stop;
+    // SGP_STOP_ERROR: the Gauss-Radau node mu, phi_k, S_k and phi_k rho_k
+    double mu, phi, gs, gbound;
 };
 
 // The solve's stop flag, or 0 without a solve.  The address is selected

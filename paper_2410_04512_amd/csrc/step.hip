@@ -127,6 +127,9 @@ static void copy_settings(sgp_ctx to, const sgp_ctx_ *from)
     to->spmv_form = from->spmv_form;
     to->light_height = from->light_height;
     to->light_cap = from->light_cap;
+    to->fuse_step0 = from->fuse_step0;
+    to->mid_lds = from->mid_lds;
+    to->small_solve = from->small_solve;
     to->contact_model = from->contact_model;
 }
 

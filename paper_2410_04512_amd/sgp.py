@@ -32,16 +32,22 @@ class SgpError(RuntimeError):
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("fixed_iters", C.c_int32),
                 ("use_x0", C.c_int32), ("precision", C.c_int32), ("inner_rtol", C.c_double),
-                ("max_outer", C.c_int32), ("check_every", C.c_int32)]
+                ("max_outer", C.c_int32), ("check_every", C.c_int32), ("stop", C.c_int32),
+                ("reserved", C.c_int32), ("mu", C.c_double)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("outer_iters", C.c_int32),
-                ("inner_iters", C.c_int32), ("relres_rec", C.c_double), ("relres_true", C.c_double)]
+                ("inner_iters", C.c_int32), ("relres_rec", C.c_double), ("relres_true", C.c_double),
+                ("err_bound", C.c_double)]
 
     def as_dict(self):
         return {"status": self.status, "iters": self.iters, "outer_iters": self.outer_iters,
-                "inner_iters": self.inner_iters, "relres_rec": self.relres_rec, "relres_true": self.relres_true}
+                "inner_iters": self.inner_iters, "relres_rec": self.relres_rec, "relres_true": self.relres_true,
+                "err_bound": self.err_bound}
+
+
+STOP = {"residual": 0, "error": 1}
 
 
 _vp, _i64, _i32, _dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
@@ -488,16 +494,20 @@ class Context:
 
     # ---------------------------------------------------------------- Section 1.1
     @staticmethod
-    def _opts(rtol, max_iter, fixed_iters, use_x0, precision, inner_rtol, max_outer, check_every):
+    def _opts(rtol, max_iter, fixed_iters, use_x0, precision, inner_rtol, max_outer, check_every, stop="residual",
+              mu=0.0):
         return SolveOpts(rtol, max_iter, fixed_iters, 1 if use_x0 else 0,
-                         {"f64": 0, "f32ir": 1}[precision], inner_rtol, max_outer, check_every)
+                         {"f64": 0, "f32ir": 1}[precision], inner_rtol, max_outer, check_every, STOP[stop], 0, mu)
 
     def pcg_solve(self, A: Bsr, M: Prec | None, F, v=None, rtol=1e-8, max_iter=10000, fixed_iters=0,
-                  use_x0=False, precision="f64", inner_rtol=1e-5, max_outer=50, check_every=0, check=True):
+                  use_x0=False, precision="f64", inner_rtol=1e-5, max_outer=50, check_every=0, check=True,
+                  stop="residual", mu=0.0):
+        """stop="error": rtol bounds the relative energy-norm error (Gauss-Radau
+        with node mu; 0 = the default of sgp_solve_opts.mu)."""
         if v is None:
             v = torch.zeros_like(F)
             use_x0 = False
-        o = self._opts(rtol, max_iter, fixed_iters, use_x0, precision, inner_rtol, max_outer, check_every)
+        o = self._opts(rtol, max_iter, fixed_iters, use_x0, precision, inner_rtol, max_outer, check_every, stop, mu)
         info = SolveInfo()
         st = lib().sgp_pcg_solve(self.h, A.h, M.h if M is not None else None, _ptr(F, torch.float64, "F"),
                                  _ptr(v, torch.float64, "v"), C.byref(o), C.byref(info))
@@ -506,13 +516,13 @@ class Context:
         return v, info.as_dict()
 
     def pcg_solve_batched(self, A: Bsr, M: Prec | None, offsets, F, v=None, rtol=1e-8, max_iter=10000,
-                          fixed_iters=0, use_x0=False, check_every=0, check=True):
+                          fixed_iters=0, use_x0=False, check_every=0, check=True, stop="residual", mu=0.0):
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         k = off.shape[0] - 1
         if v is None:
             v = torch.zeros_like(F)
             use_x0 = False
-        o = self._opts(rtol, max_iter, fixed_iters, use_x0, "f64", 1e-5, 50, check_every)
+        o = self._opts(rtol, max_iter, fixed_iters, use_x0, "f64", 1e-5, 50, check_every, stop, mu)
         infos = (SolveInfo * k)()
         st = lib().sgp_pcg_solve_batched(self.h, A.h, M.h if M is not None else None, k,
                                          off.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(F, torch.float64, "F"),
