@@ -492,9 +492,14 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
  *                 20,000 iterations; default 1; 0: a launch per kernel).  Same
  *                 product and sweeps; the dot products are summed in another
  *                 order, so results agree to CG's rounding
+ *  "tail_side"    1: in sgp_pcg_solve*, while the one-workgroup tail of the
+ *                 tree sweeps runs, extra workgroups of its launch do the
+ *                 CG's x += alpha p (the rest of the chip would idle), and
+ *                 the later vector pass only updates p (default 1; 0: x and
+ *                 p in that pass)
  * Unknown keys or values out of range give SGP_EINVAL.  check_every,
- * graph, fuse_step0 and mid_lds leave every result bitwise unchanged, and so
- * does tail_max as long as the tail does not reach the first elimination
+ * graph, fuse_step0, mid_lds and tail_side leave every result bitwise
+ * unchanged, and so does tail_max as long as the tail does not reach the first elimination
  * step (that step forms its couplings from the contacts' (w, u) when it runs
  * as its own launch, from the stored blocks inside the tail: the same values
  * up to rounding); spmv_waves changes only the summation order of the p.q

@@ -1021,6 +1021,58 @@ SGP_DEV void tail_load_reg(TailReg<T> &p, int32_t q, int32_t i, const int32_t *t
     tail_load_common(p.d, p.f0, p.f1, q, F, fs, Dinv);
 }
 
+// x += alpha p of the CG (SideX) by workgroup wg of nwg extra workgroups of
+// the tail launch: SIDE_BLOCKS vector blocks per round, every load of a round
+// issued before its first store (blocks are disjoint row ranges, so no store
+// of a round aliases one of its loads).  Same expression as the CG's own
+// update pass, so x is bitwise the same.
+constexpr int SIDE_BLOCKS = 4;
+static_assert(2 * TAIL_THREADS >= SIDE_BLOCK_VALUES, "two values per thread cover a vector block");
+template <class T>
+SGP_DEV void side_x_update(const SideX &sd, int wg, int nwg)
+{
+    T *x = (T *)sd.x;
+    const T *p = (const T *)sd.p;
+    const int tid = threadIdx.x;
+    // wait about 7 us (2 x 127 x 64 clocks) first, so that the tail's own
+    // first loads are served before this stream fills the memory queues
+    // (1M cells: the tail launch 35.9 us without the wait, 33.6 us with it,
+    // 32.6 us without the side update, which moves as many bytes as the
+    // CG's 12.9 us p-only pass)
+    __builtin_amdgcn_s_sleep(127);
+    __builtin_amdgcn_s_sleep(127);
+    for (int b0 = wg * SIDE_BLOCKS; b0 < sd.nb; b0 += nwg * SIDE_BLOCKS) {
+        int64_t e0[SIDE_BLOCKS];
+        int nel[SIDE_BLOCKS], inst[SIDE_BLOCKS];
+#pragma unroll
+        for (int u = 0; u < SIDE_BLOCKS; u++) {
+            const int b = min(b0 + u, sd.nb - 1);
+            e0[u] = 3 * (int64_t)sd.row0[b];
+            nel[u] = b0 + u < sd.nb ? 3 * (sd.row1[b] - sd.row0[b]) : 0;
+            inst[u] = sd.inst[b];
+        }
+        T xv[SIDE_BLOCKS][2], pv[SIDE_BLOCKS][2], al[SIDE_BLOCKS];
+        int32_t dn[SIDE_BLOCKS];
+#pragma unroll
+        for (int u = 0; u < SIDE_BLOCKS; u++) {
+            dn[u] = sd.S[inst[u]].done;
+            al[u] = (T)sd.S[inst[u]].alpha;
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int64_t e = e0[u] + min(tid + TAIL_THREADS * h, max(nel[u] - 1, 0));
+                xv[u][h] = nel[u] > 0 ? x[e] : (T)0;
+                pv[u][h] = nel[u] > 0 ? p[e] : (T)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SIDE_BLOCKS; u++)
+#pragma unroll
+            for (int h = 0; h < 2; h++)
+                if (dn[u] == 0 && tid + TAIL_THREADS * h < nel[u])
+                    x[e0[u] + tid + TAIL_THREADS * h] = xv[u][h] + al[u] * pv[u][h];
+    }
+}
+
 // The tail's steps fall in two parts.  Steps whose vertices all lie in the
 // last TAIL_WINDOW tail vertices (the window, from step kw on: usually most
 // of the steps, few vertices each) give vertices base + t and base +
@@ -1036,8 +1088,13 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
                                                        const int32_t *in_ptr, const int32_t *iptr,
                                                        const int32_t *tslot, const int32_t *upq, const T *F,
                                                        int64_t fs, const T *Dinv, const T *tb, T *y, T *z,
-                                                       const PcgScalars *s)
+                                                       const PcgScalars *s, SideX side)
 {
+    // workgroups past the first: the CG's x update, meanwhile
+    if (blockIdx.x > 0) {
+        side_x_update<T>(side, blockIdx.x - 1, gridDim.x - 1);
+        return;
+    }
     extern __shared__ unsigned char lds_raw[];
     T *sv = (T *)lds_raw;
     T *slot = sv + 3 * nt;
@@ -1605,7 +1662,7 @@ int32_t prec_step0_launch(sgp_prec M)
 // it (the fused vector passes of the CG), only where prec_step0_launch > 0
 template <class T>
 static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y, T *cs, const T *r, T *z,
-                       PcgScalars *s, const T *wu0, bool skip0)
+                       PcgScalars *s, const T *wu0, bool skip0, SideX *side)
 {
     hipStream_t st = ctx->stream;
     // r and z are in the internal order
@@ -1669,9 +1726,16 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
         int32_t kw = ts;
         while (kw < S && sp[kw] - sp[ts] < base) kw++;
         const int32_t q1a = kw > ts ? sp[ts + 1] : sp[ts] + 1;
-        k_tail<T><<<1, TAIL_THREADS, lds, st>>>(ts, S, kw, sp[ts], q1a, nt, M->tail_ni, dsp, elim, in_ptr,
-                                               (const int32_t *)M->tail_iptr.p, (const int32_t *)M->tail_tslot.p,
-                                               upq, F, fs, Dinv, tb, y, z, s);
+        // extra workgroups take the CG's x update (a block holds at most
+        // 2 TAIL_THREADS values)
+        SideX sd = {};
+        if (side && side->nb > 0 && side->nwg > 0) {
+            sd = *side;
+            side->ran = true;
+        }
+        k_tail<T><<<1 + (unsigned)sd.nwg, TAIL_THREADS, lds, st>>>(
+            ts, S, kw, sp[ts], q1a, nt, M->tail_ni, dsp, elim, in_ptr, (const int32_t *)M->tail_iptr.p,
+            (const int32_t *)M->tail_tslot.p, upq, F, fs, Dinv, tb, y, z, s, sd);
     }
     for (int k = ts - 1; k >= L; k--) {
         int32_t q0 = sp[k], q1 = sp[k + 1];
@@ -1699,7 +1763,7 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
     return SGP_OK;
 }
 
-int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScalars *s, bool skip0)
+int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScalars *s, bool skip0, SideX *side)
 {
     hipStream_t st = ctx->stream;
     if (!M || M->kind == PREC_NONE) {
@@ -1714,10 +1778,10 @@ int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScala
     }
     return tree_sweeps<double>(ctx, M, (const double *)M->F.p, (const double *)M->Dinv.p, (double *)M->y.p,
                                (double *)M->cs.p, r, z, s, M->n_wu0 > 0 ? (const double *)M->wu0.p : nullptr,
-                               skip0 && prec_step0_launch(M) > 0);
+                               skip0 && prec_step0_launch(M) > 0, side);
 }
 
-int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s, bool skip0)
+int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s, bool skip0, SideX *side)
 {
     hipStream_t st = ctx->stream;
     if (M->kind == PREC_JACOBI) {
@@ -1727,7 +1791,7 @@ int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars
     }
     return tree_sweeps<float>(ctx, M, (const float *)M->F32.p, (const float *)M->Dinv32.p, (float *)M->y32.p,
                               (float *)M->cs32.p, r, z, s, M->n_wu0 > 0 ? (const float *)M->wu032.p : nullptr,
-                              skip0 && prec_step0_launch(M) > 0);
+                              skip0 && prec_step0_launch(M) > 0, side);
 }
 
 __global__ void k_to_f32(int64_t len, const double *a, float *b)

@@ -48,6 +48,9 @@ struct BlockTab {
 // element ne-1 (vec_idx) and drops the result.
 constexpr int VEC_ROWS = 256;
 constexpr int VEC_EPT = 3 * VEC_ROWS / 256;
+// the tail's extra workgroups (SideX): at most one per CU but the tail's own
+constexpr int SIDE_NWG = 255;
+static_assert(3 * VEC_ROWS <= SIDE_BLOCK_VALUES, "a vector block must fit the tail's side update");
 
 SGP_DEV int vec_idx(int u, int ne) { return min((int)threadIdx.x + 256 * u, ne - 1); }
 SGP_DEV bool vec_own(int u, int ne) { return (int)threadIdx.x + 256 * u < ne; }
@@ -642,6 +645,28 @@ __global__ __launch_bounds__(256) void k_update_xp(T *x, T *p, const T *z, Block
         }
 }
 
+// p = z + beta p, where x += alpha p ran during the tree sweeps (SideX): a
+// finishing solve has nothing left to do
+template <class T>
+__global__ __launch_bounds__(256) void k_update_p(T *p, const T *z, BlockTab tab, const PcgScalars *S)
+{
+    int inst;
+    int64_t e0;
+    const int ne = block_elems(tab, blockIdx.x, e0, inst);
+    const PcgScalars *Sc = S + inst;
+    T pv[VEC_EPT], zv[VEC_EPT];
+#pragma unroll
+    for (int u = 0; u < VEC_EPT; u++) {
+        pv[u] = p[e0 + vec_idx(u, ne)];
+        zv[u] = z[e0 + vec_idx(u, ne)];
+    }
+    if (Sc->done || ne == 0) return;
+    const T beta = (T)Sc->beta;
+#pragma unroll
+    for (int u = 0; u < VEC_EPT; u++)
+        if (vec_own(u, ne)) p[e0 + vec_idx(u, ne)] = zv[u] + beta * pv[u];
+}
+
 // partial of ||F - q||^2 (q = Gamma x)
 __global__ __launch_bounds__(256) void k_true_res(const double *F, const double *q, BlockTab tab, double *part)
 {
@@ -805,18 +830,26 @@ static int pcg_chunk(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w, 
             k_update_r_s0<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.q, w.vec, S, part, step0_tab<T>(M, w));
         else
             k_update_r<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.q, w.vec, S, part);
+        // x += alpha p by extra workgroups of the sweeps' one-workgroup tail
+        // launch, when there is one (knob tail_side)
+        SideX side = {v.x, v.p, w.vec.row0, w.vec.row1, w.vec.inst, S, w.vec_nb,
+                      std::min(SIDE_NWG, (w.vec_nb + 3) / 4), false};
+        SideX *sx = ctx->tail_side ? &side : nullptr;
         if (M) {
             if (sizeof(T) == 8)
-                SGP_TRY(prec_apply_f64(ctx, M, (const double *)v.r, (double *)v.z, gate, s0));
+                SGP_TRY(prec_apply_f64(ctx, M, (const double *)v.r, (double *)v.z, gate, s0, sx));
             else
-                SGP_TRY(prec_apply_f32(ctx, M, (const float *)v.r, (float *)v.z, gate, s0));
+                SGP_TRY(prec_apply_f32(ctx, M, (const float *)v.r, (float *)v.z, gate, s0, sx));
         }
         if (s0)
             k_rz_s0<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.z, w.vec, S, part + w.vec_nb, step0_tab<T>(M, w));
         else
             k_rz<T><<<w.vec_nb, 256, 0, st>>>(v.r, v.z, w.vec, S, part + w.vec_nb);
         SGP_TRY(fin(ctx, FIN_RR_BETA, part, w.vec_nb, w.vec.ifirst, w.vec.inb, S, K));
-        k_update_xp<T><<<w.vec_nb, 256, 0, st>>>(v.x, v.p, v.z, w.vec, S);
+        if (side.ran)
+            k_update_p<T><<<w.vec_nb, 256, 0, st>>>(v.p, v.z, w.vec, S);
+        else
+            k_update_xp<T><<<w.vec_nb, 256, 0, st>>>(v.x, v.p, v.z, w.vec, S);
         LAUNCH_CHECK(ctx);
     }
     return SGP_OK;
@@ -1310,6 +1343,11 @@ extern "C" int sgp_tune(sgp_ctx ctx, const char *key, int32_t value)
         ctx->fuse_step0 = value;
         return SGP_OK;
     }
+    if (!strcmp(key, "tail_side")) {
+        if (value < 0 || value > 1) return set_err(ctx, SGP_EINVAL, "tune: tail_side must be 0 or 1");
+        ctx->tail_side = value;
+        return SGP_OK;
+    }
     return set_err(ctx, SGP_EINVAL, "tune: unknown key '%s'", key);
 }
 
@@ -1326,6 +1364,7 @@ extern "C" int sgp_tune_get(sgp_ctx ctx, const char *key, int32_t *value)
     else if (!strcmp(key, "fuse_step0")) *value = ctx->fuse_step0;
     else if (!strcmp(key, "small_solve")) *value = ctx->small_solve;
     else if (!strcmp(key, "mid_lds")) *value = ctx->mid_lds;
+    else if (!strcmp(key, "tail_side")) *value = ctx->tail_side;
     else return set_err(ctx, SGP_EINVAL, "tune_get: unknown key '%s'", key);
     return SGP_OK;
 }

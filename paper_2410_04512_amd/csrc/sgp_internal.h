@@ -86,6 +86,7 @@ struct sgp_ctx_ {
     int fuse_step0 = 1;            // CG: first elimination step inside the vector passes around the sweeps
     int small_solve = 1;           // one-workgroup PCG for small single systems (small.hip)
     int mid_lds = 1;               // tree sweeps: the mid steps' slots and x in LDS (factor.hip)
+    int tail_side = 1;             // CG: x += alpha p by extra workgroups of the one-workgroup tail launch
     int light_height = 0;          // rake rounds whose subtrees the sweeps handle one workgroup each (0: off)
     int light_cap = 512;           // vertices of such subtrees packed into one workgroup
     hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)
@@ -281,12 +282,30 @@ int fill_i32(sgp_ctx ctx, int32_t *p, int32_t v, int64_t n);
 int fill_f64(sgp_ctx ctx, double *p, double v, int64_t n);
 int iota_i32(sgp_ctx ctx, int32_t *p, int64_t n);
 
+// The CG's x += alpha p, handed to the tree sweeps: while the tail's single
+// workgroup runs its chain of dependent steps, the rest of the chip idles, so
+// extra workgroups of the same launch stream this update meanwhile.  The
+// rows are the CG's vector blocks (row0, row1, cluster per block); a block
+// is updated while its cluster's done mark is 0, as in the CG's own pass.
+constexpr int SIDE_BLOCK_VALUES = 1024;   // values of one vector block at most
+struct SideX {
+    void *x;               // T[3 n], internal order
+    const void *p;         // T[3 n]
+    const int32_t *row0, *row1, *inst;
+    const PcgScalars *S;
+    int32_t nb;            // vector blocks
+    int32_t nwg;           // extra workgroups
+    bool ran;              // set by the sweeps when the update was launched
+};
+
 // shared by several translation units
 // r, z in the internal order (used by the CG)
-int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScalars *s, bool skip0 = false);
+int prec_apply_f64(sgp_ctx ctx, sgp_prec M, const double *r, double *z, PcgScalars *s, bool skip0 = false,
+                   SideX *side = nullptr);
 int permute_rows(sgp_ctx ctx, const int32_t *idx, const double *src, double *dst, int64_t n, int scatter);
 int copy_order(sgp_ctx ctx, DevBuf &dperm, DevBuf &dinv, const DevBuf &sperm, const DevBuf &sinv, int64_t n);
-int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s, bool skip0 = false);
+int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s, bool skip0 = false,
+                   SideX *side = nullptr);
 int32_t prec_step0_launch(sgp_prec M);
 // a number no earlier call returned (generations of matrices and factors)
 uint64_t next_gen();

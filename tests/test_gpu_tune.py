@@ -40,9 +40,9 @@ def test_defaults_and_rejections(ctx):
     assert ctx.tune_get("check_every") == 2 and ctx.tune_get("tail_max") == 2200
     assert ctx.tune_get("graph") == 0 and ctx.tune_get("spmv_waves") == 4
     assert ctx.tune_get("light_height") == 0 and ctx.tune_get("light_cap") == 512
-    assert ctx.tune_get("spmv_form") == 1
+    assert ctx.tune_get("spmv_form") == 1 and ctx.tune_get("tail_side") == 1
     for key, bad in (("check_every", 0), ("tail_max", -1), ("graph", 2), ("spmv_waves", 3), ("nope", 1),
-                     ("light_height", -1), ("light_cap", 0), ("spmv_form", 2)):
+                     ("light_height", -1), ("light_cap", 0), ("spmv_form", 2), ("tail_side", 2)):
         with pytest.raises(P.SgpError):
             ctx.tune(key, bad)
 
@@ -355,4 +355,58 @@ def test_mid_steps_in_lds_batched(ctx):
     ctx.tune("mid_lds", 1)
     assert [a["iters"] for a in i1] == [b["iters"] for b in i0]
     assert all(a["status"] == 0 for a in i1)
+    assert torch.equal(v0, v1)
+
+
+@pytest.mark.parametrize("n,seed", [(60000, 43), (1500, 44)])
+def test_tail_side_update_is_bitwise_neutral(ctx, n, seed):
+    """x += alpha p run by extra workgroups of the tail launch (knob
+    tail_side, on by default) gives the same bits as the CG's own update
+    pass: FP64 solves to a tolerance, at fixed counts, from a warm start, on
+    the error bound, with chunk graphs, and the FP32 refinement."""
+    c, g, A, T = _system(ctx, n, seed)
+    F = to_dev(c["force"])
+    M = ctx.factor_tree(g, T)
+    assert M.info()["tail_step"] < M.steps()   # the sweeps have a tail
+    x0 = torch.randn_like(F)
+    ctx.tune("small_solve", 0)
+    runs = {}
+    for on in (1, 0):
+        ctx.tune("tail_side", on)
+        r = [ctx.pcg_solve(A, M, F), ctx.pcg_solve(A, M, F, fixed_iters=7),
+             ctx.pcg_solve(A, M, F, v=x0.clone(), use_x0=True), ctx.pcg_solve(A, M, F, rtol=1e-6, stop="error"),
+             ctx.pcg_solve(A, M, F, precision="f32ir")]
+        ctx.tune("graph", 1)
+        r.append(ctx.pcg_solve(A, M, F, check_every=3))
+        ctx.tune("graph", 0)
+        runs[on] = r
+    ctx.tune("tail_side", 1)
+    ctx.tune("small_solve", 1)
+    for (va, ia), (vb, ib) in zip(runs[1], runs[0]):
+        assert ia["iters"] == ib["iters"] and ia["status"] == ib["status"] == 0
+        assert torch.equal(va, vb)
+    if n <= 2000:
+        og = O.collide(c["pos"], c["radius"])
+        check_velocity(host(runs[1][0][0]), runs[1][0][1]["iters"], O.assemble(og), c["force"],
+                       O.tree_factor(og, O.build_tree(og)))
+
+
+def test_tail_side_update_batched(ctx):
+    """Instances converge at different iterations: the side update stops
+    with each, as the CG's own pass does."""
+    sizes = [40000, 3000, 70000, 500, 9000]
+    parts = [batched_instance(k + 21, n_override=s) for k, s in enumerate(sizes)]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = to_dev(np.concatenate([p["pos"] for p in parts]))
+    R = to_dev(np.concatenate([p["radius"] for p in parts]))
+    F = to_dev(np.concatenate([p["force"] for p in parts]))
+    g = ctx.collide_batched(off, pos, R)
+    A = ctx.assemble_gamma(g)
+    M = ctx.factor_tree(g, ctx.build_tree(g))
+    v1, i1 = ctx.pcg_solve_batched(A, M, off, F)
+    ctx.tune("tail_side", 0)
+    v0, i0 = ctx.pcg_solve_batched(A, M, off, F)
+    ctx.tune("tail_side", 1)
+    assert [a["iters"] for a in i1] == [b["iters"] for b in i0]
+    assert len({a["iters"] for a in i1}) > 1 and all(a["status"] == 0 for a in i1)
     assert torch.equal(v0, v1)
