@@ -532,8 +532,9 @@ def main():
                      "traffic_unit": "B/launch (counters)",
                      "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_spmv_ms,
                      "launches": spmv_launches,
-                     "timed": f"HIP events around the third product of every {ctx.tune_get('check_every')}-iteration "
-                              "CG chunk of the timed region (products after convergence excluded)"},
+                     "timed": "HIP events around one product in every 16 CG iterations (the third of a "
+                              f"{ctx.tune_get('check_every')}-iteration chunk, or its last) in the timed region "
+                              "(products after convergence excluded)"},
         "phase_ms": {k: v_ / args.steps for k, v_ in phase.items()},
     }
     if not args.no_extra:

@@ -40,6 +40,7 @@ extern "C" void sgp_destroy(sgp_ctx c)
     for (auto &b : c->ws) release(b);
     if (c->tickets) (void)hipFree(c->tickets);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);
     for (int k = 0; k < 12; k++)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     delete c;

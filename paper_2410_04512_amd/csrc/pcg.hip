@@ -718,7 +718,10 @@ __global__ void k_any_open(const PcgScalars *S, int64_t K, int32_t *open)
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < K && !S[k].done) {
         atomicAdd(open, 1);
-        const double q = S[k].tol2 > 0.0 ? S[k].relres2 / S[k].tol2 : 0.0;
+        // the stopping quantity over its target (squared)
+        const double g = S[k].gs + S[k].gbound;
+        const double e2 = S[k].stop == SGP_STOP_ERROR ? (g > 0.0 ? S[k].gbound / g : 1.0) : S[k].relres2;
+        const double q = S[k].tol2 > 0.0 ? e2 / S[k].tol2 : 0.0;
         if (q > 0.0 && isfinite(q))
             atomicMax((unsigned long long *)(open + 2), (unsigned long long)__double_as_longlong(q));
     }
@@ -794,6 +797,9 @@ static int fin(sgp_ctx ctx, int op, const double *part, int nblk, const int32_t 
     return SGP_OK;
 }
 
+// CG iterations per timed product (at most one per chunk)
+constexpr int KT_STRIDE = 16;
+
 // PCG iterations on prepared r, z (z = M r) and p, until every cluster is done.
 // `count` CG iterations, launched on ctx->stream (no host synchronisation,
 // allocation or memset inside, so the sequence can be captured into a graph).
@@ -808,11 +814,12 @@ static int pcg_chunk(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w, 
     // one cluster: the sweeps stop with it; several: every sweep runs
     PcgScalars *gate = K == 1 ? S : nullptr;
     for (int c = 0; c < count; c++) {
-        // kernel timing brackets one product per chunk, the third (by then
-        // the host has queued well ahead of the GPU, so the pair times the
-        // kernel and not the wait for its launch); an event pair per product
-        // would itself cost time
-        const bool timed = c == std::min(2, count - 1);
+        // kernel timing brackets one product in every KT_STRIDE iterations,
+        // the third of a chunk that starts a new stride (by then the host has
+        // queued well ahead of the GPU, so the pair times the kernel and not
+        // the wait for its launch); each event holds the stream for ~6 us,
+        // so pairs stay rare
+        const bool timed = c == std::min(2, count - 1) && it0 % KT_STRIDE < count;
         if (timed) SGP_TRY(ktimer_begin(ctx, it0 + c));
         if (K == 1) {
             SGP_TRY(spmv_t<T>(ctx, A, v.p, v.q, S, part, 1));
@@ -905,7 +912,8 @@ static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w
     ChunkGraph cg;
     // Chunks issued between two polls of the host.  A fixed iteration count
     // needs no poll before its end.  Otherwise, after two polls, the decay per
-    // iteration of log(||r||^2 / (tol ||F||)^2) of the slowest open cluster
+    // iteration of log(||r||^2 / (tol ||F||)^2) (or of the squared relative
+    // error bound over tol^2, when that stops the solve) of the slowest open cluster
     // predicts the iterations it still needs, and the next poll comes after
     // half of them (whole chunks, at least one): polls thin out while the
     // solve is far from the tolerance, and iterations issued past
@@ -915,24 +923,53 @@ static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w
     int per_poll = fixed > 0 ? (limit + check_every - 1) / check_every : 1;
     int it_prev = -1;
     double lg_prev = 0.0;
-    for (int it = 0; it < limit;) {
-        for (int b = 0; b < per_poll && it < limit; b++) {
-            int chunk = std::min(check_every, limit - it);
-            if (graph && chunk == check_every) {
-                if (!cg.exec) SGP_TRY(capture_chunk<T>(ctx, A, M, v, w, S, part, chunk, cg));
-                HIP_TRY(ctx, hipGraphLaunch(cg.exec, st));
-            } else {
-                SGP_TRY(pcg_chunk<T>(ctx, A, M, v, w, S, part, chunk, it));
-            }
-            it += chunk;
+    // Look-ahead: while the host waits for a poll's flags, the GPU runs one
+    // more chunk, issued right after the poll (every kernel returns at once
+    // for a cluster that has converged), so a poll leaves the GPU no idle
+    // gap.  Not while a step is recorded or captured, whose readbacks are
+    // replayed in order, nor for a fixed count (no poll before its end).
+    const bool ahead = ctx->plan_mode == PLAN_OFF && fixed == 0;
+    if (ahead && !ctx->poll_ev) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->poll_ev, hipEventDisableTiming));
+    int it = 0;                // iterations issued
+    bool issued_ahead = false;   // the current group's first chunk went out with the last poll
+    auto issue = [&]() -> int {
+        const int chunk = std::min(check_every, limit - it);
+        if (graph && chunk == check_every) {
+            if (!cg.exec) SGP_TRY(capture_chunk<T>(ctx, A, M, v, w, S, part, chunk, cg));
+            HIP_TRY(ctx, hipGraphLaunch(cg.exec, st));
+        } else {
+            SGP_TRY(pcg_chunk<T>(ctx, A, M, v, w, S, part, chunk, it));
         }
+        it += chunk;
+        return SGP_OK;
+    };
+    int32_t iters_done = INT32_MAX;
+    while (it < limit) {
+        for (int b = issued_ahead ? 1 : 0; b < per_poll && it < limit; b++) SGP_TRY(issue());
+        issued_ahead = false;
+        const int it_poll = it;
         SGP_TRY(fill_i32(ctx, open, 0, 4));
         k_any_open<<<grid_for(K, 256), 256, 0, st>>>(S, K, open);
-        SGP_TRY(readback(ctx, hopen, open, 16));
-        // one cluster: its products past the final iteration were no-ops
-        // (batched products always run for every cluster)
-        SGP_TRY(ktimer_flush(ctx, K == 1 && hopen[0] == 0 ? hopen[1] : INT32_MAX));
-        if (hopen[0] == 0) break;
+        if (ahead) {
+            HIP_TRY(ctx, hipMemcpyAsync(hopen, open, 16, hipMemcpyDeviceToHost, st));
+            HIP_TRY(ctx, hipEventRecord(ctx->poll_ev, st));
+            if (it < limit) {
+                SGP_TRY(issue());
+                issued_ahead = true;
+            }
+            HIP_TRY(ctx, hipEventSynchronize(ctx->poll_ev));
+        } else {
+            SGP_TRY(readback(ctx, hopen, open, 16));
+        }
+        if (hopen[0] == 0) {
+            // one cluster: its products past the final iteration were no-ops
+            // (batched products always run for every cluster)
+            if (K == 1) iters_done = hopen[1];
+            break;
+        }
+        // timed pairs pile up only in long solves: fold in now and then those
+        // of the iterations before this poll (all still open)
+        if (ctx->kev_used >= 1024) SGP_TRY(ktimer_flush(ctx, it_poll));
         if (fixed > 0) continue;
         double worst;
         memcpy(&worst, hopen + 2, 8);
@@ -940,14 +977,15 @@ static int pcg_iterate(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w
         if (worst > 1.0 && std::isfinite(worst)) {
             const double lg = log(worst);
             if (it_prev >= 0 && lg < lg_prev) {
-                const double rem = -lg / ((lg - lg_prev) / (it - it_prev));
-                const double cap = std::max(8.0, 0.25 * it) / check_every;
+                const double rem = -lg / ((lg - lg_prev) / (it_poll - it_prev));
+                const double cap = std::max(8.0, 0.25 * it_poll) / check_every;
                 per_poll = (int)std::max(1.0, std::min(cap, 0.5 * rem / check_every));
             }
-            it_prev = it;
+            it_prev = it_poll;
             lg_prev = lg;
         }
     }
+    SGP_TRY(ktimer_flush(ctx, iters_done));
     return SGP_OK;
 }
 

@@ -66,6 +66,7 @@ struct sgp_ctx_ {
     unsigned *tickets = nullptr;   // device counters for last-block reductions (kept at 0 between uses)
     int n_tickets = 0;
     void *pinned = nullptr;        // small pinned host block for readbacks
+    hipEvent_t poll_ev = nullptr;  // the CG's poll readback (created on first use)
     DevBuf ws[24];                 // scratch workspaces (by role index)
     hipEvent_t ev[12] = {};
     float phase_ms[5] = {0, 0, 0, 0, 0};
