@@ -450,7 +450,8 @@ __global__ void k_step0_ranges(int32_t nb, BlockTab tab, const int32_t *elim, in
 }
 
 // r -= alpha q with the partial of ||r||^2, then the forward substitution of
-// the block's first-step vertices: y = P_qq^{-1} r and the pushes
+// the block's first-step vertices: y = P_qq^{-1} r and its pushes (y itself
+// is formed again by k_rz_s0)
 template <class T>
 __global__ __launch_bounds__(256) void k_update_r_s0(T *r, const T *q, BlockTab tab, const PcgScalars *S,
                                                      double *part, Step0Tab<T> t)
@@ -507,9 +508,8 @@ __global__ __launch_bounds__(256) void k_update_r_s0(T *r, const T *q, BlockTab 
             sym_mv(d, b0, b1, b2, o0, o1, o2);
         else
             leaf_pivot_solve(w0, t.gpar, t.gperp, t.gmed, b0, b1, b2, o0, o1, o2);
-        t.y[3 * (int64_t)qc] = o0;
-        t.y[3 * (int64_t)qc + 1] = o1;
-        t.y[3 * (int64_t)qc + 2] = o2;
+        // y = P_qq^{-1} r is not stored: the backward pass forms it again
+        // from the same r
         if (to0 >= 0) {
             T *c = t.cs + 3 * (int64_t)to0;
             neg_w_mv(w0, t.gpar, t.gperp, o0, o1, o2, c[0], c[1], c[2]);
@@ -530,7 +530,7 @@ __global__ __launch_bounds__(256) void k_rz_s0(const T *r, T *z, BlockTab tab, c
                                                Step0Tab<T> t)
 {
     __shared__ double sh[256];
-    __shared__ T zl[3 * VEC_ROWS];
+    __shared__ T zl[3 * VEC_ROWS], rl[3 * VEC_ROWS];
     int inst;
     int64_t e0;
     // XCD-contiguous rows: the up-links an XCD's blocks read stay in its L2
@@ -553,7 +553,6 @@ __global__ __launch_bounds__(256) void k_rz_s0(const T *r, T *z, BlockTab tab, c
     const int64_t v = t.elim[qc];
     T w0[4], w1[4], d[6];
     for (int k = 0; k < 4; k++) w0[k] = t.wu[4 * (int64_t)qc + k];
-    const T y0 = t.y[3 * (int64_t)qc], y1 = t.y[3 * (int64_t)qc + 1], y2 = t.y[3 * (int64_t)qc + 2];
     const int64_t u0 = a0 >= 0 ? a0 : qc, u1 = a1 >= 0 ? a1 : qc;
     const T p0 = t.y[3 * u0], p1 = t.y[3 * u0 + 1], p2 = t.y[3 * u0 + 2];
     const T x0 = t.y[3 * u1], x1 = t.y[3 * u1 + 1], x2 = t.y[3 * u1 + 2];
@@ -563,14 +562,25 @@ __global__ __launch_bounds__(256) void k_rz_s0(const T *r, T *z, BlockTab tab, c
     }
     keep_loads_above();
     // z of the block's rows as the sweeps left them (the first-step rows are
-    // overwritten below)
+    // overwritten below), and r
     if (ne > 0) {
 #pragma unroll
         for (int u = 0; u < VEC_EPT; u++)
-            if (vec_own(u, ne)) zl[threadIdx.x + 256 * u] = zv[u];
+            if (vec_own(u, ne)) {
+                zl[threadIdx.x + 256 * u] = zv[u];
+                rl[threadIdx.x + 256 * u] = rv[u];
+            }
     }
     __syncthreads();
     if (mine) {
+        // the forward substitution's y = P_qq^{-1} r again (a first-step
+        // vertex has no in-slots), in the same operations
+        const int64_t i = 3 * (v - e0 / 3);
+        T y0, y1, y2;
+        if (a1 >= 0)
+            sym_mv(d, rl[i], rl[i + 1], rl[i + 2], y0, y1, y2);
+        else
+            leaf_pivot_solve(w0, t.gpar, t.gperp, t.gmed, rl[i], rl[i + 1], rl[i + 2], y0, y1, y2);
         T c0 = 0, c1 = 0, c2 = 0;
         if (a0 >= 0) {
             T e0_, e1_, e2_;
@@ -595,7 +605,6 @@ __global__ __launch_bounds__(256) void k_rz_s0(const T *r, T *z, BlockTab tab, c
         z[3 * v] = n0;
         z[3 * v + 1] = n1;
         z[3 * v + 2] = n2;
-        const int64_t i = 3 * (v - e0 / 3);
         zl[i] = n0;
         zl[i + 1] = n1;
         zl[i + 2] = n2;
