@@ -18,7 +18,8 @@ Prints ONE JSON line.  Besides the headline value it carries:
                 iterations, extrapolated to the GPU's iteration count);
   extra         the other workloads, each bounded to seconds of GPU time:
                 block-Jacobi PCG, the solve stopped on the Gauss-Radau
-                bound of the energy error, the local-MST forest (Z-order clusters
+                bound of the energy error, the whole step recorded once and
+                replayed as one hipGraph, the local-MST forest (Z-order clusters
                 of 512 to 2048 cells) and the augmented tree with its nested
                 flexible CG on the same 1M system; the 1k-cell solve's
                 latency with and without hipGraph replay; FP32-inner refinement
@@ -129,6 +130,34 @@ def extra_errstop(ctx, A, M, F):
             if stop == "error":
                 r["err_bound"] = info["err_bound"]
             out[f"{stop}_{tol:.0e}"] = r
+    return out
+
+
+def extra_graph_step(P, ctx, pos, R, F, v_eager, reps=10):
+    """The same 1M step (collide -> assemble -> tree -> factor -> tree-PCG)
+    recorded once and replayed as one hipGraph (sgp_step_*): every kernel
+    runs again on the GPU, the host's mid-step readbacks are replayed from
+    the recording and checked on the device.  Not the headline (which
+    launches every kernel eagerly); the replayed velocity is compared bit
+    for bit with the eager step's."""
+    import numpy as np
+    import torch
+    n = pos.shape[0]
+    S = P.Step(ctx)
+    v = torch.zeros_like(F)
+    t_rec, infos = _sync_time(lambda: S.record_batched([0, n], pos, R, F, v))
+    times = []
+    for _ in range(reps):
+        t, (code, rinfos) = _sync_time(lambda: S.replay())
+        times.append(t)
+    ms = 1e3 * float(np.median(times))
+    nv, nb = S.size()
+    out = {"workload": f"jittered FCC ball, {n} spheres, seed 0; whole step recorded once, replayed {reps} times",
+           "replay_ms_per_step": ms, "replay_solves_per_s": 1e3 / ms, "record_ms": 1e3 * t_rec,
+           "recorded_values": nv, "recorded_bytes": nb, "iters": rinfos[0]["iters"],
+           "v_equal_eager": bool(torch.equal(v, v_eager)),
+           "v_max_diff_rel": float((v - v_eager).abs().max() / v_eager.abs().max())}
+    del S
     return out
 
 
@@ -420,7 +449,7 @@ def main():
     ap.add_argument("--schedule", default="contract", choices=["contract", "level"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--extras", default="jacobi,errstop,forest,augmented,small,mixed,batched,learned,paper",
+    ap.add_argument("--extras", default="jacobi,errstop,graph1M,forest,augmented,small,mixed,batched,learned,paper",
                     help="comma list of extra workloads to run after the headline")
     ap.add_argument("--spmv-form", type=int, choices=[0, 1], default=None,
                     help="product form: 0 stored 3x3 blocks, 1 contacts' (w, u) (the library default)")
@@ -548,6 +577,8 @@ def main():
                 ex.update(extra_jacobi(ctx, A, M, F))
             elif name == "errstop":
                 ex["error_rule_1M"] = extra_errstop(ctx, A, M, F)
+            elif name == "graph1M":
+                ex["graph_step_1M"] = extra_graph_step(P, ctx, pos, R, F, v)
             elif name == "forest":
                 ex["forest_1M"] = extra_forest(ctx, g, A, F, pos, R)
             elif name == "augmented":
