@@ -11,8 +11,8 @@ Prints ONE JSON line.  Besides the headline value it carries:
   roofline      the CG's product Gamma p (the dominant kernel; by default the
                 edge form k_spmv_edge, from the contacts' v = sqrt(w) u and
                 the diagonal blocks): algorithmic bytes per launch / its average
-                launch time, measured with HIP events on the library's stream
-                inside the timed region;
+                launch time, measured with HIP events attached to sampled
+                launches on the library's stream inside the timed region;
   cpu_baseline  the FP64 CPU oracle timed on this host's cores on a bounded
                 sample of the same workload (setup + a fixed number of CG
                 iterations, extrapolated to the GPU's iteration count);
@@ -561,7 +561,8 @@ def main():
                      "traffic_unit": "B/launch (counters)",
                      "bytes_per_launch": bytes_spmv, "avg_launch_ms": avg_spmv_ms,
                      "launches": spmv_launches,
-                     "timed": "HIP events around one product in every 16 CG iterations (the third of a "
+                     "timed": "HIP start/stop events carried by the launch itself (hipExtLaunchKernel) of one "
+                              "product in every 4 CG iterations (the third of a "
                               f"{ctx.tune_get('check_every')}-iteration chunk, or its last) in the timed region "
                               "(products after convergence excluded)"},
         "phase_ms": {k: v_ / args.steps for k, v_ in phase.items()},

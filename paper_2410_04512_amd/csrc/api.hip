@@ -132,7 +132,7 @@ extern "C" void sgp_prec_free(sgp_prec M)
 
 int ktimer_begin(sgp_ctx c, int32_t iter)
 {
-    if (!c->ktiming) return SGP_OK;
+    if (!c->ktiming || c->plan_mode != PLAN_OFF) return SGP_OK;
     if ((int)c->kev_iter.size() <= c->kev_used / 2) c->kev_iter.resize(c->kev_used / 2 + 64);
     c->kev_iter[c->kev_used / 2] = iter;
     if (c->kev_used + 2 > (int)c->kev.size()) {
@@ -142,15 +142,21 @@ int ktimer_begin(sgp_ctx c, int32_t iter)
             c->kev.push_back(e);
         }
     }
-    HIP_TRY(c, hipEventRecord(c->kev[c->kev_used], c->stream));
+    // the product launched next takes the pair as its own start and stop
+    // (hipExtLaunchKernel): the events time the kernel itself and add no
+    // packets of their own to the stream
+    c->kt_start = c->kev[c->kev_used];
+    c->kt_stop = c->kev[c->kev_used + 1];
+    c->kt_used = false;
     return SGP_OK;
 }
 
 int ktimer_end(sgp_ctx c)
 {
     if (!c->ktiming) return SGP_OK;
-    HIP_TRY(c, hipEventRecord(c->kev[c->kev_used + 1], c->stream));
-    c->kev_used += 2;
+    if (c->kt_used) c->kev_used += 2;   // else nothing was launched (an empty product)
+    c->kt_start = c->kt_stop = nullptr;
+    c->kt_used = false;
     return SGP_OK;
 }
 

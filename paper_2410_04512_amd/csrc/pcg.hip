@@ -807,7 +807,7 @@ static int fin(sgp_ctx ctx, int op, const double *part, int nblk, const int32_t 
 }
 
 // CG iterations per timed product (at most one per chunk)
-constexpr int KT_STRIDE = 16;
+constexpr int KT_STRIDE = 4;
 
 // PCG iterations on prepared r, z (z = M r) and p, until every cluster is done.
 // `count` CG iterations, launched on ctx->stream (no host synchronisation,
@@ -823,11 +823,9 @@ static int pcg_chunk(sgp_ctx ctx, sgp_bsr A, sgp_prec M, Vecs<T> v, PcgWork &w, 
     // one cluster: the sweeps stop with it; several: every sweep runs
     PcgScalars *gate = K == 1 ? S : nullptr;
     for (int c = 0; c < count; c++) {
-        // kernel timing brackets one product in every KT_STRIDE iterations,
-        // the third of a chunk that starts a new stride (by then the host has
-        // queued well ahead of the GPU, so the pair times the kernel and not
-        // the wait for its launch); each event holds the stream for ~6 us,
-        // so pairs stay rare
+        // kernel timing: one product in every KT_STRIDE iterations carries a
+        // pair of events on its own launch, the third of a chunk that starts
+        // a new stride
         const bool timed = c == std::min(2, count - 1) && it0 % KT_STRIDE < count;
         if (timed) SGP_TRY(ktimer_begin(ctx, it0 + c));
         if (K == 1) {

@@ -73,7 +73,9 @@ struct sgp_ctx_ {
     bool phase_pending[5] = {false, false, false, false, false};   // end recorded, time not read yet
     // per-launch timing of the CG's matrix product (events on ctx->stream)
     int ktiming = 0;
-    std::vector<hipEvent_t> kev;   // pairs (before, after)
+    std::vector<hipEvent_t> kev;   // pairs (start, stop)
+    hipEvent_t kt_start = nullptr, kt_stop = nullptr;   // the pair the next product launch carries
+    bool kt_used = false;          // a launch took that pair
     std::vector<int32_t> kev_iter; // CG iteration index (from 0) of each pair's launch
     int kev_used = 0;
     double ktime_ms = 0.0;

@@ -27,6 +27,8 @@
 // without entries).
 #include "sgp_internal.h"
 
+#include <hip/hip_ext.h>
+
 constexpr int WAVE_GROUPS = 2;                       // 64-block groups per wave
 constexpr int WAVE_BLOCKS = 64 * WAVE_GROUPS;
 constexpr int ROW_MAX = 65;                          // blocks per row at most (max_deg 64 + diagonal)
@@ -328,8 +330,14 @@ static int spmv_launch(sgp_ctx ctx, sgp_bsr A, const T *val, const T *ew, const 
         const int32_t *ec = (const int32_t *)A->ecol.p, *ewr = (const int32_t *)A->ewrow.p;
         const T gp = (T)A->gpar, gq = (T)A->gperp;
         const int64_t ne = A->nnzb - A->n;
-#define SGP_EDGE_LAUNCH(W, E) \
-    k_spmv_edge<T, W, E><<<nb, 64 * W, 0, st>>>(rp, ec, ew, dg, gp, gq, x, y, ewr, nw, ne, S, part, mode)
+// a timed launch carries the kernel timer's events (ktimer_begin)
+#define SGP_EDGE_LAUNCH(W, E)                                                                                 \
+    if (ctx->kt_start) {                                                                                      \
+        hipExtLaunchKernelGGL(k_spmv_edge<T, W, E>, dim3(nb), dim3(64 * W), 0, st, ctx->kt_start, ctx->kt_stop, \
+                              0, rp, ec, ew, dg, gp, gq, x, y, ewr, nw, ne, S, part, mode);                   \
+        ctx->kt_used = true;                                                                                  \
+    } else                                                                                                    \
+        k_spmv_edge<T, W, E><<<nb, 64 * W, 0, st>>>(rp, ec, ew, dg, gp, gq, x, y, ewr, nw, ne, S, part, mode)
         switch (ctx->spmv_waves * 2 + (ne > 0)) {
         case 4: SGP_EDGE_LAUNCH(2, false); break;
         case 5: SGP_EDGE_LAUNCH(2, true); break;
@@ -341,12 +349,20 @@ static int spmv_launch(sgp_ctx ctx, sgp_bsr A, const T *val, const T *ew, const 
         }
 #undef SGP_EDGE_LAUNCH
     } else {
+#define SGP_SYM_LAUNCH(W)                                                                                     \
+    if (ctx->kt_start) {                                                                                      \
+        hipExtLaunchKernelGGL(k_spmv_sym<T, W>, dim3(nb), dim3(64 * W), 0, st, ctx->kt_start, ctx->kt_stop, 0,  \
+                              rp, bc, val, x, y, wr, nw, S, part, mode);                                      \
+        ctx->kt_used = true;                                                                                  \
+    } else                                                                                                    \
+        k_spmv_sym<T, W><<<nb, 64 * W, 0, st>>>(rp, bc, val, x, y, wr, nw, S, part, mode)
         switch (ctx->spmv_waves) {
-        case 2: k_spmv_sym<T, 2><<<nb, 128, 0, st>>>(rp, bc, val, x, y, wr, nw, S, part, mode); break;
-        case 4: k_spmv_sym<T, 4><<<nb, 256, 0, st>>>(rp, bc, val, x, y, wr, nw, S, part, mode); break;
-        case 8: k_spmv_sym<T, 8><<<nb, 512, 0, st>>>(rp, bc, val, x, y, wr, nw, S, part, mode); break;
+        case 2: SGP_SYM_LAUNCH(2); break;
+        case 4: SGP_SYM_LAUNCH(4); break;
+        case 8: SGP_SYM_LAUNCH(8); break;
         default: return set_err(ctx, SGP_EINVAL, "spmv: unsupported waves per workgroup %d", ctx->spmv_waves);
         }
+#undef SGP_SYM_LAUNCH
     }
     LAUNCH_CHECK(ctx);
     return SGP_OK;
