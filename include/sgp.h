@@ -497,8 +497,12 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
  *                 CG's x += alpha p (the rest of the chip would idle), and
  *                 the later vector pass only updates p (default 1; 0: x and
  *                 p in that pass)
+ *  "prefetch"     1: the launch before the one-workgroup tail of the tree
+ *                 sweeps also loads the tail's constants into the L2 of the
+ *                 XCD that runs the tail, so that its start-up loads hit
+ *                 there (default 1; 0: off)
  * Unknown keys or values out of range give SGP_EINVAL.  check_every,
- * graph, fuse_step0, mid_lds and tail_side leave every result bitwise
+ * graph, fuse_step0, mid_lds, tail_side and prefetch leave every result bitwise
  * unchanged, and so does tail_max as long as the tail does not reach the first elimination
  * step (that step forms its couplings from the contacts' (w, u) when it runs
  * as its own launch, from the stored blocks inside the tail: the same values

@@ -1393,6 +1393,11 @@ extern "C" int sgp_tune(sgp_ctx ctx, const char *key, int32_t value)
         ctx->tail_side = value;
         return SGP_OK;
     }
+    if (!strcmp(key, "prefetch")) {
+        if (value < 0 || value > 1) return set_err(ctx, SGP_EINVAL, "tune: prefetch must be 0 or 1");
+        ctx->prefetch = value;
+        return SGP_OK;
+    }
     return set_err(ctx, SGP_EINVAL, "tune: unknown key '%s'", key);
 }
 
@@ -1410,6 +1415,7 @@ extern "C" int sgp_tune_get(sgp_ctx ctx, const char *key, int32_t *value)
     else if (!strcmp(key, "small_solve")) *value = ctx->small_solve;
     else if (!strcmp(key, "mid_lds")) *value = ctx->mid_lds;
     else if (!strcmp(key, "tail_side")) *value = ctx->tail_side;
+    else if (!strcmp(key, "prefetch")) *value = ctx->prefetch;
     else return set_err(ctx, SGP_EINVAL, "tune_get: unknown key '%s'", key);
     return SGP_OK;
 }

@@ -90,6 +90,7 @@ struct sgp_ctx_ {
     int small_solve = 1;           // one-workgroup PCG for small single systems (small.hip)
     int mid_lds = 1;               // tree sweeps: the mid steps' slots and x in LDS (factor.hip)
     int tail_side = 1;             // CG: x += alpha p by extra workgroups of the one-workgroup tail launch
+    int prefetch = 1;              // tree sweeps: the tail's constants loaded into its XCD's L2 ahead of it
     int light_height = 0;          // rake rounds whose subtrees the sweeps handle one workgroup each (0: off)
     int light_cap = 512;           // vertices of such subtrees packed into one workgroup
     hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)

@@ -130,6 +130,7 @@ static void copy_settings(sgp_ctx to, const sgp_ctx_ *from)
     to->fuse_step0 = from->fuse_step0;
     to->mid_lds = from->mid_lds;
     to->tail_side = from->tail_side;
+    to->prefetch = from->prefetch;
     to->small_solve = from->small_solve;
     to->contact_model = from->contact_model;
 }

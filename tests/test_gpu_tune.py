@@ -40,9 +40,10 @@ def test_defaults_and_rejections(ctx):
     assert ctx.tune_get("check_every") == 2 and ctx.tune_get("tail_max") == 2200
     assert ctx.tune_get("graph") == 0 and ctx.tune_get("spmv_waves") == 4
     assert ctx.tune_get("light_height") == 0 and ctx.tune_get("light_cap") == 512
-    assert ctx.tune_get("spmv_form") == 1 and ctx.tune_get("tail_side") == 1
+    assert ctx.tune_get("spmv_form") == 1 and ctx.tune_get("tail_side") == 1 and ctx.tune_get("prefetch") == 1
     for key, bad in (("check_every", 0), ("tail_max", -1), ("graph", 2), ("spmv_waves", 3), ("nope", 1),
-                     ("light_height", -1), ("light_cap", 0), ("spmv_form", 2), ("tail_side", 2)):
+                     ("light_height", -1), ("light_cap", 0), ("spmv_form", 2), ("tail_side", 2),
+                     ("prefetch", -1)):
         with pytest.raises(P.SgpError):
             ctx.tune(key, bad)
 
@@ -410,3 +411,22 @@ def test_tail_side_update_batched(ctx):
     assert [a["iters"] for a in i1] == [b["iters"] for b in i0]
     assert len({a["iters"] for a in i1}) > 1 and all(a["status"] == 0 for a in i1)
     assert torch.equal(v0, v1)
+
+
+def test_tail_prefetch_is_bitwise_neutral(ctx):
+    """The tail's constants prefetched into L2 by the launch before it (knob
+    prefetch, on by default): the apply, the FP64 solve and the FP32
+    refinement give the same bits with it off."""
+    c, g, A, T = _system(ctx, 60000, 45)
+    F = to_dev(c["force"])
+    M = ctx.factor_tree(g, T)
+    assert M.info()["tail_step"] < M.steps()
+    b = torch.randn_like(F)
+    runs = {}
+    for on in (1, 0):
+        ctx.tune("prefetch", on)
+        runs[on] = (ctx.prec_apply(M, b), ctx.pcg_solve(A, M, F), ctx.pcg_solve(A, M, F, precision="f32ir"))
+    ctx.tune("prefetch", 1)
+    assert torch.equal(runs[1][0], runs[0][0])
+    for (va, ia), (vb, ib) in zip(runs[1][1:], runs[0][1:]):
+        assert ia["iters"] == ib["iters"] and torch.equal(va, vb)
