@@ -1090,13 +1090,6 @@ SGP_DEV void side_x_update(const SideX &sd, int wg, int nwg)
     T *x = (T *)sd.x;
     const T *p = (const T *)sd.p;
     const int tid = threadIdx.x;
-    // wait about 7 us (2 x 127 x 64 clocks) first, so that the tail's own
-    // first loads are served before this stream fills the memory queues
-    // (1M cells: the tail launch 35.9 us without the wait, 33.6 us with it,
-    // 32.6 us without the side update, which moves as many bytes as the
-    // CG's 12.9 us p-only pass)
-    __builtin_amdgcn_s_sleep(127);
-    __builtin_amdgcn_s_sleep(127);
     for (int b0 = wg * SIDE_BLOCKS; b0 < sd.nb; b0 += nwg * SIDE_BLOCKS) {
         int64_t e0[SIDE_BLOCKS];
         int nel[SIDE_BLOCKS], inst[SIDE_BLOCKS];
@@ -1129,6 +1122,70 @@ SGP_DEV void side_x_update(const SideX &sd, int wg, int nwg)
     }
 }
 
+// The backward mid steps' constants (ids, up-links, their local indices,
+// pivots, both coupling planes) loaded into the L2 of the XCD whose
+// k_bwd_mid workgroups will sweep them, by this XCD's extra workgroups of
+// the tail launch (block b of a launch runs on XCD b mod 8; k_bwd_mid's
+// group of block b is xcd_block(b), so XCD x sweeps one contiguous range of
+// groups, and in every mid step their positions are contiguous).  The
+// step ranges go through LDS; each workgroup takes its share of the
+// positions, two per thread per round, every load of a round issued before
+// any is used; the sums are stored only if sd.never says so.
+template <class T>
+SGP_DEV void mid_prefetch(const SideX &sd, int32_t nside, const int32_t *elim, const int32_t *upq, const T *F,
+                          int64_t fs, const T *Dinv, int32_t *rg, T *sink)
+{
+    const int32_t b = (int32_t)blockIdx.x, x = b % NUM_XCD, L = sd.mid_L;
+    const int32_t firstb = x == 0 ? NUM_XCD : x;   // this XCD's extra workgroups: firstb, firstb + 8, ...
+    const int32_t nx = (nside - firstb) / NUM_XCD + 1, ix = (b - firstb) / NUM_XCD;
+    const int32_t nw = sd.mid_nwg, q8 = nw / NUM_XCD, r8 = nw % NUM_XCD;
+    const int32_t w0 = x < r8 ? x * (q8 + 1) : r8 * (q8 + 1) + (x - r8) * q8;
+    const int32_t w1 = w0 + q8 + (x < r8 ? 1 : 0);
+    const int tid = threadIdx.x;
+    if (tid < 2 * L) rg[tid] = sd.mid_wptr[(int64_t)(tid >> 1) * nw + ((tid & 1) ? w1 : w0)];
+    __syncthreads();
+    int32_t P = 0;
+    for (int32_t k = 0; k < L; k++) P += rg[2 * k + 1] - rg[2 * k];
+    const int32_t f0 = (int32_t)((int64_t)P * ix / nx), f1 = (int32_t)((int64_t)P * (ix + 1) / nx);
+    T acc = 0;
+    int32_t iacc = 0;
+    for (int32_t f = f0 + tid; f < f1; f += 2 * TAIL_THREADS) {
+        int32_t q[2];
+        bool on[2];
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            int32_t l = f + TAIL_THREADS * u, k = 0;
+            on[u] = l < f1;
+            while (k < L - 1 && l >= rg[2 * k + 1] - rg[2 * k]) {
+                l -= rg[2 * k + 1] - rg[2 * k];
+                k++;
+            }
+            q[u] = on[u] ? rg[2 * k] + l : rg[0];
+        }
+        T d[2][6], g0[2][9], g1[2][9];
+        int32_t iv[2][5];
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int64_t qq = q[u];
+            iv[u][0] = elim[qq];
+            iv[u][1] = upq[2 * qq];
+            iv[u][2] = upq[2 * qq + 1];
+            iv[u][3] = sd.mid_lup[2 * (qq - sd.mid_Q0)];
+            iv[u][4] = sd.mid_lup[2 * (qq - sd.mid_Q0) + 1];
+            for (int t = 0; t < 6; t++) d[u][t] = Dinv[6 * qq + t];
+            for (int t = 0; t < 9; t++) g0[u][t] = F[9 * qq + t];
+            for (int t = 0; t < 9; t++) g1[u][t] = F[fs + 9 * qq + t];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            for (int t = 0; t < 5; t++) iacc += iv[u][t];
+            for (int t = 0; t < 6; t++) acc += d[u][t];
+            for (int t = 0; t < 9; t++) acc += g0[u][t] + g1[u][t];
+        }
+    }
+    if (sd.never) sink[0] = acc + (T)iacc;
+}
+
 // The tail's steps fall in two parts.  Steps whose vertices all lie in the
 // last TAIL_WINDOW tail vertices (the window, from step kw on: usually most
 // of the steps, few vertices each) give vertices base + t and base +
@@ -1146,12 +1203,25 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
                                                        int64_t fs, const T *Dinv, const T *tb, T *y, T *z,
                                                        const PcgScalars *s, SideX side)
 {
-    // workgroups past the first: the CG's x update, meanwhile
+    extern __shared__ unsigned char lds_raw[];
+    // workgroups past the first: the CG's x update, meanwhile, then the
+    // backward mid steps' constants into this XCD's L2
     if (blockIdx.x > 0) {
-        side_x_update<T>(side, blockIdx.x - 1, gridDim.x - 1);
+        // unless the tail's constants were prefetched into L2 (k_tail_pre),
+        // wait about 7 us (2 x 127 x 64 clocks) first, so that the tail's
+        // own first loads are served before these streams fill the memory
+        // queues (1M cells, without the prefetches: the tail launch with the
+        // x update 35.9 us without the wait, 33.6 us with it, 32.6 us without
+        // the x update; with both prefetches, 26.3 us without the wait and
+        // 30.3 us with it)
+        if (side.wait) {
+            __builtin_amdgcn_s_sleep(127);
+            __builtin_amdgcn_s_sleep(127);
+        }
+        if (side.nb > 0) side_x_update<T>(side, blockIdx.x - 1, gridDim.x - 1);
+        if (side.mid_L > 0) mid_prefetch<T>(side, gridDim.x - 1, elim, upq, F, fs, Dinv, (int32_t *)lds_raw, z);
         return;
     }
-    extern __shared__ unsigned char lds_raw[];
     T *sv = (T *)lds_raw;
     T *slot = sv + 3 * nt;
     // step bounds of the tail steps, sp[k] for k = s0..S, kept in LDS
@@ -1358,6 +1428,8 @@ struct MidTab {
 };
 
 constexpr int MID_MAX_STEPS = 64;   // mid steps at most for the LDS sweeps
+constexpr int TAIL_EXTRA_WG = 255;   // extra workgroups of the tail launch that prefetch: one per other CU
+static_assert(2 * MID_MAX_STEPS <= TAIL_THREADS, "the step ranges load in one round");
 
 // the group's position range of each of its L steps, rg[2k] .. rg[2k + 1],
 // loaded into LDS in one round (a walk over global memory would take a
@@ -1792,6 +1864,18 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
         if (side && side->nb > 0 && side->nwg > 0) {
             sd = *side;
             side->ran = true;
+        }
+        // and, one per other CU, they load the backward mid steps' constants
+        // into the L2 of the XCD that sweeps them (knob prefetch)
+        sd.wait = !ctx->prefetch;
+        if (ctx->prefetch && mid_lds) {
+            sd.mid_wptr = mptr;
+            sd.mid_lup = mtab.lup;
+            sd.mid_L = m1 - m0;
+            sd.mid_nwg = M->mid_nwg;
+            sd.mid_Q0 = sp[m0];
+            sd.nwg = TAIL_EXTRA_WG;
+            lds = std::max(lds, (size_t)(2 * MID_MAX_STEPS * sizeof(int32_t)));
         }
         k_tail<T><<<1 + (unsigned)sd.nwg, TAIL_THREADS, lds, st>>>(
             ts, S, kw, sp[ts], q1a, nt, M->tail_ni, dsp, elim, in_ptr, (const int32_t *)M->tail_iptr.p,

@@ -300,6 +300,12 @@ struct SideX {
     int32_t nb;            // vector blocks
     int32_t nwg;           // extra workgroups
     bool ran;              // set by the sweeps when the update was launched
+    // filled by the sweeps (knob prefetch): after the update, the same
+    // workgroups load the backward mid steps' constants into the L2 of the
+    // XCD that will sweep them (mid_L = 0: none)
+    const int32_t *mid_wptr, *mid_lup;
+    int32_t mid_L, mid_nwg, mid_Q0, never;
+    int32_t wait;          // sleep ~7 us before either job (the tail's constants not prefetched)
 };
 
 // shared by several translation units
