@@ -498,9 +498,10 @@ int sgp_mpnn_warm_start(sgp_ctx ctx, sgp_mpnn M, sgp_graph g, sgp_bsr Gamma, con
  *                 the later vector pass only updates p (default 1; 0: x and
  *                 p in that pass)
  *  "prefetch"     1: the launch before the one-workgroup tail of the tree
- *                 sweeps also loads the tail's constants into the L2 of the
- *                 XCD that runs the tail, so that its start-up loads hit
- *                 there (default 1; 0: off)
+ *                 sweeps also loads the tail's constants, from the XCD that
+ *                 runs the tail, and the tail launch's other workgroups load
+ *                 the backward mid steps' constants, so that those launches'
+ *                 start-up loads hit in the caches (default 1; 0: off)
  * Unknown keys or values out of range give SGP_EINVAL.  check_every,
  * graph, fuse_step0, mid_lds, tail_side and prefetch leave every result bitwise
  * unchanged, and so does tail_max as long as the tail does not reach the first elimination

@@ -932,15 +932,15 @@ constexpr int TAIL_RHS_PER_THREAD = (3 * TAIL_MAX_VERTICES + TAIL_THREADS - 1) /
 constexpr int64_t MID_MAX_VERTICES = 1 << 17;   // vertices left at the first mid step at most
 
 // The tail's constants (pivots, both coupling planes, push slots, up-links,
-// ids, in-slot bounds of its nt vertices) loaded into the L2 of the XCD
-// that runs the tail's single workgroup, so that its start-up loads hit
-// there.  Workgroup i of a launch runs on XCD i mod 8; the tail launch's
+// ids, in-slot bounds of its nt vertices) loaded ahead, from the XCD that
+// runs the tail's single workgroup, so that its start-up loads hit in the
+// caches.  Workgroup i of a launch runs on XCD i mod 8; the tail launch's
 // first workgroup is the tail, so the prefetching workgroups are the
 // TAIL_PF_WG / 8 of this launch with blockIdx = 0 mod 8, 64 threads each, a
 // thread's loads all issued before any is used.  Their sum is stored only if
 // `never` (0) says so, which keeps the loads.  1M cells: the tail launch
-// 33.8 -> 28.0 us (29.0 us with the same loads spread over all XCDs, which
-// warms only the shared last-level cache); the pre-tail launch unchanged.
+// 33.8 -> 28.0 us (29.0 us with the same loads spread over all XCDs); the
+// pre-tail launch unchanged.
 constexpr int TAIL_PF_WG = 1024;
 constexpr int TAIL_PF_THREADS = TAIL_PF_WG / 8 * 64;
 static_assert(9 * TAIL_MAX_VERTICES <= 4 * TAIL_PF_THREADS && 2 * TAIL_MAX_VERTICES + 1 <= 2 * TAIL_PF_THREADS,
@@ -1123,8 +1123,10 @@ SGP_DEV void side_x_update(const SideX &sd, int wg, int nwg)
 }
 
 // The backward mid steps' constants (ids, up-links, their local indices,
-// pivots, both coupling planes) loaded into the L2 of the XCD whose
-// k_bwd_mid workgroups will sweep them, by this XCD's extra workgroups of
+// pivots, both coupling planes) loaded ahead, from the XCD whose k_bwd_mid
+// workgroups will sweep them (the counters show k_bwd_mid fetching as many
+// bytes from beyond L2 as without it: the gain, 14.7 -> 12.7 us at 1M cells,
+// is the last-level cache's), by this XCD's extra workgroups of
 // the tail launch (block b of a launch runs on XCD b mod 8; k_bwd_mid's
 // group of block b is xcd_block(b), so XCD x sweeps one contiguous range of
 // groups, and in every mid step their positions are contiguous).  The
@@ -1205,9 +1207,9 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
 {
     extern __shared__ unsigned char lds_raw[];
     // workgroups past the first: the CG's x update, meanwhile, then the
-    // backward mid steps' constants into this XCD's L2
+    // backward mid steps' constants into the caches
     if (blockIdx.x > 0) {
-        // unless the tail's constants were prefetched into L2 (k_tail_pre),
+        // unless the tail's constants were prefetched (k_tail_pre),
         // wait about 7 us (2 x 127 x 64 clocks) first, so that the tail's
         // own first loads are served before these streams fill the memory
         // queues (1M cells, without the prefetches: the tail launch with the
@@ -1866,7 +1868,7 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
             side->ran = true;
         }
         // and, one per other CU, they load the backward mid steps' constants
-        // into the L2 of the XCD that sweeps them (knob prefetch)
+        // ahead of k_bwd_mid (knob prefetch)
         sd.wait = !ctx->prefetch;
         if (ctx->prefetch && mid_lds) {
             sd.mid_wptr = mptr;

@@ -90,7 +90,7 @@ struct sgp_ctx_ {
     int small_solve = 1;           // one-workgroup PCG for small single systems (small.hip)
     int mid_lds = 1;               // tree sweeps: the mid steps' slots and x in LDS (factor.hip)
     int tail_side = 1;             // CG: x += alpha p by extra workgroups of the one-workgroup tail launch
-    int prefetch = 1;              // tree sweeps: the tail's constants loaded into its XCD's L2 ahead of it
+    int prefetch = 1;              // tree sweeps: the tail's and the backward mid steps' constants loaded ahead
     int light_height = 0;          // rake rounds whose subtrees the sweeps handle one workgroup each (0: off)
     int light_cap = 512;           // vertices of such subtrees packed into one workgroup
     hipStream_t cap_stream = nullptr;   // private stream for graph capture (created on first use)
@@ -301,8 +301,8 @@ struct SideX {
     int32_t nwg;           // extra workgroups
     bool ran;              // set by the sweeps when the update was launched
     // filled by the sweeps (knob prefetch): after the update, the same
-    // workgroups load the backward mid steps' constants into the L2 of the
-    // XCD that will sweep them (mid_L = 0: none)
+    // workgroups load the backward mid steps' constants ahead, from the XCD
+    // that will sweep them (mid_L = 0: none)
     const int32_t *mid_wptr, *mid_lup;
     int32_t mid_L, mid_nwg, mid_Q0, never;
     int32_t wait;          // sleep ~7 us before either job (the tail's constants not prefetched)
