@@ -1420,7 +1420,9 @@ constexpr int MID_THREADS = 512;
 // vertices of one group at most (components are packed by their first
 // vertex's offset / light_cap, so a group can exceed light_cap by up to one
 // component less a vertex)
-constexpr int MID_LDS_MAX = 2 * MID_THREADS;
+constexpr int MID_LDS_MAX = 1024;
+constexpr int MID_VPT = MID_LDS_MAX / MID_THREADS;   // a thread's vertices
+static_assert(MID_VPT * MID_THREADS == MID_LDS_MAX, "whole vertices per thread");
 
 // per mid vertex (index q - Q0): local index, first LDS slot and number of
 // in-entries from mid vertices; per push (2 (q - Q0) + k): its LDS slot or -1;
@@ -1489,8 +1491,8 @@ __global__ __launch_bounds__(MID_THREADS) void k_mid_local(int32_t L, int32_t nw
         if (tid == 0) flag[0] = 1;
         return;
     }
-    int32_t q[2], st[2];
-    for (int u = 0; u < 2; u++) {
+    int32_t q[MID_VPT], st[MID_VPT];
+    for (int u = 0; u < MID_VPT; u++) {
         const int32_t l = tid + MID_THREADS * u;
         q[u] = mid_local(L, rg, l, st[u]);
         cnt[l] = l < tot ? nint[q[u] - Q0] : 0;
@@ -1507,7 +1509,7 @@ __global__ __launch_bounds__(MID_THREADS) void k_mid_local(int32_t L, int32_t nw
         if (s > 2 * MID_LDS_MAX) flag[0] = 1;
     }
     __syncthreads();
-    for (int u = 0; u < 2; u++) {
+    for (int u = 0; u < MID_VPT; u++) {
         const int32_t l = tid + MID_THREADS * u;
         if (l >= tot) continue;
         lid[q[u] - Q0] = l;
@@ -1552,14 +1554,14 @@ __global__ __launch_bounds__(MID_THREADS) void k_fwd_mid(int32_t L, int32_t nwg,
     if (s && s->done) return;
     const int32_t w = (int32_t)xcd_block(blockIdx.x, gridDim.x), tid = threadIdx.x;
     mid_ranges(L, nwg, wptr, w, rg);
-    int32_t q[2], st[2], ni[2], l0[2], ls[2][2], to[2][2], t0[2], t1[2];
-    int64_t v[2];
-    T d[2][6], f0[2][9], f1[2][9], b[2][3], h[2][12];
+    int32_t q[MID_VPT], st[MID_VPT], ni[MID_VPT], l0[MID_VPT], ls[MID_VPT][2], to[MID_VPT][2], t0[MID_VPT], t1[MID_VPT];
+    int64_t v[MID_VPT];
+    T d[MID_VPT][6], f0[MID_VPT][9], f1[MID_VPT][9], b[MID_VPT][3], h[MID_VPT][12];
     // two rounds of loads for both vertices: what the position gives, then
     // what those values address (r, the second coupling, the first four slots
     // filled by earlier launches, clamped); one wait between them
 #pragma unroll
-    for (int u = 0; u < 2; u++) {
+    for (int u = 0; u < MID_VPT; u++) {
         q[u] = mid_local(L, rg, tid + MID_THREADS * u, st[u]);
         const int32_t qc = st[u] >= 0 ? q[u] : Q0;   // a thread without a vertex loads a valid one
         v[u] = elim[qc];
@@ -1576,7 +1578,7 @@ __global__ __launch_bounds__(MID_THREADS) void k_fwd_mid(int32_t L, int32_t nwg,
     }
     keep_loads_above();
 #pragma unroll
-    for (int u = 0; u < 2; u++) {
+    for (int u = 0; u < MID_VPT; u++) {
         const int32_t qc = st[u] >= 0 ? q[u] : Q0;
         b[u][0] = r[3 * v[u]];
         b[u][1] = r[3 * v[u] + 1];
@@ -1595,7 +1597,7 @@ __global__ __launch_bounds__(MID_THREADS) void k_fwd_mid(int32_t L, int32_t nwg,
     // r minus the slots filled by earlier launches (the first in-entries), in
     // slot order: the first four from h, any further ones loaded here
 #pragma unroll
-    for (int u = 0; u < 2; u++) {
+    for (int u = 0; u < MID_VPT; u++) {
         const int32_t te = t1[u] - ni[u];
         for (int m = 0; m < 4; m++)
             if (t0[u] + m < te) {
@@ -1607,7 +1609,7 @@ __global__ __launch_bounds__(MID_THREADS) void k_fwd_mid(int32_t L, int32_t nwg,
     }
     for (int32_t k = 0; k < L; k++) {
 #pragma unroll
-        for (int u = 0; u < 2; u++) {
+        for (int u = 0; u < MID_VPT; u++) {
             if (st[u] != k) continue;
             T c0 = b[u][0], c1 = b[u][1], c2 = b[u][2];
             for (int32_t j = 0; j < ni[u]; j++) {
@@ -1651,12 +1653,12 @@ __global__ __launch_bounds__(MID_THREADS) void k_bwd_mid(int32_t L, int32_t nwg,
     if (s && s->done) return;
     const int32_t w = (int32_t)xcd_block(blockIdx.x, gridDim.x), tid = threadIdx.x;
     mid_ranges(L, nwg, wptr, w, rg);
-    int32_t q[2], st[2], lu[2][2], ua[2][2];
-    int64_t v[2];
-    T d[2][6], f0[2][9], f1[2][9], yo[2][3], xo[2][2][3];
+    int32_t q[MID_VPT], st[MID_VPT], lu[MID_VPT][2], ua[MID_VPT][2];
+    int64_t v[MID_VPT];
+    T d[MID_VPT][6], f0[MID_VPT][9], f1[MID_VPT][9], yo[MID_VPT][3], xo[MID_VPT][2][3];
     // two rounds of loads for both vertices, one wait between them
 #pragma unroll
-    for (int u = 0; u < 2; u++) {
+    for (int u = 0; u < MID_VPT; u++) {
         q[u] = mid_local(L, rg, tid + MID_THREADS * u, st[u]);
         const int32_t qc = st[u] >= 0 ? q[u] : Q0;
         v[u] = elim[qc];
@@ -1672,7 +1674,7 @@ __global__ __launch_bounds__(MID_THREADS) void k_bwd_mid(int32_t L, int32_t nwg,
     keep_loads_above();
     // x of up-links outside the group (final: swept by earlier launches)
 #pragma unroll
-    for (int u = 0; u < 2; u++) {
+    for (int u = 0; u < MID_VPT; u++) {
         const int32_t qc = st[u] >= 0 ? q[u] : Q0;
         for (int k = 0; k < 2; k++) {
             const int64_t a = ua[u][k] >= 0 && lu[u][k] < 0 ? ua[u][k] : qc;
@@ -1681,7 +1683,7 @@ __global__ __launch_bounds__(MID_THREADS) void k_bwd_mid(int32_t L, int32_t nwg,
     }
     for (int32_t k = L - 1; k >= 0; k--) {
 #pragma unroll
-        for (int u = 0; u < 2; u++) {
+        for (int u = 0; u < MID_VPT; u++) {
             if (st[u] != k) continue;
             T a0 = 0, a1 = 0, a2 = 0;
             for (int m = 0; m < 2; m++) {
