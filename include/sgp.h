@@ -52,7 +52,8 @@ typedef enum {
     SGP_ENOCONV = -6,     /* max_iter reached before the tolerance */
     SGP_EBREAKDOWN = -7,  /* CG breakdown: p.Gamma p <= 0 or not finite */
     SGP_ENONFINITE = -8,  /* NaN or Inf in an input or an iterate */
-    SGP_ESTALE = -9       /* a recorded step cannot replay these inputs: record it again */
+    SGP_ESTALE = -9       /* a recorded step cannot replay these inputs (record it again), or
+                             Gamma's 3x3 blocks are asked for after its graph was collided again */
 } sgp_status;
 
 typedef struct sgp_ctx_ *sgp_ctx;
@@ -133,7 +134,12 @@ void sgp_bsr_free(sgp_bsr A);
  * W_e = w_e (g_par u u^T + g_perp (I - u u^T)), Gamma_ij = Gamma_ji = -W_e;
  * Gamma_ii = g_med I + the W_e of cell i's contacts added in ascending
  * neighbour order.  Row i holds its neighbours and itself, columns ascending.
- * g_par, g_perp > 0 and g_med >= 0, else SGP_EINVAL. */
+ * g_par, g_perp > 0 and g_med >= 0, else SGP_EINVAL.  Stored in the form the
+ * product reads (tune key spmv_form): the contacts' v = sqrt(w) u with the
+ * diagonal blocks, and the 3x3 blocks themselves only for the block-CSR
+ * product (spmv_form 0; assembled on first use when that key changes after
+ * the assembly, which needs g not collided again since: SGP_ESTALE
+ * otherwise).  sgp_bsr_export always rebuilds the blocks from g. */
 int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double g_perp, double g_med,
                        sgp_bsr A);
 

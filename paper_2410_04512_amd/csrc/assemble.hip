@@ -95,16 +95,20 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t n, const int32_t *rowp
             double B[9];
             friction_block_asm(q.x, q.y, q.z, q.w, gpar, gperp, W);
             for (int x = 0; x < 9; x++) B[x] = -W[x];
-            put_sym(val, k0 + c, B);
-            bcol[k0 + c] = jc;
-            // edge form: entry k0 + c - i keeps v = sqrt(w) u
-            const int64_t ke = k0 + c - i;
-            double *g = ew + (ke >> 6) * (64 * EDGE_PLANES) + (ke & 63);
-            const double sw = sqrt(q.x);
-            g[0] = sw * q.y;
-            g[64] = sw * q.z;
-            g[128] = sw * q.w;
-            ecol[ke] = jc;
+            if (val) {
+                put_sym(val, k0 + c, B);
+                bcol[k0 + c] = jc;
+            }
+            if (ew) {
+                // edge form: entry k0 + c - i keeps v = sqrt(w) u
+                const int64_t ke = k0 + c - i;
+                double *g = ew + (ke >> 6) * (64 * EDGE_PLANES) + (ke & 63);
+                const double sw = sqrt(q.x);
+                g[0] = sw * q.y;
+                g[64] = sw * q.z;
+                g[128] = sw * q.w;
+                ecol[ke] = jc;
+            }
         }
         for (int x = 0; x < 9; x++) sW[grp][c0][x] = W[x];
         // lanes exchange through LDS within their wave only
@@ -124,10 +128,10 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t n, const int32_t *rowp
     const int slot = c0 == 0 ? 0 : c0 == 1 ? 1 : c0 == 2 ? 2 : c0 == 4 ? 3 : c0 == 5 ? 4 : c0 == 8 ? 5 : -1;
     const int64_t k = k0 + deg;
     if (slot >= 0) {
-        val[(k >> 6) * 384 + 64 * slot + (k & 63)] = d;
-        dg[(i >> 6) * 384 + 64 * slot + (i & 63)] = d;
+        if (val) val[(k >> 6) * 384 + 64 * slot + (k & 63)] = d;
+        if (ew) dg[(i >> 6) * 384 + 64 * slot + (i & 63)] = d;
     }
-    if (c0 == 0) {
+    if (c0 == 0 && val) {
         bcol[k] = (int32_t)i;
         diagpos[i] = (int32_t)k;
     }
@@ -182,14 +186,13 @@ extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double
     A->gen = next_gen();
     A->n = n;
     A->nnzb = nnzb;
-    A->have32 = false;
-    int32_t *brow, *bcol, *dpos, *deg, *ecol;
-    double *val, *ew, *dg;
+    A->have32 = A->have_val32 = false;
+    A->have_blocks = false;
+    A->src_version = g->version;
+    int32_t *brow, *deg, *ecol;
+    double *ew, *dg;
     const int64_t ne = 2 * g->m;
     SGP_TRY(ensure_t(ctx, A->rowptr, n + 1, &brow));
-    SGP_TRY(ensure_t(ctx, A->bcol, nnzb + 1, &bcol));
-    SGP_TRY(ensure_t(ctx, A->val, sym_group_size(nnzb) + 8, &val));
-    SGP_TRY(ensure_t(ctx, A->diagpos, n + 1, &dpos));
     SGP_TRY(ensure_t(ctx, A->ecol, ne + 1, &ecol));
     SGP_TRY(ensure_t(ctx, A->ew, edge_group_size(ne) + 8, &ew));
     SGP_TRY(ensure_t(ctx, A->dg, sym_group_size(n) + 8, &dg));
@@ -203,7 +206,6 @@ extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double
     }
     SGP_TRY(copy_order(ctx, A->perm, A->inv, g->perm, g->inv, n));
     // zero the padding of the last groups (read by no row, kept finite)
-    SGP_TRY(fill_f64(ctx, val + (sym_group_size(nnzb) - 384), 0.0, 384));
     SGP_TRY(fill_f64(ctx, dg + (sym_group_size(n) - 384), 0.0, 384));
     if (ne > 0) SGP_TRY(fill_f64(ctx, ew + (edge_group_size(ne) - 64 * EDGE_PLANES), 0.0, 64 * EDGE_PLANES));
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_DEG], n + 1, &deg));
@@ -212,10 +214,41 @@ extern "C" int sgp_assemble_gamma(sgp_ctx ctx, sgp_graph g, double g_par, double
     k_assemble<<<grid_for(ASM_LANES * n, 256), 256, 0, st>>>(n, (const int32_t *)g->rowptr.p, (const int32_t *)g->col.p,
                                                  (const int32_t *)g->ent_edge.p, (const double4 *)g->wu.p,
                                                  (const int32_t *)g->perm.p, (const int32_t *)g->inv.p, g_par,
-                                                 g_perp, g_med, brow, bcol, val, dpos, ecol, ew, dg);
+                                                 g_perp, g_med, brow, nullptr, nullptr, nullptr, ecol, ew, dg);
     LAUNCH_CHECK(ctx);
+    // the 3x3 blocks only for the block-CSR product (else on first use)
+    if (ctx->spmv_form == 0) SGP_TRY(bsr_blocks(ctx, A));
     SGP_TRY(bsr_prepare(ctx, A));
     phase_end(ctx, 1);
+    return SGP_OK;
+}
+
+// Gamma's 3x3 blocks in block CSR (val, bcol, diagpos), read only by the
+// block-CSR product (spmv_form 0) and its FP32 copy: assembled with the edge
+// form when that product is the knob's choice, else on first use, by the
+// same kernel from the same graph (so bit for bit the same values; an error
+// if the graph has been collided again since).
+int bsr_blocks(sgp_ctx ctx, sgp_bsr A)
+{
+    if (A->have_blocks) return SGP_OK;
+    const int64_t n = A->n, nnzb = A->nnzb;
+    int32_t *bcol, *dpos;
+    double *val;
+    SGP_TRY(ensure_t(ctx, A->bcol, nnzb + 1, &bcol));
+    SGP_TRY(ensure_t(ctx, A->val, sym_group_size(nnzb) + 8, &val));
+    SGP_TRY(ensure_t(ctx, A->diagpos, n + 1, &dpos));
+    if (n > 0) {
+        sgp_graph g = A->src;
+        if (!g || g->n != n || g->version != A->src_version)
+            return set_err(ctx, SGP_ESTALE, "Gamma's blocks: the graph was collided again since the assembly");
+        SGP_TRY(fill_f64(ctx, val + (sym_group_size(nnzb) - 384), 0.0, 384));
+        k_assemble<<<grid_for(ASM_LANES * n, 256), 256, 0, ctx->stream>>>(
+            n, (const int32_t *)g->rowptr.p, (const int32_t *)g->col.p, (const int32_t *)g->ent_edge.p,
+            (const double4 *)g->wu.p, (const int32_t *)g->perm.p, (const int32_t *)g->inv.p, A->gpar, A->gperp,
+            A->gmed, (const int32_t *)A->rowptr.p, bcol, val, dpos, nullptr, nullptr, nullptr);
+        LAUNCH_CHECK(ctx);
+    }
+    A->have_blocks = true;
     return SGP_OK;
 }
 
@@ -255,11 +288,17 @@ __global__ void k_round32(int64_t len, const double *a, float *b)
 // same layout)
 int bsr_make32(sgp_ctx ctx, sgp_bsr A)
 {
+    // the blocks' FP32 copy for the block-CSR product only
+    if (ctx->spmv_form == 0 && !A->have_val32) {
+        SGP_TRY(bsr_blocks(ctx, A));
+        float *v32;
+        int64_t len = sym_group_size(A->nnzb);
+        SGP_TRY(ensure_t(ctx, A->val32, len + 8, &v32));
+        if (A->nnzb > 0) k_round32<<<grid_for(len, 256), 256, 0, ctx->stream>>>(len, (const double *)A->val.p, v32);
+        LAUNCH_CHECK(ctx);
+        A->have_val32 = true;
+    }
     if (A->have32) return SGP_OK;
-    float *v32;
-    int64_t len = sym_group_size(A->nnzb);
-    SGP_TRY(ensure_t(ctx, A->val32, len + 8, &v32));
-    if (A->nnzb > 0) k_round32<<<grid_for(len, 256), 256, 0, ctx->stream>>>(len, (const double *)A->val.p, v32);
     // the edge form: (w, u) and the diagonal blocks, rounded once
     float *e32, *d32;
     const int64_t elen = edge_group_size(A->nnzb - A->n), dlen = sym_group_size(A->n);

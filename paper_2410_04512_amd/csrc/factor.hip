@@ -2390,12 +2390,12 @@ extern "C" int sgp_factor_tree(sgp_ctx ctx, sgp_graph g, sgp_tree T, double g_pa
     return SGP_OK;
 }
 
-__global__ void k_jacobi_make(int64_t n, const int32_t *diagpos, const double *val, double *dinv, int32_t *status)
+// from the diagonal blocks of the edge form (64-row groups of 6 planes)
+__global__ void k_jacobi_make(int64_t n, const double *dg, double *dinv, int32_t *status)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t k = diagpos[i];
-    const double *g = val + (k >> 6) * 384 + (k & 63);
+    const double *g = dg + (i >> 6) * 384 + (i & 63);
     double D[9] = {g[0], g[64], g[128], g[64], g[192], g[256], g[128], g[256], g[320]};
     double inv[6];
     if (!spd_inverse3(D, inv)) {
@@ -2422,8 +2422,7 @@ extern "C" int sgp_make_jacobi(sgp_ctx ctx, sgp_bsr A, sgp_prec M)
     SGP_TRY(ensure_t(ctx, ctx->ws[WS_TMP9], 4, &status));
     SGP_TRY(fill_i32(ctx, status, 0, 1));
     if (A->n > 0)
-        k_jacobi_make<<<grid_for(A->n, 256), 256, 0, st>>>(A->n, (const int32_t *)A->diagpos.p,
-                                                         (const double *)A->val.p, dinv, status);
+        k_jacobi_make<<<grid_for(A->n, 256), 256, 0, st>>>(A->n, (const double *)A->dg.p, dinv, status);
     LAUNCH_CHECK(ctx);
     int32_t *h = (int32_t *)ctx->pinned;
     SGP_TRY(readback(ctx, h, status, 4));

@@ -1238,6 +1238,8 @@ static int solve_common(sgp_ctx ctx, sgp_bsr A, sgp_prec M, const std::vector<in
     if (M && M->kind != PREC_NONE && M->n != A->n) return set_err(ctx, SGP_EINVAL, "pcg_solve: M and A differ in size");
     if (!(opts->rtol >= 0.0)) return set_err(ctx, SGP_EINVAL, "pcg_solve: rtol must be >= 0");
     if (M && M->kind == PREC_NONE) M = nullptr;
+    // the block-CSR product's blocks, before any iteration is captured
+    if (!ctx->spmv_form) SGP_TRY(bsr_blocks(ctx, A));
     if (opts->stop != SGP_STOP_RESIDUAL && opts->stop != SGP_STOP_ERROR)
         return set_err(ctx, SGP_EINVAL, "pcg_solve: unknown stopping rule %d", opts->stop);
     if (opts->stop == SGP_STOP_ERROR) {

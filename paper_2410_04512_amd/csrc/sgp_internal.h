@@ -134,7 +134,10 @@ struct sgp_graph_ {
 struct sgp_bsr_ {
     int64_t n = 0, nnzb = 0;
     uint64_t gen = 0;   // new at every assembly (next_gen)
-    DevBuf rowptr, bcol, val, val32, diagpos;   // internal order
+    DevBuf rowptr, bcol, val, val32, diagpos;   // internal order; bcol, val, diagpos only once have_blocks
+    bool have_blocks = false;                   // the 3x3 blocks assembled (bsr_blocks)
+    bool have_val32 = false;                    // their FP32 copy
+    uint64_t src_version = 0;                   // the graph's version at assembly
     DevBuf perm, inv;                           // copy of the graph's order
     sgp_graph src = nullptr;                    // graph it was assembled from (canonical export)
     double gpar = 0, gperp = 0, gmed = 0;
@@ -317,6 +320,8 @@ int copy_order(sgp_ctx ctx, DevBuf &dperm, DevBuf &dinv, const DevBuf &sperm, co
 int prec_apply_f32(sgp_ctx ctx, sgp_prec M, const float *r, float *z, PcgScalars *s, bool skip0 = false,
                    SideX *side = nullptr);
 int32_t prec_step0_launch(sgp_prec M);
+// Gamma's 3x3 blocks (block-CSR product), assembled on first use
+int bsr_blocks(sgp_ctx ctx, sgp_bsr A);
 // a number no earlier call returned (generations of matrices and factors)
 uint64_t next_gen();
 // the whole PCG of one small system in one workgroup (small.hip)

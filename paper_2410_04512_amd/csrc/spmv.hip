@@ -323,6 +323,9 @@ static int spmv_launch(sgp_ctx ctx, sgp_bsr A, const T *val, const T *ew, const 
 {
     const int64_t nw = ctx->spmv_form ? A->enwaves : A->nwaves;
     if (nw == 0) return SGP_OK;
+    // the block form reads blocks its caller built (spmv_f64 / spmv_f32)
+    if (!ctx->spmv_form && (!val || !A->have_blocks))
+        return set_err(ctx, SGP_EINVAL, "spmv: the block-CSR product without its blocks");
     const int nb = spmv_blocks(ctx, A);
     hipStream_t st = ctx->stream;
     const int32_t *rp = (const int32_t *)A->rowptr.p, *bc = (const int32_t *)A->bcol.p, *wr = (const int32_t *)A->wrow.p;
@@ -370,12 +373,16 @@ static int spmv_launch(sgp_ctx ctx, sgp_bsr A, const T *val, const T *ew, const 
 
 int spmv_f64(sgp_ctx ctx, sgp_bsr A, const double *x, double *y, const PcgScalars *S, double *part, int mode)
 {
+    // the blocks are assembled on first use: before their pointer is taken
+    if (!ctx->spmv_form && A->n > 0) SGP_TRY(bsr_blocks(ctx, A));
     return spmv_launch<double>(ctx, A, (const double *)A->val.p, (const double *)A->ew.p, (const double *)A->dg.p,
                                x, y, S, part, mode);
 }
 
 int spmv_f32(sgp_ctx ctx, sgp_bsr A, const float *x, float *y, const PcgScalars *S, double *part, int mode)
 {
+    // the FP32 copies (and the blocks they round) before their pointers are taken
+    if (A->n > 0) SGP_TRY(bsr_make32(ctx, A));
     return spmv_launch<float>(ctx, A, (const float *)A->val32.p, (const float *)A->ew32.p, (const float *)A->dg32.p,
                               x, y, S, part, mode);
 }

@@ -430,3 +430,43 @@ def test_tail_prefetch_is_bitwise_neutral(ctx):
     assert torch.equal(runs[1][0], runs[0][0])
     for (va, ia), (vb, ib) in zip(runs[1][1:], runs[0][1:]):
         assert ia["iters"] == ib["iters"] and torch.equal(va, vb)
+
+
+def test_blocks_assembled_on_first_use(ctx):
+    """Gamma's 3x3 blocks are assembled only for the block-CSR product: a
+    matrix assembled under the edge form and then multiplied in block form
+    gives that form's product (within rounding of the edge form's, and bit
+    for bit the product of a matrix assembled under the block form); block
+    Jacobi, built from the diagonal blocks of the edge form, is unchanged;
+    a graph collided again before the blocks are built is refused."""
+    c = sphere_cluster(20000, 46)
+    pos, R = to_dev(c["pos"]), to_dev(c["radius"])
+    g = ctx.collide(pos, R)
+    A = ctx.assemble_gamma(g)
+    x = torch.randn_like(pos)
+    y1 = ctx.spmv(A, x)
+    ctx.tune("spmv_form", 0)
+    try:
+        y0 = ctx.spmv(A, x)   # blocks built now
+        A0 = ctx.assemble_gamma(g)   # blocks built with the assembly
+        assert torch.equal(ctx.spmv(A0, x), y0)
+        assert float((y0 - y1).abs().max() / y1.abs().max()) <= 1e-13
+        F = to_dev(c["force"])
+        M = ctx.factor_tree(g, ctx.build_tree(g))
+        v0, i0 = ctx.pcg_solve(A, M, F)
+        assert i0["status"] == 0
+    finally:
+        ctx.tune("spmv_form", 1)
+    J = ctx.make_jacobi(A)
+    v, info = ctx.pcg_solve(A, J, to_dev(c["force"]))
+    assert info["status"] == 0
+    # a second graph handle keeps the first one's version intact; collide the
+    # same handle again with moved cells, then ask for the blocks
+    A2 = ctx.assemble_gamma(g)
+    ctx.collide(pos + 0.01, R, 32, g)
+    ctx.tune("spmv_form", 0)
+    try:
+        with pytest.raises(P.SgpError):
+            ctx.spmv(A2, x)
+    finally:
+        ctx.tune("spmv_form", 1)
