@@ -1198,7 +1198,8 @@ SGP_DEV void mid_prefetch(const SideX &sd, int32_t nside, const int32_t *elim, c
 // step of each sweep is loaded ahead (while the prologue or the window's
 // steps run), the others when their step comes.
 template <class T>
-__global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, int32_t kw, int32_t Qt, int32_t q1a,
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, int32_t kw, int32_t kx, int32_t wx,
+                                                       int32_t Qt, int32_t q1a,
                                                        int32_t nt, int32_t ni, const int32_t *sp_g, const int32_t *elim,
                                                        const int32_t *in_ptr, const int32_t *iptr,
                                                        const int32_t *tslot, const int32_t *upq, const T *F,
@@ -1332,12 +1333,22 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
         lds_barrier();
     };
     for (int32_t k = s0; k < kw; k++) fstep(k);
-    for (int32_t k = kw; k < S; k++) {
+    // the window's steps; from kx on (the last few, all of whose vertices
+    // belong to wave wx) that wave alone, with wave-level syncs
+    for (int32_t k = kw; k < kx; k++) {
         const int32_t lo = sp[k] - Qt, hi = sp[k + 1] - Qt;
         if (ir0 >= lo && ir0 < hi) fwd_one(ir0, R0.d, R0.f0, R0.f1, R0.slot0, R0.slot1, R0.in0, R0.in1);
         if (ir1 >= lo && ir1 < hi) fwd_one(ir1, R1.d, R1.f0, R1.f1, R1.slot0, R1.slot1, R1.in0, R1.in1);
         lds_barrier();
     }
+    const bool top = (tid >> 6) == wx;
+    if (top)
+        for (int32_t k = kx; k < S; k++) {
+            const int32_t lo = sp[k] - Qt, hi = sp[k + 1] - Qt;
+            if (ir0 >= lo && ir0 < hi) fwd_one(ir0, R0.d, R0.f0, R0.f1, R0.slot0, R0.slot1, R0.in0, R0.in1);
+            if (ir1 >= lo && ir1 < hi) fwd_one(ir1, R1.d, R1.f0, R1.f1, R1.slot0, R1.slot1, R1.in0, R1.in1);
+            lds_wave_barrier();
+        }
     // backward: x_q = y_q - Dinv_q (sum over up-links of F^T x), also written
     // to y (global) for the steps before the tail and to z
     auto bwd_one = [&](int32_t i, const T *d, const T *f0, const T *f1, int32_t a0, int32_t a1, int64_t v) {
@@ -1379,7 +1390,15 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(int32_t s0, int32_t S, in
         const int32_t q = vtx(sp, kw > s0 ? kw - 1 : s0);
         tail_load_bwd(pa, q, upq, elim, F, fs, Dinv);
     }
-    for (int32_t k = S - 1; k >= kw; k--) {
+    if (top)
+        for (int32_t k = S - 1; k >= kx; k--) {
+            const int32_t lo = sp[k] - Qt, hi = sp[k + 1] - Qt;
+            if (ir0 >= lo && ir0 < hi) bwd_one(ir0, R0.d, R0.f0, R0.f1, R0.up0, R0.up1, R0.id);
+            if (ir1 >= lo && ir1 < hi) bwd_one(ir1, R1.d, R1.f0, R1.f1, R1.up0, R1.up1, R1.id);
+            lds_wave_barrier();
+        }
+    lds_barrier();   // the top steps' x for every wave
+    for (int32_t k = kx - 1; k >= kw; k--) {
         const int32_t lo = sp[k] - Qt, hi = sp[k + 1] - Qt;
         if (ir0 >= lo && ir0 < hi) bwd_one(ir0, R0.d, R0.f0, R0.f1, R0.up0, R0.up1, R0.id);
         if (ir1 >= lo && ir1 < hi) bwd_one(ir1, R1.d, R1.f0, R1.f1, R1.up0, R1.up1, R1.id);
@@ -1881,8 +1900,23 @@ static int tree_sweeps(sgp_ctx ctx, sgp_prec M, const T *F, const T *Dinv, T *y,
             sd.nwg = TAIL_EXTRA_WG;
             lds = std::max(lds, (size_t)(2 * MID_MAX_STEPS * sizeof(int32_t)));
         }
+        // the last window steps whose vertices all belong to one wave (the
+        // owner of tail-local index i: i - base in the first half of the
+        // window, i - base - TAIL_THREADS in the second), which sweeps them
+        // alone
+        int32_t kx = S, wx = 0;
+        if (kw < S) {
+            auto owner = [&](int32_t i) { return i < base + TAIL_THREADS ? i - base : i - base - TAIL_THREADS; };
+            const bool hi_half = nt - 1 >= base + TAIL_THREADS;
+            wx = owner(nt - 1) / 64;
+            for (int32_t k = S - 1; k >= kw; k--) {
+                const int32_t lo = sp[k] - sp[ts];
+                if (lo < base || (lo >= base + TAIL_THREADS) != hi_half || owner(lo) / 64 != wx) break;
+                kx = k;
+            }
+        }
         k_tail<T><<<1 + (unsigned)sd.nwg, TAIL_THREADS, lds, st>>>(
-            ts, S, kw, sp[ts], q1a, nt, M->tail_ni, dsp, elim, in_ptr, (const int32_t *)M->tail_iptr.p,
+            ts, S, kw, kx, wx, sp[ts], q1a, nt, M->tail_ni, dsp, elim, in_ptr, (const int32_t *)M->tail_iptr.p,
             tslot, upq, F, fs, Dinv, tb, y, z, s, sd);
     }
     for (int k = ts - 1; k >= L; k--) {

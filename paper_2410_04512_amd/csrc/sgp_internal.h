@@ -360,6 +360,15 @@ SGP_DEV void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Wave-level counterpart of lds_barrier: orders the LDS accesses of the
+// lanes of one wave (for steps that only one wave works on).
+SGP_DEV void lds_wave_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // Sum over a 256-thread block in a fixed order; result valid in thread 0.
 SGP_DEV double block_sum_256(double v, double *sh)
 {
