@@ -169,12 +169,17 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int op, const double *part,
     __shared__ double sh[3 * FIN_THREADS / 64];
     const int k = blockIdx.x;
     PcgScalars *Sc = S + k;
-    if (op != FIN_INIT && op != FIN_TRUE && op != FIN_NORM2 && Sc->done) {
+    // the cluster's flag and its partials' range are loaded together (the
+    // range does not depend on the flag), so the partials wait for one round
+    // trip instead of two
+    const int32_t dn = Sc->done;
+    const int f = ifirst[k], nbk = inb[k];
+    keep_loads_above();
+    if (op != FIN_INIT && op != FIN_TRUE && op != FIN_NORM2 && dn) {
         // a finishing solve (its last x update has run): finished
-        if (op == FIN_ALPHA && Sc->done == 3 && threadIdx.x == 0) Sc->done = 1;
+        if (op == FIN_ALPHA && dn == 3 && threadIdx.x == 0) Sc->done = 1;
         return;
     }
-    const int f = ifirst[k], nbk = inb[k];
     double t[3] = {0.0, 0.0, 0.0};
     if (op == FIN_INIT)
         sum_partials<3>(part + f, nblk, nbk, sh, t);
