@@ -25,10 +25,12 @@ written in that form so that its gradient is exactly 2 sV (Gamma v_hat - F) /
 (v' F) with respect to `out`: it needs the residual of the guess, not v.
 
 `forward` keeps what the manual `backward` needs; gradients are pinned by
-central finite differences in the tests.  There is no reference optimiser
-here: the trained weights, and so the trained network's guesses, are parity
-unpinned (the CG solve that follows a guess is checked against the solver
-oracle instead).
+central finite differences in the tests, and `adam_step` (one update of
+the optimiser) by values worked out by hand.  The weights after a whole
+training run, and so the trained network's guesses, are parity unpinned:
+each update is checked, but the BF16 forward changes every gradient slightly
+and the differences compound over a run (the CG solve that follows a guess
+is checked against the solver oracle instead).
 """
 from __future__ import annotations
 
@@ -195,3 +197,18 @@ def bf16_round(a):
     lsb = (b >> 16) & 1
     r = ((b + 0x7FFF + lsb) >> 16) << 16
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def adam_step(theta, g, m1, m2, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba, 2015, Algorithm 1), the optimiser that
+    trains the network: the moment estimates are exponential averages of the
+    gradient and of its square, each divided by (1 - beta^t) to undo their
+    start at zero, and every parameter moves by lr times the corrected first
+    moment over (the root of the corrected second moment plus eps).  t counts
+    updates from 1.  Returns (theta, m1, m2), new arrays in float64."""
+    g = np.asarray(g, dtype=np.float64)
+    m1 = b1 * np.asarray(m1, dtype=np.float64) + (1.0 - b1) * g
+    m2 = b2 * np.asarray(m2, dtype=np.float64) + (1.0 - b2) * g * g
+    mh = m1 / (1.0 - b1 ** t)
+    vh = m2 / (1.0 - b2 ** t)
+    return np.asarray(theta, dtype=np.float64) - lr * mh / (np.sqrt(vh) + eps), m1, m2

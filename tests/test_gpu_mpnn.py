@@ -90,6 +90,37 @@ def test_training_lowers_the_loss(ctx):
     assert losses[-1] < 0.5 * losses[0], losses[::10]
 
 
+def test_adam_updates_match_oracle(ctx):
+    """Each training update (sgp_mpnn_train_step) against the oracle's Adam
+    step applied to the same gradient (sgp_mpnn_grad at the same parameters:
+    bitwise the gradient the update uses) from the same parameters, with the
+    moments carried in FP64 from the GPU's gradients.  Tolerance: the
+    update runs in FP32, whose 1 - beta2^t for t = 2, 3 loses ~3e-5 to
+    cancellation, so 1e-4 of the step size lr (Adam's steps are about lr)
+    plus one FP32 rounding of the parameter; a wrong moment, bias
+    correction, eps placement or sign moves a step by a large fraction."""
+    c, og, vprev, v = _sample(3000, 7)
+    M = P.Mpnn(ctx)
+    M.set_params(N.init_params(3), float(c["force"].std()), float(v.std()), 0.1)
+    g = ctx.collide(to_dev(c["pos"]), to_dev(c["radius"]))
+    args = (g, to_dev(c["force"]), to_dev(vprev), to_dev(v))
+    lr = 1e-3
+    th = host(M.get_params()).astype(np.float64)
+    m1 = m2 = np.zeros_like(th)
+    for t in range(1, 4):
+        _, gr = M.grad(*args)
+        gr = host(gr).astype(np.float64)
+        M.train_step(*args, lr)
+        th_gpu = host(M.get_params()).astype(np.float64)
+        ref, m1, m2 = N.adam_step(th, gr, m1, m2, t, lr)
+        err = np.abs(th_gpu - ref)
+        tol = 1e-4 * lr + 2.0 ** -23 * np.abs(ref)
+        print(f"adam step {t}: max |gpu - oracle| {err.max():.3e}, moved {np.abs(th_gpu - th).max():.3e}", flush=True)
+        assert np.all(err <= tol), (t, int(np.argmax(err - tol)))
+        assert np.count_nonzero(th_gpu != th) >= 0.5 * np.count_nonzero(gr) > 0
+        th = th_gpu
+
+
 def test_energy_gradients_match_oracle(ctx):
     """Energy loss ||v_hat - v||^2_Gamma / ||v||^2_Gamma: value and gradient
     against the oracle (Gamma from the oracle's assembly), same tolerance."""

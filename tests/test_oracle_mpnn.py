@@ -191,3 +191,31 @@ def test_hand_computed_three_cell_forward():
     rows, e = N.edge_features(g.rowptr, g.col, g.ei, g.ej, g.w, g.u, ee, scales[2])
     out, _ = N.forward(theta, F, vprev, g.rowptr, g.col, e, rows, scales)
     assert np.allclose(scales[1] * out, want, rtol=1e-12, atol=1e-15), scales[1] * out
+
+
+def test_adam_step_closed_forms():
+    """The optimiser's update against values worked out by hand from its
+    definition: the first step from zero moments moves every parameter by
+    lr g / (|g| + eps) (the bias corrections give back g and g^2); a constant
+    gradient keeps that step at every t; two different gradients give the
+    rational moments below; eps sits outside the root; no gradient, no move."""
+    lr, eps = 1e-3, 1e-8
+    th0 = np.array([0.5, -1.0, 2.0, 0.0, 3.0])
+    g = np.array([0.25, -4.0, 1e-9, 0.0, 7.0])
+    z = np.zeros_like(g)
+    th1, m1, m2 = N.adam_step(th0, g, z, z, 1, lr)
+    assert np.allclose(th1 - th0, -lr * g / (np.abs(g) + eps), rtol=1e-12, atol=0.0)
+    # |g| = 1e-9: a step of lr / 11 (eps under the root would give ~lr 1e-5)
+    assert abs((th1[2] - th0[2]) + lr / 11.0) <= 1e-12 * lr
+    assert th1[3] == th0[3]
+    # fifty steps of one constant gradient
+    th, a, b = th0, z, z
+    for t in range(1, 51):
+        th, a, b = N.adam_step(th, g, a, b, t, lr)
+    assert np.allclose(th - th0, -50 * lr * g / (np.abs(g) + eps), rtol=1e-10, atol=1e-15)
+    # g = 1 then g = -2: corrected moments -11/19 and 4999/1999 at t = 2
+    s, a, b = N.adam_step(np.array([0.0]), np.array([1.0]), np.zeros(1), np.zeros(1), 1, lr)
+    assert abs(s[0] + lr / (1.0 + eps)) <= 1e-15
+    s2, a, b = N.adam_step(s, np.array([-2.0]), a, b, 2, lr)
+    step2 = -lr * (-11.0 / 19.0) / (np.sqrt(4999.0 / 1999.0) + eps)
+    assert abs((s2[0] - s[0]) - step2) <= 1e-12 * abs(step2)
