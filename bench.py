@@ -48,7 +48,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a 512 MiB copy
 # read and write 512 MiB (summary and commands under profiles/).  Must be
 # re-measured, or set to None, whenever that kernel changes.
-SPMV_TRAFFIC_1M = {0: None, 1: 418.0e6}
+SPMV_TRAFFIC_1M = {0: None, 1: 418.2e6}
 
 
 def spmv_bytes(n: int, nnzb: int, form: int = 1, val_bytes: int = 48) -> int:

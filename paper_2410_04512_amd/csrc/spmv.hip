@@ -221,6 +221,13 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_edge(const int32_t *__
     // bounds, the first row's diagonal block, x and row pointers, and the
     // gathers.
     // EDGES = false: a product without entries (ne = 0), diagonal blocks only.
+    // The entries, columns and diagonal blocks are read once per product,
+    // and each load instruction takes whole cache lines of them (64-wide
+    // planes), so they are loaded non-temporally: the ~340 MB they stream
+    // then no longer pushes out of the caches the vectors that the next
+    // kernels read (q just written, r).  Data read by a thread as several
+    // short loads of one line loses from it (the line leaves before its
+    // other loads come), so the sweeps' constants keep ordinary loads.
     const int64_t wc = min(w, nwaves - 1);
     int32_t r_lo = wrow[wc], r_hi = wrow[wc + 1];
     T e[EDGE_GROUPS][EDGE_PLANES], xv[EDGE_GROUPS][3];
@@ -230,8 +237,8 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_edge(const int32_t *__
         for (int q = 0; q < EDGE_GROUPS; q++) {
             const int64_t k = min(base + 64 * q + lane, ne - 1);
             const T *g = ew + (k >> 6) * (64 * EDGE_PLANES) + (k & 63);
-            for (int t = 0; t < EDGE_PLANES; t++) e[q][t] = g[64 * t];
-            j[q] = ecol[k];
+            for (int t = 0; t < EDGE_PLANES; t++) e[q][t] = __builtin_nontemporal_load(g + 64 * t);
+            j[q] = __builtin_nontemporal_load(ecol + k);
         }
     }
     if (w >= nwaves) r_hi = r_lo;
@@ -244,7 +251,7 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_edge(const int32_t *__
     {
         const int32_t rc = max(min(row0, r_hi - 1), 0);
         const T *dgr = dg + ((int64_t)rc >> 6) * 384 + (rc & 63);
-        for (int t = 0; t < 6; t++) dr[t] = dgr[64 * t];
+        for (int t = 0; t < 6; t++) dr[t] = __builtin_nontemporal_load(dgr + 64 * t);
         for (int t = 0; t < 3; t++) pr[t] = x[3 * (int64_t)rc + t];
         rp0 = rowptr[rc];
         rp1 = rowptr[rc + 1];
@@ -279,7 +286,7 @@ __global__ __launch_bounds__(64 * SPMV_WAVES) void k_spmv_edge(const int32_t *__
     for (int32_t row = row0; row < r_hi; row += 64) {
         if (row != row0) {
             const T *dgr = dg + ((int64_t)row >> 6) * 384 + (row & 63);
-            for (int t = 0; t < 6; t++) dr[t] = dgr[64 * t];
+            for (int t = 0; t < 6; t++) dr[t] = __builtin_nontemporal_load(dgr + 64 * t);
             for (int t = 0; t < 3; t++) pr[t] = x[3 * (int64_t)row + t];
             rp0 = rowptr[row];
             rp1 = rowptr[row + 1];
