@@ -476,7 +476,8 @@ __global__ __launch_bounds__(256) void k_update_r_s0(T *r, const T *q, BlockTab 
 #pragma unroll
         for (int u = 0; u < VEC_EPT; u++) {
             rv[u] = r[e0 + vec_idx(u, ne)];
-            qx[u] = q[e0 + vec_idx(u, ne)];
+            // q's last read (non-temporal: r and the sweeps' data stay cached)
+            qx[u] = __builtin_nontemporal_load(q + e0 + vec_idx(u, ne));
         }
     }
     // this thread's first-step vertex (a thread without one reads position 0
@@ -672,7 +673,9 @@ __global__ __launch_bounds__(256) void k_update_p(T *p, const T *z, BlockTab tab
 #pragma unroll
     for (int u = 0; u < VEC_EPT; u++) {
         pv[u] = p[e0 + vec_idx(u, ne)];
-        zv[u] = z[e0 + vec_idx(u, ne)];
+        // z's last read in an iteration: non-temporal, so that it does not
+        // displace p, which the product gathers next
+        zv[u] = __builtin_nontemporal_load(z + e0 + vec_idx(u, ne));
     }
     if (Sc->done || ne == 0) return;
     const T beta = (T)Sc->beta;
