@@ -184,3 +184,44 @@ def test_workload_tree_depth_and_components():
     assert (t.parent < 0).sum() == 1 and t.parent[0] == -1
     assert len(t.tree_edge) == 999
     assert t.depth.max() == 83
+
+
+def _elimination_game_fill(n, edges, order):
+    """Fill edges made by eliminating vertices in `order` (Section 3.2's
+    elimination game): each eliminated vertex's remaining neighbours become
+    pairwise adjacent."""
+    adj = [set() for _ in range(n)]
+    for a, b in edges:
+        adj[a].add(b)
+        adj[b].add(a)
+    fill = 0
+    for v in order:
+        nb = sorted(adj[v])
+        for i in range(len(nb)):
+            for j in range(i + 1, len(nb)):
+                a, b = nb[i], nb[j]
+                if b not in adj[a]:
+                    adj[a].add(b)
+                    adj[b].add(a)
+                    fill += 1
+        for a in nb:
+            adj[a].discard(v)
+        adj[v].clear()
+    return fill
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_elimination_game_no_fill(seed):
+    """Lemma nofill: the oracle's order (no vertex before its children) plays
+    the elimination game on its spanning tree without a single fill edge; the
+    reversed order (roots first) on the same tree does make fill, so the
+    game counts it."""
+    c = sphere_cluster(80, seed)
+    g = O.collide(c["pos"], c["radius"])
+    t = O.build_tree(g)
+    edges = [(int(g.ei[e]), int(g.ej[e])) for e in t.tree_edge]
+    assert _elimination_game_fill(g.n, edges, list(t.order)) == 0
+    assert _elimination_game_fill(g.n, edges, list(t.order)[::-1]) > 0
+    # and on a hand-made path 0-1-2: eliminating the middle first makes one fill edge
+    assert _elimination_game_fill(3, [(0, 1), (1, 2)], [1, 0, 2]) == 1
+    assert _elimination_game_fill(3, [(0, 1), (1, 2)], [0, 1, 2]) == 0
